@@ -1,0 +1,273 @@
+"""Discrete operators of the oracle (test infrastructure only).
+
+Every operator follows the weak forms of the "Hybrid fluid-BTE solver" section.
+Readings used here (where the paper is silent, garbled or ambiguous):
+
+* collision weight: the speed integrals of eq. (c_en_mat_1d) carry v^3 (the
+  v^2 of the volume element times the collision frequency n0 v sigma), so that
+  the mass-scaled operator has units of 1/s;
+* gain multiplicity g_s: 1 for elastic and excitation, 2 for ionization (two
+  electrons leave each ionizing collision, each with half the excess energy,
+  Table of collisions); excitation leaves eps - eps_th;
+* eq. (c_T0_mat_1d): negative semi-definite, acting on the l = 0 block only and
+  built from the elastic cross section, so that the gas Maxwellian at T0 is the
+  null state of the elastic operator;
+* eq. (adv_v_ws): the printed coupling coefficients are not used; the operator
+  is the Galerkin projection of (eE/m_e)(cos th d/dv - sin th / v d/dth) of
+  eq. (bte-1d) with q_e = +e, its angular factors <Y_q|mu|Y_l> and
+  <Y_q|(1-mu^2) d/dmu|Y_l> evaluated exactly by Gauss-Legendre quadrature;
+* speed boundary conditions: none (natural) at v = 0 and v = vmax.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import scipy.linalg as sla
+
+from .basis import (bspline_basis, bspline_basis_deriv, bspline_knots, cheb_diff, cgl_nodes,
+                    composite_gauss, gl_nodes, sph_harm_m0, sph_harm_m0_deriv)
+
+# Physical constants (CODATA 2018)
+E_CHARGE = 1.602176634e-19
+M_ELECTRON = 9.1093837015e-31
+K_BOLTZMANN = 1.380649e-23
+EPS0 = 8.8541878128e-12
+
+KIND_ELASTIC, KIND_EXCITATION, KIND_IONIZATION = 0, 1, 2
+N_GAUSS = 12   # points per smooth sub-interval (exact for polynomial degree 23)
+
+
+def speed_of(eps_eV):
+    return np.sqrt(2.0 * E_CHARGE * np.asarray(eps_eV, dtype=np.float64) / M_ELECTRON)
+
+
+def energy_of(v):
+    return 0.5 * M_ELECTRON * np.asarray(v, dtype=np.float64) ** 2 / E_CHARGE
+
+
+def sigma_of_speed(proc, v):
+    """Cross section at speed v: linear interpolation of the table in energy."""
+    return np.interp(energy_of(v), proc["eps_eV"], proc["sigma_m2"])
+
+
+# --- speed-space integrals ------------------------------------------------------------
+def mass_like(knots, nr, weight_pow):
+    """int_0^vmax v^weight_pow phi_p phi_k dv (M: pow 2, G: pow 3)."""
+    x, w = composite_gauss(knots, N_GAUSS)
+    P = bspline_basis(knots, x, nr)
+    return P.T @ (P * (w * x ** weight_pow)[:, None])
+
+
+def adv_speed_parts(knots, nr):
+    """D1[p,k] = int v^2 phi_p phi_k' dv and D0[p,k] = int v phi_p phi_k dv."""
+    x, w = composite_gauss(knots, N_GAUSS)
+    P = bspline_basis(knots, x, nr)
+    dP = bspline_basis_deriv(knots, x, nr)
+    D1 = P.T @ (dP * (w * x ** 2)[:, None])
+    D0 = P.T @ (P * (w * x)[:, None])
+    return D1, D0
+
+
+def moment_vector(knots, nr, power, weight_fn=None, extra_breaks=()):
+    """int_0^vmax v^power w(v) phi_k dv (w piecewise smooth between knots and extra_breaks)."""
+    vmax = knots[-1]
+    br = np.concatenate([knots, np.asarray(extra_breaks, dtype=np.float64)])
+    x, w = composite_gauss(br[(br >= 0) & (br <= vmax)], N_GAUSS)
+    P = bspline_basis(knots, x, nr)
+    ww = w * x ** power
+    if weight_fn is not None:
+        ww = ww * weight_fn(x)
+    return P.T @ ww
+
+
+def _breaks_in_v(knots, proc, bin_edges_v, vmax):
+    tab_v = speed_of(proc["eps_eV"])
+    br = np.concatenate([knots, tab_v[tab_v < vmax], bin_edges_v, [0.0, vmax]])
+    if proc["threshold_eV"] > 0:
+        br = np.concatenate([br, [speed_of(proc["threshold_eV"])]])
+    return br[(br >= 0) & (br <= vmax)]
+
+
+def collision_parts(knots, nr, proc, bin_edges_v, T0_K):
+    """Per energy bin b: (Loss_b, Gain_b, CT_b) Nr x Nr matrices of process ``proc``.
+
+    Loss_b[p,k] = int_{bin b} v^3 sigma phi_p(v) phi_k(v) dv
+    Gain_b[p,k] = int_{bin b} v^3 sigma phi_k(v) phi_p(u(v)) dv   (u = post-collision speed)
+    CT_b[p,k]   = -(k_B T0 / m0) int_{bin b} v^3 sigma phi_p'(v) phi_k'(v) dv  (elastic only)
+    Bins refer to the pre-collision energy.
+    """
+    vmax = knots[-1]
+    kind = proc["kind"]
+    nb = len(bin_edges_v) - 1
+    out = []
+    # loss term, C_T and elastic gain: polynomial integrands between the breakpoints in v
+    br = _breaks_in_v(knots, proc, bin_edges_v, vmax)
+    c_el = math.sqrt(1.0 - 2.0 * proc["mass_ratio"]) if kind == KIND_ELASTIC else None
+    if kind == KIND_ELASTIC:
+        br = np.concatenate([br, knots / c_el])
+        br = br[br <= vmax]
+    x, w = composite_gauss(br, N_GAUSS)
+    sig = sigma_of_speed(proc, x)
+    P = bspline_basis(knots, x, nr)
+    dP = bspline_basis_deriv(knots, x, nr)
+    Pu = bspline_basis(knots, c_el * x, nr) if kind == KIND_ELASTIC else None
+    bin_of_x = np.clip(np.searchsorted(bin_edges_v, x, side="right") - 1, 0, nb - 1)
+    # inelastic gain: integrate in the post-collision speed u where phi_p(u) is polynomial
+    if kind != KIND_ELASTIC:
+        alpha = 1.0 if kind == KIND_EXCITATION else 2.0
+        vth = speed_of(proc["threshold_eV"])
+        if vth < vmax:
+            def u_of_v(v):
+                return np.sqrt(np.maximum(v * v - vth * vth, 0.0) / alpha)
+            umax = u_of_v(vmax)
+            vb = np.concatenate([knots, speed_of(proc["eps_eV"]), bin_edges_v])
+            vb = vb[(vb > vth) & (vb < vmax)]
+            ubr = np.concatenate([[0.0, umax], knots[knots < umax], u_of_v(vb)])
+            xu, wu = composite_gauss(ubr[(ubr >= 0) & (ubr <= umax)], N_GAUSS)
+            vv = np.sqrt(alpha * xu * xu + vth * vth)
+            sig_u = sigma_of_speed(proc, vv)
+            Pk = bspline_basis(knots, vv, nr)
+            Pp = bspline_basis(knots, xu, nr)
+            bin_u = np.clip(np.searchsorted(bin_edges_v, vv, side="right") - 1, 0, nb - 1)
+    kT_m0 = K_BOLTZMANN * T0_K * proc["mass_ratio"] / M_ELECTRON
+    for b in range(nb):
+        m = (bin_of_x == b).astype(np.float64)
+        wt = w * x ** 3 * sig * m
+        Loss = P.T @ (P * wt[:, None])
+        CT = np.zeros((nr, nr))
+        if kind == KIND_ELASTIC:
+            Gain = Pu.T @ (P * wt[:, None])
+            if T0_K > 0:
+                CT = -kT_m0 * (dP.T @ (dP * wt[:, None]))
+        else:
+            Gain = np.zeros((nr, nr))
+            if vth < vmax:
+                mu_ = (bin_u == b).astype(np.float64)
+                wtu = wu * vv ** 2 * sig_u * alpha * xu * mu_
+                Gain = Pp.T @ (Pk * wtu[:, None])
+        out.append((Loss, Gain, CT))
+    return out
+
+
+def gain_multiplicity(kind):
+    return 2.0 if kind == KIND_IONIZATION else 1.0
+
+
+# --- angular couplings -----------------------------------------------------------------
+def angular_parts(nth, nl):
+    """T_O, T_S (eq. proj_ops) and the exact Galerkin couplings a_ql, b_ql."""
+    mu, w = gl_nodes(nth)
+    W = 2.0 * math.pi * w
+    Y = np.stack([sph_harm_m0(l, mu) for l in range(nl)], axis=1)        # [a, l]
+    dY = np.stack([sph_harm_m0_deriv(l, mu) for l in range(nl)], axis=1)
+    T_O = Y.copy()                                                       # [a, l]
+    T_S = (Y * W[:, None]).T                                             # [l, a]
+    a_cpl = (Y * (W * mu)[:, None]).T @ Y                                # <Y_q | mu | Y_l>
+    b_cpl = (Y * (W * (1.0 - mu ** 2))[:, None]).T @ dY                  # <Y_q | (1-mu^2) d_mu | Y_l>
+    return mu, w, T_O, T_S, a_cpl, b_cpl
+
+
+@dataclasses.dataclass
+class Operators:
+    cfg: dict
+    nx: int
+    nr: int
+    nth: int
+    nl: int
+    L: float
+    dt: float
+    n0: float
+    vmax: float
+    knots: np.ndarray
+    xhat: np.ndarray
+    Dx: np.ndarray
+    mu: np.ndarray
+    w: np.ndarray
+    T_O: np.ndarray
+    T_S: np.ndarray
+    M: np.ndarray
+    G: np.ndarray
+    lam: np.ndarray
+    U: np.ndarray
+    Uinv: np.ndarray
+    Cord_sb: list          # [(s, b)] -> ordinate-space collision operator per unit n0, scal = 1
+    scal: np.ndarray       # [n_proc, n_bins]
+    Cord: np.ndarray       # sum_sb scal * Cord_sb
+    Aord: np.ndarray       # ordinate-space acceleration operator per unit E
+    u_ord: np.ndarray      # number-density functional
+    e_ord: np.ndarray      # energy-density functional [eV m^-3]
+    ki_ord: np.ndarray     # ionization-rate functional (times n_e) [m^3/s m^-3]
+    moment_m: np.ndarray   # int v^2 phi_k
+    Poisson: np.ndarray    # E = Poisson @ rhs with rhs = [V_left, -(e/eps0)(ni-ne)_interior, 0]
+
+
+def ordinate(Minv, T_O, T_S, Xharm):
+    """P_O (M^-1 (x) I_l) X P_S with P_S = I_v (x) T_S, P_O = I_v (x) T_O (eq. proj_ops)."""
+    nr = Minv.shape[0]
+    left = np.kron(Minv, T_O)
+    right = np.kron(np.eye(nr), T_S)
+    return left @ Xharm @ right
+
+
+def build_operators(cfg: dict, scal=None, with_bins=True) -> Operators:
+    """Assemble every operator of the semi-implicit step from a workload dict."""
+    nx, nr, nth, nl = cfg["nx"], cfg["nr"], cfg["ntheta"], cfg["nl"]
+    L = cfg["L_m"]
+    vmax = float(speed_of(cfg["eps_max_eV"]))
+    knots = bspline_knots(nr, vmax, cfg.get("v_bc", "natural"))
+    xhat = cgl_nodes(nx)
+    Dx = (2.0 / L) * cheb_diff(nx)
+    mu, w, T_O, T_S, a_cpl, b_cpl = angular_parts(nth, nl)
+    M = mass_like(knots, nr, 2)
+    G = mass_like(knots, nr, 3)
+    Minv = np.linalg.inv(M)
+    lam, U = sla.eigh(G, M)                 # G u = lam M u, U^T M U = I
+    Uinv = U.T @ M
+    procs = cfg["processes"]
+    nb = int(cfg.get("n_bins", 1))
+    bin_edges_v = speed_of(np.asarray(cfg.get("bin_edges_eV", np.linspace(0, cfg["eps_max_eV"], nb + 1))))
+    if scal is None:
+        scal = np.asarray(cfg.get("scal", np.ones((len(procs), nb))), dtype=np.float64).reshape(len(procs), nb)
+    e00 = np.zeros((nl, nl))
+    e00[0, 0] = 1.0
+    Il = np.eye(nl)
+    Cord_sb = []
+    Cord = np.zeros((nr * nth, nr * nth))
+    for s, proc in enumerate(procs):
+        g = gain_multiplicity(proc["kind"])
+        for b, (Loss, Gain, CT) in enumerate(collision_parts(knots, nr, proc, bin_edges_v, cfg["T0_K"])):
+            Charm = np.kron(g * Gain + CT, e00) - np.kron(Loss, Il)
+            Cb = ordinate(Minv, T_O, T_S, Charm)
+            Cord_sb.append(Cb)
+            Cord += scal[s, b] * Cb
+    D1, D0 = adv_speed_parts(knots, nr)
+    Aharm = (E_CHARGE / M_ELECTRON) * (np.kron(D1, a_cpl) + np.kron(D0, b_cpl))
+    Aord = ordinate(Minv, T_O, T_S, Aharm)
+    W = 2.0 * math.pi * w
+    m2 = moment_vector(knots, nr, 2)
+    m4 = moment_vector(knots, nr, 4)
+    u_ord = np.kron(m2, W)
+    e_ord = (0.5 * M_ELECTRON / E_CHARGE) * np.kron(m4, W)
+    ki = np.zeros(nr)
+    for s, proc in enumerate(procs):
+        if proc["kind"] == KIND_IONIZATION:
+            for b in range(nb):
+                lo, hi = bin_edges_v[b], bin_edges_v[b + 1]
+                ki += scal[s, b] * moment_vector(
+                    knots, nr, 3, lambda v, p=proc, lo=lo, hi=hi: sigma_of_speed(p, v) * ((v >= lo) & (v < hi)),
+                    extra_breaks=_breaks_in_v(knots, proc, bin_edges_v, vmax))
+    ki_ord = np.kron(ki, W)
+    # Poisson: Delta V = -(e/eps0)(ni - ne), V(x=0) = V_left, V(x=L) = 0, E = -dV/dx
+    D2 = Dx @ Dx
+    D2[0, :] = 0.0
+    D2[0, 0] = 1.0
+    D2[-1, :] = 0.0
+    D2[-1, -1] = 1.0
+    Poisson = -Dx @ np.linalg.inv(D2)
+    n0 = cfg["n0_m3"]
+    return Operators(cfg=cfg, nx=nx, nr=nr, nth=nth, nl=nl, L=L, dt=cfg["dt_s"], n0=n0, vmax=vmax,
+                     knots=knots, xhat=xhat, Dx=Dx, mu=mu, w=w, T_O=T_O, T_S=T_S, M=M, G=G,
+                     lam=lam, U=U, Uinv=Uinv, Cord_sb=Cord_sb, scal=scal, Cord=Cord, Aord=Aord,
+                     u_ord=u_ord, e_ord=e_ord, ki_ord=ki_ord, moment_m=m2, Poisson=Poisson)
