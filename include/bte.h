@@ -1,0 +1,221 @@
+/*
+ * bte.h -- C-ABI of the MI355X (gfx950) semi-implicit 1D-space electron BTE step.
+ *
+ * The library advances the electron distribution f(x, v, theta) of the
+ * 1D3V Boltzmann transport equation (eq. bte-1d of the paper, "The electron
+ * Boltzmann transport equation" section) by the semi-implicit split step of
+ * eq. (bte_semi_implicit), "Hybrid solver time integration" section:
+ *
+ *     X(dt/2) -> field E^{1/2} -> V(dt) -> X(dt/2)
+ *
+ * with Chebyshev collocation in x, a Galerkin cubic B-spline basis in speed
+ * and Gauss-Legendre discrete ordinates in the polar angle (eqs. f_expansion,
+ * proj_ops, A_x, bte_1d_discrete).  The velocity-space step solves, at every
+ * collocation point x_i, the dense system of eq. (vspace_batched_system)
+ *
+ *     (I - dt (n0 C + E_i A)) F*_i = F_i        (n = Nr * Ntheta unknowns)
+ *
+ * by a batched LU factorization with partial pivoting on the GPU; the spatial
+ * step applies the precomputed inverses Q_ij of the per-(eigen-speed,
+ * ordinate) Chebyshev systems (Alg. bte_spatial_adv).
+ *
+ * State layout (all device arrays, FP64, owned by the caller):
+ *   F[x][k][a]  x: collocation point (ascending xhat = -cos(pi i/(Nx-1))),
+ *               k: B-spline in speed, a: ordinate (ascending cos theta_a);
+ *               f(x_i, v, theta_a) = sum_k F[i][k][a] phi_k(v)  [m^-3 (m/s)^-3].
+ *   With several discharges the per-discharge blocks are concatenated along x
+ *   (total sum_d Nx_d rows).
+ *
+ * Conventions:
+ *   - Every device buffer passed in is allocated and owned by the caller; the
+ *     library only reads/writes it on the given stream.  The handle owns all
+ *     operator and workspace memory from setup until bte_destroy.
+ *   - Argument errors are returned synchronously.  Device-side failures
+ *     (refinement not converged, non-finite values, zero pivot) are latched in
+ *     a device status word; bte_get_status or the next synchronous query
+ *     returns them.
+ *   - A handle must not be used on two streams at the same time.
+ *   - Units are SI, energies at this boundary are in eV.
+ *   - ``stream`` is a hipStream_t (NULL = the null stream).
+ */
+#ifndef BTE_H
+#define BTE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BTE_OK = 0,
+  BTE_EINVAL = -1,        /* invalid argument (sizes, null pointers, modes)            */
+  BTE_EHIP = -2,          /* a HIP runtime call failed                                  */
+  BTE_ESINGULAR = -3,     /* exactly zero pivot in a velocity-space factorization       */
+  BTE_ENOCONV = -4,       /* mixed-precision refinement did not reach refine_rtol       */
+  BTE_ENOMEM = -5,        /* device allocation failed                                   */
+  BTE_ENONFINITE = -6,    /* NaN/Inf found in the state                                 */
+  BTE_EUNSUPPORTED = -7   /* valid request that this build does not implement           */
+} bte_status;
+
+typedef enum {
+  BTE_FP64 = 0,           /* FP64 LU (MFMA f64) and FP64 advection                       */
+  BTE_MIXED_FP32 = 1,     /* FP32 LU + FP64 iterative refinement of the V-step residual  */
+  BTE_MIXED_BF16 = 2      /* as MIXED_FP32, trailing updates split into bf16 hi/lo terms */
+} bte_precision;
+
+typedef enum { BTE_ELASTIC = 0, BTE_EXCITATION = 1, BTE_IONIZATION = 2 } bte_process_kind;
+
+typedef enum {
+  BTE_VBC_NATURAL = 0,    /* no condition at v = 0 or v = vmax (Nr clamped splines)             */
+  BTE_VBC_ZERO_VMAX = 1   /* f(vmax) = 0: Nr+1 clamped splines, the one non-zero at vmax dropped */
+} bte_vbc;
+
+typedef enum {
+  BTE_FIELD_CONST = 0,    /* E = E0_d everywhere                                                */
+  BTE_FIELD_RF = 1,       /* E = E0_d sin(2 pi f (t + dt/2)) (1 + a1 xhat)                      */
+  BTE_FIELD_GIVEN = 2,    /* E^{1/2} supplied by the caller (bte_field.E_half)                  */
+  BTE_FIELD_POISSON = 3   /* eq. bte_semi_implicit_efield: Delta V = -(e/eps0)(n_i - n_e),     */
+                          /* V(0) = V0 sin(2 pi f (t + dt/2)), V(L) = 0, E = -dV/dx              */
+} bte_field_mode;
+
+/* One electron-neutral collision process (Table of collisions; the hybrid
+ * model's operator sum of the "Hybrid fluid-BTE solver" section).  The cross
+ * section is a table interpolated linearly in energy.  Host arrays, copied. */
+typedef struct {
+  int32_t kind;             /* bte_process_kind                                      */
+  double threshold_eV;      /* excitation / ionization threshold (ignored: elastic)  */
+  double mass_ratio;        /* m_e / m0 (elastic energy loss, gas-temperature term)  */
+  int32_t n_tab;            /* >= 2                                                  */
+  const double* eps_eV;     /* [n_tab] ascending                                     */
+  const double* sigma_m2;   /* [n_tab]                                               */
+} bte_process;
+
+typedef struct {
+  int32_t nx, nr, ntheta, nl;   /* nl must equal ntheta; nx per discharge if n_discharges == 1 */
+  int32_t v_bc;                 /* bte_vbc                                                      */
+  double L_m;                   /* electrode gap                                                */
+  double eps_max_eV;            /* speed domain [0, sqrt(2 e eps_max / m_e)]                    */
+  double T0_K;                  /* gas temperature (eq. c_T0_mat_1d)                            */
+  double dt_s;                  /* time step                                                    */
+  int32_t n_proc;
+  const bte_process* proc;      /* host [n_proc]                                                */
+  int32_t n_bins;               /* energy bins of the cross-section scalings (>= 1)             */
+  const double* bin_edges_eV;   /* host [n_bins+1] or NULL (= one bin [0, eps_max])             */
+  const double* scal;           /* host [n_proc*n_bins] multiplicative scalings or NULL (= 1)   */
+  int32_t precision;            /* bte_precision                                                */
+  int32_t refine_max_iter;      /* mixed modes: max refinement sweeps (<= 0: 10)                */
+  double refine_rtol;           /* mixed modes: stop at max|r| <= rtol max|b| (<= 0: 1e-14)     */
+  int32_t field_mode;           /* bte_field_mode                                               */
+  double field_freq_hz;         /* RF / Poisson voltage frequency                               */
+  double field_a1;              /* RF spatial profile coefficient                               */
+  double poisson_V0;            /* Poisson mode: peak electrode voltage                         */
+  int32_t n_discharges;         /* >= 1; >1 = uneven ensemble (batching form)                   */
+  const int32_t* nx_per;        /* host [n_discharges] or NULL when n_discharges == 1           */
+  const double* n0_per;         /* host [n_discharges] neutral densities [m^-3]                  */
+  const double* E0_per;         /* host [n_discharges] field amplitudes [V/m] (CONST / RF)       */
+} bte_config;
+
+/* Per-call field data for the GIVEN and POISSON modes (device arrays, [sum Nx]). */
+typedef struct {
+  const double* E_half;         /* GIVEN: E^{1/2} at every collocation point */
+  const double* ni;             /* POISSON: ion density                      */
+} bte_field;
+
+typedef struct bte_handle bte_handle;   /* opaque */
+
+typedef struct {
+  int32_t nx_total;             /* sum_d Nx_d                          */
+  int32_t n;                    /* Nr * Ntheta                          */
+  int32_t n_params;             /* n_proc * n_bins                      */
+  int32_t n_discharges;
+  double vmax;                  /* m/s                                  */
+  double bytes_device;          /* device memory held by the handle     */
+  double lu_flops_per_step;     /* (2/3) n^3 * nx_total                 */
+  double q_bytes_per_half_step; /* HBM bytes of Q streamed per X(dt/2)  */
+} bte_info;
+
+/* Setup (synchronous).  Assembles every operator in FP64 on the host --
+ * mass matrices, collision operator eq. (c_en_mat_1d) with the gas-temperature
+ * term eq. (c_T0_mat_1d), acceleration eq. (adv_v_ws), projections
+ * eq. (proj_ops), the eigen-decomposition of G_v and the inverses Q_ij of the
+ * X systems (with zero-inflow rows, eq. hybrid_cnt_b_bdy) -- and uploads them to
+ * device ``hip_device``.  On success *out owns the device memory.
+ * Errors: BTE_EINVAL (bad sizes/modes), BTE_ENOMEM, BTE_EHIP. */
+bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle** out);
+
+/* One semi-implicit step F^n -> F^{n+1} at time t_s (eq. bte_semi_implicit),
+ * in place.  Asynchronous on ``stream``; no host synchronization.
+ * Errors (synchronous): BTE_EINVAL.  Device errors are latched. */
+bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void* stream);
+
+/* Moments of F (eq. hybrid_discrete_c; k_i of the hybrid model): out[0][x] =
+ * n_e [m^-3], out[1][x] = mean energy [eV], out[2][x] = ionization rate
+ * coefficient k_i [m^3/s] (0 where n_e == 0).  out is device [3][sum Nx]. */
+bte_status bte_moments(bte_handle* h, const double* F, double* out, void* stream);
+
+/* Vector-Jacobian product of bte_moments: lam[x] += sum_q gbar[q][x] d out[q][x] / d F[x].
+ * gbar: device [3][sum Nx]; lam: device like F (accumulated). */
+bte_status bte_moments_vjp(bte_handle* h, const double* F, const double* gbar, double* lam, void* stream);
+
+/* Transposed (adjoint) step for the specified-field modes (CONST, RF, GIVEN).
+ * F_n is the state at t_s (the step is recomputed internally).  On entry lam
+ * holds dL/dF^{n+1}; on exit dL/dF^n through this step.  With F* = A^-1 X F^n
+ * and mu = A^-T X^T lam:
+ *   grad_scal[s*n_bins+b] += dt n0_d sum_x mu_x^T C^(s,b) F*_x   (device [n_params], accumulated)
+ *   grad_E0[d]           += sum_{x in d} (dL/dE_x) dE_x/dE0_d    (device [n_discharges], accumulated; may be NULL)
+ *   grad_E[x]             = dt mu_x^T A F*_x                     (device [sum Nx], overwritten; may be NULL)
+ * POISSON mode returns BTE_EUNSUPPORTED. */
+bte_status bte_adjoint_step(bte_handle* h, const double* F_n, double t_s, bte_field field, double* lam,
+                            double* grad_scal, double* grad_E0, double* grad_E, void* stream);
+
+/* F = n_e(x) * (Galerkin projection of the unit-density Maxwellian at Te), the
+ * same on every ordinate.  ne: device [sum Nx]; F: device like the state. */
+bte_status bte_initial_maxwellian(bte_handle* h, const double* ne, double Te_eV, double* F, void* stream);
+
+/* Sub-steps of bte_step, for tests and instrumentation (same kernels):
+ *   bte_xstep:   F <- X(dt/2) F                         (Alg. bte_spatial_adv)
+ *   bte_xstep_T: F <- X(dt/2)^T F
+ *   bte_vstep:   F <- (I - dt(n0 C + E A))^-1 F at every x, E device [sum Nx]
+ *   bte_field_eval: E_out <- E^{1/2} at t_s for state F^{n+1/2} (device [sum Nx]) */
+bte_status bte_xstep(bte_handle* h, double* F, void* stream);
+bte_status bte_xstep_T(bte_handle* h, double* F, void* stream);
+bte_status bte_vstep(bte_handle* h, double* F, const double* E, void* stream);
+bte_status bte_field_eval(bte_handle* h, const double* F_half, double t_s, bte_field field, double* E_out,
+                          void* stream);
+
+/* Host copies of the assembled operators (synchronous), for verification.
+ * which: 0 C_ord [n][n] (sum_sb scal C^(s,b), per unit n0), 1 A_ord [n][n],
+ *        2 M_v [Nr][Nr], 3 G_v [Nr][Nr], 4 eigenvalues Lambda [Nr], 5 U [Nr][Nr],
+ *        6 xhat [sum Nx], 7 moment weights [3][n] (number, energy in eV, k_i),
+ *        8 C^(s,b) [n_params][n][n], 9 Q of discharge 0 [Nr][Ntheta][Nx][Nx] (row-major Q_ia).
+ * host_out must hold the documented number of doubles. */
+bte_status bte_get_operator(bte_handle* h, int32_t which, double* host_out);
+
+/* The same operators (which = 0..9) assembled on the host from a configuration,
+ * without a device or handle (synchronous).  Used to verify the assembly. */
+bte_status bte_host_operator(const bte_config* cfg, int32_t which, double* host_out);
+
+bte_status bte_get_info(bte_handle* h, bte_info* out);
+
+/* Synchronizes the handle's last stream and returns the latched device status
+ * (then clears it), the refinement sweeps used by the last mixed V-step and the
+ * final max|r|/max|b|.  Any pointer may be NULL. */
+bte_status bte_get_status(bte_handle* h, int32_t* refine_iters, double* final_resid);
+
+/* Kernel-level timing on the stream of bte_step (HIP events; each timed step
+ * synchronizes that stream).  enable (1) / disable (0, default); enabling
+ * clears the sums.  bte_get_timing fills ms_out[0..5] with the summed
+ * milliseconds of {LU trailing updates, LU panels + interchanges/TRSM, rest of
+ * the V step (formation, solves, refinement), unused, X half-steps + field}
+ * and the number of timed steps. */
+bte_status bte_set_timing(bte_handle* h, int32_t enable);
+bte_status bte_get_timing(bte_handle* h, double* ms_out);
+
+void bte_destroy(bte_handle* h);
+const char* bte_status_string(bte_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BTE_H */

@@ -1,0 +1,650 @@
+// C-ABI of the semi-implicit BTE step: handle lifetime, operator upload, and the
+// orchestration of the kernels of one step on the caller's stream.
+#include "bte.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "assemble.h"
+#include "internal.h"
+
+namespace {
+
+using bte::DevOps;
+
+struct HipError : std::runtime_error {
+  hipError_t code;
+  HipError(hipError_t c, const char* what) : std::runtime_error(what), code(c) {}
+};
+
+#define HIP_OK(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) throw HipError(e_, #expr);   \
+  } while (0)
+
+}  // namespace
+
+struct bte_handle {
+  int device = 0;
+  bte_config cfg{};
+  bte::HostOps host;
+  DevOps d;
+  std::vector<int> nx_per, x_off;
+  std::vector<void*> allocs;
+  hipStream_t last_stream = nullptr;
+  int refine_max_iter = 10;
+  double refine_rtol = 1e-14;
+  double bytes = 0.0;
+  bool timing = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> lu_ev;   // 4 * max_panels
+  bte::LuTimer lu_timer;
+  double ms_acc[6] = {0, 0, 0, 0, 0, 0};
+  double* d_coeff = nullptr;   // [nr] Maxwellian coefficients
+  double* d_gE = nullptr;      // [nx_total] adjoint field-gradient scratch
+  double* d_tmpF = nullptr;    // [nx_total*n]
+
+  template <typename T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    const size_t bytes_req = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes_req);
+    if (e != hipSuccess) throw HipError(e, "hipMalloc");
+    allocs.push_back(p);
+    bytes += static_cast<double>(bytes_req);
+    return static_cast<T*>(p);
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v) {
+    T* p = alloc<T>(v.size());
+    HIP_OK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+  ~bte_handle() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : lu_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+bte_status map_exc(const std::exception& e) {
+  if (auto* h = dynamic_cast<const HipError*>(&e)) return h->code == hipErrorOutOfMemory ? BTE_ENOMEM : BTE_EHIP;
+  if (dynamic_cast<const std::bad_alloc*>(&e)) return BTE_ENOMEM;
+  return BTE_EINVAL;
+}
+
+bte::AssemblyInput make_input(const bte_config* c) {
+  if (!c) throw std::invalid_argument("null config");
+  bte::AssemblyInput in;
+  in.nr = c->nr;
+  in.ntheta = c->ntheta;
+  in.nl = c->nl;
+  in.v_bc = c->v_bc;
+  in.eps_max_eV = c->eps_max_eV;
+  in.T0_K = c->T0_K;
+  in.dt = c->dt_s;
+  in.L = c->L_m;
+  if (c->n_proc < 1 || !c->proc) throw std::invalid_argument("no processes");
+  if (!(c->eps_max_eV > 0) || !(c->L_m > 0) || !(c->dt_s > 0) || c->T0_K < 0) throw std::invalid_argument("bad scalars");
+  for (int s = 0; s < c->n_proc; ++s) {
+    const bte_process& p = c->proc[s];
+    if (p.n_tab < 2 || !p.eps_eV || !p.sigma_m2 || p.kind < 0 || p.kind > 2) throw std::invalid_argument("bad process");
+    bte::Process q;
+    q.kind = p.kind;
+    q.threshold_eV = p.threshold_eV;
+    q.mass_ratio = p.mass_ratio;
+    q.eps_eV.assign(p.eps_eV, p.eps_eV + p.n_tab);
+    q.sigma_m2.assign(p.sigma_m2, p.sigma_m2 + p.n_tab);
+    for (int i = 1; i < p.n_tab; ++i)
+      if (!(q.eps_eV[i] > q.eps_eV[i - 1])) throw std::invalid_argument("table energies must increase");
+    if (p.kind == 0 && !(p.mass_ratio > 0 && p.mass_ratio < 0.5)) throw std::invalid_argument("bad mass ratio");
+    in.proc.push_back(q);
+  }
+  const int nb = std::max(1, c->n_bins);
+  if (c->bin_edges_eV) in.bin_edges_eV.assign(c->bin_edges_eV, c->bin_edges_eV + nb + 1);
+  else {
+    for (int b = 0; b <= nb; ++b) in.bin_edges_eV.push_back(c->eps_max_eV * b / nb);
+  }
+  in.scal.assign(static_cast<size_t>(c->n_proc) * nb, 1.0);
+  if (c->scal) in.scal.assign(c->scal, c->scal + static_cast<size_t>(c->n_proc) * nb);
+  const int nd = std::max(1, c->n_discharges);
+  if (nd == 1) in.nx_per.push_back(c->nx_per ? c->nx_per[0] : c->nx);
+  else {
+    if (!c->nx_per) throw std::invalid_argument("nx_per required for ensembles");
+    in.nx_per.assign(c->nx_per, c->nx_per + nd);
+  }
+  for (int nx : in.nx_per)
+    if (nx < 3 || nx > 1024) throw std::invalid_argument("nx must be in [3, 1024]");
+  if (!c->n0_per || !c->E0_per) throw std::invalid_argument("n0_per and E0_per required");
+  if (c->precision < 0 || c->precision > 2) throw std::invalid_argument("bad precision");
+  if (c->field_mode < 0 || c->field_mode > 3) throw std::invalid_argument("bad field mode");
+  return in;
+}
+
+inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+void fill_devops(bte_handle* h) {
+  const bte_config& c = h->cfg;
+  bte::HostOps& H = h->host;
+  DevOps& d = h->d;
+  const int nd = static_cast<int>(H.xops.size());
+  d.nr = H.nr;
+  d.nth = H.nth;
+  d.n = H.n;
+  d.nh = H.nth / 2;
+  d.npad = ((H.n + bte::kNB - 1) / bte::kNB) * bte::kNB;
+  d.nd = nd;
+  d.n_params = H.n_params;
+  d.n_bins = H.n_bins;
+  d.precision = c.precision;
+  d.dt = c.dt_s;
+  h->x_off.assign(nd + 1, 0);
+  h->nx_per.resize(nd);
+  std::vector<size_t> qoff(nd), poff(nd);
+  size_t qtot = 0, ptot = 0;
+  int maxnx = 0;
+  for (int i = 0; i < nd; ++i) {
+    const int nx = H.xops[i].nx;
+    h->nx_per[i] = nx;
+    h->x_off[i + 1] = h->x_off[i] + nx;
+    qoff[i] = qtot;
+    poff[i] = ptot;
+    qtot += H.xops[i].Qt.size();
+    ptot += H.xops[i].poisson.size();
+    maxnx = std::max(maxnx, nx);
+  }
+  d.nx_total = h->x_off[nd];
+  d.max_nx = maxnx;
+  if (d.npad > 4 * bte::kPanelThreads) throw std::invalid_argument("Nr*Ntheta must be <= 2048");
+  std::vector<int> x_disc(d.nx_total);
+  std::vector<double> xhat(d.nx_total), n0x(d.nx_total);
+  std::vector<double> n0(c.n0_per, c.n0_per + nd), E0(c.E0_per, c.E0_per + nd);
+  for (int i = 0; i < nd; ++i)
+    for (int j = 0; j < h->nx_per[i]; ++j) {
+      const int x = h->x_off[i] + j;
+      x_disc[x] = i;
+      xhat[x] = H.xops[i].xhat[j];
+      n0x[x] = n0[i];
+    }
+  d.x_off = h->upload(h->x_off);
+  d.nx_of = h->upload(h->nx_per);
+  d.q_off = h->upload(qoff);
+  d.p_off = h->upload(poff);
+  d.n0_of = h->upload(n0);
+  d.E0_of = h->upload(E0);
+  d.x_disc = h->upload(x_disc);
+  d.xhat = h->upload(xhat);
+  d.n0x = h->upload(n0x);
+  d.U = h->upload(H.U);
+  d.Uinv = h->upload(H.Uinv);
+  d.Cord = h->upload(H.Cord);
+  d.Aord = h->upload(H.Aord);
+  d.Csb = h->upload(H.Csb);
+  d.mom = h->upload(H.mom);
+  {
+    std::vector<double> Q;
+    Q.reserve(qtot);
+    std::vector<double> P;
+    P.reserve(ptot);
+    for (auto& X : H.xops) {
+      Q.insert(Q.end(), X.Qt.begin(), X.Qt.end());
+      P.insert(P.end(), X.poisson.begin(), X.poisson.end());
+    }
+    d.Qt = h->upload(Q);
+    d.poisson = h->upload(P);
+    if (c.precision != BTE_FP64) {
+      std::vector<float> Q32(Q.begin(), Q.end());
+      d.Qt32 = h->upload(Q32);
+    }
+  }
+  const size_t nxt = d.nx_total;
+  d.Y = h->alloc<double>(nxt * d.n);
+  const size_t elt = (c.precision == BTE_FP64) ? sizeof(double) : sizeof(float);
+  d.lu = h->alloc<char>(nxt * d.npad * d.npad * elt);
+  d.piv = h->alloc<int>(nxt * d.npad);
+  d.perm = h->alloc<int>(nxt * (2 * bte::kMaxSwapRows + 1));
+  d.E = h->alloc<double>(nxt);
+  d.B = h->alloc<double>(nxt * d.npad);
+  d.X = h->alloc<double>(nxt * d.npad);
+  d.R = h->alloc<double>(nxt * d.npad);
+  d.Fs = h->alloc<double>(nxt * d.n);
+  d.mu = h->alloc<double>(nxt * d.n);
+  d.rmax = h->alloc<unsigned long long>(nxt);
+  d.bmax = h->alloc<unsigned long long>(nxt);
+  d.status = h->alloc<int>(4);
+  d.resid = h->alloc<double>(1);
+  d.scratch3 = h->alloc<double>(3 * nxt);
+  h->d_coeff = h->alloc<double>(d.nr);
+  h->d_gE = h->alloc<double>(nxt);
+  h->d_tmpF = h->alloc<double>(nxt * d.n);
+  HIP_OK(hipMemset(d.status, 0, 4 * sizeof(int)));
+  HIP_OK(hipMemset(d.resid, 0, sizeof(double)));
+  HIP_OK(hipMemset(d.piv, 0, nxt * d.npad * sizeof(int)));
+}
+
+// X(dt/2) in place on F.
+void x_half(bte_handle* h, double* F, bool transpose, hipStream_t s) {
+  const bool fp32 = (h->cfg.precision != BTE_FP64);
+  if (!transpose) {
+    bte::launch_x_to_modes(h->d, F, s);
+    bte::launch_advect(h->d, fp32, false, s);
+    bte::launch_modes_to_x(h->d, F, s);
+  } else {
+    bte::launch_x_to_modes_T(h->d, F, s);
+    bte::launch_advect(h->d, fp32, true, s);
+    bte::launch_modes_to_x_T(h->d, F, s);
+  }
+}
+
+// V(dt) in place on F (field already in d.E).  transpose: solve with A^T.
+void v_solve(bte_handle* h, double* F, bool transpose, hipStream_t s) {
+  DevOps& d = h->d;
+  const int prec = h->cfg.precision;
+  bte::launch_pad_rows(d, F, d.B, s);
+  bte::launch_lu_factor(d, prec, s, h->timing ? &h->lu_timer : nullptr);
+  bte::launch_lu_solve(d, prec, transpose, d.B, d.X, false, false, s);
+  if (prec != BTE_FP64) {
+    bte::launch_reset_refine(d, s);
+    for (int it = 1; it <= h->refine_max_iter; ++it) {
+      bte::launch_residual(d, transpose, s);
+      bte::launch_refine_check(d, h->refine_rtol, it - 1, false, s);
+      bte::launch_lu_solve(d, prec, transpose, d.R, d.X, true, true, s);
+    }
+    bte::launch_residual(d, transpose, s);
+    bte::launch_refine_check(d, h->refine_rtol, h->refine_max_iter, true, s);
+  }
+  bte::launch_unpad_rows(d, d.X, F, s);
+}
+
+// Solve with existing factors (no refactorization), used by the adjoint.
+void v_solve_again(bte_handle* h, double* F, bool transpose, hipStream_t s) {
+  DevOps& d = h->d;
+  const int prec = h->cfg.precision;
+  bte::launch_pad_rows(d, F, d.B, s);
+  bte::launch_lu_solve(d, prec, transpose, d.B, d.X, false, false, s);
+  if (prec != BTE_FP64) {
+    bte::launch_reset_refine(d, s);
+    for (int it = 1; it <= h->refine_max_iter; ++it) {
+      bte::launch_residual(d, transpose, s);
+      bte::launch_refine_check(d, h->refine_rtol, it - 1, false, s);
+      bte::launch_lu_solve(d, prec, transpose, d.R, d.X, true, true, s);
+    }
+    bte::launch_residual(d, transpose, s);
+    bte::launch_refine_check(d, h->refine_rtol, h->refine_max_iter, true, s);
+  }
+  bte::launch_unpad_rows(d, d.X, F, s);
+}
+
+bool field_ok(const bte_handle* h, const bte_field& f) {
+  if (h->cfg.field_mode == BTE_FIELD_GIVEN && !f.E_half) return false;
+  if (h->cfg.field_mode == BTE_FIELD_POISSON && !f.ni) return false;
+  return true;
+}
+
+void eval_field(bte_handle* h, const double* Fh, double t_s, const bte_field& f, hipStream_t s) {
+  const bte_config& c = h->cfg;
+  bte::launch_field(h->d, c.field_mode, t_s + 0.5 * c.dt_s, c.field_freq_hz, c.field_a1, c.poisson_V0, Fh, f.E_half,
+                    f.ni, h->d.E, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bte_status_string(bte_status s) {
+  switch (s) {
+    case BTE_OK: return "ok";
+    case BTE_EINVAL: return "invalid argument";
+    case BTE_EHIP: return "HIP runtime error";
+    case BTE_ESINGULAR: return "zero pivot in a velocity-space factorization";
+    case BTE_ENOCONV: return "iterative refinement did not converge";
+    case BTE_ENOMEM: return "out of device memory";
+    case BTE_ENONFINITE: return "non-finite value in the state";
+    case BTE_EUNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle** out) {
+  if (!out) return BTE_EINVAL;
+  *out = nullptr;
+  bte_handle* h = nullptr;
+  try {
+    bte::AssemblyInput in = make_input(cfg);
+    h = new bte_handle();
+    h->cfg = *cfg;
+    h->device = hip_device;
+    h->refine_max_iter = cfg->refine_max_iter > 0 ? cfg->refine_max_iter : 10;
+    h->refine_rtol = cfg->refine_rtol > 0 ? cfg->refine_rtol : 1e-14;
+    HIP_OK(hipSetDevice(hip_device));
+    bte::assemble(in, &h->host);
+    fill_devops(h);
+    for (auto& e : h->ev) HIP_OK(hipEventCreate(&e));
+    h->lu_timer.max_panels = h->d.npad / bte::kNB;
+    h->lu_ev.assign(4 * h->lu_timer.max_panels, nullptr);
+    for (auto& e : h->lu_ev) HIP_OK(hipEventCreate(&e));
+    h->lu_timer.ev = h->lu_ev.data();
+    // pointers inside cfg are not retained
+    h->cfg.proc = nullptr;
+    h->cfg.bin_edges_eV = nullptr;
+    h->cfg.scal = nullptr;
+    h->cfg.nx_per = nullptr;
+    h->cfg.n0_per = nullptr;
+    h->cfg.E0_per = nullptr;
+    *out = h;
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    delete h;
+    return map_exc(e);
+  }
+}
+
+void bte_destroy(bte_handle* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  delete h;
+}
+
+bte_status bte_get_info(bte_handle* h, bte_info* out) {
+  if (!h || !out) return BTE_EINVAL;
+  out->nx_total = h->d.nx_total;
+  out->n = h->d.n;
+  out->n_params = h->d.n_params;
+  out->n_discharges = h->d.nd;
+  out->vmax = h->host.vmax;
+  out->bytes_device = h->bytes;
+  out->lu_flops_per_step = (2.0 / 3.0) * std::pow(static_cast<double>(h->d.n), 3) * h->d.nx_total;
+  double qb = 0.0;
+  const double el = (h->cfg.precision == BTE_FP64) ? 8.0 : 4.0;
+  for (int nx : h->nx_per) qb += static_cast<double>(h->d.nr) * h->d.nh * nx * nx * el;
+  out->q_bytes_per_half_step = qb;
+  return BTE_OK;
+}
+
+bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void* stream) {
+  if (!h || !F || !field_ok(h, field)) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    hipStream_t s = S(stream);
+    h->last_stream = s;
+    if (h->timing) HIP_OK(hipEventRecord(h->ev[0], s));
+    x_half(h, F, false, s);
+    eval_field(h, F, t_s, field, s);
+    if (h->timing) HIP_OK(hipEventRecord(h->ev[1], s));
+    v_solve(h, F, false, s);
+    if (h->timing) HIP_OK(hipEventRecord(h->ev[2], s));
+    x_half(h, F, false, s);
+    if (h->timing) {
+      HIP_OK(hipEventRecord(h->ev[3], s));
+      HIP_OK(hipEventSynchronize(h->ev[3]));
+      float a = 0, b = 0, c = 0;
+      HIP_OK(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
+      HIP_OK(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
+      HIP_OK(hipEventElapsedTime(&c, h->ev[2], h->ev[3]));
+      float upd = 0.f, pan = 0.f;
+      const int P = h->lu_timer.max_panels;
+      for (int p = 0; p < h->lu_timer.used; ++p) {
+        float t1 = 0.f, t2 = 0.f;
+        HIP_OK(hipEventElapsedTime(&t1, h->lu_ev[2 * p], h->lu_ev[2 * p + 1]));
+        HIP_OK(hipEventElapsedTime(&t2, h->lu_ev[2 * P + 2 * p], h->lu_ev[2 * P + 2 * p + 1]));
+        upd += t1;
+        pan += t2;
+      }
+      h->ms_acc[0] += upd;        // LU trailing updates
+      h->ms_acc[1] += pan;        // LU panels + interchanges/TRSM
+      h->ms_acc[2] += b - upd - pan;  // formation, solves, refinement
+      h->ms_acc[4] += a + c;      // X half-steps (+ field)
+      h->ms_acc[5] += 1.0;
+    }
+    HIP_OK(hipGetLastError());
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_xstep(bte_handle* h, double* F, void* stream) {
+  if (!h || !F) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    h->last_stream = S(stream);
+    x_half(h, F, false, S(stream));
+    HIP_OK(hipGetLastError());
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_xstep_T(bte_handle* h, double* F, void* stream) {
+  if (!h || !F) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    h->last_stream = S(stream);
+    x_half(h, F, true, S(stream));
+    HIP_OK(hipGetLastError());
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_vstep(bte_handle* h, double* F, const double* E, void* stream) {
+  if (!h || !F || !E) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    hipStream_t s = S(stream);
+    h->last_stream = s;
+    HIP_OK(hipMemcpyAsync(h->d.E, E, sizeof(double) * h->d.nx_total, hipMemcpyDeviceToDevice, s));
+    v_solve(h, F, false, s);
+    HIP_OK(hipGetLastError());
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_field_eval(bte_handle* h, const double* F_half, double t_s, bte_field field, double* E_out,
+                          void* stream) {
+  if (!h || !E_out || !field_ok(h, field)) return BTE_EINVAL;
+  if (h->cfg.field_mode == BTE_FIELD_POISSON && !F_half) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    hipStream_t s = S(stream);
+    h->last_stream = s;
+    eval_field(h, F_half, t_s, field, s);
+    HIP_OK(hipMemcpyAsync(E_out, h->d.E, sizeof(double) * h->d.nx_total, hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipGetLastError());
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_moments(bte_handle* h, const double* F, double* out, void* stream) {
+  if (!h || !F || !out) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    h->last_stream = S(stream);
+    bte::launch_moments(h->d, F, out, S(stream));
+    HIP_OK(hipGetLastError());
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_moments_vjp(bte_handle* h, const double* F, const double* gbar, double* lam, void* stream) {
+  if (!h || !F || !gbar || !lam) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    h->last_stream = S(stream);
+    bte::launch_moments_vjp(h->d, F, gbar, lam, S(stream));
+    HIP_OK(hipGetLastError());
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_initial_maxwellian(bte_handle* h, const double* ne, double Te_eV, double* F, void* stream) {
+  if (!h || !ne || !F || !(Te_eV > 0)) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    hipStream_t s = S(stream);
+    h->last_stream = s;
+    std::vector<double> c = bte::maxwellian_coeffs(h->host, Te_eV);
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipMemcpy(h->d_coeff, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice));
+    bte::launch_maxwellian(h->d, ne, h->d_coeff, F, s);
+    HIP_OK(hipGetLastError());
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_adjoint_step(bte_handle* h, const double* F_n, double t_s, bte_field field, double* lam,
+                            double* grad_scal, double* grad_E0, double* grad_E, void* stream) {
+  if (!h || !F_n || !lam || !grad_scal || !field_ok(h, field)) return BTE_EINVAL;
+  if (h->cfg.field_mode == BTE_FIELD_POISSON) return BTE_EUNSUPPORTED;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    hipStream_t s = S(stream);
+    h->last_stream = s;
+    DevOps& d = h->d;
+    const size_t nb = sizeof(double) * d.nx_total * d.n;
+    // forward recompute: F* = A^-1 X F_n (factors stay in the workspace)
+    HIP_OK(hipMemcpyAsync(d.Fs, F_n, nb, hipMemcpyDeviceToDevice, s));
+    x_half(h, d.Fs, false, s);
+    eval_field(h, d.Fs, t_s, field, s);
+    v_solve(h, d.Fs, false, s);
+    // mu = A^-T X^T lam
+    HIP_OK(hipMemcpyAsync(d.mu, lam, nb, hipMemcpyDeviceToDevice, s));
+    x_half(h, d.mu, true, s);
+    v_solve_again(h, d.mu, true, s);
+    // gradients
+    HIP_OK(hipMemsetAsync(h->d_gE, 0, sizeof(double) * d.nx_total, s));
+    bte::launch_adjoint_grads(d, grad_scal, h->d_gE, s);
+    if (grad_E) HIP_OK(hipMemcpyAsync(grad_E, h->d_gE, sizeof(double) * d.nx_total, hipMemcpyDeviceToDevice, s));
+    if (grad_E0 && h->cfg.field_mode != BTE_FIELD_GIVEN)
+      bte::launch_field_dE0(d, h->cfg.field_mode, t_s + 0.5 * h->cfg.dt_s, h->cfg.field_freq_hz, h->cfg.field_a1,
+                            h->d_gE, grad_E0, s);
+    // lam^n = X^T mu
+    HIP_OK(hipMemcpyAsync(lam, d.mu, nb, hipMemcpyDeviceToDevice, s));
+    x_half(h, lam, true, s);
+    HIP_OK(hipGetLastError());
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_get_status(bte_handle* h, int32_t* refine_iters, double* final_resid) {
+  if (!h) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    HIP_OK(hipStreamSynchronize(h->last_stream));
+    int st[4];
+    double r = 0.0;
+    HIP_OK(hipMemcpy(st, h->d.status, sizeof(st), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&r, h->d.resid, sizeof(double), hipMemcpyDeviceToHost));
+    if (refine_iters) *refine_iters = st[2];
+    if (final_resid) *final_resid = r;
+    const int zero = 0;
+    HIP_OK(hipMemcpy(h->d.status, &zero, sizeof(int), hipMemcpyHostToDevice));
+    if (st[0] & bte::kStNonFinite) return BTE_ENONFINITE;
+    if (st[0] & bte::kStSingular) return BTE_ESINGULAR;
+    if (st[0] & bte::kStNoConv) return BTE_ENOCONV;
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_set_timing(bte_handle* h, int32_t enable) {
+  if (!h) return BTE_EINVAL;
+  h->timing = enable != 0;
+  std::fill(std::begin(h->ms_acc), std::end(h->ms_acc), 0.0);
+  return BTE_OK;
+}
+
+bte_status bte_get_timing(bte_handle* h, double* ms_out) {
+  if (!h || !ms_out) return BTE_EINVAL;
+  for (int i = 0; i < 6; ++i) ms_out[i] = h->ms_acc[i];
+  return BTE_OK;
+}
+
+bte_status bte_get_operator(bte_handle* h, int32_t which, double* host_out) {
+  if (!h || !host_out) return BTE_EINVAL;
+  const bte::HostOps& H = h->host;
+  auto put = [&](const std::vector<double>& v) { std::memcpy(host_out, v.data(), v.size() * sizeof(double)); };
+  switch (which) {
+    case 0: put(H.Cord); break;
+    case 1: put(H.Aord); break;
+    case 2: put(H.M); break;
+    case 3: put(H.G); break;
+    case 4: put(H.lam); break;
+    case 5: put(H.U); break;
+    case 6: {
+      size_t o = 0;
+      for (auto& X : H.xops) {
+        std::memcpy(host_out + o, X.xhat.data(), X.xhat.size() * sizeof(double));
+        o += X.xhat.size();
+      }
+      break;
+    }
+    case 7: put(H.mom); break;
+    case 8: put(H.Csb); break;
+    case 9: {
+      // expand Q of discharge 0 to [nr][ntheta][nx][nx] row-major Q_ia
+      const bte::XOps& X = H.xops[0];
+      const int nx = X.nx, nr = H.nr, nth = H.nth, nh = nth / 2;
+      for (int i = 0; i < nr; ++i)
+        for (int a = 0; a < nth; ++a) {
+          double* Q = host_out + ((size_t)i * nth + a) * nx * nx;
+          const bool pos = a >= nh;
+          const int hh = pos ? a - nh : nh - 1 - a;
+          const double* Qt = X.Qt.data() + ((size_t)i * nh + hh) * nx * nx;
+          for (int r = 0; r < nx; ++r)
+            for (int c = 0; c < nx; ++c) {
+              // Q_pos[r][c] = Qt[c][r]; Q_neg = J Q_pos J
+              const int rr = pos ? r : nx - 1 - r, cc = pos ? c : nx - 1 - c;
+              Q[(size_t)r * nx + c] = Qt[(size_t)cc * nx + rr];
+            }
+        }
+      break;
+    }
+    default: return BTE_EINVAL;
+  }
+  return BTE_OK;
+}
+
+// Host-only assembly (no device needed): the same operators as bte_get_operator
+// for which = 0..8 (and 9 with nx of the first discharge), for verification.
+bte_status bte_host_operator(const bte_config* cfg, int32_t which, double* host_out) {
+  if (!host_out) return BTE_EINVAL;
+  try {
+    bte::AssemblyInput in = make_input(cfg);
+    bte_handle tmp;
+    bte::assemble(in, &tmp.host);
+    return bte_get_operator(&tmp, which, host_out);
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Internal declarations shared by the C-ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace bte {
+
+// Blocking of the batched LU: outer panel width (trailing-update rank); the
+// register-resident sub-panel inside the panel factorization is 8 (FP64) or
+// 16 (FP32) columns wide.
+constexpr int kNB = 64;
+constexpr int kPanelThreads = 512;
+constexpr int kMaxSwapRows = 2 * kNB;   // rows touched by one panel's interchanges
+
+// Device status word bits.
+enum : int { kStSingular = 1, kStNoConv = 2, kStNonFinite = 4 };
+
+struct DevOps {
+  int nr = 0, nth = 0, n = 0, npad = 0, nh = 0;
+  int nd = 0, nx_total = 0, n_params = 0, n_bins = 1, precision = 0;
+  int max_nx = 0;
+  double dt = 0.0;
+  // per discharge (device)
+  int* x_off = nullptr;        // [nd+1]
+  int* nx_of = nullptr;        // [nd]
+  size_t* q_off = nullptr;     // [nd] element offset of Q (per discharge)
+  size_t* p_off = nullptr;     // [nd] element offset of the Poisson matrix
+  double* n0_of = nullptr;     // [nd]
+  double* E0_of = nullptr;     // [nd]
+  // per global x (device)
+  int* x_disc = nullptr;       // [nx_total]
+  double* xhat = nullptr;      // [nx_total]
+  double* n0x = nullptr;       // [nx_total]
+  // operators (device)
+  double* U = nullptr;         // [nr*nr]
+  double* Uinv = nullptr;      // [nr*nr]
+  double* Cord = nullptr;      // [n*n]
+  double* Aord = nullptr;      // [n*n]
+  double* Csb = nullptr;       // [n_params*n*n]
+  double* mom = nullptr;       // [3*n]
+  double* Qt = nullptr;        // concatenated Q of all discharges, FP64
+  float* Qt32 = nullptr;       // FP32 copy (mixed modes)
+  double* poisson = nullptr;   // concatenated [nx_d][nx_d]
+  // workspaces (device)
+  double* Y = nullptr;         // [nx_total*n] mode-major scratch of the X step
+  void* lu = nullptr;          // [nx_total][npad][npad] of T (double or float)
+  int* piv = nullptr;          // [nx_total][npad]
+  int* perm = nullptr;         // [nx_total][2*kMaxSwapRows] row list / source list of one panel
+  double* E = nullptr;         // [nx_total]
+  double* B = nullptr;         // [nx_total][npad] right-hand side copy
+  double* X = nullptr;         // [nx_total][npad] solution (mixed refinement)
+  double* R = nullptr;         // [nx_total][npad] residual / correction
+  double* Fs = nullptr;        // [nx_total][n] adjoint: post-V state
+  double* mu = nullptr;        // [nx_total][n] adjoint: A^-T X^T lambda
+  unsigned long long* rmax = nullptr;  // [nx_total] max|r| (as ordered bits)
+  unsigned long long* bmax = nullptr;  // [nx_total]
+  int* status = nullptr;       // [4]: status bits, done flag, sweeps, spare
+  double* resid = nullptr;     // [1] final max_x |r|/|b|
+  double* scratch3 = nullptr;  // [3*nx_total] moments scratch
+};
+
+// ---- X step (kernels_x.hip) -------------------------------------------------
+void launch_x_to_modes(const DevOps& d, const double* F, hipStream_t s);
+void launch_advect(const DevOps& d, bool fp32, bool transpose, hipStream_t s);
+void launch_modes_to_x(const DevOps& d, double* F, hipStream_t s);
+void launch_x_to_modes_T(const DevOps& d, const double* F, hipStream_t s);   // U^T contraction
+void launch_modes_to_x_T(const DevOps& d, double* F, hipStream_t s);         // Uinv^T contraction
+void launch_field(const DevOps& d, int mode, double t_half, double freq, double a1, double V0,
+                  const double* Fh, const double* E_given, const double* ni, double* E, hipStream_t s);
+void launch_field_dE0(const DevOps& d, int mode, double t_half, double freq, double a1, const double* gE,
+                      double* gE0, hipStream_t s);
+void launch_moments(const DevOps& d, const double* F, double* out, hipStream_t s);
+void launch_moments_vjp(const DevOps& d, const double* F, const double* gbar, double* lam, hipStream_t s);
+void launch_maxwellian(const DevOps& d, const double* ne, const double* coeff, double* F, hipStream_t s);
+
+// Event pairs recorded around the LU kernels when timing is enabled:
+// pairs [0, n_panels) bracket the trailing updates, [n_panels, 2 n_panels) the
+// panel + interchange/TRSM launches of each panel step.
+struct LuTimer {
+  hipEvent_t* ev = nullptr;   // 4 * max_panels events
+  int max_panels = 0;
+  int used = 0;               // panel steps recorded
+};
+
+// ---- V step (kernels_lu.hip) ------------------------------------------------
+// Forms I - dt (n0 C + E A) (padded to npad with identity) and factors it in place.
+void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer = nullptr);
+// X = LU^-1 B (or LU^-T B with transpose), rows of length npad, FP64 right-hand sides.
+void launch_lu_solve(const DevOps& d, int precision, bool transpose, const double* Bin, double* Xout,
+                     bool accumulate, bool check_done, hipStream_t s);
+// Copy F (rows of n) into padded rows of npad and back.
+void launch_pad_rows(const DevOps& d, const double* F, double* Bp, hipStream_t s);
+void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t s);
+// FP64 residual R = B - (I - dt (n0 C + E A)) X (or with A^T for transpose) + per-x norms.
+void launch_residual(const DevOps& d, bool transpose, hipStream_t s);
+void launch_refine_check(const DevOps& d, double rtol, int sweep, bool final_sweep, hipStream_t s);
+void launch_reset_refine(const DevOps& d, hipStream_t s);
+// Adjoint gradient contractions.
+void launch_adjoint_grads(const DevOps& d, double* grad_scal, double* grad_E, hipStream_t s);
+
+}  // namespace bte

@@ -1,0 +1,106 @@
+"""CPU-side checks of the boundary: the C-ABI library loads and exports every
+symbol that include/bte.h declares, and the C++ host assembly of the operators
+agrees with the FP64 oracle (no device needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import semi_implicit as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2502_16555_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libbte.so is not built (run __graft_entry__.build())")
+    return L
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    hdr = open(os.path.join(ROOT, "include", "bte.h")).read()
+    declared = set(re.findall(r"\b(bte_[a-z_0-9]+)\s*\(", hdr))
+    assert {"bte_setup_operators", "bte_step", "bte_moments", "bte_adjoint_step"} <= declared
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared <= set(L.EXPORTS), declared - set(L.EXPORTS)
+
+
+def test_status_strings_and_argument_errors():
+    L = _lib()
+    lib = L.load()
+    assert lib.bte_status_string(0) == b"ok"
+    assert lib.bte_status_string(L.BTE_ENOCONV).startswith(b"iterative")
+    h = ctypes.c_void_p()
+    assert lib.bte_setup_operators(None, 0, ctypes.byref(h)) == L.BTE_EINVAL
+    # calls on a null handle are argument errors, not crashes
+    assert lib.bte_step(None, None, 0.0, L.bte_field(None, None), None) == L.BTE_EINVAL
+    assert lib.bte_moments(None, None, None, None) == L.BTE_EINVAL
+
+
+def test_bad_configs_are_rejected():
+    from paper_2502_16555_amd import host_operator
+    from paper_2502_16555_amd._lib import BteError
+    cfg = workloads.config("C0")
+    bad = dict(cfg, ntheta=7, nl=7)          # odd number of ordinates
+    with pytest.raises(BteError):
+        host_operator(bad, 2, 16 * 16)
+    bad = dict(cfg, nl=4)                    # nl != ntheta
+    with pytest.raises(BteError):
+        host_operator(bad, 2, 16 * 16)
+
+
+CASES = {
+    "C0": lambda: workloads.config("C0"),
+    "three_processes_binned": lambda: workloads.small_config(nx=9, nr=10, nth=6,
+                                                             kinds=("elastic", "excitation", "ionization"), n_bins=3),
+    "natural_bc": lambda: dict(workloads.small_config(nx=5, nr=7, nth=4, kinds=("elastic", "ionization")),
+                               v_bc="natural"),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_host_assembly_matches_oracle(case):
+    """The library's C++ FP64 assembly (an independent implementation) against the oracle.
+
+    Tolerances: mass-like matrices, eigenvalues, moment weights and Q are formed
+    from exactly integrated polynomials -> rounding level (1e-13).  C and A carry
+    M^-1 (condition number up to ~1e4 for these grids), and the elastic operator
+    is a difference of gain and loss terms equal to O(1e-5) -> 5e-12 / 1e-12."""
+    from paper_2502_16555_amd import host_operator
+    cfg = CASES[case]()
+    ops = oracle.build_operators(cfg)
+    n, nr, nth, nx = ops.nr * ops.nth, ops.nr, ops.nth, ops.nx
+
+    def rel(a, b):
+        return np.abs(a - b).max() / np.abs(b).max()
+
+    assert rel(host_operator(cfg, 2, nr * nr).reshape(nr, nr), ops.M) < 1e-13
+    assert rel(host_operator(cfg, 3, nr * nr).reshape(nr, nr), ops.G) < 1e-13
+    assert rel(host_operator(cfg, 4, nr), ops.lam) < 1e-13
+    assert rel(host_operator(cfg, 0, n * n).reshape(n, n), ops.Cord) < 5e-12
+    assert rel(host_operator(cfg, 1, n * n).reshape(n, n), ops.Aord) < 1e-12
+    Csb = host_operator(cfg, 8, len(ops.Cord_sb) * n * n).reshape(-1, n, n)
+    for i, Cb in enumerate(ops.Cord_sb):
+        if np.abs(Cb).max() > 0:
+            assert rel(Csb[i], Cb) < 5e-12
+    mom = host_operator(cfg, 7, 3 * n).reshape(3, n)
+    assert rel(mom[0], ops.u_ord) < 1e-13 and rel(mom[1], ops.e_ord) < 1e-13
+    if np.abs(ops.ki_ord).max() > 0:
+        assert rel(mom[2], ops.ki_ord) < 1e-12
+    xh = host_operator(cfg, 6, nx)
+    assert np.abs(xh - ops.xhat).max() < 1e-15
+    Q = host_operator(cfg, 9, nr * nth * nx * nx).reshape(nr, nth, nx, nx)
+    for i in range(nr):
+        for a in range(nth):
+            B, b = S._x_system(ops, i, a, 0.5 * ops.dt)
+            Qo = np.linalg.inv(B)
+            Qo[:, b] = 0.0
+            assert rel(Q[i, a], Qo) < 1e-12
