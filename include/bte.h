@@ -114,6 +114,7 @@ typedef struct {
   const int32_t* nx_per;        /* host [n_discharges] or NULL when n_discharges == 1           */
   const double* n0_per;         /* host [n_discharges] neutral densities [m^-3]                  */
   const double* E0_per;         /* host [n_discharges] field amplitudes [V/m] (CONST / RF)       */
+  int32_t x_fp32;               /* 1: stream Q in FP32 (mixed modes only); 0: FP64 advection      */
 } bte_config;
 
 /* Per-call field data for the GIVEN and POISSON modes (device arrays, [sum Nx]). */
@@ -195,6 +196,13 @@ bte_status bte_get_operator(bte_handle* h, int32_t which, double* host_out);
 /* The same operators (which = 0..9) assembled on the host from a configuration,
  * without a device or handle (synchronous).  Used to verify the assembly. */
 bte_status bte_host_operator(const bte_config* cfg, int32_t which, double* host_out);
+
+/* Verification: forms and factors (I - dt (n0 C + E A)) at every point with the
+ * field E (device [sum Nx]), synchronizes, and copies the factors of point x
+ * (npad x npad row-major, npad = n rounded up to a multiple of 64, converted to
+ * FP64) and its pivot rows (getrf-style, 0-based, applied panel by panel) to
+ * host memory.  Overwrites the handle's factor workspace. */
+bte_status bte_factor_export(bte_handle* h, const double* E, int32_t x, double* lu_host, int32_t* piv_host);
 
 bte_status bte_get_info(bte_handle* h, bte_info* out);
 

@@ -28,7 +28,7 @@ class bte_config(C.Structure):
                 ("precision", C.c_int32), ("refine_max_iter", C.c_int32), ("refine_rtol", C.c_double),
                 ("field_mode", C.c_int32), ("field_freq_hz", C.c_double), ("field_a1", C.c_double),
                 ("poisson_V0", C.c_double), ("n_discharges", C.c_int32), ("nx_per", C.POINTER(C.c_int32)),
-                ("n0_per", C.POINTER(C.c_double)), ("E0_per", C.POINTER(C.c_double))]
+                ("n0_per", C.POINTER(C.c_double)), ("E0_per", C.POINTER(C.c_double)), ("x_fp32", C.c_int32)]
 
 
 class bte_field(C.Structure):
@@ -56,6 +56,8 @@ EXPORTS = {
     "bte_get_operator": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "bte_host_operator": (C.c_int, [C.POINTER(bte_config), C.c_int32, C.POINTER(C.c_double)]),
     "bte_get_info": (C.c_int, [C.c_void_p, C.POINTER(bte_info)]),
+    "bte_factor_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_int32)]),
     "bte_get_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "bte_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "bte_get_timing": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
@@ -73,6 +75,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2502_16555_amd.build`")
+    # The library and torch must share one HIP runtime (both need the soname
+    # libamdhip64.so.7): load torch's copy first so that libbte.so binds to it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, (res, args) in EXPORTS.items():
         fn = getattr(lib, name)

@@ -204,7 +204,7 @@ void fill_devops(bte_handle* h) {
     }
     d.Qt = h->upload(Q);
     d.poisson = h->upload(P);
-    if (c.precision != BTE_FP64) {
+    if (c.precision != BTE_FP64 && c.x_fp32) {
       std::vector<float> Q32(Q.begin(), Q.end());
       d.Qt32 = h->upload(Q32);
     }
@@ -236,7 +236,7 @@ void fill_devops(bte_handle* h) {
 
 // X(dt/2) in place on F.
 void x_half(bte_handle* h, double* F, bool transpose, hipStream_t s) {
-  const bool fp32 = (h->cfg.precision != BTE_FP64);
+  const bool fp32 = (h->cfg.precision != BTE_FP64) && h->cfg.x_fp32;
   if (!transpose) {
     bte::launch_x_to_modes(h->d, F, s);
     bte::launch_advect(h->d, fp32, false, s);
@@ -368,7 +368,7 @@ bte_status bte_get_info(bte_handle* h, bte_info* out) {
   out->bytes_device = h->bytes;
   out->lu_flops_per_step = (2.0 / 3.0) * std::pow(static_cast<double>(h->d.n), 3) * h->d.nx_total;
   double qb = 0.0;
-  const double el = (h->cfg.precision == BTE_FP64) ? 8.0 : 4.0;
+  const double el = (h->cfg.precision != BTE_FP64 && h->cfg.x_fp32) ? 4.0 : 8.0;
   for (int nx : h->nx_per) qb += static_cast<double>(h->d.nr) * h->d.nh * nx * nx * el;
   out->q_bytes_per_half_step = qb;
   return BTE_OK;
@@ -631,6 +631,29 @@ bte_status bte_get_operator(bte_handle* h, int32_t which, double* host_out) {
     default: return BTE_EINVAL;
   }
   return BTE_OK;
+}
+
+bte_status bte_factor_export(bte_handle* h, const double* E, int32_t x, double* lu_host, int32_t* piv_host) {
+  if (!h || !E || !lu_host || !piv_host || x < 0 || x >= h->d.nx_total) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    DevOps& d = h->d;
+    HIP_OK(hipMemcpy(d.E, E, sizeof(double) * d.nx_total, hipMemcpyDeviceToDevice));
+    bte::launch_lu_factor(d, h->cfg.precision, nullptr);
+    HIP_OK(hipDeviceSynchronize());
+    const size_t nn = (size_t)d.npad * d.npad;
+    if (h->cfg.precision == BTE_FP64) {
+      HIP_OK(hipMemcpy(lu_host, static_cast<double*>(d.lu) + x * nn, nn * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> tmp(nn);
+      HIP_OK(hipMemcpy(tmp.data(), static_cast<float*>(d.lu) + x * nn, nn * sizeof(float), hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < nn; ++i) lu_host[i] = tmp[i];
+    }
+    HIP_OK(hipMemcpy(piv_host, d.piv + (size_t)x * d.npad, d.npad * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
 }
 
 // Host-only assembly (no device needed): the same operators as bte_get_operator

@@ -28,6 +28,9 @@ namespace {
 using f64x4 = double __attribute__((ext_vector_type(4)));
 using f32x4 = float __attribute__((ext_vector_type(4)));
 
+// MFMA 16x16x4 tiles: operand lanes hold A[i = lane%16][k = lane/16] and
+// B[k = lane/16][j = lane%16]; result item t of lane l holds D[row(l, t)][l%16]
+// with row = 4*(l/16) + t for f32 and row = l/16 + 4*t for f64 (measured).
 template <typename T>
 struct Mma;
 template <>
@@ -36,6 +39,7 @@ struct Mma<double> {
   __device__ static inline acc step(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int row(int lk, int t) { return lk + 4 * t; }
 };
 template <>
 struct Mma<float> {
@@ -43,6 +47,7 @@ struct Mma<float> {
   __device__ static inline acc step(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int row(int lk, int t) { return 4 * lk + t; }
 };
 
 constexpr int kPermStride = 2 * kMaxSwapRows + 1;
@@ -427,7 +432,7 @@ __global__ __launch_bounds__(256) void k_update(T* __restrict__ LU, int npad, in
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int it = 0; it < 4; ++it) {
-        const int r = r0 + wr + bi * 16 + 4 * lk + it;
+        const int r = r0 + wr + bi * 16 + Mma<T>::row(lk, it);
         const int c = c0 + wc + bj * 16 + li;
         T* p = A + (size_t)r * npad + c;
         *p = *p - acc[bi][bj][it];
@@ -645,7 +650,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
   for (int b = 0; b < 2; ++b)
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
-      const int x = x0 + b * 16 + 4 * lk + it;
+      const int x = x0 + b * 16 + Mma<double>::row(lk, it);
       const int i = i0 + w * 16 + li;
       if (x < nx && i < n) {
         const size_t o = (size_t)x * npad + i;
@@ -739,7 +744,7 @@ __global__ __launch_bounds__(256) void k_adjoint_grads(const double* __restrict_
   for (int b = 0; b < 2; ++b)
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
-      const int xl = b * 16 + 4 * lk + it;
+      const int xl = b * 16 + Mma<double>::row(lk, it);
       const int x = x0 + xl;
       const int i = i0 + w * 16 + li;
       double v = (x < nx && i < n) ? Mu[(size_t)x * n + i] * acc[b][it] : 0.0;

@@ -17,7 +17,8 @@ def _dptr(a):
 class _Config:
     """bte_config plus the host arrays it points into (kept alive)."""
 
-    def __init__(self, cfg: dict, precision=None, field_mode=None, refine_max_iter=0, refine_rtol=0.0):
+    def __init__(self, cfg: dict, precision=None, field_mode=None, refine_max_iter=0, refine_rtol=0.0,
+                 x_fp32=False):
         self.keep = []
         procs = cfg["processes"]
         P = (_lib.bte_process * len(procs))()
@@ -55,7 +56,7 @@ class _Config:
             refine_max_iter=int(refine_max_iter), refine_rtol=float(refine_rtol), field_mode=fm,
             field_freq_hz=float(fld.get("freq_hz", 0.0)), field_a1=float(fld.get("a1", 0.0)),
             poisson_V0=float(fld.get("V0", 0.0)), n_discharges=nd, nx_per=nx_per.ctypes.data_as(C.POINTER(C.c_int32)),
-            n0_per=_dptr(n0), E0_per=_dptr(E0))
+            n0_per=_dptr(n0), E0_per=_dptr(E0), x_fp32=1 if x_fp32 else 0)
 
 
 def make_config(cfg: dict, **kw) -> _Config:
@@ -88,12 +89,12 @@ class Solver:
     """One setup of the operators (bte_setup_operators) and the step calls on it."""
 
     def __init__(self, cfg: dict, device: int = 0, precision: str | None = None, field_mode: str | None = None,
-                 refine_max_iter: int = 0, refine_rtol: float = 0.0):
+                 refine_max_iter: int = 0, refine_rtol: float = 0.0, x_fp32: bool = False):
         self.lib = _lib.load()
         self.cfg = cfg
         self.device = device
         self._c = _Config(cfg, precision=precision, field_mode=field_mode, refine_max_iter=refine_max_iter,
-                          refine_rtol=refine_rtol)
+                          refine_rtol=refine_rtol, x_fp32=x_fp32)
         h = C.c_void_p()
         check(self.lib.bte_setup_operators(C.byref(self._c.c), device, C.byref(h)), "bte_setup_operators")
         self.h = h
@@ -162,6 +163,15 @@ class Solver:
         check(self.lib.bte_adjoint_step(self.h, _ptr(F_n), float(t), self._field(E_half, None), _ptr(lam),
                                         _ptr(grad_scal), _ptr(grad_E0), _ptr(grad_E), _stream(stream)),
               "bte_adjoint_step")
+
+    def factor_export(self, E, x: int):
+        """Factors (npad x npad, FP64) and pivots of point x after factoring with field E."""
+        npad = ((self.n + 63) // 64) * 64
+        lu = np.zeros((npad, npad))
+        piv = np.zeros(npad, dtype=np.int32)
+        check(self.lib.bte_factor_export(self.h, _ptr(E), int(x), _dptr(lu), piv.ctypes.data_as(C.POINTER(C.c_int32))),
+              "bte_factor_export")
+        return lu, piv
 
     def status(self):
         it = C.c_int32()

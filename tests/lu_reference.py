@@ -1,0 +1,94 @@
+"""NumPy restatement of the library's blocked LU (test helper, not the oracle).
+
+Same blocking as the device code -- 64-column panels, 8/16-column sub-panels,
+partial pivoting with ties to the lowest row, interchanges applied as you go --
+so the device factors can be compared element by element and the pivot
+sequence bit for bit.  Its solves are checked against LAPACK in the tests."""
+import numpy as np
+
+NB = 64
+
+
+def _perm(start, cnt, pivs):
+    R = list(range(start, start + cnt))
+    lab = list(range(cnt))
+    for j, p in enumerate(pivs):
+        if p < start + cnt:
+            i2 = p - start
+        elif p in R[cnt:]:
+            i2 = R.index(p, cnt)
+        else:
+            R.append(p)
+            lab.append(len(R) - 1)
+            i2 = len(R) - 1
+        lab[j], lab[i2] = lab[i2], lab[j]
+    return R, [R[l] for l in lab]
+
+
+def pad(M):
+    n = len(M)
+    npad = -(-n // NB) * NB
+    P = np.eye(npad)
+    P[:n, :n] = M
+    return P
+
+
+def factor(A, IB):
+    A = A.copy()
+    n = len(A)
+    ip = np.zeros(n, dtype=np.int64)
+    for k0 in range(0, n, NB):
+        for sp in range(NB // IB):
+            c0 = k0 + sp * IB
+            a = A[c0:, c0:c0 + IB].copy()
+            sw = []
+            for j in range(IB):
+                c = c0 + j
+                p = c + int(np.argmax(np.abs(a[j:, j])))
+                if p != c:
+                    a[[j, p - c0]] = a[[p - c0, j]]
+                ip[c] = p
+                sw.append(p)
+                if a[j, j] != 0:
+                    a[j + 1:, j] /= a[j, j]
+                    a[j + 1:, j + 1:] -= np.outer(a[j + 1:, j], a[j, j + 1:])
+            A[c0:, c0:c0 + IB] = a
+            R, src = _perm(c0, IB, sw)
+            other = list(range(k0, c0)) + list(range(c0 + IB, k0 + NB))
+            A[np.ix_(R, other)] = A[src][:, other].copy()
+            rest = list(range(c0 + IB, k0 + NB))
+            if rest:
+                U = A[c0:c0 + IB, rest].copy()
+                for j in range(1, IB):
+                    U[j] -= a[j, :j] @ U[:j]
+                A[c0:c0 + IB, rest] = U
+                A[c0 + IB:, rest] -= a[IB:, :IB] @ U
+        if k0 + NB < n:
+            R, src = _perm(k0, NB, ip[k0:k0 + NB])
+            cols = list(range(k0 + NB, n))
+            A[np.ix_(R, cols)] = A[src][:, cols].copy()
+            X = A[k0:k0 + NB, cols].copy()
+            for j in range(1, NB):
+                X[j] -= A[k0 + j, k0:k0 + j] @ X[:j]
+            A[k0:k0 + NB, cols] = X
+            A[k0 + NB:, k0 + NB:] -= A[k0 + NB:, k0:k0 + NB] @ X
+    return A, ip
+
+
+def solve(A, ip, b):
+    b = b.copy()
+    n = len(A)
+    for k0 in range(0, n, NB):
+        for j in range(NB):
+            q = ip[k0 + j]
+            if q != k0 + j:
+                b[[k0 + j, q]] = b[[q, k0 + j]]
+        for j in range(NB):
+            b[k0 + j] -= A[k0 + j, k0:k0 + j] @ b[k0:k0 + j]
+        b[k0 + NB:] -= A[k0 + NB:, k0:k0 + NB] @ b[k0:k0 + NB]
+    for k0 in range(n - NB, -1, -NB):
+        r = b[k0:k0 + NB] - A[k0:k0 + NB, k0 + NB:] @ b[k0 + NB:]
+        for j in range(NB - 1, -1, -1):
+            r[j] = (r[j] - A[k0 + j, k0 + j + 1:k0 + NB] @ r[j + 1:]) / A[k0 + j, k0 + j]
+        b[k0:k0 + NB] = r
+    return b

@@ -41,6 +41,12 @@ def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+def close(a, b, tol, what=""):
+    e = rel(a, b)
+    if not e < tol:
+        raise AssertionError(f"{what}: max relative difference {e:.3e} >= {tol:.1e}")
+
+
 def cuda(torch, a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
 
@@ -86,13 +92,13 @@ def test_xstep_matches_oracle(torch, case):
     Fg = cuda(torch, F)
     s.xstep(Fg)
     got = Fg.cpu().numpy()
-    assert rel(got, S.x_half_step(ops, F)) < 1e-11
+    close(got, S.x_half_step(ops, F), 1e-11, '')
     # transpose: against the oracle and the dot-product identity
     L = _state(ops, 2)
     Lg = cuda(torch, L)
     s.xstep_T(Lg)
     gotT = Lg.cpu().numpy()
-    assert rel(gotT, S.x_half_step_T(ops, L)) < 1e-11
+    close(gotT, S.x_half_step_T(ops, L), 1e-11, '')
     lhs = np.vdot(got, L)
     rhs = np.vdot(F, gotT)
     assert abs(lhs - rhs) < 1e-11 * np.abs(got).max() * np.abs(L).sum()
@@ -113,7 +119,7 @@ def test_vstep_matches_oracle(torch, case, prec):
     code, sweeps, resid = s.status()
     assert code == 0, (code, sweeps, resid)
     ref = S.v_step(ops, F, E)
-    assert rel(Fg.cpu().numpy(), ref) < (1e-11 if prec == "fp64" else 1e-10)
+    close(Fg.cpu().numpy(), ref, (1e-11 if prec == "fp64" else 1e-10), '')
     if prec != "fp64":
         assert resid <= 1e-14 and sweeps >= 1
     s.close()
@@ -127,13 +133,13 @@ def test_initial_state_and_moments(torch, case):
     ne = workloads.density_profile(s.xhat(), 1e16)
     Fg = s.initial_state(cuda(torch, ne), 1.0)
     F0 = S.initial_state(ops, ne, 1.0)
-    assert rel(Fg.cpu().numpy(), F0) < 1e-12
+    close(Fg.cpu().numpy(), F0, 1e-12, '')
     F = np.abs(_state(ops, 5))
     m = s.moments(cuda(torch, F)).cpu().numpy()
     mo = S.moments(ops, F)
     for q in range(3):
         if np.abs(mo[q]).max() > 0:
-            assert rel(m[q], mo[q]) < 1e-12, q
+            close(m[q], mo[q], 1e-12, q)
     s.close()
 
 
@@ -152,10 +158,10 @@ def test_c0_full_run_matches_oracle(torch):
         if (n + 1) % 10 == 0:
             mg = s.moments(Fg).cpu().numpy()
             mo = S.moments(ops, F)
-            assert rel(mg[0], mo[0]) < 1e-10, n
+            close(mg[0], mo[0], 1e-10, n)
             inner = mo[0] > 1e-3 * mo[0].max()
-            assert rel(mg[1][inner], mo[1][inner]) < 1e-10, n
-    assert rel(Fg.cpu().numpy(), F) < 1e-10
+            close(mg[1][inner], mo[1][inner], 1e-10, n)
+    close(Fg.cpu().numpy(), F, 1e-10, '')
     assert s.status()[0] == 0
     s.close()
 
@@ -178,23 +184,27 @@ def test_step_is_the_composition_of_substeps(torch, prec):
     assert torch.equal(A, B)
     # and the field kernel matches the specified RF form
     Eo = S.field_half(ops, t)
-    assert rel(E.cpu().numpy(), Eo) < 1e-14
+    close(E.cpu().numpy(), Eo, 1e-14, '')
     s.close()
 
 
-def test_rf_steps_match_oracle(torch):
-    """A few full steps of the realistic case with ionization and excitation."""
+@pytest.mark.parametrize("prec,x_fp32,tol", [("fp64", False, 1e-10), ("mixed_fp32", False, 1e-10),
+                                             ("mixed_fp32", True, 2e-5)])
+def test_rf_steps_match_oracle(torch, prec, x_fp32, tol):
+    """A few full steps of the realistic case with ionization and excitation.
+    With Q streamed in FP32 every X(dt/2) rounds Q to 2^-24 relative, which after
+    amplification by the Chebyshev systems measured ~2e-7 per half-step."""
     cfg = CASES["ragged"]()
     ops = oracle.build_operators(cfg)
-    for prec in ("fp64", "mixed_fp32"):
-        s = solver(cfg, precision=prec)
+    if True:
+        s = solver(cfg, precision=prec, x_fp32=x_fp32)
         F = S.initial_state(ops, workloads.density_profile(ops.xhat, 1e16), 1.0)
         Fg = cuda(torch, F)
         for n in range(5):
             t = (n + 200) * ops.dt
             F = S.step(ops, F, t)
             s.step(Fg, t)
-        assert rel(Fg.cpu().numpy(), F) < 1e-10, prec
+        close(Fg.cpu().numpy(), F, tol, prec)
         s.close()
 
 
@@ -210,7 +220,7 @@ def test_poisson_field_matches_oracle(torch):
     s.field(cuda(torch, F), t, E, ni=cuda(torch, ni))
     V_left = 100.0 * math.sin(2 * math.pi * workloads.RF_FREQ_HZ * (t + 0.5 * ops.dt))
     Eo = S.field_half(ops, t, F, ni=ni, V_left=V_left)
-    assert rel(E.cpu().numpy(), Eo) < 1e-11
+    close(E.cpu().numpy(), Eo, 1e-11, '')
     s.close()
 
 
@@ -227,9 +237,9 @@ def test_adjoint_step_matches_oracle(torch):
     gE0 = torch.zeros(1, dtype=torch.float64, device="cuda:0")
     gE = torch.zeros(s.nx_total, dtype=torch.float64, device="cuda:0")
     s.adjoint_step(cuda(torch, F), t, Lg, gs, gE0, gE)
-    assert rel(Lg.cpu().numpy(), lam_o) < 1e-10
-    assert rel(gs.cpu().numpy(), gs_o) < 1e-10
-    assert rel(gE.cpu().numpy(), gE_o) < 1e-10
+    close(Lg.cpu().numpy(), lam_o, 1e-10, '')
+    close(gs.cpu().numpy(), gs_o, 1e-10, '')
+    close(gE.cpu().numpy(), gE_o, 1e-10, '')
     assert abs(gE0.item() - gE_o @ S.field_dE0(ops, t)) < 1e-10 * np.abs(gE_o).sum()
     s.close()
 
@@ -263,8 +273,35 @@ def test_c1_golden_cycle(torch):
         if (n + 1) % every == 0:
             mg = s.moments(Fg).cpu().numpy()
             mo = g["moments"][(n + 1) // every]
-            assert rel(mg[0], mo[0]) < 1e-8, n
-            assert rel(mg[0] * mg[1], mo[0] * mo[1]) < 1e-8, n
-    assert rel(Fg.cpu().numpy(), g["F"]) < 1e-8
+            close(mg[0], mo[0], 1e-8, n)
+            close(mg[0] * mg[1], mo[0] * mo[1], 1e-8, n)
+    close(Fg.cpu().numpy(), g["F"], 1e-8, '')
     assert s.status()[0] == 0
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_device_factors_match_blocked_restatement(torch, prec):
+    """Device LU factors and pivots against the NumPy restatement of the same blocked
+    algorithm: identical pivots, factors equal to rounding (FP32: 1e-4 relative)."""
+    import lu_reference as LR
+    cfg = workloads.config("C0")
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg, precision=prec)
+    E = np.array([0.0, 1.2e4, -1.4e4, 3e3] * 4)[:ops.nx]
+    Eg = cuda(torch, E)
+    IB = 8 if prec == "fp64" else 16
+    for x in (0, 1, 2):
+        lu, piv = s.factor_export(Eg, x)
+        M = LR.pad(S.v_matrix(ops, E[x]))
+        if prec != "fp64":
+            M = M.astype(np.float32).astype(np.float64)
+        ref, ip = LR.factor(M, IB)
+        nb = LR.NB
+        for k0 in range(0, len(M), nb):
+            blk = slice(k0, k0 + nb)
+            close(lu[k0:, blk], ref[k0:, blk], (1e-12 if prec == "fp64" else 1e-4), (x, "L panel", k0))
+            close(lu[blk, k0:], ref[blk, k0:], (1e-12 if prec == "fp64" else 1e-4), (x, "U rows", k0))
+        if prec == "fp64":
+            assert np.array_equal(piv, ip), x
     s.close()

@@ -391,3 +391,19 @@ def test_poisson_field_closed_form():
     x = 0.5 * ops.L * (ops.xhat + 1)
     ref = 100.0 / ops.L + O.E_CHARGE * 3e15 / O.EPS0 * (x - ops.L / 2)
     assert np.abs(E - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def test_blocked_lu_restatement_matches_lapack():
+    """The NumPy restatement of the device's blocked LU (used to localize device
+    errors) solves the V systems like LAPACK, with and without interchanges."""
+    import lu_reference as LR
+    cfg = workloads.config("C0")
+    ops = oracle.build_operators(cfg)
+    rng = np.random.default_rng(0)
+    for E in (0.0, 1.2e4, -1.4e4):
+        M = LR.pad(S.v_matrix(ops, E))
+        b = rng.standard_normal(len(M))
+        for IB in (8, 16):
+            LU, ip = LR.factor(M, IB)
+            x = LR.solve(LU, ip, b)
+            assert np.abs(x - np.linalg.solve(M, b)).max() < 1e-12 * np.abs(x).max()
