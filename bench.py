@@ -140,11 +140,11 @@ def main():
         fp64 = run_gpu(cfg, "fp64", max(args.steps // 2, 5), args.warmup, torch)
     info = main_run["info"]
     nx_total, n = info.nx_total, info.n
-    npad = ((n + 63) // 64) * 64
+    npad = ((n + 127) // 128) * 128
     dtype = {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64"}[args.precision]
     mfma = {"fp64": "fp64", "mixed_fp32": "fp32", "mixed_bf16": "bf16"}[args.precision]
-    upd_flops = _update_flops(npad, 64, nx_total)
-    n_upd_launches = len([k for k in range(0, npad, 64) if npad - k - 64 > 0])
+    upd_flops = _update_flops(npad, 128, nx_total)
+    n_upd_launches = len([k for k in range(0, npad, 128) if npad - k - 128 > 0])
     achieved = upd_flops / (main_run["ms_update"] * 1e-3) / 1e12
     peak = MI355X_PEAK_TFLOPS[mfma]
     value = 1000.0 / main_run["ms_per_step"]
@@ -169,7 +169,7 @@ def main():
         line["fp64"] = {"steps_per_s": 1000.0 / fp64["ms_per_step"], "ms_per_step": fp64["ms_per_step"],
                         "speedup_mixed_over_fp64": fp64["ms_per_step"] / main_run["ms_per_step"],
                         "ms_update": fp64["ms_update"], "ms_panel": fp64["ms_panel"],
-                        "update_tflops": _update_flops(npad, 64, nx_total) / (fp64["ms_update"] * 1e-3) / 1e12}
+                        "update_tflops": _update_flops(npad, 128, nx_total) / (fp64["ms_update"] * 1e-3) / 1e12}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

@@ -199,8 +199,8 @@ bte_status bte_host_operator(const bte_config* cfg, int32_t which, double* host_
 
 /* Verification: forms and factors (I - dt (n0 C + E A)) at every point with the
  * field E (device [sum Nx]), synchronizes, and copies the factors of point x
- * (npad x npad row-major, npad = n rounded up to a multiple of 64, converted to
- * FP64) and its pivot rows (getrf-style, 0-based, applied panel by panel) to
+ * (npad x npad column-major, npad = n rounded up to a multiple of 128, converted
+ * to FP64) and its pivot rows (getrf-style, 0-based, applied panel by panel) to
  * host memory.  Overwrites the handle's factor workspace. */
 bte_status bte_factor_export(bte_handle* h, const double* E, int32_t x, double* lu_host, int32_t* piv_host);
 

@@ -16,7 +16,11 @@ Readings used here (where the paper is silent, garbled or ambiguous):
   is the Galerkin projection of (eE/m_e)(cos th d/dv - sin th / v d/dth) of
   eq. (bte-1d) with q_e = +e, its angular factors <Y_q|mu|Y_l> and
   <Y_q|(1-mu^2) d/dmu|Y_l> evaluated exactly by Gauss-Legendre quadrature;
-* speed boundary conditions: none (natural) at v = 0 and v = vmax.
+* speed boundary conditions: natural at v = 0; at v = vmax either natural
+  ("natural") or f(vmax) = 0 ("zero_vmax": the clamped spline that is nonzero
+  at vmax is dropped from the basis).  The natural form keeps the exact
+  invariants used by the pins; the workloads use zero_vmax, which keeps the
+  explicit-in-E speed advection from amplifying the outflow spline.
 """
 from __future__ import annotations
 

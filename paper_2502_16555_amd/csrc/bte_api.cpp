@@ -167,7 +167,7 @@ void fill_devops(bte_handle* h) {
   }
   d.nx_total = h->x_off[nd];
   d.max_nx = maxnx;
-  if (d.npad > 4 * bte::kPanelThreads) throw std::invalid_argument("Nr*Ntheta must be <= 2048");
+  if (d.npad > bte::kMaxRows) throw std::invalid_argument("Nr*Ntheta must be <= 2048");
   std::vector<int> x_disc(d.nx_total);
   std::vector<double> xhat(d.nx_total), n0x(d.nx_total);
   std::vector<double> n0(c.n0_per, c.n0_per + nd), E0(c.E0_per, c.E0_per + nd);
@@ -191,6 +191,16 @@ void fill_devops(bte_handle* h) {
   d.Uinv = h->upload(H.Uinv);
   d.Cord = h->upload(H.Cord);
   d.Aord = h->upload(H.Aord);
+  {
+    std::vector<double> T1((size_t)H.n * H.n), T2((size_t)H.n * H.n);
+    for (int r = 0; r < H.n; ++r)
+      for (int c = 0; c < H.n; ++c) {
+        T1[(size_t)c * H.n + r] = H.Cord[(size_t)r * H.n + c];
+        T2[(size_t)c * H.n + r] = H.Aord[(size_t)r * H.n + c];
+      }
+    d.CordT = h->upload(T1);
+    d.AordT = h->upload(T2);
+  }
   d.Csb = h->upload(H.Csb);
   d.mom = h->upload(H.mom);
   {
@@ -213,6 +223,7 @@ void fill_devops(bte_handle* h) {
   d.Y = h->alloc<double>(nxt * d.n);
   const size_t elt = (c.precision == BTE_FP64) ? sizeof(double) : sizeof(float);
   d.lu = h->alloc<char>(nxt * d.npad * d.npad * elt);
+  d.xscr = h->alloc<char>(nxt * d.npad * bte::kNB * elt);
   d.piv = h->alloc<int>(nxt * d.npad);
   d.perm = h->alloc<int>(nxt * (2 * bte::kMaxSwapRows + 1));
   d.E = h->alloc<double>(nxt);

@@ -12,9 +12,10 @@ namespace bte {
 // Blocking of the batched LU: outer panel width (trailing-update rank); the
 // register-resident sub-panel inside the panel factorization is 8 (FP64) or
 // 16 (FP32) columns wide.
-constexpr int kNB = 64;
+constexpr int kNB = 128;
 constexpr int kPanelThreads = 512;
 constexpr int kMaxSwapRows = 2 * kNB;   // rows touched by one panel's interchanges
+constexpr int kMaxRows = 2048;          // largest padded system (n = Nr * Ntheta <= 2048)
 
 // Device status word bits.
 enum : int { kStSingular = 1, kStNoConv = 2, kStNonFinite = 4 };
@@ -40,6 +41,8 @@ struct DevOps {
   double* Uinv = nullptr;      // [nr*nr]
   double* Cord = nullptr;      // [n*n]
   double* Aord = nullptr;      // [n*n]
+  double* CordT = nullptr;     // [n*n] transposed (columns contiguous), for the matrix formation
+  double* AordT = nullptr;     // [n*n]
   double* Csb = nullptr;       // [n_params*n*n]
   double* mom = nullptr;       // [3*n]
   double* Qt = nullptr;        // concatenated Q of all discharges, FP64
@@ -47,7 +50,8 @@ struct DevOps {
   double* poisson = nullptr;   // concatenated [nx_d][nx_d]
   // workspaces (device)
   double* Y = nullptr;         // [nx_total*n] mode-major scratch of the X step
-  void* lu = nullptr;          // [nx_total][npad][npad] of T (double or float)
+  void* lu = nullptr;          // [nx_total][npad][npad] of T (double or float), column-major
+  void* xscr = nullptr;        // [nx_total][npad][kNB] of T: interchange staging of extra rows
   int* piv = nullptr;          // [nx_total][npad]
   int* perm = nullptr;         // [nx_total][2*kMaxSwapRows] row list / source list of one panel
   double* E = nullptr;         // [nx_total]

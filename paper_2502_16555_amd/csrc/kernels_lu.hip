@@ -2,21 +2,24 @@
 // eq. (vspace_batched_system),  (I - dt (n0 C + E_i A)) F*_i = F_i,  solved by a
 // batched right-looking blocked LU factorization with partial pivoting.
 //
-// Storage: one row-major npad x npad matrix per collocation point (npad = n
-// rounded up to the panel width, padded with identity).  Interchanges are
-// applied "as you go": a panel's interchanges are applied to that panel and
-// to the trailing columns only, so the solve applies P_1, L_1^-1, P_2, L_2^-1,
-// ..., U^-1 in that order (A = P_1^T L_1 P_2^T L_2 ... U).
+// Storage: one column-major npad x npad matrix per collocation point (npad = n
+// rounded up to the panel width kNB = 128, padded with identity), so panel
+// columns, interchanges and the column-oriented solves are all unit-stride.
+// Interchanges are applied "as you go": a panel's interchanges reach that
+// panel and the trailing columns only, so the solve applies P_1, L_1^-1, P_2,
+// L_2^-1, ..., U^-1 in that order (A = P_1^T L_1 P_2^T L_2 ... U).
 //
-// Per panel k0 (width kNB):
-//   k_panel      one 512-thread block per matrix: partial pivoting (max |a|,
-//                ties to the lowest row), elimination of 8/16-column sub-panels
-//                held in registers, in-panel updates of the remaining columns;
-//   k_swap_trsm  interchanges + U12 = L11^-1 A12 on 64-column chunks;
-//   k_update     A22 -= L21 U12 as a batched MFMA GEMM (64 x 64 tiles, K = kNB).
-// Mixed precision (FP32 factors) refines in FP64: r = b - A x with A applied
-// from the FP64 operators (the residual is the operator action of
-// Alg. vspace_action), x += LU^-1 r, until max|r| <= rtol max|b|.
+// Per panel k0:
+//   k_panel   one 512-thread block per matrix: partial pivoting (max |a|, ties
+//             to the lowest row) over register-resident sub-panels of 8 (FP64)
+//             or 16 (FP32) columns, in-panel updates of the remaining columns,
+//             and the panel's row permutation for the trailing columns;
+//   k_u12     per 64/128 trailing columns: the panel's interchanges and
+//             U12 = L11^-1 P A12 by 16-row blocks (MFMA off-diagonal products,
+//             short substitutions on the diagonal blocks);
+//   k_update  A22 -= L21 U12: 128 x 128 MFMA tiles, K = 128 in double-buffered
+//             LDS chunks; blocks of one matrix are kept on one XCD so that L21
+//             and U12 stay in that XCD's L2.
 #include <climits>
 #include <cmath>
 
@@ -27,6 +30,10 @@ namespace {
 
 using f64x4 = double __attribute__((ext_vector_type(4)));
 using f32x4 = float __attribute__((ext_vector_type(4)));
+
+constexpr int NB = kNB;
+constexpr int kPermStride = 1 + 2 * kMaxSwapRows;
+constexpr int kXcd = 8;  // XCDs of an MI355X; workgroups are dealt to them round-robin
 
 // MFMA 16x16x4 tiles: operand lanes hold A[i = lane%16][k = lane/16] and
 // B[k = lane/16][j = lane%16]; result item t of lane l holds D[row(l, t)][l%16]
@@ -50,67 +57,86 @@ struct Mma<float> {
   __device__ static inline int row(int lk, int t) { return 4 * lk + t; }
 };
 
-constexpr int kPermStride = 2 * kMaxSwapRows + 1;
+// Block id -> (matrix, item) such that all items of a matrix run on one XCD.
+__device__ inline void xcd_map(int bid, int items, int nmat, int* mat, int* item) {
+  const int xcd = bid % kXcd, j = bid / kXcd;
+  *mat = xcd + kXcd * (j / items);
+  *item = j % items;
+}
+
+inline int xcd_grid(int items, int nmat) { return kXcd * items * ((nmat + kXcd - 1) / kXcd); }
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using type = float4;
+  static constexpr int per = 4;
+};
+template <>
+struct Vec4<double> {
+  using type = double2;
+  static constexpr int per = 2;
+};
+
 
 // ---------------------------------------------------------------------------
-// Matrix formation: LU[x] = I - dt (n0_x C + E_x A), identity on the padding.
+// Matrix formation, column c of point x: I - dt (n0_x C + E_x A), identity padding.
+// CT/AT hold C^T and A^T row-major, i.e. the columns of C and A contiguously.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* __restrict__ C,
-                                              const double* __restrict__ Aop, const double* __restrict__ E,
-                                              const double* __restrict__ n0x, const int* __restrict__ status,
-                                              double dt, int n, int npad) {
-  const int x = blockIdx.y;
-  const int r = blockIdx.x;  // one block per row
+__global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* __restrict__ CT,
+                                              const double* __restrict__ AT, const double* __restrict__ E,
+                                              const double* __restrict__ n0x, double dt, int n, int npad) {
+  const int x = blockIdx.y, c = blockIdx.x;
   const double e = E[x], nn = n0x[x];
-  T* row = LU + ((size_t)x * npad + r) * npad;
-  if (r < n) {
-    const double* cr = C + (size_t)r * n;
-    const double* ar = Aop + (size_t)r * n;
-    for (int c = threadIdx.x; c < npad; c += blockDim.x) {
-      double v = (c < n) ? -dt * (nn * cr[c] + e * ar[c]) : 0.0;
-      if (c == r) v += 1.0;
-      row[c] = static_cast<T>(v);
+  T* col = LU + ((size_t)x * npad + c) * npad;
+  if (c < n) {
+    const double* cc = CT + (size_t)c * n;
+    const double* ac = AT + (size_t)c * n;
+    for (int r = threadIdx.x; r < npad; r += blockDim.x) {
+      double v = (r < n) ? -dt * (nn * cc[r] + e * ac[r]) : 0.0;
+      if (r == c) v += 1.0;
+      col[r] = static_cast<T>(v);
     }
   } else {
-    for (int c = threadIdx.x; c < npad; c += blockDim.x) row[c] = static_cast<T>(c == r ? 1.0 : 0.0);
+    for (int r = threadIdx.x; r < npad; r += blockDim.x) col[r] = static_cast<T>(r == c ? 1.0 : 0.0);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Panel factorization (rows k0.., columns k0..k0+kNB-1), one block per matrix.
+// Panel factorization: rows k0.., columns k0..k0+NB-1, one block per matrix.
 // ---------------------------------------------------------------------------
 template <typename T, int RPT, int IB>
 __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int* __restrict__ piv,
                                                          int* __restrict__ perm, int* __restrict__ status, int npad,
                                                          int k0) {
-  constexpr int NW = kPanelThreads / 64;
+  constexpr int NT = kPanelThreads, NW = NT / 64;
   const int mat = blockIdx.x;
   T* A = LU + (size_t)mat * npad * npad;
   int* ip = piv + (size_t)mat * npad;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  __shared__ double s_val[NW];
-  __shared__ int s_idx[NW];
-  __shared__ int s_p;
-  __shared__ T s_row[2][IB];
+  __shared__ double s_val[2][NW];
+  __shared__ int s_idx[2][NW];
+  __shared__ T s_row[2][2][IB];
   __shared__ T s_L11[IB][IB + 1];
-  __shared__ T s_U[IB][kNB];
+  __shared__ T s_U[IB][NB];
   __shared__ int s_sw[IB];
   __shared__ int s_R[2 * IB];
   __shared__ int s_src[2 * IB];
-  __shared__ int s_nR;
-  __shared__ int s_any;
   __shared__ int s_lab[kMaxSwapRows];
+  __shared__ int s_pos[kMaxRows];
+  __shared__ int s_nR, s_any;
   bool singular = false;
 
-  for (int sp = 0; sp < kNB / IB; ++sp) {
+  for (int sp = 0; sp < NB / IB; ++sp) {
     const int c0 = k0 + sp * IB;
     T a[RPT][IB];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int r = c0 + tid + q * kPanelThreads;
+      const int r = c0 + tid + q * NT;
 #pragma unroll
-      for (int j = 0; j < IB; ++j) a[q][j] = (r < npad) ? A[(size_t)r * npad + c0 + j] : T(0);
+      for (int j = 0; j < IB; ++j) a[q][j] = (r < npad) ? A[(size_t)(c0 + j) * npad + r] : T(0);
     }
 #pragma clang loop unroll(full)
     for (int j = 0; j < IB; ++j) {
@@ -119,7 +145,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
       int bi = INT_MAX;
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        const int r = c0 + tid + q * kPanelThreads;
+        const int r = c0 + tid + q * NT;
         if (r >= c && r < npad) {
           const double v = fabs(static_cast<double>(a[q][j]));
           if (v > best) {
@@ -136,53 +162,55 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
           bi = oi;
         }
       }
+      // Partials and pivot rows live in buffers of parity j & 1: a buffer is
+      // rewritten two columns later, after every thread has passed both
+      // barriers of the column in between, so two barriers per column suffice.
+      const int par = j & 1;
       if (lane == 0) {
-        s_val[wid] = best;
-        s_idx[wid] = bi;
+        s_val[par][wid] = best;
+        s_idx[par][wid] = bi;
       }
       __syncthreads();
-      if (wid == 0) {
-        double v = (lane < NW) ? s_val[lane] : -1.0;
-        int i = (lane < NW) ? s_idx[lane] : INT_MAX;
-        for (int off = NW / 2; off > 0; off >>= 1) {
-          const double ov = __shfl_xor(v, off);
-          const int oi = __shfl_xor(i, off);
-          if (ov > v || (ov == v && oi < i)) {
+      int p = INT_MAX;
+      {
+        double v = -1.0;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+          const double ov = s_val[par][u];
+          const int oi = s_idx[par][u];
+          if (ov > v || (ov == v && oi < p)) {
             v = ov;
-            i = oi;
+            p = oi;
           }
         }
-        if (lane == 0) s_p = i;
       }
-      __syncthreads();
-      const int p = s_p;
-      // row c is owned by thread j (q = 0); exchange rows c and p through LDS
+      // row c is owned by thread j (q = 0); publish rows c and p
       if (tid == j) {
 #pragma unroll
-        for (int jj = 0; jj < IB; ++jj) s_row[0][jj] = a[0][jj];
+        for (int jj = 0; jj < IB; ++jj) s_row[par][0][jj] = a[0][jj];
       }
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        if (c0 + tid + q * kPanelThreads == p) {
+        if (c0 + tid + q * NT == p) {
 #pragma unroll
-          for (int jj = 0; jj < IB; ++jj) s_row[1][jj] = a[q][jj];
+          for (int jj = 0; jj < IB; ++jj) s_row[par][1][jj] = a[q][jj];
         }
       }
       __syncthreads();
       if (p != c) {
         if (tid == j) {
 #pragma unroll
-          for (int jj = 0; jj < IB; ++jj) a[0][jj] = s_row[1][jj];
+          for (int jj = 0; jj < IB; ++jj) a[0][jj] = s_row[par][1][jj];
         }
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
-          if (c0 + tid + q * kPanelThreads == p) {
+          if (c0 + tid + q * NT == p) {
 #pragma unroll
-            for (int jj = 0; jj < IB; ++jj) a[q][jj] = s_row[0][jj];
+            for (int jj = 0; jj < IB; ++jj) a[q][jj] = s_row[par][0][jj];
           }
         }
       }
-      const T pv = s_row[1][j];
+      const T pv = s_row[par][1][j];
       if (tid == 0) {
         ip[c] = p;
         s_sw[j] = p;
@@ -190,24 +218,24 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
       if (pv == T(0)) singular = true;
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        const int r = c0 + tid + q * kPanelThreads;
+        const int r = c0 + tid + q * NT;
         if (r > c && r < npad && pv != T(0)) {
           const T l = a[q][j] / pv;
           a[q][j] = l;
 #pragma unroll
           for (int jj = 0; jj < IB; ++jj)
-            if (jj > j) a[q][jj] -= l * s_row[1][jj];
+            if (jj > j) a[q][jj] -= l * s_row[par][1][jj];
         }
       }
-      __syncthreads();
     }
-    // write the factored sub-panel back
+    __syncthreads();
+    // write the factored sub-panel back (coalesced: consecutive threads, consecutive rows)
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int r = c0 + tid + q * kPanelThreads;
+      const int r = c0 + tid + q * NT;
       if (r < npad) {
 #pragma unroll
-        for (int j = 0; j < IB; ++j) A[(size_t)r * npad + c0 + j] = a[q][j];
+        for (int j = 0; j < IB; ++j) A[(size_t)(c0 + j) * npad + r] = a[q][j];
       }
     }
     if (tid < IB) {
@@ -224,25 +252,25 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
       }
       for (int j = 0; j < IB; ++j) {
         const int p = s_sw[j];
-        int ip2;
+        int i2;
         if (p < c0 + IB) {
-          ip2 = p - c0;
+          i2 = p - c0;
         } else {
-          ip2 = -1;
+          i2 = -1;
           for (int t = IB; t < nR; ++t)
-            if (s_R[t] == p) ip2 = t;
-          if (ip2 < 0) {
-            ip2 = nR;
+            if (s_R[t] == p) i2 = t;
+          if (i2 < 0) {
+            i2 = nR;
             s_R[nR] = p;
             lab[nR] = nR;
             ++nR;
           }
         }
-        if (ip2 != j) {
+        if (i2 != j) {
           any = 1;
           const int tmp = lab[j];
-          lab[j] = lab[ip2];
-          lab[ip2] = tmp;
+          lab[j] = lab[i2];
+          lab[i2] = tmp;
         }
       }
       for (int t = 0; t < nR; ++t) s_src[t] = s_R[lab[t]];
@@ -253,82 +281,97 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
     // apply the interchanges to the other columns of the panel (rows >= c0)
     if (s_any) {
       const int nR = s_nR;
-      constexpr int NOC = kNB - IB;
-      T vb[(NOC * 2 * IB + kPanelThreads - 1) / kPanelThreads];
+      constexpr int NOC = NB - IB;
+      constexpr int NV = (NOC * 2 * IB + NT - 1) / NT;
+      T vb[NV];
 #pragma unroll
-      for (int u = 0; u < (NOC * 2 * IB + kPanelThreads - 1) / kPanelThreads; ++u) {
-        const int e = tid + u * kPanelThreads;
+      for (int u = 0; u < NV; ++u) {
+        const int e = tid + u * NT;
         if (e < NOC * nR) {
-          const int t = e / NOC, cc = e % NOC;
+          const int t = e % nR, cc = e / nR;
           const int col = (cc < sp * IB) ? k0 + cc : k0 + IB + cc;
-          vb[u] = A[(size_t)s_src[t] * npad + col];
+          vb[u] = A[(size_t)col * npad + s_src[t]];
         }
       }
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < (NOC * 2 * IB + kPanelThreads - 1) / kPanelThreads; ++u) {
-        const int e = tid + u * kPanelThreads;
+      for (int u = 0; u < NV; ++u) {
+        const int e = tid + u * NT;
         if (e < NOC * nR) {
-          const int t = e / NOC, cc = e % NOC;
+          const int t = e % nR, cc = e / nR;
           const int col = (cc < sp * IB) ? k0 + cc : k0 + IB + cc;
-          if (s_src[t] != s_R[t]) A[(size_t)s_R[t] * npad + col] = vb[u];
+          if (s_src[t] != s_R[t]) A[(size_t)col * npad + s_R[t]] = vb[u];
         }
       }
       __syncthreads();
     }
     // update the remaining columns of the panel
-    const int nrest = k0 + kNB - c0 - IB;
+    const int nrest = k0 + NB - c0 - IB;
     if (nrest > 0) {
       if (tid < nrest) {
-        const int col = c0 + IB + tid;
-        for (int j = 0; j < IB; ++j) s_U[j][tid] = A[(size_t)(c0 + j) * npad + col];
+        T* colp = A + (size_t)(c0 + IB + tid) * npad;
+        for (int j = 0; j < IB; ++j) s_U[j][tid] = colp[c0 + j];
         for (int j = 1; j < IB; ++j) {
           T v = s_U[j][tid];
           for (int i = 0; i < j; ++i) v -= s_L11[j][i] * s_U[i][tid];
           s_U[j][tid] = v;
         }
-        for (int j = 0; j < IB; ++j) A[(size_t)(c0 + j) * npad + col] = s_U[j][tid];
+        for (int j = 0; j < IB; ++j) colp[c0 + j] = s_U[j][tid];
       }
       __syncthreads();
+      // rows >= c0+IB: A[r][rest] -= L[r][c0:c0+IB] U[c0:c0+IB][rest], in batches of
+      // CB columns so that the loads of a batch are in flight together
+      constexpr int CB = (RPT * IB >= 64) ? 2 : ((RPT >= 2) ? 4 : 8);
+      for (int cb = 0; cb < nrest; cb += CB) {
+        T v[RPT][CB];
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int r = c0 + tid + q * kPanelThreads;
-        if (r >= c0 + IB && r < npad) {
-          T* row = A + (size_t)r * npad + c0 + IB;
-          for (int cc = 0; cc < nrest; ++cc) {
-            T s = row[cc];
+        for (int q = 0; q < RPT; ++q) {
+          const int r = c0 + tid + q * NT;
 #pragma unroll
-            for (int j = 0; j < IB; ++j) s -= a[q][j] * s_U[j][cc];
-            row[cc] = s;
-          }
+          for (int u = 0; u < CB; ++u)
+            v[q][u] = (r >= c0 + IB && r < npad && cb + u < nrest) ? A[(size_t)(c0 + IB + cb + u) * npad + r] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+#pragma unroll
+          for (int u = 0; u < CB; ++u)
+#pragma unroll
+            for (int j = 0; j < IB; ++j) v[q][u] -= a[q][j] * s_U[j][(cb + u) & (NB - 1)];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int r = c0 + tid + q * NT;
+#pragma unroll
+          for (int u = 0; u < CB; ++u)
+            if (r >= c0 + IB && r < npad && cb + u < nrest) A[(size_t)(c0 + IB + cb + u) * npad + r] = v[q][u];
         }
       }
       __syncthreads();
     }
   }
   if (singular && tid == 0) atomicOr(status, kStSingular);
-  // permutation of the whole panel (for the trailing columns)
+  // permutation of the whole panel for the trailing columns
+  for (int r = k0 + NB + tid; r < npad; r += NT) s_pos[r] = -1;
+  __syncthreads();
   if (tid == 0) {
     int* pm = perm + (size_t)mat * kPermStride;
     int* R = pm + 1;
     int* src = pm + 1 + kMaxSwapRows;
     int* lab = s_lab;
-    int nR = kNB;
-    for (int t = 0; t < kNB; ++t) {
+    int nR = NB;
+    for (int t = 0; t < NB; ++t) {
       R[t] = k0 + t;
       lab[t] = t;
     }
-    for (int j = 0; j < kNB; ++j) {
+    for (int j = 0; j < NB; ++j) {
       const int p = ip[k0 + j];
       int i2;
-      if (p < k0 + kNB) {
+      if (p < k0 + NB) {
         i2 = p - k0;
       } else {
-        i2 = -1;
-        for (int t = kNB; t < nR; ++t)
-          if (R[t] == p) i2 = t;
+        i2 = s_pos[p];
         if (i2 < 0) {
           i2 = nR;
+          s_pos[p] = nR;
           R[nR] = p;
           lab[nR] = nR;
           ++nR;
@@ -344,128 +387,221 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
 }
 
 // ---------------------------------------------------------------------------
-// Interchanges and U12 = L11^-1 A12 for one 64-column chunk right of the panel.
-// One wavefront per chunk; every lane owns one column (no cross-lane hazards).
+// Interchanges and U12 = L11^-1 P A12 for CT trailing columns.  The block owns
+// its columns, so all original rows are read (gathered X in LDS, extra rows
+// through a global scratch) before any of them is written back.  The triangular
+// solve runs by 16-row blocks: the off-diagonal part of each block row is an
+// MFMA product with the rows already solved, the 16 x 16 diagonal part a short
+// forward substitution (one thread per column).
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(64) void k_swap_trsm(T* __restrict__ LU, const int* __restrict__ perm, int npad, int k0) {
-  const int mat = blockIdx.y;
+template <typename T, int CT>
+__global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const int* __restrict__ perm,
+                                             T* __restrict__ xscr, int npad, int k0, int nct, int nmat) {
+  constexpr int LDB = CT + 4;
+  constexpr int NBW = CT / 64;   // 16-column MFMA blocks per wavefront
+  int mat, ct;
+  xcd_map(blockIdx.x, nct, nmat, &mat, &ct);
+  if (mat >= nmat) return;
   T* A = LU + (size_t)mat * npad * npad;
-  const int col = k0 + kNB + blockIdx.x * 64 + threadIdx.x;
+  const int c0 = k0 + NB + ct * CT;
   const int* pm = perm + (size_t)mat * kPermStride;
   const int nR = pm[0];
   const int* R = pm + 1;
   const int* src = pm + 1 + kMaxSwapRows;
-  __shared__ T sL[kNB][kNB + 1];
-  __shared__ T sX[kNB][64];
-  __shared__ T sE[kNB][64];
-  for (int e = threadIdx.x; e < kNB * kNB; e += 64) {
-    const int r = e / kNB, c = e % kNB;
-    sL[r][c] = A[(size_t)(k0 + r) * npad + k0 + c];
+  __shared__ T sB[NB][LDB];
+  __shared__ T sL[16][NB + 4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int e = tid; e < NB * CT; e += 256) {
+    const int k = e % NB, j = e / NB;
+    sB[k][j] = A[(size_t)(c0 + j) * npad + src[k]];
   }
-  const bool active = col < npad;
-  if (active) {
-    for (int t = 0; t < nR; ++t) {
-      const T v = A[(size_t)src[t] * npad + col];
-      if (t < kNB) sX[t][threadIdx.x] = v;
-      else sE[t - kNB][threadIdx.x] = v;
+  const int nx = nR - NB;
+  if (nx > 0) {
+    for (int e = tid; e < nx * CT; e += 256) {
+      const int t = NB + e % nx, j = e / nx;
+      xscr[((size_t)mat * npad + c0 + j) * NB + (t - NB)] = A[(size_t)(c0 + j) * npad + src[t]];
     }
-    for (int t = kNB; t < nR; ++t)
-      if (src[t] != R[t]) A[(size_t)R[t] * npad + col] = sE[t - kNB][threadIdx.x];
   }
   __syncthreads();
-  if (active) {
-    for (int j = 1; j < kNB; ++j) {
-      T s = sX[j][threadIdx.x];
-      for (int i = 0; i < j; ++i) s -= sL[j][i] * sX[i][threadIdx.x];
-      sX[j][threadIdx.x] = s;
+  if (nx > 0) {
+    for (int e = tid; e < nx * CT; e += 256) {
+      const int t = NB + e % nx, j = e / nx;
+      if (src[t] != R[t]) A[(size_t)(c0 + j) * npad + R[t]] = xscr[((size_t)mat * npad + c0 + j) * NB + (t - NB)];
     }
-    for (int j = 0; j < kNB; ++j) A[(size_t)(k0 + j) * npad + col] = sX[j][threadIdx.x];
+  }
+  for (int I = 0; I < NB / 16; ++I) {
+    const int r0 = 16 * I;
+    // rows r0..r0+15 of L11, columns 0..r0+15
+    for (int e = tid; e < 16 * (r0 + 16); e += 256) {
+      const int c = e / 16, r = e % 16;
+      sL[r][c] = A[(size_t)(k0 + c) * npad + k0 + r0 + r];
+    }
+    __syncthreads();
+    if (I > 0) {
+      typename Mma<T>::acc acc[NBW];
+#pragma unroll
+      for (int b = 0; b < NBW; ++b) acc[b] = typename Mma<T>::acc{0, 0, 0, 0};
+      for (int k = 0; k < r0; k += 4) {
+        const T av = sL[li][k + lk];
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) acc[b] = Mma<T>::step(av, sB[k + lk][(w * NBW + b) * 16 + li], acc[b]);
+      }
+#pragma unroll
+      for (int b = 0; b < NBW; ++b)
+#pragma unroll
+        for (int it = 0; it < 4; ++it) sB[r0 + Mma<T>::row(lk, it)][(w * NBW + b) * 16 + li] -= acc[b][it];
+      __syncthreads();
+    }
+    if (tid < CT) {
+      for (int r = 1; r < 16; ++r) {
+        T v = sB[r0 + r][tid];
+        for (int c = 0; c < r; ++c) v -= sL[r][r0 + c] * sB[r0 + c][tid];
+        sB[r0 + r][tid] = v;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NB * CT; e += 256) {
+    const int k = e % NB, j = e / NB;
+    A[(size_t)(c0 + j) * npad + k0 + k] = sB[k][j];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Trailing update A22 -= L21 U12, 64 x 64 output tiles, K = kNB, MFMA 16x16x4.
+// Trailing update A22 -= L21 U12: 128 x 128 tiles, K = NB in chunks of KC staged
+// through double-buffered LDS, four wavefronts of 64 x 64 (4 x 4 MFMA blocks).
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_update(T* __restrict__ LU, int npad, int k0) {
-  const int mat = blockIdx.y;
-  const int mt = (npad - k0 - kNB) / 64;
-  const int ti = blockIdx.x / mt, tj = blockIdx.x % mt;
+template <typename T, int KC>
+__global__ __launch_bounds__(256) void k_update(T* __restrict__ LU, int npad, int k0, int mt, int nmat) {
+  using V = typename Vec4<T>::type;
+  constexpr int PER = Vec4<T>::per;
+  constexpr int LD = 128 + 4;
+  int mat, tile;
+  xcd_map(blockIdx.x, mt * mt, nmat, &mat, &tile);
+  if (mat >= nmat) return;
+  const int ti = tile % mt, tj = tile / mt;
   T* A = LU + (size_t)mat * npad * npad;
-  const int r0 = k0 + kNB + ti * 64, c0 = k0 + kNB + tj * 64;
-  __shared__ T sA[64][kNB + 1];
-  __shared__ T sB[kNB][64 + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * kNB; e += 256) {
-    const int r = e / kNB, c = e % kNB;
-    sA[r][c] = A[(size_t)(r0 + r) * npad + k0 + c];
-  }
-  for (int e = tid; e < kNB * 64; e += 256) {
-    const int r = e / 64, c = e % 64;
-    sB[r][c] = A[(size_t)(k0 + r) * npad + c0 + c];
-  }
-  __syncthreads();
-  const int lane = tid & 63, w = tid >> 6;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  typename Mma<T>::acc acc[2][2];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = typename Mma<T>::acc{0, 0, 0, 0};
+  const int r0 = k0 + NB + ti * 128, c0 = k0 + NB + tj * 128;
+  __shared__ T sA[2][KC][LD];
+  __shared__ T sB[2][KC][LD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-#pragma unroll 4
-  for (int k = 0; k < kNB; k += 4) {
-    T av[2], bv[2];
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  // global -> register staging of one K chunk: A part KC columns x 128 rows,
+  // B part 128 columns x KC rows, both as PER-wide vectors down a column
+  constexpr int NA = KC * 128 / PER / 256, NBV = KC * 128 / PER / 256;
+  V ra[NA], rb[NBV];
+  auto load = [&](int kk) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) av[bi] = sA[wr + bi * 16 + li][k + lk];
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + u * 256;
+      const int k = e / (128 / PER), i = (e % (128 / PER)) * PER;
+      ra[u] = *reinterpret_cast<const V*>(A + (size_t)(k0 + kk + k) * npad + r0 + i);
+    }
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) bv[bj] = sB[k + lk][wc + bj * 16 + li];
+    for (int u = 0; u < NBV; ++u) {
+      const int e = tid + u * 256;
+      const int j = e / (KC / PER), k = (e % (KC / PER)) * PER;
+      rb[u] = *reinterpret_cast<const V*>(A + (size_t)(c0 + j) * npad + k0 + kk + k);
+    }
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + u * 256;
+      const int k = e / (128 / PER), i = (e % (128 / PER)) * PER;
+      const T* v = reinterpret_cast<const T*>(&ra[u]);
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mma<T>::step(av[bi], bv[bj], acc[bi][bj]);
+      for (int m = 0; m < PER; ++m) sA[buf][k][i + m] = v[m];
+    }
+#pragma unroll
+    for (int u = 0; u < NBV; ++u) {
+      const int e = tid + u * 256;
+      const int j = e / (KC / PER), k = (e % (KC / PER)) * PER;
+      const T* v = reinterpret_cast<const T*>(&rb[u]);
+#pragma unroll
+      for (int m = 0; m < PER; ++m) sB[buf][k + m][j] = v[m];
+    }
+  };
+  typename Mma<T>::acc acc[4][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = typename Mma<T>::acc{0, 0, 0, 0};
+  load(0);
+  store(0);
+  __syncthreads();
+  constexpr int NCH = NB / KC;
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < NCH) load((ch + 1) * KC);
+#pragma unroll
+    for (int k = 0; k < KC; k += 4) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][k + lk][wr + bi * 16 + li];
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][k + lk][wc + bj * 16 + li];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mma<T>::step(av[bi], bv[bj], acc[bi][bj]);
+    }
+    if (ch + 1 < NCH) {
+      store(buf ^ 1);
+      __syncthreads();
+    }
   }
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
       for (int it = 0; it < 4; ++it) {
         const int r = r0 + wr + bi * 16 + Mma<T>::row(lk, it);
         const int c = c0 + wc + bj * 16 + li;
-        T* p = A + (size_t)r * npad + c;
+        T* p = A + (size_t)c * npad + r;
         *p = *p - acc[bi][bj][it];
       }
 }
 
 // ---------------------------------------------------------------------------
-// Solve with the factors (one block per matrix), FP64 right-hand side.
+// Solve with the factors (one 1024-thread block per matrix), FP64 right-hand side.
 // transpose = 0: x = U^-1 L_m^-1 P_m ... L_1^-1 P_1 b
 // transpose = 1: y = P_1^T L_1^-T ... P_m^T L_m^-T U^-T c
+// Diagonal blocks are staged in LDS and solved by one wavefront (two rows per
+// lane); the off-diagonal strips are applied column-oriented (thread per row)
+// or, for the transposed factors, as per-column dot products (wave per column).
 // ---------------------------------------------------------------------------
 template <typename T, int TRANSPOSE>
-__global__ __launch_bounds__(256) void k_solve(const T* __restrict__ LU, const int* __restrict__ piv,
-                                               const double* __restrict__ Bin, double* __restrict__ Xout,
-                                               const int* __restrict__ status, int accumulate, int check_done,
-                                               int npad) {
+__global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const int* __restrict__ piv,
+                                                const double* __restrict__ Bin, double* __restrict__ Xout,
+                                                const int* __restrict__ status, int accumulate, int check_done,
+                                                int npad) {
   if (check_done && status[1]) return;
-  extern __shared__ double sb[];        // [npad] right-hand side / solution
-  __shared__ double sT[kNB][kNB + 1];   // diagonal block
-  __shared__ double sacc[4][kNB];
+  __shared__ double sb[kMaxRows];
+  __shared__ T sD[NB][NB + 1];
   const int mat = blockIdx.x;
   const T* A = LU + (size_t)mat * npad * npad;
   const int* ip = piv + (size_t)mat * npad;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int NWV = 1024 / 64;
   const double* b = Bin + (size_t)mat * npad;
-  for (int i = tid; i < npad; i += 256) sb[i] = b[i];
+  for (int i = tid; i < npad; i += 1024) sb[i] = b[i];
+  const int np = npad / NB;
+  auto stage_diag = [&](int k0) {
+    for (int e = tid; e < NB * NB; e += 1024) {
+      const int c = e / NB, r = e % NB;
+      sD[r][c] = A[(size_t)(k0 + c) * npad + k0 + r];
+    }
+  };
   __syncthreads();
-  const int np = npad / kNB;
   if (!TRANSPOSE) {
     for (int p = 0; p < np; ++p) {
-      const int k0 = p * kNB;
+      const int k0 = p * NB;
       if (tid == 0) {
-        for (int j = 0; j < kNB; ++j) {
+        for (int j = 0; j < NB; ++j) {
           const int q = ip[k0 + j];
           if (q != k0 + j) {
             const double t = sb[k0 + j];
@@ -474,89 +610,107 @@ __global__ __launch_bounds__(256) void k_solve(const T* __restrict__ LU, const i
           }
         }
       }
-      for (int e = tid; e < kNB * kNB; e += 256) sT[e / kNB][e % kNB] = A[(size_t)(k0 + e / kNB) * npad + k0 + e % kNB];
+      stage_diag(k0);
       __syncthreads();
-      if (w == 0) {  // unit lower triangular solve of the diagonal block
-        double v = sb[k0 + lane];
-        for (int i = 0; i < kNB - 1; ++i) {
-          const double xi = __shfl(v, i);
-          if (lane > i) v -= sT[lane][i] * xi;
+      if (w == 0) {  // unit lower triangular diagonal block
+        double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
+        for (int i = 0; i < NB - 1; ++i) {
+          const double xi = (i < 64) ? __shfl(v0, i) : __shfl(v1, i - 64);
+          if (lane > i) v0 -= static_cast<double>(sD[lane][i]) * xi;
+          if (64 + lane > i) v1 -= static_cast<double>(sD[64 + lane][i]) * xi;
         }
-        sb[k0 + lane] = v;
+        sb[k0 + lane] = v0;
+        sb[k0 + 64 + lane] = v1;
       }
       __syncthreads();
-      // b[r] -= L[r][k0:k0+64] y  for r >= k0 + 64
-      const double y = sb[k0 + lane];
-      for (int r = k0 + kNB + w; r < npad; r += 4) {
-        double s = static_cast<double>(A[(size_t)r * npad + k0 + lane]) * y;
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) sb[r] -= s;
+      for (int r = k0 + NB + tid; r < npad; r += 1024) {
+        double s = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < NB; ++j) s += static_cast<double>(A[(size_t)(k0 + j) * npad + r]) * sb[k0 + j];
+        sb[r] -= s;
       }
       __syncthreads();
     }
     for (int p = np - 1; p >= 0; --p) {
-      const int k0 = p * kNB;
-      // rhs_j = b_j - sum_{c >= k0+64} U[k0+j][c] x_c
-      for (int j = w; j < kNB; j += 4) {
-        const T* row = A + (size_t)(k0 + j) * npad;
-        double s = 0.0;
-        for (int c = k0 + kNB + lane; c < npad; c += 64) s += static_cast<double>(row[c]) * sb[c];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) sacc[0][j] = s;
-      }
-      for (int e = tid; e < kNB * kNB; e += 256) sT[e / kNB][e % kNB] = A[(size_t)(k0 + e / kNB) * npad + k0 + e % kNB];
+      const int k0 = p * NB;
+      stage_diag(k0);
       __syncthreads();
-      if (w == 0) {
-        double v = sb[k0 + lane] - sacc[0][lane];
-        for (int i = kNB - 1; i >= 0; --i) {
-          if (lane == i) v = v / sT[i][i];
-          const double xi = __shfl(v, i);
-          if (lane < i) v -= sT[lane][i] * xi;
+      if (w == 0) {  // upper triangular diagonal block
+        double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
+        for (int i = NB - 1; i >= 0; --i) {
+          if (i >= 64 && lane == i - 64) v1 = v1 / static_cast<double>(sD[i][i]);
+          if (i < 64 && lane == i) v0 = v0 / static_cast<double>(sD[i][i]);
+          const double xi = (i < 64) ? __shfl(v0, i) : __shfl(v1, i - 64);
+          if (lane < i) v0 -= static_cast<double>(sD[lane][i]) * xi;
+          if (64 + lane < i) v1 -= static_cast<double>(sD[64 + lane][i]) * xi;
         }
-        sb[k0 + lane] = v;
+        sb[k0 + lane] = v0;
+        sb[k0 + 64 + lane] = v1;
+      }
+      __syncthreads();
+      for (int r = tid; r < k0; r += 1024) {
+        double s = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < NB; ++j) s += static_cast<double>(A[(size_t)(k0 + j) * npad + r]) * sb[k0 + j];
+        sb[r] -= s;
       }
       __syncthreads();
     }
   } else {
-    // z = U^-T c: forward over panels; U^T is lower triangular
+    // z = U^-T c, forward over panels (U^T is lower triangular)
     for (int p = 0; p < np; ++p) {
-      const int k0 = p * kNB;
-      // acc_j = sum_{i < k0} U[i][k0+j] z_i
-      double s = 0.0;
-      for (int i = w; i < k0; i += 4) s += static_cast<double>(A[(size_t)i * npad + k0 + lane]) * sb[i];
-      sacc[w][lane] = s;
-      for (int e = tid; e < kNB * kNB; e += 256) sT[e / kNB][e % kNB] = A[(size_t)(k0 + e / kNB) * npad + k0 + e % kNB];
+      const int k0 = p * NB;
+      stage_diag(k0);
       __syncthreads();
       if (w == 0) {
-        double v = sb[k0 + lane] - (sacc[0][lane] + sacc[1][lane] + sacc[2][lane] + sacc[3][lane]);
-        for (int i = 0; i < kNB; ++i) {
-          if (lane == i) v = v / sT[i][i];
-          const double xi = __shfl(v, i);
-          if (lane > i) v -= sT[i][lane] * xi;  // (U^T)[lane][i] = U[i][lane]
+        double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
+        for (int i = 0; i < NB; ++i) {
+          if (i < 64 && lane == i) v0 = v0 / static_cast<double>(sD[i][i]);
+          if (i >= 64 && lane == i - 64) v1 = v1 / static_cast<double>(sD[i][i]);
+          const double xi = (i < 64) ? __shfl(v0, i) : __shfl(v1, i - 64);
+          if (lane > i) v0 -= static_cast<double>(sD[i][lane]) * xi;
+          if (64 + lane > i) v1 -= static_cast<double>(sD[i][64 + lane]) * xi;
         }
-        sb[k0 + lane] = v;
+        sb[k0 + lane] = v0;
+        sb[k0 + 64 + lane] = v1;
+      }
+      __syncthreads();
+      // c[col] -= sum_j U[k0+j][col] z_j for col >= k0 + NB (wave per column)
+      for (int col = k0 + NB + w; col < npad; col += NWV) {
+        const T* cp = A + (size_t)col * npad + k0;
+        double s = static_cast<double>(cp[lane]) * sb[k0 + lane] +
+                   static_cast<double>(cp[64 + lane]) * sb[k0 + 64 + lane];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) sb[col] -= s;
       }
       __syncthreads();
     }
     // for p = m..1: z <- L_p^-T z, then z <- P_p^T z
     for (int p = np - 1; p >= 0; --p) {
-      const int k0 = p * kNB;
-      double s = 0.0;
-      for (int r = k0 + kNB + w; r < npad; r += 4) s += static_cast<double>(A[(size_t)r * npad + k0 + lane]) * sb[r];
-      sacc[w][lane] = s;
-      for (int e = tid; e < kNB * kNB; e += 256) sT[e / kNB][e % kNB] = A[(size_t)(k0 + e / kNB) * npad + k0 + e % kNB];
+      const int k0 = p * NB;
+      // z_j -= sum_{r >= k0+NB} L[r][k0+j] z_r (wave per column j)
+      for (int j = w; j < NB; j += NWV) {
+        const T* cp = A + (size_t)(k0 + j) * npad;
+        double s = 0.0;
+        for (int r = k0 + NB + lane; r < npad; r += 64) s += static_cast<double>(cp[r]) * sb[r];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) sb[k0 + j] -= s;
+      }
+      stage_diag(k0);
       __syncthreads();
-      if (w == 0) {
-        double v = sb[k0 + lane] - (sacc[0][lane] + sacc[1][lane] + sacc[2][lane] + sacc[3][lane]);
-        for (int i = kNB - 1; i >= 0; --i) {
-          const double xi = __shfl(v, i);
-          if (lane < i) v -= sT[i][lane] * xi;  // (L^T)[lane][i] = L[i][lane], unit diagonal
+      if (w == 0) {  // L11^T is unit upper triangular
+        double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
+        for (int i = NB - 1; i >= 0; --i) {
+          const double xi = (i < 64) ? __shfl(v0, i) : __shfl(v1, i - 64);
+          if (lane < i) v0 -= static_cast<double>(sD[i][lane]) * xi;
+          if (64 + lane < i) v1 -= static_cast<double>(sD[i][64 + lane]) * xi;
         }
-        sb[k0 + lane] = v;
+        sb[k0 + lane] = v0;
+        sb[k0 + 64 + lane] = v1;
       }
       __syncthreads();
       if (tid == 0) {
-        for (int j = kNB - 1; j >= 0; --j) {
+        for (int j = NB - 1; j >= 0; --j) {
           const int q = ip[k0 + j];
           if (q != k0 + j) {
             const double t = sb[k0 + j];
@@ -569,228 +723,38 @@ __global__ __launch_bounds__(256) void k_solve(const T* __restrict__ LU, const i
     }
   }
   double* xo = Xout + (size_t)mat * npad;
-  for (int i = tid; i < npad; i += 256) xo[i] = accumulate ? xo[i] + sb[i] : sb[i];
-}
-
-__global__ void k_pad(const double* __restrict__ F, double* __restrict__ Bp, int n, int npad, int nx) {
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)nx * npad;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const size_t x = idx / npad;
-    const int j = static_cast<int>(idx % npad);
-    Bp[idx] = (j < n) ? F[x * n + j] : 0.0;
-  }
-}
-
-__global__ void k_unpad(const double* __restrict__ Bp, double* __restrict__ F, int n, int npad, int nx) {
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)nx * n;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const size_t x = idx / n;
-    const int j = static_cast<int>(idx % n);
-    F[idx] = Bp[x * npad + j];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// FP64 residual R = B - X + dt n0_x (X C^T) + dt E_x (X A^T)  (TRANSPOSE: C, A)
-// rows = collocation points, 32 x 64 output tiles, MFMA f64 16x16x4.
-// ---------------------------------------------------------------------------
-__device__ inline void atomic_max_pos(unsigned long long* p, double v) {
-  atomicMax(p, static_cast<unsigned long long>(__double_as_longlong(v)));
-}
-
-template <int TRANSPOSE>
-__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv, const double* __restrict__ Xv,
-                                                  double* __restrict__ Rv, const double* __restrict__ C,
-                                                  const double* __restrict__ Aop, const double* __restrict__ E,
-                                                  const double* __restrict__ n0x, unsigned long long* __restrict__ rmax,
-                                                  unsigned long long* __restrict__ bmax, const int* __restrict__ status,
-                                                  double dt, int n, int npad, int nx) {
-  if (status[1]) return;
-  constexpr int BM = 32, BN = 64, BK = 64;
-  __shared__ double sX[BM][BK + 1];
-  __shared__ double sC[BN][BK + 1];
-  __shared__ double sA[BN][BK + 1];
-  const int x0 = blockIdx.y * BM, i0 = blockIdx.x * BN;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  f64x4 accC[2], accA[2];
-  for (int b = 0; b < 2; ++b) accC[b] = accA[b] = f64x4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < n; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      const int r = e / BK, c = e % BK;
-      sX[r][c] = (x0 + r < nx && k0 + c < n) ? Xv[(size_t)(x0 + r) * npad + k0 + c] : 0.0;
-    }
-    for (int e = tid; e < BN * BK; e += 256) {
-      const int r = e / BK, c = e % BK;
-      const int i = i0 + r, k = k0 + c;
-      double cv = 0.0, av = 0.0;
-      if (i < n && k < n) {
-        const size_t o = TRANSPOSE ? (size_t)k * n + i : (size_t)i * n + k;
-        cv = C[o];
-        av = Aop[o];
-      }
-      sC[r][c] = cv;
-      sA[r][c] = av;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < BK; k += 4) {
-      const double bc = sC[w * 16 + li][k + lk];
-      const double ba = sA[w * 16 + li][k + lk];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const double ax = sX[b * 16 + li][k + lk];
-        accC[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bc, accC[b], 0, 0, 0);
-        accA[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, ba, accA[b], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int x = x0 + b * 16 + Mma<double>::row(lk, it);
-      const int i = i0 + w * 16 + li;
-      if (x < nx && i < n) {
-        const size_t o = (size_t)x * npad + i;
-        const double bv = Bv[o];
-        const double r = bv - Xv[o] + dt * n0x[x] * accC[b][it] + dt * E[x] * accA[b][it];
-        Rv[o] = r;
-        atomic_max_pos(&rmax[x], fabs(r));
-        atomic_max_pos(&bmax[x], fabs(bv));
-      }
-    }
-}
-
-// status[1] = done flag, status[2] = sweeps used; resid[0] = max_x |r|/|b|
-__global__ void k_refine_check(unsigned long long* __restrict__ rmax, unsigned long long* __restrict__ bmax,
-                               int* __restrict__ status, double* __restrict__ resid, double rtol, int sweep,
-                               int final_sweep, int nx) {
-  if (status[1]) return;
-  __shared__ double red[256];
-  double worst = 0.0;
-  for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-    const double r = __longlong_as_double(static_cast<long long>(rmax[x]));
-    const double b = __longlong_as_double(static_cast<long long>(bmax[x]));
-    const double q = (b > 0.0) ? r / b : (r > 0.0 ? INFINITY : 0.0);
-    worst = fmax(worst, (q == q) ? q : INFINITY);
-    rmax[x] = 0ull;
-    bmax[x] = 0ull;
-  }
-  red[threadIdx.x] = worst;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    resid[0] = red[0];
-    status[2] = sweep;
-    if (red[0] <= rtol) status[1] = 1;
-    else if (final_sweep) atomicOr(status, kStNoConv);
-  }
-}
-
-__global__ void k_reset_refine(unsigned long long* rmax, unsigned long long* bmax, int* status, int nx) {
-  for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-    rmax[x] = 0ull;
-    bmax[x] = 0ull;
-  }
-  if (threadIdx.x == 0) {
-    status[1] = 0;
-    status[2] = 0;
-  }
-}
-
-// grad_scal[op] += dt sum_x n0_x mu_x^T C^(op) F*_x  and  grad_E[x] = dt mu_x^T A F*_x.
-// Tiled like the residual: out[x][i] = sum_k F*[x][k] M[i][k] (MFMA f64), then the
-// epilogue contracts with mu[x][i].  Grid: (n/64, ceil(nx/32), n_params + 1).
-__global__ __launch_bounds__(256) void k_adjoint_grads(const double* __restrict__ Mu, const double* __restrict__ Fs,
-                                                       const double* __restrict__ Csb, const double* __restrict__ Aop,
-                                                       const double* __restrict__ n0x, double* __restrict__ gscal,
-                                                       double* __restrict__ gE, double dt, int n, int nx, int nparams) {
-  constexpr int BM = 32, BN = 64, BK = 64;
-  const int op = blockIdx.z;
-  const double* M = (op < nparams) ? Csb + (size_t)op * n * n : Aop;
-  __shared__ double sX[BM][BK + 1];
-  __shared__ double sM[BN][BK + 1];
-  __shared__ double sRed[BM];
-  const int x0 = blockIdx.y * BM, i0 = blockIdx.x * BN;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  if (tid < BM) sRed[tid] = 0.0;
-  f64x4 acc[2] = {f64x4{0, 0, 0, 0}, f64x4{0, 0, 0, 0}};
-  for (int k0 = 0; k0 < n; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      const int r = e / BK, c = e % BK;
-      sX[r][c] = (x0 + r < nx && k0 + c < n) ? Fs[(size_t)(x0 + r) * n + k0 + c] : 0.0;
-    }
-    for (int e = tid; e < BN * BK; e += 256) {
-      const int r = e / BK, c = e % BK;
-      sM[r][c] = (i0 + r < n && k0 + c < n) ? M[(size_t)(i0 + r) * n + k0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < BK; k += 4) {
-      const double bm = sM[w * 16 + li][k + lk];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[b * 16 + li][k + lk], bm, acc[b], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  // contract with mu and reduce over i within the block
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int xl = b * 16 + Mma<double>::row(lk, it);
-      const int x = x0 + xl;
-      const int i = i0 + w * 16 + li;
-      double v = (x < nx && i < n) ? Mu[(size_t)x * n + i] * acc[b][it] : 0.0;
-      // reduce over the 16 lanes sharing this x (same lk)
-      for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      if (li == 0 && x < nx) atomicAdd(&sRed[xl], v);
-    }
-  __syncthreads();
-  if (tid == 0) {
-    double total = 0.0;
-    for (int xl = 0; xl < BM; ++xl) {
-      const int x = x0 + xl;
-      if (x >= nx) break;
-      if (op < nparams) total += dt * n0x[x] * sRed[xl];
-      else atomicAdd(&gE[x], dt * sRed[xl]);
-    }
-    if (op < nparams) atomicAdd(&gscal[op], total);
-  }
+  for (int i = tid; i < npad; i += 1024) xo[i] = accumulate ? xo[i] + sb[i] : sb[i];
 }
 
 template <typename T>
 void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm) {
   T* LU = static_cast<T*>(d.lu);
-  dim3 gform(d.npad, d.nx_total);
-  k_form<T><<<gform, 256, 0, s>>>(LU, d.Cord, d.Aord, d.E, d.n0x, d.status, d.dt, d.n, d.npad);
-  const int np = d.npad / kNB;
+  T* xs = static_cast<T*>(d.xscr);
+  const int nmat = d.nx_total;
+  dim3 gform(d.npad, nmat);
+  k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E, d.n0x, d.dt, d.n, d.npad);
+  const int np = d.npad / NB;
   if (tm) tm->used = 0;
+  constexpr int IB = sizeof(T) == 8 ? 8 : 16;   // register sub-panel width (VGPR budget of 512 threads)
+  constexpr int KC = sizeof(T) == 8 ? 16 : 32;  // K chunk of the trailing update
   for (int p = 0; p < np; ++p) {
-    const int k0 = p * kNB;
+    const int k0 = p * NB;
     const bool rec = tm && p < tm->max_panels;
     if (rec) (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p], s);
-    constexpr int IB = sizeof(T) == 8 ? 8 : 16;  // register sub-panel width (VGPR budget of 512 threads)
-    if (d.npad <= kPanelThreads) k_panel<T, 1, IB><<<d.nx_total, kPanelThreads, 0, s>>>(LU, d.piv, d.perm, d.status, d.npad, k0);
-    else if (d.npad <= 2 * kPanelThreads) k_panel<T, 2, IB><<<d.nx_total, kPanelThreads, 0, s>>>(LU, d.piv, d.perm, d.status, d.npad, k0);
-    else k_panel<T, 4, IB><<<d.nx_total, kPanelThreads, 0, s>>>(LU, d.piv, d.perm, d.status, d.npad, k0);  // npad <= 2048
-    const int rest = d.npad - k0 - kNB;
+    const int rest = d.npad - k0 - NB;
+    if (d.npad <= kPanelThreads) k_panel<T, 1, IB><<<nmat, kPanelThreads, 0, s>>>(LU, d.piv, d.perm, d.status, d.npad, k0);
+    else if (d.npad <= 2 * kPanelThreads) k_panel<T, 2, IB><<<nmat, kPanelThreads, 0, s>>>(LU, d.piv, d.perm, d.status, d.npad, k0);
+    else k_panel<T, 4, IB><<<nmat, kPanelThreads, 0, s>>>(LU, d.piv, d.perm, d.status, d.npad, k0);
     if (rest > 0) {
-      dim3 gs(rest / 64, d.nx_total);
-      k_swap_trsm<T><<<gs, 64, 0, s>>>(LU, d.perm, d.npad, k0);
+      constexpr int CT = sizeof(T) == 8 ? 64 : 128;  // U12 columns per block (LDS budget)
+      const int nct = rest / CT;
+      k_u12<T, CT><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, d.perm, xs, d.npad, k0, nct, nmat);
       if (rec) {
         (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p + 1], s);
         (void)hipEventRecord(tm->ev[2 * p], s);
       }
-      const int mt = rest / 64;
-      dim3 gu(mt * mt, d.nx_total);
-      k_update<T><<<gu, 256, 0, s>>>(LU, d.npad, k0);
+      const int mt = rest / 128;
+      k_update<T, KC><<<xcd_grid(mt * mt, nmat), 256, 0, s>>>(LU, d.npad, k0, mt, nmat);
       if (rec) (void)hipEventRecord(tm->ev[2 * p + 1], s);
     } else if (rec) {
       (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p + 1], s);
@@ -810,48 +774,15 @@ void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* ti
 
 void launch_lu_solve(const DevOps& d, int precision, bool transpose, const double* Bin, double* Xout, bool accumulate,
                      bool check_done, hipStream_t s) {
-  const size_t sh = sizeof(double) * d.npad;
   if (precision == 0) {
     const double* LU = static_cast<const double*>(d.lu);
-    if (transpose) k_solve<double, 1><<<d.nx_total, 256, sh, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
-    else k_solve<double, 0><<<d.nx_total, 256, sh, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
+    if (transpose) k_solve<double, 1><<<d.nx_total, 1024, 0, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
+    else k_solve<double, 0><<<d.nx_total, 1024, 0, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
   } else {
     const float* LU = static_cast<const float*>(d.lu);
-    if (transpose) k_solve<float, 1><<<d.nx_total, 256, sh, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
-    else k_solve<float, 0><<<d.nx_total, 256, sh, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
+    if (transpose) k_solve<float, 1><<<d.nx_total, 1024, 0, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
+    else k_solve<float, 0><<<d.nx_total, 1024, 0, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
   }
-}
-
-void launch_pad_rows(const DevOps& d, const double* F, double* Bp, hipStream_t s) {
-  k_pad<<<1024, 256, 0, s>>>(F, Bp, d.n, d.npad, d.nx_total);
-}
-
-void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t s) {
-  k_unpad<<<1024, 256, 0, s>>>(Bp, F, d.n, d.npad, d.nx_total);
-}
-
-void launch_residual(const DevOps& d, bool transpose, hipStream_t s) {
-  dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32);
-  if (transpose)
-    k_residual<1><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.status, d.dt, d.n,
-                                    d.npad, d.nx_total);
-  else
-    k_residual<0><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.status, d.dt, d.n,
-                                    d.npad, d.nx_total);
-}
-
-void launch_refine_check(const DevOps& d, double rtol, int sweep, bool final_sweep, hipStream_t s) {
-  k_refine_check<<<1, 256, 0, s>>>(d.rmax, d.bmax, d.status, d.resid, rtol, sweep, final_sweep ? 1 : 0, d.nx_total);
-}
-
-void launch_reset_refine(const DevOps& d, hipStream_t s) {
-  k_reset_refine<<<1, 256, 0, s>>>(d.rmax, d.bmax, d.status, d.nx_total);
-}
-
-void launch_adjoint_grads(const DevOps& d, double* grad_scal, double* grad_E, hipStream_t s) {
-  dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32, d.n_params + 1);
-  k_adjoint_grads<<<g, 256, 0, s>>>(d.mu, d.Fs, d.Csb, d.Aord, d.n0x, grad_scal, grad_E, d.dt, d.n, d.nx_total,
-                                    d.n_params);
 }
 
 }  // namespace bte

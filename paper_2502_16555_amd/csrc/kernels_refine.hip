@@ -1,0 +1,245 @@
+// FP64 refinement of the mixed-precision V step and the adjoint gradient
+// contractions.  The residual r = b - (I - dt (n0 C + E A)) x is the operator
+// action of Alg. vspace_action of the paper evaluated in FP64 with MFMA f64;
+// the refinement x += LU^-1 r repeats until max|r| <= rtol max|b| (a device
+// flag stops the remaining sweeps without a host synchronization).
+#include <cmath>
+
+#include "internal.h"
+
+namespace bte {
+namespace {
+
+using f64x4 = double __attribute__((ext_vector_type(4)));
+
+// Result row of item t of lane group lk for MFMA f64 16x16x4 (measured layout).
+__device__ inline int f64_row(int lk, int t) { return lk + 4 * t; }
+
+__global__ void k_pad(const double* __restrict__ F, double* __restrict__ Bp, int n, int npad, int nx) {
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)nx * npad;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t x = idx / npad;
+    const int j = static_cast<int>(idx % npad);
+    Bp[idx] = (j < n) ? F[x * n + j] : 0.0;
+  }
+}
+
+__global__ void k_unpad(const double* __restrict__ Bp, double* __restrict__ F, int n, int npad, int nx) {
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)nx * n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t x = idx / n;
+    const int j = static_cast<int>(idx % n);
+    F[idx] = Bp[x * npad + j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residual R = B - X + dt n0_x (X C^T) + dt E_x (X A^T)  (TRANSPOSE: C, A)
+// rows = collocation points, 32 x 64 output tiles, MFMA f64 16x16x4.
+// ---------------------------------------------------------------------------
+__device__ inline void atomic_max_pos(unsigned long long* p, double v) {
+  atomicMax(p, static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+template <int TRANSPOSE>
+__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv, const double* __restrict__ Xv,
+                                                  double* __restrict__ Rv, const double* __restrict__ C,
+                                                  const double* __restrict__ Aop, const double* __restrict__ E,
+                                                  const double* __restrict__ n0x, unsigned long long* __restrict__ rmax,
+                                                  unsigned long long* __restrict__ bmax, const int* __restrict__ status,
+                                                  double dt, int n, int npad, int nx) {
+  if (status[1]) return;
+  constexpr int BM = 32, BN = 64, BK = 64;
+  __shared__ double sX[BM][BK + 1];
+  __shared__ double sC[BN][BK + 1];
+  __shared__ double sA[BN][BK + 1];
+  const int x0 = blockIdx.y * BM, i0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 accC[2], accA[2];
+  for (int b = 0; b < 2; ++b) accC[b] = accA[b] = f64x4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < n; k0 += BK) {
+    for (int e = tid; e < BM * BK; e += 256) {
+      const int r = e / BK, c = e % BK;
+      sX[r][c] = (x0 + r < nx && k0 + c < n) ? Xv[(size_t)(x0 + r) * npad + k0 + c] : 0.0;
+    }
+    for (int e = tid; e < BN * BK; e += 256) {
+      const int r = e / BK, c = e % BK;
+      const int i = i0 + r, k = k0 + c;
+      double cv = 0.0, av = 0.0;
+      if (i < n && k < n) {
+        const size_t o = TRANSPOSE ? (size_t)k * n + i : (size_t)i * n + k;
+        cv = C[o];
+        av = Aop[o];
+      }
+      sC[r][c] = cv;
+      sA[r][c] = av;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < BK; k += 4) {
+      const double bc = sC[w * 16 + li][k + lk];
+      const double ba = sA[w * 16 + li][k + lk];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const double ax = sX[b * 16 + li][k + lk];
+        accC[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bc, accC[b], 0, 0, 0);
+        accA[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, ba, accA[b], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int x = x0 + b * 16 + f64_row(lk, it);
+      const int i = i0 + w * 16 + li;
+      if (x < nx && i < n) {
+        const size_t o = (size_t)x * npad + i;
+        const double bv = Bv[o];
+        const double r = bv - Xv[o] + dt * n0x[x] * accC[b][it] + dt * E[x] * accA[b][it];
+        Rv[o] = r;
+        atomic_max_pos(&rmax[x], fabs(r));
+        atomic_max_pos(&bmax[x], fabs(bv));
+      }
+    }
+}
+
+// status[1] = done flag, status[2] = sweeps used; resid[0] = max_x |r|/|b|
+__global__ void k_refine_check(unsigned long long* __restrict__ rmax, unsigned long long* __restrict__ bmax,
+                               int* __restrict__ status, double* __restrict__ resid, double rtol, int sweep,
+                               int final_sweep, int nx) {
+  if (status[1]) return;
+  __shared__ double red[256];
+  double worst = 0.0;
+  for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+    const double r = __longlong_as_double(static_cast<long long>(rmax[x]));
+    const double b = __longlong_as_double(static_cast<long long>(bmax[x]));
+    const double q = (b > 0.0) ? r / b : (r > 0.0 ? INFINITY : 0.0);
+    worst = fmax(worst, (q == q) ? q : INFINITY);
+    rmax[x] = 0ull;
+    bmax[x] = 0ull;
+  }
+  red[threadIdx.x] = worst;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    resid[0] = red[0];
+    status[2] = sweep;
+    if (red[0] <= rtol) status[1] = 1;
+    else if (final_sweep) atomicOr(status, kStNoConv);
+  }
+}
+
+__global__ void k_reset_refine(unsigned long long* rmax, unsigned long long* bmax, int* status, int nx) {
+  for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+    rmax[x] = 0ull;
+    bmax[x] = 0ull;
+  }
+  if (threadIdx.x == 0) {
+    status[1] = 0;
+    status[2] = 0;
+  }
+}
+
+// grad_scal[op] += dt sum_x n0_x mu_x^T C^(op) F*_x  and  grad_E[x] = dt mu_x^T A F*_x.
+// Tiled like the residual: out[x][i] = sum_k F*[x][k] M[i][k] (MFMA f64), then the
+// epilogue contracts with mu[x][i].  Grid: (n/64, ceil(nx/32), n_params + 1).
+__global__ __launch_bounds__(256) void k_adjoint_grads(const double* __restrict__ Mu, const double* __restrict__ Fs,
+                                                       const double* __restrict__ Csb, const double* __restrict__ Aop,
+                                                       const double* __restrict__ n0x, double* __restrict__ gscal,
+                                                       double* __restrict__ gE, double dt, int n, int nx, int nparams) {
+  constexpr int BM = 32, BN = 64, BK = 64;
+  const int op = blockIdx.z;
+  const double* M = (op < nparams) ? Csb + (size_t)op * n * n : Aop;
+  __shared__ double sX[BM][BK + 1];
+  __shared__ double sM[BN][BK + 1];
+  __shared__ double sRed[BM];
+  const int x0 = blockIdx.y * BM, i0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  if (tid < BM) sRed[tid] = 0.0;
+  f64x4 acc[2] = {f64x4{0, 0, 0, 0}, f64x4{0, 0, 0, 0}};
+  for (int k0 = 0; k0 < n; k0 += BK) {
+    for (int e = tid; e < BM * BK; e += 256) {
+      const int r = e / BK, c = e % BK;
+      sX[r][c] = (x0 + r < nx && k0 + c < n) ? Fs[(size_t)(x0 + r) * n + k0 + c] : 0.0;
+    }
+    for (int e = tid; e < BN * BK; e += 256) {
+      const int r = e / BK, c = e % BK;
+      sM[r][c] = (i0 + r < n && k0 + c < n) ? M[(size_t)(i0 + r) * n + k0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < BK; k += 4) {
+      const double bm = sM[w * 16 + li][k + lk];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[b * 16 + li][k + lk], bm, acc[b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // contract with mu and reduce over i within the block
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int xl = b * 16 + f64_row(lk, it);
+      const int x = x0 + xl;
+      const int i = i0 + w * 16 + li;
+      double v = (x < nx && i < n) ? Mu[(size_t)x * n + i] * acc[b][it] : 0.0;
+      // reduce over the 16 lanes sharing this x (same lk)
+      for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (li == 0 && x < nx) atomicAdd(&sRed[xl], v);
+    }
+  __syncthreads();
+  if (tid == 0) {
+    double total = 0.0;
+    for (int xl = 0; xl < BM; ++xl) {
+      const int x = x0 + xl;
+      if (x >= nx) break;
+      if (op < nparams) total += dt * n0x[x] * sRed[xl];
+      else atomicAdd(&gE[x], dt * sRed[xl]);
+    }
+    if (op < nparams) atomicAdd(&gscal[op], total);
+  }
+}
+
+}  // namespace
+
+void launch_pad_rows(const DevOps& d, const double* F, double* Bp, hipStream_t s) {
+  k_pad<<<1024, 256, 0, s>>>(F, Bp, d.n, d.npad, d.nx_total);
+}
+
+void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t s) {
+  k_unpad<<<1024, 256, 0, s>>>(Bp, F, d.n, d.npad, d.nx_total);
+}
+
+void launch_residual(const DevOps& d, bool transpose, hipStream_t s) {
+  dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32);
+  if (transpose)
+    k_residual<1><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.status, d.dt, d.n,
+                                    d.npad, d.nx_total);
+  else
+    k_residual<0><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.status, d.dt, d.n,
+                                    d.npad, d.nx_total);
+}
+
+void launch_refine_check(const DevOps& d, double rtol, int sweep, bool final_sweep, hipStream_t s) {
+  k_refine_check<<<1, 256, 0, s>>>(d.rmax, d.bmax, d.status, d.resid, rtol, sweep, final_sweep ? 1 : 0, d.nx_total);
+}
+
+void launch_reset_refine(const DevOps& d, hipStream_t s) {
+  k_reset_refine<<<1, 256, 0, s>>>(d.rmax, d.bmax, d.status, d.nx_total);
+}
+
+void launch_adjoint_grads(const DevOps& d, double* grad_scal, double* grad_E, hipStream_t s) {
+  dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32, d.n_params + 1);
+  k_adjoint_grads<<<g, 256, 0, s>>>(d.mu, d.Fs, d.Csb, d.Aord, d.n0x, grad_scal, grad_E, d.dt, d.n, d.nx_total,
+                                    d.n_params);
+}
+
+}  // namespace bte

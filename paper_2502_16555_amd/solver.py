@@ -166,12 +166,12 @@ class Solver:
 
     def factor_export(self, E, x: int):
         """Factors (npad x npad, FP64) and pivots of point x after factoring with field E."""
-        npad = ((self.n + 63) // 64) * 64
+        npad = ((self.n + 127) // 128) * 128
         lu = np.zeros((npad, npad))
         piv = np.zeros(npad, dtype=np.int32)
         check(self.lib.bte_factor_export(self.h, _ptr(E), int(x), _dptr(lu), piv.ctypes.data_as(C.POINTER(C.c_int32))),
               "bte_factor_export")
-        return lu, piv
+        return lu.T.copy(), piv   # stored column-major
 
     def status(self):
         it = C.c_int32()

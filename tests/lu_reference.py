@@ -1,12 +1,12 @@
 """NumPy restatement of the library's blocked LU (test helper, not the oracle).
 
-Same blocking as the device code -- 64-column panels, 8/16-column sub-panels,
+Same blocking as the device code -- 128-column panels, 8/16-column sub-panels,
 partial pivoting with ties to the lowest row, interchanges applied as you go --
 so the device factors can be compared element by element and the pivot
 sequence bit for bit.  Its solves are checked against LAPACK in the tests."""
 import numpy as np
 
-NB = 64
+NB = 128
 
 
 def _perm(start, cnt, pivs):

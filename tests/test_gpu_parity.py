@@ -59,12 +59,15 @@ def solver(cfg, **kw):
 CASES = {
     # name: (config factory, tolerance scale)
     "C0": lambda: workloads.config("C0"),
-    # ragged: n = 60 is padded to 64, nx odd, three processes, two energy bins
+    # ragged: n = 60 is padded to 128, nx odd, three processes, two energy bins
     "ragged": lambda: workloads.small_config(nx=9, nr=10, nth=6, kinds=("elastic", "excitation", "ionization"),
                                              E=5e3, field_kind="rf", n_bins=2),
-    # several panels with a ragged tail: n = 12 * 16 = 192 -> 3 panels of 64
+    # two panels with a ragged tail: n = 12 * 16 = 192 -> padded to 256
     "panels": lambda: workloads.small_config(nx=7, nr=12, nth=16, kinds=("elastic", "ionization"), E=8e3,
                                              field_kind="rf"),
+    # four panels: n = 20 * 20 = 400 -> padded to 512
+    "panels4": lambda: workloads.small_config(nx=5, nr=20, nth=20, kinds=("elastic", "excitation", "ionization"),
+                                              E=1.2e4, field_kind="rf"),
 }
 
 
@@ -285,10 +288,10 @@ def test_device_factors_match_blocked_restatement(torch, prec):
     """Device LU factors and pivots against the NumPy restatement of the same blocked
     algorithm: identical pivots, factors equal to rounding (FP32: 1e-4 relative)."""
     import lu_reference as LR
-    cfg = workloads.config("C0")
+    cfg = CASES["panels4"]()
     ops = oracle.build_operators(cfg)
     s = solver(cfg, precision=prec)
-    E = np.array([0.0, 1.2e4, -1.4e4, 3e3] * 4)[:ops.nx]
+    E = np.array([0.0, 1.2e4, -1.4e4, 3e3, -6e3])[:ops.nx]
     Eg = cuda(torch, E)
     IB = 8 if prec == "fp64" else 16
     for x in (0, 1, 2):
