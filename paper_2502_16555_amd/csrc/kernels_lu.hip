@@ -81,26 +81,47 @@ struct Vec4<double> {
 
 
 // ---------------------------------------------------------------------------
-// Matrix formation, column c of point x: I - dt (n0_x C + E_x A), identity padding.
-// CT/AT hold C^T and A^T row-major, i.e. the columns of C and A contiguously.
+// Matrix formation, column c of points x0..x0+xpb-1: I - dt (n0_x C + E_x A) with
+// identity padding.  CT/AT hold C^T and A^T row-major, i.e. the columns of C
+// and A contiguously; a block reads its column of each once and writes it into
+// xpb matrices with 16-byte stores, so the launch is bound by the writes.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* __restrict__ CT,
                                               const double* __restrict__ AT, const double* __restrict__ E,
-                                              const double* __restrict__ n0x, double dt, int n, int npad) {
-  const int x = blockIdx.y, c = blockIdx.x;
-  const double e = E[x], nn = n0x[x];
-  T* col = LU + ((size_t)x * npad + c) * npad;
-  if (c < n) {
-    const double* cc = CT + (size_t)c * n;
-    const double* ac = AT + (size_t)c * n;
-    for (int r = threadIdx.x; r < npad; r += blockDim.x) {
-      double v = (r < n) ? -dt * (nn * cc[r] + e * ac[r]) : 0.0;
-      if (r == c) v += 1.0;
-      col[r] = static_cast<T>(v);
+                                              const double* __restrict__ n0x, double dt, int n, int npad, int nmat,
+                                              int xpb) {
+  constexpr int CH = kMaxRows / 1024;  // 4-row groups per thread
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int x0 = blockIdx.y * xpb, x1 = min(nmat, x0 + xpb);
+  double cv[CH][4], av[CH][4];
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = 4 * tid + 1024 * ch + u;
+      const bool in = c < n && r < n;
+      cv[ch][u] = in ? CT[(size_t)c * n + r] : 0.0;
+      av[ch][u] = in ? AT[(size_t)c * n + r] : 0.0;
     }
-  } else {
-    for (int r = threadIdx.x; r < npad; r += blockDim.x) col[r] = static_cast<T>(r == c ? 1.0 : 0.0);
+  for (int x = x0; x < x1; ++x) {
+    const double e = E[x], nn = n0x[x];
+    T* col = LU + ((size_t)x * npad + c) * npad;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+      const int r0 = 4 * tid + 1024 * ch;
+      if (r0 < npad) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = static_cast<T>(-dt * (nn * cv[ch][u] + e * av[ch][u]) + (r0 + u == c ? 1.0 : 0.0));
+        if constexpr (sizeof(T) == 4) {
+          *reinterpret_cast<float4*>(col + r0) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+          *reinterpret_cast<double2*>(col + r0) = make_double2(v[0], v[1]);
+          *reinterpret_cast<double2*>(col + r0 + 2) = make_double2(v[2], v[3]);
+        }
+      }
+    }
   }
 }
 
@@ -731,8 +752,9 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm) {
   T* LU = static_cast<T*>(d.lu);
   T* xs = static_cast<T*>(d.xscr);
   const int nmat = d.nx_total;
-  dim3 gform(d.npad, nmat);
-  k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E, d.n0x, d.dt, d.n, d.npad);
+  constexpr int kFormXpb = 16;  // matrices per formation block
+  dim3 gform(d.npad, (nmat + kFormXpb - 1) / kFormXpb);
+  k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E, d.n0x, d.dt, d.n, d.npad, nmat, kFormXpb);
   const int np = d.npad / NB;
   if (tm) tm->used = 0;
   constexpr int IB = sizeof(T) == 8 ? 8 : 16;   // register sub-panel width (VGPR budget of 512 threads)

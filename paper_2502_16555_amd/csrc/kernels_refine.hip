@@ -37,10 +37,6 @@ __global__ void k_unpad(const double* __restrict__ Bp, double* __restrict__ F, i
 // FP64 residual R = B - X + dt n0_x (X C^T) + dt E_x (X A^T)  (TRANSPOSE: C, A)
 // rows = collocation points, 32 x 64 output tiles, MFMA f64 16x16x4.
 // ---------------------------------------------------------------------------
-__device__ inline void atomic_max_pos(unsigned long long* p, double v) {
-  atomicMax(p, static_cast<unsigned long long>(__double_as_longlong(v)));
-}
-
 template <int TRANSPOSE>
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv, const double* __restrict__ Xv,
                                                   double* __restrict__ Rv, const double* __restrict__ C,
@@ -50,21 +46,36 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
                                                   double dt, int n, int npad, int nx) {
   if (status[1]) return;
   constexpr int BM = 32, BN = 64, BK = 64;
+  constexpr int LX = BM * BK / 256, LO = BN * BK / 256;  // loads per thread and tile
   __shared__ double sX[BM][BK + 1];
   __shared__ double sC[BN][BK + 1];
   __shared__ double sA[BN][BK + 1];
+  __shared__ unsigned long long s_rm[4][BM], s_bm[4][BM];
   const int x0 = blockIdx.y * BM, i0 = blockIdx.x * BN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  f64x4 accC[2], accA[2];
-  for (int b = 0; b < 2; ++b) accC[b] = accA[b] = f64x4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < n; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      const int r = e / BK, c = e % BK;
-      sX[r][c] = (x0 + r < nx && k0 + c < n) ? Xv[(size_t)(x0 + r) * npad + k0 + c] : 0.0;
+  // operator element e of a tile: row r (output index i), column c (k); the
+  // transposed form walks i fastest so that its loads stay coalesced
+  auto op_rc = [&](int e, int* r, int* c) {
+    if (TRANSPOSE) {
+      *r = e % BN;
+      *c = e / BN;
+    } else {
+      *r = e / BK;
+      *c = e % BK;
     }
-    for (int e = tid; e < BN * BK; e += 256) {
-      const int r = e / BK, c = e % BK;
+  };
+  double px[LX], pc[LO], pa[LO];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < LX; ++u) {
+      const int e = tid + 256 * u, r = e / BK, c = e % BK;
+      px[u] = (x0 + r < nx && k0 + c < n) ? Xv[(size_t)(x0 + r) * npad + k0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < LO; ++u) {
+      int r, c;
+      op_rc(tid + 256 * u, &r, &c);
       const int i = i0 + r, k = k0 + c;
       double cv = 0.0, av = 0.0;
       if (i < n && k < n) {
@@ -72,10 +83,28 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
         cv = C[o];
         av = Aop[o];
       }
-      sC[r][c] = cv;
-      sA[r][c] = av;
+      pc[u] = cv;
+      pa[u] = av;
+    }
+  };
+  f64x4 accC[2], accA[2];
+  for (int b = 0; b < 2; ++b) accC[b] = accA[b] = f64x4{0, 0, 0, 0};
+  fetch(0);
+  for (int k0 = 0; k0 < n; k0 += BK) {
+#pragma unroll
+    for (int u = 0; u < LX; ++u) {
+      const int e = tid + 256 * u;
+      sX[e / BK][e % BK] = px[u];
+    }
+#pragma unroll
+    for (int u = 0; u < LO; ++u) {
+      int r, c;
+      op_rc(tid + 256 * u, &r, &c);
+      sC[r][c] = pc[u];
+      sA[r][c] = pa[u];
     }
     __syncthreads();
+    if (k0 + BK < n) fetch(k0 + BK);  // next tile in flight during the products
 #pragma unroll 4
     for (int k = 0; k < BK; k += 4) {
       const double bc = sC[w * 16 + li][k + lk];
@@ -89,21 +118,47 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
     }
     __syncthreads();
   }
+  // epilogue: residual, then max |r| and max |b| per point, reduced over the
+  // block before one atomic per point (bit patterns of non-negative doubles
+  // order like the values, and a NaN orders above +inf)
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
-      const int x = x0 + b * 16 + f64_row(lk, it);
+      const int xl = b * 16 + f64_row(lk, it);
+      const int x = x0 + xl;
       const int i = i0 + w * 16 + li;
+      unsigned long long rb = 0ull, bb = 0ull;
       if (x < nx && i < n) {
         const size_t o = (size_t)x * npad + i;
         const double bv = Bv[o];
         const double r = bv - Xv[o] + dt * n0x[x] * accC[b][it] + dt * E[x] * accA[b][it];
         Rv[o] = r;
-        atomic_max_pos(&rmax[x], fabs(r));
-        atomic_max_pos(&bmax[x], fabs(bv));
+        rb = static_cast<unsigned long long>(__double_as_longlong(fabs(r)));
+        bb = static_cast<unsigned long long>(__double_as_longlong(fabs(bv)));
+      }
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        const unsigned long long orb = __shfl_xor(rb, off), obb = __shfl_xor(bb, off);
+        rb = orb > rb ? orb : rb;
+        bb = obb > bb ? obb : bb;
+      }
+      if (li == 0) {
+        s_rm[w][xl] = rb;
+        s_bm[w][xl] = bb;
       }
     }
+  __syncthreads();
+  if (tid < BM && x0 + tid < nx) {
+    unsigned long long rb = 0ull, bb = 0ull;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      rb = s_rm[u][tid] > rb ? s_rm[u][tid] : rb;
+      bb = s_bm[u][tid] > bb ? s_bm[u][tid] : bb;
+    }
+    atomicMax(&rmax[x0 + tid], rb);
+    atomicMax(&bmax[x0 + tid], bb);
+  }
 }
 
 // status[1] = done flag, status[2] = sweeps used; resid[0] = max_x |r|/|b|
