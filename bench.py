@@ -36,11 +36,13 @@ def _update_flops(npad: int, nb: int, nmat: int) -> float:
     return tot * nmat
 
 
-def run_gpu(cfg, precision, steps, warmup, torch):
-    from paper_2502_16555_amd import Solver
+def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None):
+    from paper_2502_16555_amd import Solver, _lib
     t0 = time.time()
     s = Solver(cfg, precision=precision)
     setup_s = time.time() - t0
+    if lu_streams is not None:
+        s.set_tuning(_lib.TUNE_LU_STREAMS, lu_streams)
     import workloads
     ne = workloads.density_profile(s.xhat(), cfg["ic"]["ne_peak"])
     F = s.initial_state(torch.as_tensor(ne, device="cuda:0"), cfg["ic"]["Te_eV"])
@@ -80,7 +82,8 @@ def run_gpu(cfg, precision, steps, warmup, torch):
     s.set_timing(False)
     out = {"ms_per_step": ms, "wall_s": wall, "setup_s": setup_s, "refine_sweeps": sweeps, "refine_resid": resid,
            "moments": mom, "t_final": n * dt,
-           "ms_update": tm[0] / nt, "ms_panel": tm[1] / nt, "ms_vrest": tm[2] / nt, "ms_x": tm[4] / nt,
+           "ms_update": tm[0] / nt, "ms_panel": tm[1] / nt, "ms_vwall": tm[2] / nt, "ms_x": tm[4] / nt,
+           "update_launches": tm[3] / nt, "lu_streams": s.get_tuning(_lib.TUNE_LU_STREAMS),
            "info": s.info}
     s.close()
     return out
@@ -121,6 +124,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--nx", type=int, default=256)
+    ap.add_argument("--lu-streams", type=int, default=None, help="concurrent factorization groups (library default 2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hot path is single-GPU in this build",
@@ -134,17 +138,18 @@ def main():
     cfg = workloads.config("C2")
     if args.nx != 256:
         cfg = dict(cfg, nx=args.nx, nx_per=[args.nx])
-    main_run = run_gpu(cfg, args.precision, args.steps, args.warmup, torch)
+    main_run = run_gpu(cfg, args.precision, args.steps, args.warmup, torch, args.lu_streams)
     fp64 = None
     if not args.no_fp64 and args.precision != "fp64":
-        fp64 = run_gpu(cfg, "fp64", max(args.steps // 2, 5), args.warmup, torch)
+        fp64 = run_gpu(cfg, "fp64", max(args.steps // 2, 5), args.warmup, torch, args.lu_streams)
     info = main_run["info"]
     nx_total, n = info.nx_total, info.n
     npad = ((n + 127) // 128) * 128
     dtype = {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64"}[args.precision]
     mfma = {"fp64": "fp64", "mixed_fp32": "fp32", "mixed_bf16": "bf16"}[args.precision]
+    # update flops of one step over the summed durations of its update launches
     upd_flops = _update_flops(npad, 128, nx_total)
-    n_upd_launches = len([k for k in range(0, npad, 128) if npad - k - 128 > 0])
+    n_upd_launches = main_run["update_launches"]
     achieved = upd_flops / (main_run["ms_update"] * 1e-3) / 1e12
     peak = MI355X_PEAK_TFLOPS[mfma]
     value = 1000.0 / main_run["ms_per_step"]
@@ -160,8 +165,9 @@ def main():
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "launches_per_step": n_upd_launches,
                      "avg_launch_ms": main_run["ms_update"] / n_upd_launches},
-        "breakdown_ms": {"lu_update": main_run["ms_update"], "lu_panel_trsm": main_run["ms_panel"],
-                         "v_rest": main_run["ms_vrest"], "x_and_field": main_run["ms_x"]},
+        "breakdown_ms": {"lu_update_launches": main_run["ms_update"], "lu_panel_u12_launches": main_run["ms_panel"],
+                         "v_step_wall": main_run["ms_vwall"], "x_and_field_wall": main_run["ms_x"],
+                         "lu_streams": main_run["lu_streams"]},
         "lu_tflops_step": info.lu_flops_per_step / (main_run["ms_per_step"] * 1e-3) / 1e12,
         "refine": {"sweeps": main_run["refine_sweeps"], "resid": main_run["refine_resid"]},
     }

@@ -211,14 +211,29 @@ bte_status bte_get_info(bte_handle* h, bte_info* out);
  * final max|r|/max|b|.  Any pointer may be NULL. */
 bte_status bte_get_status(bte_handle* h, int32_t* refine_iters, double* final_resid);
 
-/* Kernel-level timing on the stream of bte_step (HIP events; each timed step
- * synchronizes that stream).  enable (1) / disable (0, default); enabling
- * clears the sums.  bte_get_timing fills ms_out[0..5] with the summed
- * milliseconds of {LU trailing updates, LU panels + interchanges/TRSM, rest of
- * the V step (formation, solves, refinement), unused, X half-steps + field}
- * and the number of timed steps. */
+/* Kernel-level timing of bte_step (HIP events on the streams the kernels run
+ * on; each timed step synchronizes the caller's stream).  enable (1) /
+ * disable (0, default); enabling clears the sums.  bte_get_timing fills
+ * ms_out[0..5] with sums over the timed steps of: [0] the durations of the LU
+ * trailing-update launches, [1] the durations of the LU panel + U12 launches
+ * (both summed over the concurrent factorization streams, so they can exceed
+ * the wall time), [2] the wall time of the V step, [3] the number of
+ * trailing-update launches timed, [4] the wall time of the X half-steps and
+ * the field, [5] the number of timed steps. */
 bte_status bte_set_timing(bte_handle* h, int32_t enable);
 bte_status bte_get_timing(bte_handle* h, double* ms_out);
+
+/* Launch-shape tuning; results do not depend on it (every matrix is factored
+ * by the same kernels in the same order whatever the grouping).
+ *   BTE_TUNE_LU_STREAMS: the points are split into this many groups of
+ *   consecutive points, factored concurrently on the handle's own side
+ *   streams (default priority) and joined back into the caller's stream with
+ *   events, so that the latency-bound panel kernels of one group overlap the
+ *   MFMA updates of another.  1..4, default 2.
+ * Returns BTE_EINVAL for an unknown key or a value out of range. */
+typedef enum { BTE_TUNE_LU_STREAMS = 0 } bte_tune_key;
+bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value);
+bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value);
 
 void bte_destroy(bte_handle* h);
 const char* bte_status_string(bte_status s);

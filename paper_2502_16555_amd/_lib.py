@@ -41,6 +41,8 @@ class bte_info(C.Structure):
                 ("q_bytes_per_half_step", C.c_double)]
 
 
+TUNE_LU_STREAMS = 0
+
 EXPORTS = {
     "bte_setup_operators": (C.c_int, [C.POINTER(bte_config), C.c_int, C.POINTER(C.c_void_p)]),
     "bte_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, bte_field, C.c_void_p]),
@@ -61,6 +63,8 @@ EXPORTS = {
     "bte_get_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "bte_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "bte_get_timing": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "bte_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "bte_get_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "bte_destroy": (None, [C.c_void_p]),
     "bte_status_string": (C.c_char_p, [C.c_int]),
 }

@@ -45,8 +45,16 @@ struct bte_handle {
   double bytes = 0.0;
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  std::vector<hipEvent_t> lu_ev;   // 4 * max_panels
-  bte::LuTimer lu_timer;
+  // the factorization runs as lu_streams groups of points on side streams
+  // (fork/join by events) so that one group's latency-bound panels overlap
+  // another group's MFMA updates
+  static constexpr int kMaxLuStreams = 4;
+  int lu_streams = 2;
+  hipStream_t gs[kMaxLuStreams] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kMaxLuStreams] = {};
+  std::vector<hipEvent_t> lu_ev;   // kMaxLuStreams * 4 * max_panels
+  bte::LuTimer lu_timer[kMaxLuStreams];
   double ms_acc[6] = {0, 0, 0, 0, 0, 0};
   double* d_coeff = nullptr;   // [nr] Maxwellian coefficients
   double* d_gE = nullptr;      // [nx_total] adjoint field-gradient scratch
@@ -73,6 +81,11 @@ struct bte_handle {
       if (e) (void)hipEventDestroy(e);
     for (auto& e : lu_ev)
       if (e) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    for (auto& e : join_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& q : gs)
+      if (q) (void)hipStreamDestroy(q);
     for (void* p : allocs) (void)hipFree(p);
   }
 };
@@ -259,12 +272,33 @@ void x_half(bte_handle* h, double* F, bool transpose, hipStream_t s) {
   }
 }
 
+// Form and factor every point's matrix (field already in d.E), in lu_streams
+// groups of consecutive points on the side streams, joined back into s.
+void factor_all(bte_handle* h, hipStream_t s) {
+  DevOps& d = h->d;
+  const int prec = h->cfg.precision;
+  const int G = std::max(1, std::min(h->lu_streams, d.nx_total));
+  if (G == 1) {
+    bte::launch_lu_factor(d, prec, s, h->timing ? &h->lu_timer[0] : nullptr);
+    return;
+  }
+  HIP_OK(hipEventRecord(h->fork_ev, s));
+  for (int g = 0; g < G; ++g) {
+    const int m0 = static_cast<int>((static_cast<long long>(g) * d.nx_total) / G);
+    const int m1 = static_cast<int>((static_cast<long long>(g + 1) * d.nx_total) / G);
+    HIP_OK(hipStreamWaitEvent(h->gs[g], h->fork_ev, 0));
+    bte::launch_lu_factor(d, prec, h->gs[g], h->timing ? &h->lu_timer[g] : nullptr, m0, m1 - m0);
+    HIP_OK(hipEventRecord(h->join_ev[g], h->gs[g]));
+    HIP_OK(hipStreamWaitEvent(s, h->join_ev[g], 0));
+  }
+}
+
 // V(dt) in place on F (field already in d.E).  transpose: solve with A^T.
 void v_solve(bte_handle* h, double* F, bool transpose, hipStream_t s) {
   DevOps& d = h->d;
   const int prec = h->cfg.precision;
   bte::launch_pad_rows(d, F, d.B, s);
-  bte::launch_lu_factor(d, prec, s, h->timing ? &h->lu_timer : nullptr);
+  factor_all(h, s);
   bte::launch_lu_solve(d, prec, transpose, d.B, d.X, false, false, s);
   if (prec != BTE_FP64) {
     bte::launch_reset_refine(d, s);
@@ -343,10 +377,16 @@ bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle
     bte::assemble(in, &h->host);
     fill_devops(h);
     for (auto& e : h->ev) HIP_OK(hipEventCreate(&e));
-    h->lu_timer.max_panels = h->d.npad / bte::kNB;
-    h->lu_ev.assign(4 * h->lu_timer.max_panels, nullptr);
+    const int P = h->d.npad / bte::kNB;
+    h->lu_ev.assign(static_cast<size_t>(bte_handle::kMaxLuStreams) * 4 * P, nullptr);
     for (auto& e : h->lu_ev) HIP_OK(hipEventCreate(&e));
-    h->lu_timer.ev = h->lu_ev.data();
+    for (int g = 0; g < bte_handle::kMaxLuStreams; ++g) {
+      h->lu_timer[g].max_panels = P;
+      h->lu_timer[g].ev = h->lu_ev.data() + static_cast<size_t>(g) * 4 * P;
+      HIP_OK(hipStreamCreateWithFlags(&h->gs[g], hipStreamNonBlocking));
+      HIP_OK(hipEventCreateWithFlags(&h->join_ev[g], hipEventDisableTiming));
+    }
+    HIP_OK(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
     // pointers inside cfg are not retained
     h->cfg.proc = nullptr;
     h->cfg.bin_edges_eV = nullptr;
@@ -406,17 +446,23 @@ bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void*
       HIP_OK(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
       HIP_OK(hipEventElapsedTime(&c, h->ev[2], h->ev[3]));
       float upd = 0.f, pan = 0.f;
-      const int P = h->lu_timer.max_panels;
-      for (int p = 0; p < h->lu_timer.used; ++p) {
-        float t1 = 0.f, t2 = 0.f;
-        HIP_OK(hipEventElapsedTime(&t1, h->lu_ev[2 * p], h->lu_ev[2 * p + 1]));
-        HIP_OK(hipEventElapsedTime(&t2, h->lu_ev[2 * P + 2 * p], h->lu_ev[2 * P + 2 * p + 1]));
-        upd += t1;
-        pan += t2;
+      int n_upd = 0;
+      for (const auto& tm : h->lu_timer) {
+        const int P = tm.max_panels;
+        for (int p = 0; p < tm.used; ++p) {
+          float t1 = 0.f, t2 = 0.f;
+          HIP_OK(hipEventElapsedTime(&t1, tm.ev[2 * p], tm.ev[2 * p + 1]));
+          HIP_OK(hipEventElapsedTime(&t2, tm.ev[2 * P + 2 * p], tm.ev[2 * P + 2 * p + 1]));
+          upd += t1;
+          pan += t2;
+          if (p + 1 < P) ++n_upd;
+        }
       }
-      h->ms_acc[0] += upd;        // LU trailing updates
-      h->ms_acc[1] += pan;        // LU panels + interchanges/TRSM
-      h->ms_acc[2] += b - upd - pan;  // formation, solves, refinement
+      for (auto& tm : h->lu_timer) tm.used = 0;
+      h->ms_acc[0] += upd;        // LU trailing-update launches (summed over streams)
+      h->ms_acc[1] += pan;        // LU panel + U12 launches (summed over streams)
+      h->ms_acc[2] += b;          // V step, wall
+      h->ms_acc[3] += n_upd;      // trailing-update launches timed
       h->ms_acc[4] += a + c;      // X half-steps (+ field)
       h->ms_acc[5] += 1.0;
     }
@@ -591,6 +637,25 @@ bte_status bte_set_timing(bte_handle* h, int32_t enable) {
   h->timing = enable != 0;
   std::fill(std::begin(h->ms_acc), std::end(h->ms_acc), 0.0);
   return BTE_OK;
+}
+
+bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value) {
+  if (!h) return BTE_EINVAL;
+  if (key == BTE_TUNE_LU_STREAMS) {
+    if (value < 1 || value > bte_handle::kMaxLuStreams) return BTE_EINVAL;
+    h->lu_streams = value;
+    return BTE_OK;
+  }
+  return BTE_EINVAL;
+}
+
+bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value) {
+  if (!h || !value) return BTE_EINVAL;
+  if (key == BTE_TUNE_LU_STREAMS) {
+    *value = h->lu_streams;
+    return BTE_OK;
+  }
+  return BTE_EINVAL;
 }
 
 bte_status bte_get_timing(bte_handle* h, double* ms_out) {

@@ -91,8 +91,10 @@ struct LuTimer {
 };
 
 // ---- V step (kernels_lu.hip) ------------------------------------------------
-// Forms I - dt (n0 C + E A) (padded to npad with identity) and factors it in place.
-void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer = nullptr);
+// Forms I - dt (n0 C + E A) (padded to npad with identity) and factors it in
+// place, for the points m0 .. m0+count-1 (count < 0: to the last point).
+void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer = nullptr, int m0 = 0,
+                      int count = -1);
 // X = LU^-1 B (or LU^-T B with transpose), rows of length npad, FP64 right-hand sides.
 void launch_lu_solve(const DevOps& d, int precision, bool transpose, const double* Bin, double* Xout,
                      bool accumulate, bool check_done, hipStream_t s);

@@ -20,6 +20,7 @@
 //   k_update  A22 -= L21 U12: 128 x 128 MFMA tiles, K = 128 in double-buffered
 //             LDS chunks; blocks of one matrix are kept on one XCD so that L21
 //             and U12 stay in that XCD's L2.
+#include <cfloat>
 #include <climits>
 #include <cmath>
 
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
   __shared__ int s_lab[kMaxSwapRows];
   __shared__ int s_pos[kMaxRows];
   __shared__ int s_nR, s_any;
-  bool singular = false;
+  bool singular = false, nonfinite = false;
 
   for (int sp = 0; sp < NB / IB; ++sp) {
     const int c0 = k0 + sp * IB;
@@ -205,6 +206,9 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
           }
         }
       }
+      // a column of NaNs has no candidate: keep row c (every index stays in
+      // range whatever the data) and report the non-finite value
+      if (p == INT_MAX) p = c;
       // row c is owned by thread j (q = 0); publish rows c and p
       if (tid == j) {
 #pragma unroll
@@ -237,6 +241,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
         s_sw[j] = p;
       }
       if (pv == T(0)) singular = true;
+      if (!(fabs(static_cast<double>(pv)) <= DBL_MAX)) nonfinite = true;
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         const int r = c0 + tid + q * NT;
@@ -370,6 +375,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
     }
   }
   if (singular && tid == 0) atomicOr(status, kStSingular);
+  if (nonfinite && tid == 0) atomicOr(status, kStNonFinite);
   // permutation of the whole panel for the trailing columns
   for (int r = k0 + NB + tid; r < npad; r += NT) s_pos[r] = -1;
   __syncthreads();
@@ -748,13 +754,15 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
 }
 
 template <typename T>
-void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm) {
-  T* LU = static_cast<T*>(d.lu);
-  T* xs = static_cast<T*>(d.xscr);
-  const int nmat = d.nx_total;
+void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat) {
+  const size_t np2 = (size_t)d.npad * d.npad;
+  T* LU = static_cast<T*>(d.lu) + (size_t)m0 * np2;
+  T* xs = static_cast<T*>(d.xscr) + (size_t)m0 * d.npad * NB;
+  int* piv = d.piv + (size_t)m0 * d.npad;
+  int* perm = d.perm + (size_t)m0 * kPermStride;
   constexpr int kFormXpb = 16;  // matrices per formation block
   dim3 gform(d.npad, (nmat + kFormXpb - 1) / kFormXpb);
-  k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E, d.n0x, d.dt, d.n, d.npad, nmat, kFormXpb);
+  k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, kFormXpb);
   const int np = d.npad / NB;
   if (tm) tm->used = 0;
   constexpr int IB = sizeof(T) == 8 ? 8 : 16;   // register sub-panel width (VGPR budget of 512 threads)
@@ -764,13 +772,13 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm) {
     const bool rec = tm && p < tm->max_panels;
     if (rec) (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p], s);
     const int rest = d.npad - k0 - NB;
-    if (d.npad <= kPanelThreads) k_panel<T, 1, IB><<<nmat, kPanelThreads, 0, s>>>(LU, d.piv, d.perm, d.status, d.npad, k0);
-    else if (d.npad <= 2 * kPanelThreads) k_panel<T, 2, IB><<<nmat, kPanelThreads, 0, s>>>(LU, d.piv, d.perm, d.status, d.npad, k0);
-    else k_panel<T, 4, IB><<<nmat, kPanelThreads, 0, s>>>(LU, d.piv, d.perm, d.status, d.npad, k0);
+    if (d.npad <= kPanelThreads) k_panel<T, 1, IB><<<nmat, kPanelThreads, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
+    else if (d.npad <= 2 * kPanelThreads) k_panel<T, 2, IB><<<nmat, kPanelThreads, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
+    else k_panel<T, 4, IB><<<nmat, kPanelThreads, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
     if (rest > 0) {
       constexpr int CT = sizeof(T) == 8 ? 64 : 128;  // U12 columns per block (LDS budget)
       const int nct = rest / CT;
-      k_u12<T, CT><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, d.perm, xs, d.npad, k0, nct, nmat);
+      k_u12<T, CT><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, xs, d.npad, k0, nct, nmat);
       if (rec) {
         (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p + 1], s);
         (void)hipEventRecord(tm->ev[2 * p], s);
@@ -789,9 +797,11 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm) {
 
 }  // namespace
 
-void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer) {
-  if (precision == 0) factor_impl<double>(d, s, timer);
-  else factor_impl<float>(d, s, timer);
+void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer, int m0, int count) {
+  if (count < 0) count = d.nx_total - m0;
+  if (count <= 0) return;
+  if (precision == 0) factor_impl<double>(d, s, timer, m0, count);
+  else factor_impl<float>(d, s, timer, m0, count);
 }
 
 void launch_lu_solve(const DevOps& d, int precision, bool transpose, const double* Bin, double* Xout, bool accumulate,

@@ -187,6 +187,14 @@ class Solver:
         check(self.lib.bte_get_timing(self.h, out), "bte_get_timing")
         return list(out)
 
+    def set_tuning(self, key: int, value: int):
+        check(self.lib.bte_set_tuning(self.h, int(key), int(value)), "bte_set_tuning")
+
+    def get_tuning(self, key: int) -> int:
+        v = C.c_int32()
+        check(self.lib.bte_get_tuning(self.h, int(key), C.byref(v)), "bte_get_tuning")
+        return v.value
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.bte_destroy(self.h)

@@ -43,6 +43,9 @@ def test_status_strings_and_argument_errors():
     # calls on a null handle are argument errors, not crashes
     assert lib.bte_step(None, None, 0.0, L.bte_field(None, None), None) == L.BTE_EINVAL
     assert lib.bte_moments(None, None, None, None) == L.BTE_EINVAL
+    assert lib.bte_set_tuning(None, L.TUNE_LU_STREAMS, 2) == L.BTE_EINVAL
+    v = ctypes.c_int32()
+    assert lib.bte_get_tuning(None, L.TUNE_LU_STREAMS, ctypes.byref(v)) == L.BTE_EINVAL
 
 
 def test_bad_configs_are_rejected():

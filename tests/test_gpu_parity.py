@@ -259,6 +259,26 @@ def test_nonfinite_state_is_reported(torch):
     s.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_nonfinite_field_is_reported(torch, prec):
+    """A NaN field makes whole pivot columns NaN: the factorization keeps every
+    row index in range (no interchange) and reports the non-finite value."""
+    from paper_2502_16555_amd import _lib
+    cfg = CASES["panels"]()
+    s = solver(cfg, precision=prec, field_mode="given")
+    ops = oracle.build_operators(cfg)
+    F = cuda(torch, _state(ops, 5))
+    E = torch.full((s.nx_total,), 1e3, dtype=torch.float64, device="cuda:0")
+    E[2] = float("nan")
+    s.vstep(F, E)
+    assert s.status()[0] == _lib.BTE_ENONFINITE
+    E[2] = 1e3
+    F = cuda(torch, _state(ops, 5))
+    s.vstep(F, E)                      # the handle stays usable
+    assert s.status()[0] == 0
+    s.close()
+
+
 def test_c1_golden_cycle(torch):
     """Realistic RF case, one full cycle (1000 steps), FP64 on the GPU against the
     stored oracle moments (written by tests/golden/make_golden.py)."""
@@ -308,3 +328,25 @@ def test_device_factors_match_blocked_restatement(torch, prec):
         if prec == "fp64":
             assert np.array_equal(piv, ip), x
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_factorization_grouping_does_not_change_results(torch, prec):
+    """Factoring the points in 1..4 concurrent groups gives bit-identical steps."""
+    from paper_2502_16555_amd import _lib
+    cfg = CASES["panels"]()
+    ops = oracle.build_operators(cfg)
+    F0 = _state(ops, 11)
+    outs = []
+    for g in (1, 2, 3, 4):
+        s = solver(cfg, precision=prec)
+        s.set_tuning(_lib.TUNE_LU_STREAMS, g)
+        assert s.get_tuning(_lib.TUNE_LU_STREAMS) == g
+        F = cuda(torch, F0)
+        for n in range(3):
+            s.step(F, n * cfg["dt_s"])
+        assert s.status()[0] == 0
+        outs.append(F.cpu().numpy())
+        s.close()
+    for g, o in enumerate(outs[1:], start=2):
+        assert np.array_equal(o, outs[0]), f"{g} groups differ from 1"
