@@ -36,7 +36,7 @@ def _update_flops(npad: int, nb: int, nmat: int) -> float:
     return tot * nmat
 
 
-def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None):
+def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=False):
     from paper_2502_16555_amd import Solver, _lib
     t0 = time.time()
     s = Solver(cfg, precision=precision)
@@ -47,10 +47,13 @@ def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None):
     ne = workloads.density_profile(s.xhat(), cfg["ic"]["ne_peak"])
     F = s.initial_state(torch.as_tensor(ne, device="cuda:0"), cfg["ic"]["Te_eV"])
     dt = cfg["dt_s"]
+    first = None
     n = 0
     for _ in range(warmup):
         s.step(F, n * dt)
         n += 1
+        if n == 1 and one_step:
+            first = s.moments(F).cpu().numpy()
     torch.cuda.synchronize()
     code, sweeps, resid = s.status()
     if code != 0:
@@ -72,6 +75,7 @@ def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None):
     if code != 0:
         raise RuntimeError(f"{precision}: device status {code} in the timed steps")
     mom = s.moments(F).cpu().numpy()
+    n_end = n
     # kernel-level breakdown (separate, instrumented steps)
     s.set_timing(True)
     nt = 3
@@ -81,7 +85,7 @@ def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None):
     tm = s.timing()
     s.set_timing(False)
     out = {"ms_per_step": ms, "wall_s": wall, "setup_s": setup_s, "refine_sweeps": sweeps, "refine_resid": resid,
-           "moments": mom, "t_final": n * dt,
+           "moments": mom, "n_end": n_end, "first_step_moments": first,
            "ms_update": tm[0] / nt, "ms_panel": tm[1] / nt, "ms_vwall": tm[2] / nt, "ms_x": tm[4] / nt,
            "update_launches": tm[3] / nt, "lu_streams": s.get_tuning(_lib.TUNE_LU_STREAMS),
            "info": s.info}
@@ -89,30 +93,68 @@ def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None):
     return out
 
 
-def cpu_baseline(cfg, budget_s=20.0):
-    """The FP64 oracle on the host cores, on a bounded sample of one step's work:
-    one full X(dt/2) plus as many of the per-point V solves as fit the budget;
-    the step time is 2 t_X + Nx t_V."""
+def rel_err(a, b, mask=None):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if mask is not None:
+        a, b = a[mask], b[mask]
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def moment_errors(got, ref):
+    """Relative max-norm errors per result: density, mean energy (on points with
+    n_e > 1e-3 max n_e; the walls have n_e -> 0), energy density, k_i n_e."""
+    mask = ref[0] > 1e-3 * ref[0].max()
+    return {"n_e": rel_err(got[0], ref[0]), "mean_energy": rel_err(got[1], ref[1], mask),
+            "energy_density": rel_err(got[0] * got[1], ref[0] * ref[1]),
+            "k_i_n_e": rel_err(got[0] * got[2], ref[0] * ref[2])}
+
+
+def run_adjoint(torch, n_steps=100, every=50):
+    """Adjoint cost on the differentiation workload (Nx=128, Nr=64, Ntheta=32,
+    8 bins x 3 processes + E0, FP64): time of the checkpointed forward pass vs
+    forward + reverse pass, operators set up beforehand."""
+    import workloads
+    from paper_2502_16555_amd import Solver
+    from paper_2502_16555_amd.autograd import forward_cycle, reverse_cycle
+    cfg = workloads.config("C4")
+    s = Solver(cfg, precision="fp64")
+    ne = workloads.density_profile(s.xhat(), cfg["ic"]["ne_peak"])
+    F0 = s.initial_state(torch.as_tensor(ne, device="cuda:0"), cfg["ic"]["Te_eV"])
+    forward_cycle(s, F0, 2, 0)               # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    nbar, ckpts = forward_cycle(s, F0, n_steps, every)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t
+    g = 2.0 * (nbar - 1.05 * nbar.detach()) / 1e32
+    t = time.perf_counter()
+    gs, gE0, _ = reverse_cycle(s, ckpts, g, n_steps)
+    torch.cuda.synchronize()
+    t_rev = time.perf_counter() - t
+    s.close()
+    return {"workload": f"Nx=128, Nr=64, Ntheta=32, FP64, {s.n_params} scalings + E0, {n_steps} steps, "
+                        f"checkpoint every {every}",
+            "forward_s": t_fwd, "reverse_s": t_rev, "cost_ratio": (t_fwd + t_rev) / t_fwd,
+            "grad_finite": bool(torch.isfinite(gs).all() and torch.isfinite(gE0).all())}
+
+
+def cpu_baseline(cfg):
+    """The FP64 oracle on the host cores: one full step from the initial state
+    (both X half-steps and all Nx velocity-space solves).  Returns the timing and
+    the moments after the step (the reference of the one-step accuracy check)."""
     import oracle
     from oracle import semi_implicit as S
     import workloads
     ops = oracle.build_operators(cfg)
     F = S.initial_state(ops, workloads.density_profile(ops.xhat, cfg["ic"]["ne_peak"]), cfg["ic"]["Te_eV"])
     t = time.perf_counter()
-    Fh = S.x_half_step(ops, F)
-    tx = time.perf_counter() - t
-    E = S.field_half(ops, 0.0)
-    nv = 0
-    t = time.perf_counter()
-    while nv < ops.nx and (time.perf_counter() - t) < max(budget_s - tx, 1.0):
-        S.v_step(ops, Fh, E, xs=[nv])
-        nv += 1
-    tv = (time.perf_counter() - t) / nv
-    step_s = 2 * tx + ops.nx * tv
-    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / step_s, "unit": "steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"one X(dt/2) over all {ops.nx} points ({tx:.2f} s) + {nv} of {ops.nx} V solves "
-                      f"({tv:.3f} s each), scaled to one step = 2 t_X + Nx t_V"}
+    F1 = S.step(ops, F, 0.0)
+    step_s = time.perf_counter() - t
+    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    res = {"value": 1.0 / step_s, "unit": "steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"one full step (t=0, from the initial state) at Nx={ops.nx}: {step_s:.1f} s"}
+    return res, S.moments(ops, F1)
 
 
 def main():
@@ -124,7 +166,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--nx", type=int, default=256)
-    ap.add_argument("--lu-streams", type=int, default=None, help="concurrent factorization groups (library default 2)")
+    ap.add_argument("--lu-streams", type=int, default=None, help="concurrent factorization groups (library default 1)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hot path is single-GPU in this build",
@@ -138,10 +181,12 @@ def main():
     cfg = workloads.config("C2")
     if args.nx != 256:
         cfg = dict(cfg, nx=args.nx, nx_per=[args.nx])
-    main_run = run_gpu(cfg, args.precision, args.steps, args.warmup, torch, args.lu_streams)
+    warm = max(args.warmup, 1)
+    main_run = run_gpu(cfg, args.precision, args.steps, warm, torch, args.lu_streams, one_step=True)
     fp64 = None
     if not args.no_fp64 and args.precision != "fp64":
-        fp64 = run_gpu(cfg, "fp64", max(args.steps // 2, 5), args.warmup, torch, args.lu_streams)
+        # same number of steps from the same state, so the final moments compare
+        fp64 = run_gpu(cfg, "fp64", args.steps, warm, torch, args.lu_streams, one_step=True)
     info = main_run["info"]
     nx_total, n = info.nx_total, info.n
     npad = ((n + 127) // 128) * 128
@@ -175,9 +220,21 @@ def main():
         line["fp64"] = {"steps_per_s": 1000.0 / fp64["ms_per_step"], "ms_per_step": fp64["ms_per_step"],
                         "speedup_mixed_over_fp64": fp64["ms_per_step"] / main_run["ms_per_step"],
                         "ms_update": fp64["ms_update"], "ms_panel": fp64["ms_panel"],
-                        "update_tflops": _update_flops(npad, 128, nx_total) / (fp64["ms_update"] * 1e-3) / 1e12}
+                        "update_tflops": _update_flops(npad, 128, nx_total) / (fp64["ms_update"] * 1e-3) / 1e12,
+                        "update_frac_fp64_peak": _update_flops(npad, 128, nx_total) / (fp64["ms_update"] * 1e-3)
+                        / 1e12 / MI355X_PEAK_TFLOPS["fp64"]}
+        line["accuracy"] = {
+            "mixed_vs_fp64_gpu": dict(moment_errors(main_run["moments"], fp64["moments"]),
+                                      steps=main_run["n_end"])}
+    if not args.no_adjoint:
+        line["adjoint"] = run_adjoint(torch)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(cfg)
+        cb, mom1 = cpu_baseline(cfg)
+        line["cpu_baseline"] = cb
+        acc = line.setdefault("accuracy", {})
+        acc["vs_oracle_one_step"] = {args.precision: moment_errors(main_run["first_step_moments"], mom1)}
+        if fp64 is not None:
+            acc["vs_oracle_one_step"]["fp64"] = moment_errors(fp64["first_step_moments"], mom1)
     print(json.dumps(line), flush=True)
 
 

@@ -105,7 +105,9 @@ typedef struct {
   const double* scal;           /* host [n_proc*n_bins] multiplicative scalings or NULL (= 1)   */
   int32_t precision;            /* bte_precision                                                */
   int32_t refine_max_iter;      /* mixed modes: max refinement sweeps (<= 0: 10)                */
-  double refine_rtol;           /* mixed modes: stop at max|r| <= rtol max|b| (<= 0: 1e-14)     */
+  double refine_rtol;           /* mixed modes: stop when, at every point, the normwise backward
+                                 * error max|r| / (||M|| max|x| + max|b|) <= rtol, with ||M|| <=
+                                 * 1 + dt (n0 ||C_ord|| + |E| ||A_ord||) (<= 0: 1e-14)            */
   int32_t field_mode;           /* bte_field_mode                                               */
   double field_freq_hz;         /* RF / Poisson voltage frequency                               */
   double field_a1;              /* RF spatial profile coefficient                               */
@@ -229,7 +231,7 @@ bte_status bte_get_timing(bte_handle* h, double* ms_out);
  *   consecutive points, factored concurrently on the handle's own side
  *   streams (default priority) and joined back into the caller's stream with
  *   events, so that the latency-bound panel kernels of one group overlap the
- *   MFMA updates of another.  1..4, default 2.
+ *   MFMA updates of another.  1..4, default 1.
  * Returns BTE_EINVAL for an unknown key or a value out of range. */
 typedef enum { BTE_TUNE_LU_STREAMS = 0 } bte_tune_key;
 bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value);

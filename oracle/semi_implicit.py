@@ -209,3 +209,38 @@ def run(ops: Operators, F0: np.ndarray, n_steps: int, t0: float = 0.0, every: in
         if callback is not None and every and (n + 1) % every == 0:
             callback(n + 1, F)
     return F
+
+
+def cycle_mean_density(ops: Operators, F0: np.ndarray, n_steps: int, t0: float = 0.0) -> np.ndarray:
+    """Mean over the step-end states F^1..F^N of the density n_e = u^T F (per x)."""
+    F = F0.copy()
+    acc = np.zeros(ops.nx)
+    for n in range(n_steps):
+        F = step(ops, F, t0 + n * ops.dt)
+        acc += F.reshape(ops.nx, -1) @ ops.u_ord
+    return acc / n_steps
+
+
+def cycle_mean_density_vjp(ops: Operators, F0: np.ndarray, n_steps: int, g: np.ndarray, t0: float = 0.0):
+    """Reverse-mode derivative of ``cycle_mean_density`` for a cotangent g [nx].
+
+    All states are kept (no checkpointing): lam^N = (1/N) u g, and for n = N-1..0
+    lam^n = S_n^T lam^{n+1} (+ (1/N) u g for n >= 1), with the parameter
+    gradients of every transposed step summed.  The field derivative is chained
+    to the amplitude E0 of the specified field.
+    Returns (grad_scal [n_proc * n_bins], dL/dE0, dL/dF^0).
+    """
+    states = [F0.copy()]
+    for n in range(n_steps):
+        states.append(step(ops, states[-1], t0 + n * ops.dt))
+    direct = np.outer(g / n_steps, ops.u_ord).reshape(F0.shape)
+    lam = np.zeros_like(F0)
+    grad_scal = np.zeros(len(ops.Cord_sb))
+    grad_E0 = 0.0
+    for n in range(n_steps, 0, -1):
+        lam = lam + direct
+        t = t0 + (n - 1) * ops.dt
+        lam, gs, gE = adjoint_step(ops, states[n - 1], t, lam)
+        grad_scal += gs
+        grad_E0 += float(gE @ field_dE0(ops, t))
+    return grad_scal, grad_E0, lam

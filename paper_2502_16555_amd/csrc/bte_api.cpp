@@ -49,7 +49,7 @@ struct bte_handle {
   // (fork/join by events) so that one group's latency-bound panels overlap
   // another group's MFMA updates
   static constexpr int kMaxLuStreams = 4;
-  int lu_streams = 2;
+  int lu_streams = 1;
   hipStream_t gs[kMaxLuStreams] = {};
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kMaxLuStreams] = {};
@@ -247,6 +247,23 @@ void fill_devops(bte_handle* h) {
   d.mu = h->alloc<double>(nxt * d.n);
   d.rmax = h->alloc<unsigned long long>(nxt);
   d.bmax = h->alloc<unsigned long long>(nxt);
+  d.xmax = h->alloc<unsigned long long>(nxt);
+  {
+    const int n = d.n;
+    std::vector<double> rc(n, 0.0), ra(n, 0.0), cc(n, 0.0), ca(n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double c = std::fabs(H.Cord[(size_t)i * n + j]), a = std::fabs(H.Aord[(size_t)i * n + j]);
+        rc[i] += c;
+        ra[i] += a;
+        cc[j] += c;
+        ca[j] += a;
+      }
+    d.c_inf = *std::max_element(rc.begin(), rc.end());
+    d.a_inf = *std::max_element(ra.begin(), ra.end());
+    d.c_one = *std::max_element(cc.begin(), cc.end());
+    d.a_one = *std::max_element(ca.begin(), ca.end());
+  }
   d.status = h->alloc<int>(4);
   d.resid = h->alloc<double>(1);
   d.scratch3 = h->alloc<double>(3 * nxt);
@@ -304,11 +321,11 @@ void v_solve(bte_handle* h, double* F, bool transpose, hipStream_t s) {
     bte::launch_reset_refine(d, s);
     for (int it = 1; it <= h->refine_max_iter; ++it) {
       bte::launch_residual(d, transpose, s);
-      bte::launch_refine_check(d, h->refine_rtol, it - 1, false, s);
+      bte::launch_refine_check(d, transpose, h->refine_rtol, it - 1, false, s);
       bte::launch_lu_solve(d, prec, transpose, d.R, d.X, true, true, s);
     }
     bte::launch_residual(d, transpose, s);
-    bte::launch_refine_check(d, h->refine_rtol, h->refine_max_iter, true, s);
+    bte::launch_refine_check(d, transpose, h->refine_rtol, h->refine_max_iter, true, s);
   }
   bte::launch_unpad_rows(d, d.X, F, s);
 }
@@ -323,11 +340,11 @@ void v_solve_again(bte_handle* h, double* F, bool transpose, hipStream_t s) {
     bte::launch_reset_refine(d, s);
     for (int it = 1; it <= h->refine_max_iter; ++it) {
       bte::launch_residual(d, transpose, s);
-      bte::launch_refine_check(d, h->refine_rtol, it - 1, false, s);
+      bte::launch_refine_check(d, transpose, h->refine_rtol, it - 1, false, s);
       bte::launch_lu_solve(d, prec, transpose, d.R, d.X, true, true, s);
     }
     bte::launch_residual(d, transpose, s);
-    bte::launch_refine_check(d, h->refine_rtol, h->refine_max_iter, true, s);
+    bte::launch_refine_check(d, transpose, h->refine_rtol, h->refine_max_iter, true, s);
   }
   bte::launch_unpad_rows(d, d.X, F, s);
 }

@@ -61,7 +61,11 @@ struct DevOps {
   double* Fs = nullptr;        // [nx_total][n] adjoint: post-V state
   double* mu = nullptr;        // [nx_total][n] adjoint: A^-T X^T lambda
   unsigned long long* rmax = nullptr;  // [nx_total] max|r| (as ordered bits)
-  unsigned long long* bmax = nullptr;  // [nx_total]
+  unsigned long long* bmax = nullptr;  // [nx_total] max|b|
+  unsigned long long* xmax = nullptr;  // [nx_total] max|x|
+  // bounds of the operator norms for the refinement stop: inf-norm (row sums)
+  // and 1-norm (column sums) of C_ord and A_ord
+  double c_inf = 0.0, a_inf = 0.0, c_one = 0.0, a_one = 0.0;
   int* status = nullptr;       // [4]: status bits, done flag, sweeps, spare
   double* resid = nullptr;     // [1] final max_x |r|/|b|
   double* scratch3 = nullptr;  // [3*nx_total] moments scratch
@@ -103,7 +107,7 @@ void launch_pad_rows(const DevOps& d, const double* F, double* Bp, hipStream_t s
 void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t s);
 // FP64 residual R = B - (I - dt (n0 C + E A)) X (or with A^T for transpose) + per-x norms.
 void launch_residual(const DevOps& d, bool transpose, hipStream_t s);
-void launch_refine_check(const DevOps& d, double rtol, int sweep, bool final_sweep, hipStream_t s);
+void launch_refine_check(const DevOps& d, bool transpose, double rtol, int sweep, bool final_sweep, hipStream_t s);
 void launch_reset_refine(const DevOps& d, hipStream_t s);
 // Adjoint gradient contractions.
 void launch_adjoint_grads(const DevOps& d, double* grad_scal, double* grad_E, hipStream_t s);

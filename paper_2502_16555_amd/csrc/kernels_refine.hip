@@ -42,7 +42,8 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
                                                   double* __restrict__ Rv, const double* __restrict__ C,
                                                   const double* __restrict__ Aop, const double* __restrict__ E,
                                                   const double* __restrict__ n0x, unsigned long long* __restrict__ rmax,
-                                                  unsigned long long* __restrict__ bmax, const int* __restrict__ status,
+                                                  unsigned long long* __restrict__ bmax,
+                                                  unsigned long long* __restrict__ xmax, const int* __restrict__ status,
                                                   double dt, int n, int npad, int nx) {
   if (status[1]) return;
   constexpr int BM = 32, BN = 64, BK = 64;
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
   __shared__ double sX[BM][BK + 1];
   __shared__ double sC[BN][BK + 1];
   __shared__ double sA[BN][BK + 1];
-  __shared__ unsigned long long s_rm[4][BM], s_bm[4][BM];
+  __shared__ unsigned long long s_rm[4][BM], s_bm[4][BM], s_xm[4][BM];
   const int x0 = blockIdx.y * BM, i0 = blockIdx.x * BN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -128,41 +129,54 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
       const int xl = b * 16 + f64_row(lk, it);
       const int x = x0 + xl;
       const int i = i0 + w * 16 + li;
-      unsigned long long rb = 0ull, bb = 0ull;
+      unsigned long long rb = 0ull, bb = 0ull, xb = 0ull;
       if (x < nx && i < n) {
         const size_t o = (size_t)x * npad + i;
-        const double bv = Bv[o];
-        const double r = bv - Xv[o] + dt * n0x[x] * accC[b][it] + dt * E[x] * accA[b][it];
+        const double bv = Bv[o], xv = Xv[o];
+        const double r = bv - xv + dt * n0x[x] * accC[b][it] + dt * E[x] * accA[b][it];
         Rv[o] = r;
         rb = static_cast<unsigned long long>(__double_as_longlong(fabs(r)));
         bb = static_cast<unsigned long long>(__double_as_longlong(fabs(bv)));
+        xb = static_cast<unsigned long long>(__double_as_longlong(fabs(xv)));
       }
 #pragma unroll
       for (int off = 1; off < 16; off <<= 1) {
-        const unsigned long long orb = __shfl_xor(rb, off), obb = __shfl_xor(bb, off);
+        const unsigned long long orb = __shfl_xor(rb, off), obb = __shfl_xor(bb, off), oxb = __shfl_xor(xb, off);
         rb = orb > rb ? orb : rb;
         bb = obb > bb ? obb : bb;
+        xb = oxb > xb ? oxb : xb;
       }
       if (li == 0) {
         s_rm[w][xl] = rb;
         s_bm[w][xl] = bb;
+        s_xm[w][xl] = xb;
       }
     }
   __syncthreads();
   if (tid < BM && x0 + tid < nx) {
-    unsigned long long rb = 0ull, bb = 0ull;
+    unsigned long long rb = 0ull, bb = 0ull, xb = 0ull;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       rb = s_rm[u][tid] > rb ? s_rm[u][tid] : rb;
       bb = s_bm[u][tid] > bb ? s_bm[u][tid] : bb;
+      xb = s_xm[u][tid] > xb ? s_xm[u][tid] : xb;
     }
     atomicMax(&rmax[x0 + tid], rb);
     atomicMax(&bmax[x0 + tid], bb);
+    atomicMax(&xmax[x0 + tid], xb);
   }
 }
 
-// status[1] = done flag, status[2] = sweeps used; resid[0] = max_x |r|/|b|
+// Stop test of the refinement: the normwise backward error of every point,
+//   eta_x = max|r_x| / (||M_x|| max|x_x| + max|b_x|),
+// with ||M_x|| <= 1 + dt (n0_x ||C|| + |E_x| ||A||) in the norm that matches
+// max-norms of the vectors (inf-norm for M, 1-norm for M^T).  The residual's own
+// FP64 rounding is of order sqrt(n) eps ||M|| |x|, so a bound relative to |b|
+// alone is unreachable once dt |E| ||A|| grows; eta is not.
+// status[1] = done flag, status[2] = sweeps used; resid[0] = max_x eta_x.
 __global__ void k_refine_check(unsigned long long* __restrict__ rmax, unsigned long long* __restrict__ bmax,
+                               unsigned long long* __restrict__ xmax, const double* __restrict__ E,
+                               const double* __restrict__ n0x, double dt, double cnorm, double anorm,
                                int* __restrict__ status, double* __restrict__ resid, double rtol, int sweep,
                                int final_sweep, int nx) {
   if (status[1]) return;
@@ -171,10 +185,14 @@ __global__ void k_refine_check(unsigned long long* __restrict__ rmax, unsigned l
   for (int x = threadIdx.x; x < nx; x += blockDim.x) {
     const double r = __longlong_as_double(static_cast<long long>(rmax[x]));
     const double b = __longlong_as_double(static_cast<long long>(bmax[x]));
-    const double q = (b > 0.0) ? r / b : (r > 0.0 ? INFINITY : 0.0);
+    const double xm = __longlong_as_double(static_cast<long long>(xmax[x]));
+    const double mn = 1.0 + dt * (n0x[x] * cnorm + fabs(E[x]) * anorm);
+    const double den = mn * xm + b;
+    const double q = (den > 0.0) ? r / den : (r > 0.0 ? INFINITY : 0.0);
     worst = fmax(worst, (q == q) ? q : INFINITY);
     rmax[x] = 0ull;
     bmax[x] = 0ull;
+    xmax[x] = 0ull;
   }
   red[threadIdx.x] = worst;
   __syncthreads();
@@ -190,10 +208,12 @@ __global__ void k_refine_check(unsigned long long* __restrict__ rmax, unsigned l
   }
 }
 
-__global__ void k_reset_refine(unsigned long long* rmax, unsigned long long* bmax, int* status, int nx) {
+__global__ void k_reset_refine(unsigned long long* rmax, unsigned long long* bmax, unsigned long long* xmax,
+                               int* status, int nx) {
   for (int x = threadIdx.x; x < nx; x += blockDim.x) {
     rmax[x] = 0ull;
     bmax[x] = 0ull;
+    xmax[x] = 0ull;
   }
   if (threadIdx.x == 0) {
     status[1] = 0;
@@ -276,19 +296,21 @@ void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t
 void launch_residual(const DevOps& d, bool transpose, hipStream_t s) {
   dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32);
   if (transpose)
-    k_residual<1><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.status, d.dt, d.n,
+    k_residual<1><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt, d.n,
                                     d.npad, d.nx_total);
   else
-    k_residual<0><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.status, d.dt, d.n,
+    k_residual<0><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt, d.n,
                                     d.npad, d.nx_total);
 }
 
-void launch_refine_check(const DevOps& d, double rtol, int sweep, bool final_sweep, hipStream_t s) {
-  k_refine_check<<<1, 256, 0, s>>>(d.rmax, d.bmax, d.status, d.resid, rtol, sweep, final_sweep ? 1 : 0, d.nx_total);
+void launch_refine_check(const DevOps& d, bool transpose, double rtol, int sweep, bool final_sweep, hipStream_t s) {
+  k_refine_check<<<1, 256, 0, s>>>(d.rmax, d.bmax, d.xmax, d.E, d.n0x, d.dt, transpose ? d.c_one : d.c_inf,
+                                   transpose ? d.a_one : d.a_inf, d.status, d.resid, rtol, sweep, final_sweep ? 1 : 0,
+                                   d.nx_total);
 }
 
 void launch_reset_refine(const DevOps& d, hipStream_t s) {
-  k_reset_refine<<<1, 256, 0, s>>>(d.rmax, d.bmax, d.status, d.nx_total);
+  k_reset_refine<<<1, 256, 0, s>>>(d.rmax, d.bmax, d.xmax, d.status, d.nx_total);
 }
 
 void launch_adjoint_grads(const DevOps& d, double* grad_scal, double* grad_E, hipStream_t s) {

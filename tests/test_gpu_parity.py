@@ -350,3 +350,67 @@ def test_factorization_grouping_does_not_change_results(torch, prec):
         s.close()
     for g, o in enumerate(outs[1:], start=2):
         assert np.array_equal(o, outs[0]), f"{g} groups differ from 1"
+
+
+def _grad_case():
+    cfg = workloads.small_config(nx=5, nr=6, nth=4, kinds=("elastic", "excitation", "ionization"), E=6e3,
+                                 field_kind="rf", n_bins=2)
+    cfg["dt_s"] = 0.02 * cfg["T_rf_s"]
+    return cfg
+
+
+def test_cycle_gradient_matches_oracle_adjoint(torch):
+    """autograd through bte_step / bte_adjoint_step with checkpoints (every 4 of
+    10 steps, a ragged last segment) against the oracle's reverse-mode gradient."""
+    from paper_2502_16555_amd.autograd import cycle_mean_density
+    cfg = _grad_case()
+    ops = oracle.build_operators(cfg)
+    F0 = S.initial_state(ops, workloads.density_profile(ops.xhat, 1e16), 1.0)
+    n_steps, t0 = 10, 0.1 * cfg["T_rf_s"]
+    g = np.random.default_rng(3).standard_normal(ops.nx)
+    ref_s, ref_e0, ref_lam = S.cycle_mean_density_vjp(ops, F0, n_steps, g, t0=t0)
+    ref_nbar = S.cycle_mean_density(ops, F0, n_steps, t0=t0)
+    scal = torch.ones(ops.scal.shape, dtype=torch.float64, requires_grad=True)
+    e0 = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    F0d = cuda(torch, F0).requires_grad_(True)
+    nbar = cycle_mean_density(scal, e0, F0d, cfg, n_steps, every=4, precision="fp64", t0=t0)
+    close(nbar.detach().cpu().numpy(), ref_nbar, 1e-10, "cycle-mean density")
+    (torch.as_tensor(g, device="cuda:0") * nbar).sum().backward()
+    close(scal.grad.numpy().ravel(), ref_s, 1e-9, "dL/dscal")
+    close([float(e0.grad)], [ref_e0 * cfg["field"]["E0"]], 1e-9, "dL/de0_scale")
+    close(F0d.grad.cpu().numpy(), ref_lam, 1e-9, "dL/dF0")
+
+
+def test_cycle_gradient_matches_central_differences(torch):
+    """Tied scalings (one per energy bin across the processes) and the RF
+    amplitude, differentiated by the adjoint and by central differences of the
+    GPU forward (h = 1e-6 relative): agreement to 1e-5."""
+    from paper_2502_16555_amd.autograd import cycle_mean_density
+    cfg = workloads.small_config(nx=7, nr=12, nth=16, kinds=("elastic", "excitation", "ionization"), E=8e3,
+                                 field_kind="rf", n_bins=3)
+    ops = oracle.build_operators(cfg)
+    F0 = cuda(torch, S.initial_state(ops, workloads.density_profile(ops.xhat, 1e16), 1.0))
+    n_steps, every = 24, 10
+    w = torch.as_tensor(np.random.default_rng(4).uniform(0.5, 1.5, ops.nx), device="cuda:0")
+    target = 1.05e16 * torch.as_tensor(workloads.density_profile(ops.xhat, 1.0), device="cuda:0")
+
+    def loss(theta):
+        scal = theta[:3].reshape(1, 3).expand(3, 3)   # bins tied across the processes
+        nbar = cycle_mean_density(scal, theta[3], F0, cfg, n_steps, every=every)
+        return (w * (nbar - target) ** 2).sum() / 1e32
+
+    theta = torch.tensor([1.0, 1.1, 0.9, 1.0], dtype=torch.float64, requires_grad=True)
+    L = loss(theta)
+    L.backward()
+    grad = theta.grad.numpy()
+    h = 1e-6
+    fd = np.zeros(4)
+    with torch.no_grad():
+        for j in range(4):
+            tp = theta.detach().clone()
+            tm = theta.detach().clone()
+            tp[j] *= 1 + h
+            tm[j] *= 1 - h
+            fd[j] = float(loss(tp) - loss(tm)) / (2 * h * float(theta[j]))
+    scale = np.abs(fd).max()
+    assert np.abs(grad - fd).max() < 1e-5 * scale, (grad, fd)

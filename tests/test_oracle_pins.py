@@ -335,6 +335,42 @@ def test_adjoint_dot_product_and_fd():
     assert abs(fd - gE @ dE) < 1e-6 * abs(fd)
 
 
+def test_cycle_density_gradient_against_central_differences():
+    """Reverse-mode gradient of the cycle-mean density (the differentiation
+    workload's loss ingredient) against central differences of the forward
+    oracle: per-(process, bin) scalings, the RF amplitude and the initial state."""
+    cfg = small(nx=5, nr=6, nth=4, kinds=("elastic", "excitation", "ionization"), E=6e3, field_kind="rf", n_bins=2)
+    cfg["dt_s"] = 0.02 * cfg["T_rf_s"]
+    ops = oracle.build_operators(cfg)
+    rng = np.random.default_rng(3)
+    F0 = S.initial_state(ops, workloads.density_profile(ops.xhat, 1e16), 1.0)
+    n_steps = 6
+    g = rng.standard_normal(ops.nx)
+    t0 = 0.1 * cfg["T_rf_s"]
+    gs, gE0, lam0 = S.cycle_mean_density_vjp(ops, F0, n_steps, g, t0=t0)
+
+    def loss(o, F=F0):
+        return float(g @ S.cycle_mean_density(o, F, n_steps, t0=t0))
+
+    h = 1e-6
+    for j in range(ops.scal.size):
+        sp = ops.scal.copy().ravel()
+        sm = sp.copy()
+        sp[j] += h
+        sm[j] -= h
+        fd = (loss(oracle.build_operators(cfg, scal=sp.reshape(ops.scal.shape)))
+              - loss(oracle.build_operators(cfg, scal=sm.reshape(ops.scal.shape)))) / (2 * h)
+        assert abs(fd - gs[j]) < 1e-6 * (abs(fd) + 1e-3 * np.abs(gs).max()), (j, fd, gs[j])
+    E0 = cfg["field"]["E0"]
+    cp = dict(cfg, field=dict(cfg["field"], E0=E0 * (1 + h)))
+    cm = dict(cfg, field=dict(cfg["field"], E0=E0 * (1 - h)))
+    fd = (loss(oracle.build_operators(cp)) - loss(oracle.build_operators(cm))) / (2 * h * E0)
+    assert abs(fd - gE0) < 1e-6 * abs(fd), (fd, gE0)
+    d = rng.standard_normal(F0.shape) * np.abs(F0).max()
+    fd = (loss(ops, F0 + h * d) - loss(ops, F0 - h * d)) / (2 * h)
+    assert abs(fd - np.vdot(lam0, d)) < 1e-6 * abs(fd)
+
+
 # --- P12 / P13: printed constants ---------------------------------------------------------------
 def test_neutral_densities_match_paper():
     printed = {0.1: 0.322e22, 0.5: 1.61e22, 1.0: 3.22e22, 2.0: 6.44e22}
