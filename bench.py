@@ -139,6 +139,43 @@ def run_adjoint(torch, n_steps=100, every=50):
             "grad_finite": bool(torch.isfinite(gs).all() and torch.isfinite(gE0).all())}
 
 
+def run_ensemble(torch, steps=3):
+    """Batching form: 64 discharges (Nx ~ U{32..200}, 0.1-2 Torr, E0 ~ U[1e3, 1e4]
+    V/m, seed 1), mixed precision, all discharges in the same launches; the
+    steps are captured once into a HIP graph and replayed."""
+    import workloads
+    from paper_2502_16555_amd import Solver
+    cfg = workloads.config("C3")
+    t = time.time()
+    s = Solver(cfg, precision="mixed_fp32")
+    setup_s = time.time() - t
+    xh = s.xhat()
+    ne = np.concatenate([workloads.density_profile(xh[o:o + n], cfg["ic"]["ne_peak"])
+                         for o, n in zip(np.cumsum([0] + cfg["nx_per"][:-1]), cfg["nx_per"])])
+    F = s.initial_state(torch.as_tensor(ne, device="cuda:0"), cfg["ic"]["Te_eV"])
+    t = time.time()
+    s.graph_capture(F, 0.0, steps)
+    capture_s = time.time() - t
+    s.graph_launch()                      # warm-up replay
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.graph_launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    code = s.status()[0]
+    info = s.info
+    s.close()
+    if code != 0:
+        raise RuntimeError(f"ensemble: device status {code}")
+    return {"workload": f"{info.n_discharges} discharges, sum Nx = {info.nx_total}, Nr=64, Ntheta=32, mixed FP32",
+            "steps_per_s": 1000.0 / ms, "ms_per_step": ms, "point_steps_per_s": info.nx_total * 1000.0 / ms,
+            "graph_steps": steps, "setup_s": setup_s, "capture_s": capture_s,
+            "device_GB": info.bytes_device / 1e9}
+
+
 def cpu_baseline(cfg):
     """The FP64 oracle on the host cores: one full step from the initial state
     (both X half-steps and all Nx velocity-space solves).  Returns the timing and
@@ -168,6 +205,7 @@ def main():
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--lu-streams", type=int, default=None, help="concurrent factorization groups (library default 1)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
+    ap.add_argument("--ensemble", action="store_true", help="also time the 64-discharge batching form")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hot path is single-GPU in this build",
@@ -228,6 +266,9 @@ def main():
                                       steps=main_run["n_end"])}
     if not args.no_adjoint:
         line["adjoint"] = run_adjoint(torch)
+    if args.ensemble:
+        line["ensemble"] = run_ensemble(torch)
+        line["ensemble"]["point_steps_per_s_single_discharge"] = nx_total * value
     if not args.no_cpu:
         cb, mom1 = cpu_baseline(cfg)
         line["cpu_baseline"] = cb

@@ -152,6 +152,17 @@ bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle
  * Errors (synchronous): BTE_EINVAL.  Device errors are latched. */
 bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void* stream);
 
+/* Captures n_steps consecutive steps of F (times t0_s + k dt, k = 0..n_steps-1,
+ * the same launches as bte_step) into a HIP graph owned by the handle,
+ * replacing a previously captured one; nothing runs at capture.  The graph
+ * holds the addresses of F and of the field buffers: they must stay valid and
+ * are read and written at every bte_graph_launch.  A capture of one RF period
+ * (1000 steps of dt = T/1000) replays every later period with the same field
+ * phases.  Not with timing enabled.  Errors: BTE_EINVAL, BTE_EHIP. */
+bte_status bte_graph_capture(bte_handle* h, double* F, double t0_s, int32_t n_steps, bte_field field);
+/* Replays the captured graph on ``stream`` (asynchronous).  BTE_EINVAL if none. */
+bte_status bte_graph_launch(bte_handle* h, void* stream);
+
 /* Moments of F (eq. hybrid_discrete_c; k_i of the hybrid model): out[0][x] =
  * n_e [m^-3], out[1][x] = mean energy [eV], out[2][x] = ionization rate
  * coefficient k_i [m^3/s] (0 where n_e == 0).  out is device [3][sum Nx]. */

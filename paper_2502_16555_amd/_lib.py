@@ -64,6 +64,8 @@ EXPORTS = {
     "bte_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "bte_get_timing": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "bte_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "bte_graph_capture": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, bte_field]),
+    "bte_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "bte_get_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "bte_destroy": (None, [C.c_void_p]),
     "bte_status_string": (C.c_char_p, [C.c_int]),

@@ -56,6 +56,18 @@ struct bte_handle {
   std::vector<hipEvent_t> lu_ev;   // kMaxLuStreams * 4 * max_panels
   bte::LuTimer lu_timer[kMaxLuStreams];
   double ms_acc[6] = {0, 0, 0, 0, 0, 0};
+  // captured run of steps (bte_graph_capture / bte_graph_launch)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_steps = 0;
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+    graph_steps = 0;
+  }
   double* d_coeff = nullptr;   // [nr] Maxwellian coefficients
   double* d_gE = nullptr;      // [nx_total] adjoint field-gradient scratch
   double* d_tmpF = nullptr;    // [nx_total*n]
@@ -86,6 +98,8 @@ struct bte_handle {
       if (e) (void)hipEventDestroy(e);
     for (auto& q : gs)
       if (q) (void)hipStreamDestroy(q);
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocs) (void)hipFree(p);
   }
 };
@@ -404,6 +418,7 @@ bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle
       HIP_OK(hipEventCreateWithFlags(&h->join_ev[g], hipEventDisableTiming));
     }
     HIP_OK(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+    HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     // pointers inside cfg are not retained
     h->cfg.proc = nullptr;
     h->cfg.bin_edges_eV = nullptr;
@@ -484,6 +499,50 @@ bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void*
       h->ms_acc[5] += 1.0;
     }
     HIP_OK(hipGetLastError());
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_graph_capture(bte_handle* h, double* F, double t0_s, int32_t n_steps, bte_field field) {
+  if (!h || !F || n_steps < 1 || !field_ok(h, field) || h->timing) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    h->drop_graph();
+    hipStream_t c = h->cap_stream;
+    HIP_OK(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int k = 0; k < n_steps; ++k) {
+        const double t = t0_s + k * h->cfg.dt_s;
+        x_half(h, F, false, c);
+        eval_field(h, F, t, field, c);
+        v_solve(h, F, false, c);
+        x_half(h, F, false, c);
+      }
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(c, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIP_OK(hipStreamEndCapture(c, &h->graph));
+    HIP_OK(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+    h->graph_steps = n_steps;
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    h->drop_graph();
+    return map_exc(e);
+  }
+}
+
+bte_status bte_graph_launch(bte_handle* h, void* stream) {
+  if (!h || !h->graph_exec) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    hipStream_t s = S(stream);
+    h->last_stream = s;
+    HIP_OK(hipGraphLaunch(h->graph_exec, s));
     return BTE_OK;
   } catch (const std::exception& e) {
     return map_exc(e);
@@ -611,7 +670,7 @@ bte_status bte_adjoint_step(bte_handle* h, const double* F_n, double t_s, bte_fi
     x_half(h, d.mu, true, s);
     v_solve_again(h, d.mu, true, s);
     // gradients
-    HIP_OK(hipMemsetAsync(h->d_gE, 0, sizeof(double) * d.nx_total, s));
+    bte::launch_fill(h->d_gE, 0.0, d.nx_total, s);
     bte::launch_adjoint_grads(d, grad_scal, h->d_gE, s);
     if (grad_E) HIP_OK(hipMemcpyAsync(grad_E, h->d_gE, sizeof(double) * d.nx_total, hipMemcpyDeviceToDevice, s));
     if (grad_E0 && h->cfg.field_mode != BTE_FIELD_GIVEN)

@@ -109,6 +109,8 @@ void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t
 void launch_residual(const DevOps& d, bool transpose, hipStream_t s);
 void launch_refine_check(const DevOps& d, bool transpose, double rtol, int sweep, bool final_sweep, hipStream_t s);
 void launch_reset_refine(const DevOps& d, hipStream_t s);
+// p[0..n) = v (a kernel, so that captured graphs hold no memset nodes).
+void launch_fill(double* p, double v, size_t n, hipStream_t s);
 // Adjoint gradient contractions.
 void launch_adjoint_grads(const DevOps& d, double* grad_scal, double* grad_E, hipStream_t s);
 

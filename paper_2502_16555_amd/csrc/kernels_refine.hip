@@ -3,6 +3,7 @@
 // action of Alg. vspace_action of the paper evaluated in FP64 with MFMA f64;
 // the refinement x += LU^-1 r repeats until max|r| <= rtol max|b| (a device
 // flag stops the remaining sweeps without a host synchronization).
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -301,6 +302,18 @@ void launch_residual(const DevOps& d, bool transpose, hipStream_t s) {
   else
     k_residual<0><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt, d.n,
                                     d.npad, d.nx_total);
+}
+
+namespace {
+__global__ void k_fill(double* __restrict__ p, double v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+}  // namespace
+
+void launch_fill(double* p, double v, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  const int blocks = static_cast<int>(std::min<size_t>((n + 255) / 256, 1024));
+  k_fill<<<blocks, 256, 0, s>>>(p, v, n);
 }
 
 void launch_refine_check(const DevOps& d, bool transpose, double rtol, int sweep, bool final_sweep, hipStream_t s) {

@@ -129,6 +129,14 @@ class Solver:
     def step(self, F, t, E_half=None, ni=None, stream=None):
         check(self.lib.bte_step(self.h, _ptr(F), float(t), self._field(E_half, ni), _stream(stream)), "bte_step")
 
+    def graph_capture(self, F, t0, n_steps, E_half=None, ni=None):
+        """Capture n_steps steps of F from t0 into the handle's HIP graph (nothing runs)."""
+        check(self.lib.bte_graph_capture(self.h, _ptr(F), float(t0), int(n_steps), self._field(E_half, ni)),
+              "bte_graph_capture")
+
+    def graph_launch(self, stream=None):
+        check(self.lib.bte_graph_launch(self.h, _stream(stream)), "bte_graph_launch")
+
     def xstep(self, F, stream=None):
         check(self.lib.bte_xstep(self.h, _ptr(F), _stream(stream)), "bte_xstep")
 

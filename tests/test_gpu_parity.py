@@ -414,3 +414,96 @@ def test_cycle_gradient_matches_central_differences(torch):
             fd[j] = float(loss(tp) - loss(tm)) / (2 * h * float(theta[j]))
     scale = np.abs(fd).max()
     assert np.abs(grad - fd).max() < 1e-5 * scale, (grad, fd)
+
+
+def _ensemble_case():
+    """Three discharges of different size, pressure and amplitude (the batching
+    form at test size): Nx = 5, 9, 7; 0.3, 1, 2 Torr; E0 = 3e3, 8e3, 1.2e4 V/m."""
+    base = workloads.small_config(nx=5, nr=10, nth=6, kinds=("elastic", "excitation", "ionization"), E=3e3,
+                                  field_kind="rf", n_bins=2)
+    nx_per = [5, 9, 7]
+    p = [0.3, 1.0, 2.0]
+    E0 = [3e3, 8e3, 1.2e4]
+    ens = dict(base, n_discharges=3, nx_per=nx_per, n0_per=[workloads.n0_ideal_gas(q) for q in p], E0_per=E0)
+    members = [dict(base, nx=nx_per[d], nx_per=[nx_per[d]], n0_m3=workloads.n0_ideal_gas(p[d]),
+                    field=dict(base["field"], E0=E0[d])) for d in range(3)]
+    return ens, members
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_ensemble_steps_match_oracle_per_discharge(torch, prec):
+    cfg, members = _ensemble_case()
+    ops = [oracle.build_operators(m) for m in members]
+    F0 = [S.initial_state(o, workloads.density_profile(o.xhat, 1e16), 1.0) for o in ops]
+    s = solver(cfg, precision=prec)
+    assert s.nx_total == sum(cfg["nx_per"]) and s.n_discharges == 3
+    close(s.xhat(), np.concatenate([o.xhat for o in ops]), 1e-15, "ensemble grid")
+    F = cuda(torch, np.concatenate(F0))
+    t0 = 0.2 * cfg["T_rf_s"]
+    ref = list(F0)
+    for k in range(3):
+        s.step(F, t0 + k * cfg["dt_s"])
+        ref = [S.step(o, r, t0 + k * cfg["dt_s"]) for o, r in zip(ops, ref)]
+    assert s.status()[0] == 0
+    got = F.cpu().numpy()
+    o = 0
+    for d, r in enumerate(ref):
+        nx = r.shape[0]
+        close(got[o:o + nx], r, 1e-10, f"discharge {d} ({prec})")
+        o += nx
+    mom = s.moments(F).cpu().numpy()
+    ref_mom = np.concatenate([S.moments(op, r) for op, r in zip(ops, ref)], axis=1)
+    close(mom[0], ref_mom[0], 1e-10, "ensemble n_e")
+    close(mom[1], ref_mom[1], 1e-10, "ensemble mean energy")
+    s.close()
+
+
+def test_ensemble_adjoint_matches_oracle_per_discharge(torch):
+    """Per-discharge E0 gradients and shared scaling gradients of an ensemble."""
+    cfg, members = _ensemble_case()
+    ops = [oracle.build_operators(m) for m in members]
+    rng = np.random.default_rng(9)
+    Fn = [rng.standard_normal((o.nx, o.nr, o.nth)) for o in ops]
+    lam = [rng.standard_normal((o.nx, o.nr, o.nth)) for o in ops]
+    t = 0.3 * cfg["T_rf_s"]
+    s = solver(cfg)
+    lam_d = cuda(torch, np.concatenate(lam))
+    gs = torch.zeros(s.n_params, dtype=torch.float64, device="cuda:0")
+    gE0 = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+    s.adjoint_step(cuda(torch, np.concatenate(Fn)), t, lam_d, gs, gE0)
+    ref_lam, ref_gs, ref_gE0 = [], np.zeros(s.n_params), np.zeros(3)
+    for d, (o, f, l) in enumerate(zip(ops, Fn, lam)):
+        ln, g, gE = S.adjoint_step(o, f, t, l)
+        ref_lam.append(ln)
+        ref_gs += g
+        ref_gE0[d] = gE @ S.field_dE0(o, t)
+    close(lam_d.cpu().numpy(), np.concatenate(ref_lam), 1e-10, "ensemble lambda")
+    close(gs.cpu().numpy(), ref_gs, 1e-10, "ensemble dL/dscal")
+    close(gE0.cpu().numpy(), ref_gE0, 1e-10, "ensemble dL/dE0")
+    s.close()
+
+
+@pytest.mark.parametrize("prec,groups", [("fp64", 1), ("mixed_fp32", 1), ("mixed_fp32", 2)])
+def test_graph_replays_match_eager_steps(torch, prec, groups):
+    """A captured run of 3 steps, replayed 3 times with eager work of the same
+    handle in between, equals the eager steps bit for bit after every replay."""
+    from paper_2502_16555_amd import _lib
+    cfg = CASES["panels"]()
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg, precision=prec)
+    s.set_tuning(_lib.TUNE_LU_STREAMS, groups)
+    F0 = _state(ops, 21)
+    Fg = cuda(torch, F0)
+    Fe = cuda(torch, F0)
+    t0 = 0.1 * cfg["T_rf_s"]
+    s.graph_capture(Fg, t0, 3)
+    assert np.array_equal(Fg.cpu().numpy(), F0)          # capture runs nothing
+    for rep in range(3):
+        s.graph_launch()
+        for k in range(3):
+            s.step(Fe, t0 + k * cfg["dt_s"])
+        s.moments(Fe)                                     # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert s.status()[0] == 0
+        assert np.array_equal(Fg.cpu().numpy(), Fe.cpu().numpy()), f"replay {rep}"
+    s.close()
