@@ -199,7 +199,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="mixed_fp32", choices=["mixed_fp32", "mixed_bf16", "fp64"])
+    ap.add_argument("--precision", default="mixed_fp32", choices=["mixed_fp32", "mixed_bf16x3", "mixed_bf16", "fp64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--nx", type=int, default=256)
@@ -228,8 +228,8 @@ def main():
     info = main_run["info"]
     nx_total, n = info.nx_total, info.n
     npad = ((n + 127) // 128) * 128
-    dtype = {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64"}[args.precision]
-    mfma = {"fp64": "fp64", "mixed_fp32": "fp32", "mixed_bf16": "bf16"}[args.precision]
+    dtype = {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64", "mixed_bf16x3": "bf16x3+f32+f64"}[args.precision]
+    mfma = {"fp64": "fp64", "mixed_fp32": "fp32", "mixed_bf16": "bf16", "mixed_bf16x3": "bf16"}[args.precision]
     # update flops of one step over the summed durations of its update launches
     upd_flops = _update_flops(npad, 128, nx_total)
     n_upd_launches = main_run["update_launches"]

@@ -61,7 +61,10 @@ typedef enum {
 typedef enum {
   BTE_FP64 = 0,           /* FP64 LU (MFMA f64) and FP64 advection                       */
   BTE_MIXED_FP32 = 1,     /* FP32 LU + FP64 iterative refinement of the V-step residual  */
-  BTE_MIXED_BF16 = 2      /* as MIXED_FP32, trailing updates split into bf16 hi/lo terms */
+  BTE_MIXED_BF16 = 2,     /* as MIXED_FP32, LU trailing updates with bf16 operands
+                           * (MFMA bf16, FP32 accumulation)                           */
+  BTE_MIXED_BF16X3 = 3    /* as MIXED_BF16 with operands split a = hi + lo in bf16 and
+                           * the products hi*hi + hi*lo + lo*hi                       */
 } bte_precision;
 
 typedef enum { BTE_ELASTIC = 0, BTE_EXCITATION = 1, BTE_IONIZATION = 2 } bte_process_kind;

@@ -155,7 +155,7 @@ bte::AssemblyInput make_input(const bte_config* c) {
   for (int nx : in.nx_per)
     if (nx < 3 || nx > 1024) throw std::invalid_argument("nx must be in [3, 1024]");
   if (!c->n0_per || !c->E0_per) throw std::invalid_argument("n0_per and E0_per required");
-  if (c->precision < 0 || c->precision > 2) throw std::invalid_argument("bad precision");
+  if (c->precision < 0 || c->precision > 3) throw std::invalid_argument("bad precision");
   if (c->field_mode < 0 || c->field_mode > 3) throw std::invalid_argument("bad field mode");
   return in;
 }
