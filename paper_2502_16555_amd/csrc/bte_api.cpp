@@ -251,6 +251,7 @@ void fill_devops(bte_handle* h) {
   const size_t elt = (c.precision == BTE_FP64) ? sizeof(double) : sizeof(float);
   d.lu = h->alloc<char>(nxt * d.npad * d.npad * elt);
   d.xscr = h->alloc<char>(nxt * d.npad * bte::kNB * elt);
+  d.linv = h->alloc<char>(nxt * 8 * 256 * elt);
   d.piv = h->alloc<int>(nxt * d.npad);
   d.perm = h->alloc<int>(nxt * (2 * bte::kMaxSwapRows + 1));
   d.E = h->alloc<double>(nxt);

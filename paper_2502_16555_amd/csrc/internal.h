@@ -52,6 +52,7 @@ struct DevOps {
   double* Y = nullptr;         // [nx_total*n] mode-major scratch of the X step
   void* lu = nullptr;          // [nx_total][npad][npad] of T (double or float), column-major
   void* xscr = nullptr;        // [nx_total][npad][kNB] of T: interchange staging of extra rows
+  void* linv = nullptr;        // [nx_total][8][16][16] of T: inverses of the diagonal blocks of L11
   int* piv = nullptr;          // [nx_total][npad]
   int* perm = nullptr;         // [nx_total][2*kMaxSwapRows] row list / source list of one panel
   double* E = nullptr;         // [nx_total]

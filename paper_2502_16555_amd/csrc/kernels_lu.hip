@@ -14,9 +14,10 @@
 //             to the lowest row) over register-resident sub-panels of 8 (FP64)
 //             or 16 (FP32) columns, in-panel updates of the remaining columns,
 //             and the panel's row permutation for the trailing columns;
-//   k_u12     per 64/128 trailing columns: the panel's interchanges and
-//             U12 = L11^-1 P A12 by 16-row blocks (MFMA off-diagonal products,
-//             short substitutions on the diagonal blocks);
+//   k_dinv    one block per matrix: inverses of the 16 x 16 diagonal blocks of
+//             the panel's unit lower block L11;
+//   k_u12     per 32 trailing columns: the panel's interchanges and
+//             U12 = L11^-1 P A12 by 16-row blocks, each two MFMA products;
 //   k_update  A22 -= L21 U12: 128 x 128 MFMA tiles, K = 128 in double-buffered
 //             LDS chunks; blocks of one matrix are kept on one XCD so that L21
 //             and U12 stay in that XCD's L2.
@@ -414,18 +415,48 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
 }
 
 // ---------------------------------------------------------------------------
-// Interchanges and U12 = L11^-1 P A12 for CT trailing columns.  The block owns
-// its columns, so all original rows are read (gathered X in LDS, extra rows
-// through a global scratch) before any of them is written back.  The triangular
-// solve runs by 16-row blocks: the off-diagonal part of each block row is an
-// MFMA product with the rows already solved, the 16 x 16 diagonal part a short
-// forward substitution (one thread per column).
+// Inverses of the eight 16 x 16 unit lower diagonal blocks of the panel's L11
+// (one block of 128 threads per matrix; thread = one column of one block, by
+// forward substitution in registers).  Output dinv[mat][b][r][c], row-major.
 // ---------------------------------------------------------------------------
-template <typename T, int CT>
-__global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const int* __restrict__ perm,
-                                             T* __restrict__ xscr, int npad, int k0, int nct, int nmat) {
-  constexpr int LDB = CT + 4;
-  constexpr int NBW = CT / 64;   // 16-column MFMA blocks per wavefront
+template <typename T>
+__global__ __launch_bounds__(128) void k_dinv(const T* __restrict__ LU, T* __restrict__ dinv, int npad, int k0) {
+  __shared__ T sD[8][16][17];
+  const int mat = blockIdx.x, tid = threadIdx.x;
+  const T* A = LU + (size_t)mat * npad * npad;
+  for (int e = tid; e < 8 * 256; e += 128) {
+    const int b = e >> 8, c = (e >> 4) & 15, r = e & 15;
+    sD[b][r][c] = A[(size_t)(k0 + 16 * b + c) * npad + k0 + 16 * b + r];
+  }
+  __syncthreads();
+  const int b = tid >> 4, c = tid & 15;
+  T x[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) x[r] = (r == c) ? T(1) : T(0);
+#pragma unroll
+  for (int r = 1; r < 16; ++r)
+#pragma unroll
+    for (int k = 0; k < r; ++k) x[r] -= sD[b][r][k] * x[k];
+  T* out = dinv + ((size_t)mat * 8 + b) * 256;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) out[r * 16 + c] = x[r];
+}
+
+// ---------------------------------------------------------------------------
+// Interchanges and U12 = L11^-1 P A12 for 32 trailing columns per block (two
+// wavefronts, one 16-column MFMA block each; small LDS so that several blocks
+// share a CU).  The block owns its columns, so all original rows are read
+// (gathered into LDS, rows outside the panel staged through a global scratch)
+// before any of them is written back.  The solve goes by 16-row blocks I:
+//   T_I = B_I - sum_{J<I} L_IJ U_J,   U_I = X_II T_I   (two MFMA products),
+// with X_II the inverse of the diagonal block and the next block row of L11
+// prefetched into registers while the current one is in use.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(128) void k_u12(T* __restrict__ LU, const T* __restrict__ dinv,
+                                             const int* __restrict__ perm, T* __restrict__ xscr, int npad, int k0,
+                                             int nct, int nmat) {
+  constexpr int CT = 32, LDB = CT + 4, LDL = NB + 4;
   int mat, ct;
   xcd_map(blockIdx.x, nct, nmat, &mat, &ct);
   if (mat >= nmat) return;
@@ -436,60 +467,76 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const int* __re
   const int* R = pm + 1;
   const int* src = pm + 1 + kMaxSwapRows;
   __shared__ T sB[NB][LDB];
-  __shared__ T sL[16][NB + 4];
+  __shared__ T sLr[16][LDL];   // block row I of L11: rows 16I.., columns 0..16I+15
+  __shared__ T sX[16][17];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  for (int e = tid; e < NB * CT; e += 256) {
+  const T* Xg = dinv + (size_t)mat * 8 * 256;
+  // register prefetch of one block row of L11 (16 x up to 128) and its X_II
+  T pl[16], px[2];
+  auto fetch = [&](int I) {
+    const int ncol = 16 * I + 16;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 128 * u, c = e >> 4, r = e & 15;
+      pl[u] = (c < ncol) ? A[(size_t)(k0 + c) * npad + k0 + 16 * I + r] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) px[u] = Xg[I * 256 + tid + 128 * u];
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 128 * u;
+      sLr[e & 15][e >> 4] = pl[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + 128 * u;
+      sX[e >> 4][e & 15] = px[u];
+    }
+  };
+  fetch(0);
+  for (int e = tid; e < NB * CT; e += 128) {
     const int k = e % NB, j = e / NB;
     sB[k][j] = A[(size_t)(c0 + j) * npad + src[k]];
   }
   const int nx = nR - NB;
   if (nx > 0) {
-    for (int e = tid; e < nx * CT; e += 256) {
+    for (int e = tid; e < nx * CT; e += 128) {
       const int t = NB + e % nx, j = e / nx;
       xscr[((size_t)mat * npad + c0 + j) * NB + (t - NB)] = A[(size_t)(c0 + j) * npad + src[t]];
     }
   }
+  put();
   __syncthreads();
   if (nx > 0) {
-    for (int e = tid; e < nx * CT; e += 256) {
+    for (int e = tid; e < nx * CT; e += 128) {
       const int t = NB + e % nx, j = e / nx;
       if (src[t] != R[t]) A[(size_t)(c0 + j) * npad + R[t]] = xscr[((size_t)mat * npad + c0 + j) * NB + (t - NB)];
     }
   }
+  const int col = 16 * w + li;
   for (int I = 0; I < NB / 16; ++I) {
     const int r0 = 16 * I;
-    // rows r0..r0+15 of L11, columns 0..r0+15
-    for (int e = tid; e < 16 * (r0 + 16); e += 256) {
-      const int c = e / 16, r = e % 16;
-      sL[r][c] = A[(size_t)(k0 + c) * npad + k0 + r0 + r];
-    }
-    __syncthreads();
+    if (I + 1 < NB / 16) fetch(I + 1);
     if (I > 0) {
-      typename Mma<T>::acc acc[NBW];
+      typename Mma<T>::acc acc = typename Mma<T>::acc{0, 0, 0, 0};
+      for (int k = 0; k < r0; k += 4) acc = Mma<T>::step(sLr[li][k + lk], sB[k + lk][col], acc);
 #pragma unroll
-      for (int b = 0; b < NBW; ++b) acc[b] = typename Mma<T>::acc{0, 0, 0, 0};
-      for (int k = 0; k < r0; k += 4) {
-        const T av = sL[li][k + lk];
-#pragma unroll
-        for (int b = 0; b < NBW; ++b) acc[b] = Mma<T>::step(av, sB[k + lk][(w * NBW + b) * 16 + li], acc[b]);
-      }
-#pragma unroll
-      for (int b = 0; b < NBW; ++b)
-#pragma unroll
-        for (int it = 0; it < 4; ++it) sB[r0 + Mma<T>::row(lk, it)][(w * NBW + b) * 16 + li] -= acc[b][it];
+      for (int it = 0; it < 4; ++it) sB[r0 + Mma<T>::row(lk, it)][col] -= acc[it];
       __syncthreads();
     }
-    if (tid < CT) {
-      for (int r = 1; r < 16; ++r) {
-        T v = sB[r0 + r][tid];
-        for (int c = 0; c < r; ++c) v -= sL[r][r0 + c] * sB[r0 + c][tid];
-        sB[r0 + r][tid] = v;
-      }
-    }
+    typename Mma<T>::acc u = typename Mma<T>::acc{0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 16; k += 4) u = Mma<T>::step(sX[li][k + lk], sB[r0 + k + lk][col], u);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 4; ++it) sB[r0 + Mma<T>::row(lk, it)][col] = u[it];
+    if (I + 1 < NB / 16) put();
     __syncthreads();
   }
-  for (int e = tid; e < NB * CT; e += 256) {
+  for (int e = tid; e < NB * CT; e += 128) {
     const int k = e % NB, j = e / NB;
     A[(size_t)(c0 + j) * npad + k0 + k] = sB[k][j];
   }
@@ -906,6 +953,7 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   const size_t np2 = (size_t)d.npad * d.npad;
   T* LU = static_cast<T*>(d.lu) + (size_t)m0 * np2;
   T* xs = static_cast<T*>(d.xscr) + (size_t)m0 * d.npad * NB;
+  T* li = static_cast<T*>(d.linv) + (size_t)m0 * 8 * 256;  // diagonal-block inverses
   int* piv = d.piv + (size_t)m0 * d.npad;
   int* perm = d.perm + (size_t)m0 * kPermStride;
   constexpr int kFormXpb = 16;  // matrices per formation block
@@ -924,9 +972,9 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     else if (d.npad <= 2 * kPanelThreads) k_panel<T, 2, IB><<<nmat, kPanelThreads, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
     else k_panel<T, 4, IB><<<nmat, kPanelThreads, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
     if (rest > 0) {
-      constexpr int CT = sizeof(T) == 8 ? 64 : 128;  // U12 columns per block (LDS budget)
-      const int nct = rest / CT;
-      k_u12<T, CT><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, xs, d.npad, k0, nct, nmat);
+      const int nct = rest / 32;  // U12 blocks of 32 columns
+      k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);
+      k_u12<T><<<xcd_grid(nct, nmat), 128, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
       if (rec) {
         (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p + 1], s);
         (void)hipEventRecord(tm->ev[2 * p], s);
