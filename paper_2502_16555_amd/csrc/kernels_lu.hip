@@ -23,6 +23,7 @@
 //             and U12 stay in that XCD's L2.
 #include <cfloat>
 #include <climits>
+#include <limits>
 #include <cmath>
 
 #include "internal.h"
@@ -130,11 +131,11 @@ __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* 
 // ---------------------------------------------------------------------------
 // Panel factorization: rows k0.., columns k0..k0+NB-1, one block per matrix.
 // ---------------------------------------------------------------------------
-template <typename T, int RPT, int IB>
-__global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int* __restrict__ piv,
+template <typename T, int NT, int RPT, int IB>
+__global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restrict__ piv,
                                                          int* __restrict__ perm, int* __restrict__ status, int npad,
                                                          int k0) {
-  constexpr int NT = kPanelThreads, NW = NT / 64;
+  constexpr int NW = NT / 64;
   const int mat = blockIdx.x;
   T* A = LU + (size_t)mat * npad * npad;
   int* ip = piv + (size_t)mat * npad;
@@ -243,11 +244,14 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
       }
       if (pv == T(0)) singular = true;
       if (!(fabs(static_cast<double>(pv)) <= DBL_MAX)) nonfinite = true;
+      // multipliers by the reciprocal of the pivot (division for subnormal pivots)
+      const bool by_rcp = fabs(pv) >= std::numeric_limits<T>::min();
+      const T rp = T(1) / pv;
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         const int r = c0 + tid + q * NT;
         if (r > c && r < npad && pv != T(0)) {
-          const T l = a[q][j] / pv;
+          const T l = by_rcp ? a[q][j] * rp : a[q][j] / pv;
           a[q][j] = l;
 #pragma unroll
           for (int jj = 0; jj < IB; ++jj)
@@ -347,23 +351,32 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
       }
       __syncthreads();
       // rows >= c0+IB: A[r][rest] -= L[r][c0:c0+IB] U[c0:c0+IB][rest], in batches of
-      // CB columns so that the loads of a batch are in flight together
-      constexpr int CB = (RPT * IB >= 64) ? 2 : ((RPT >= 2) ? 4 : 8);
-      for (int cb = 0; cb < nrest; cb += CB) {
-        T v[RPT][CB];
+      // CB columns; the next batch is loaded before the current one is stored so
+      // that two batches of loads are in flight per thread
+      constexpr int CB = (sizeof(T) == 8 && RPT == 4) ? 2 : 4;
+      T v[RPT][CB], nv[RPT][CB];
+      auto ld = [&](T (&dst)[RPT][CB], int cb) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
           const int r = c0 + tid + q * NT;
 #pragma unroll
           for (int u = 0; u < CB; ++u)
-            v[q][u] = (r >= c0 + IB && r < npad && cb + u < nrest) ? A[(size_t)(c0 + IB + cb + u) * npad + r] : T(0);
+            dst[q][u] = (r >= c0 + IB && r < npad && cb + u < nrest) ? A[(size_t)(c0 + IB + cb + u) * npad + r] : T(0);
         }
+      };
+      ld(v, 0);
+      for (int cb = 0; cb < nrest; cb += CB) {
+        if (cb + CB < nrest) ld(nv, cb + CB);
 #pragma unroll
-        for (int q = 0; q < RPT; ++q)
+        for (int u = 0; u < CB; ++u) {
+          T uj[IB];
 #pragma unroll
-          for (int u = 0; u < CB; ++u)
+          for (int j = 0; j < IB; ++j) uj[j] = s_U[j][(cb + u) & (NB - 1)];
 #pragma unroll
-            for (int j = 0; j < IB; ++j) v[q][u] -= a[q][j] * s_U[j][(cb + u) & (NB - 1)];
+          for (int q = 0; q < RPT; ++q)
+#pragma unroll
+            for (int j = 0; j < IB; ++j) v[q][u] -= a[q][j] * uj[j];
+        }
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
           const int r = c0 + tid + q * NT;
@@ -371,6 +384,10 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel(T* __restrict__ LU, int
           for (int u = 0; u < CB; ++u)
             if (r >= c0 + IB && r < npad && cb + u < nrest) A[(size_t)(c0 + IB + cb + u) * npad + r] = v[q][u];
         }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+#pragma unroll
+          for (int u = 0; u < CB; ++u) v[q][u] = nv[q][u];
       }
       __syncthreads();
     }
@@ -968,9 +985,10 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     const bool rec = tm && p < tm->max_panels;
     if (rec) (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p], s);
     const int rest = d.npad - k0 - NB;
-    if (d.npad <= kPanelThreads) k_panel<T, 1, IB><<<nmat, kPanelThreads, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
-    else if (d.npad <= 2 * kPanelThreads) k_panel<T, 2, IB><<<nmat, kPanelThreads, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
-    else k_panel<T, 4, IB><<<nmat, kPanelThreads, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
+    constexpr int NT = kPanelThreads;  // 512 threads holding up to 4 rows each
+    if (d.npad <= NT) k_panel<T, NT, 1, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
+    else if (d.npad <= 2 * NT) k_panel<T, NT, 2, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
+    else k_panel<T, NT, 4, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
     if (rest > 0) {
       const int nct = rest / 32;  // U12 blocks of 32 columns
       k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);

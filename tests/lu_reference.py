@@ -50,7 +50,12 @@ def factor(A, IB):
                 ip[c] = p
                 sw.append(p)
                 if a[j, j] != 0:
-                    a[j + 1:, j] /= a[j, j]
+                    # multipliers by the reciprocal of the pivot, as the device does
+                    # (division only for subnormal pivots)
+                    if abs(a[j, j]) >= np.finfo(a.dtype).tiny:
+                        a[j + 1:, j] *= 1.0 / a[j, j]
+                    else:
+                        a[j + 1:, j] /= a[j, j]
                     a[j + 1:, j + 1:] -= np.outer(a[j + 1:, j], a[j, j + 1:])
             A[c0:, c0:c0 + IB] = a
             R, src = _perm(c0, IB, sw)
