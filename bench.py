@@ -153,6 +153,10 @@ def run_ensemble(torch, steps=3):
     ne = np.concatenate([workloads.density_profile(xh[o:o + n], cfg["ic"]["ne_peak"])
                          for o, n in zip(np.cumsum([0] + cfg["nx_per"][:-1]), cfg["nx_per"])])
     F = s.initial_state(torch.as_tensor(ne, device="cuda:0"), cfg["ic"]["Te_eV"])
+    from paper_2502_16555_amd.autotune import autotune
+    t = time.time()
+    tuned = autotune(s, F, "mixed_fp32", steps=1)
+    tune_s = time.time() - t
     t = time.time()
     s.graph_capture(F, 0.0, steps)
     capture_s = time.time() - t
@@ -172,7 +176,10 @@ def run_ensemble(torch, steps=3):
         raise RuntimeError(f"ensemble: device status {code}")
     return {"workload": f"{info.n_discharges} discharges, sum Nx = {info.nx_total}, Nr=64, Ntheta=32, mixed FP32",
             "steps_per_s": 1000.0 / ms, "ms_per_step": ms, "point_steps_per_s": info.nx_total * 1000.0 / ms,
-            "graph_steps": steps, "setup_s": setup_s, "capture_s": capture_s,
+            "graph_steps": steps, "setup_s": setup_s, "capture_s": capture_s, "autotune_s": tune_s,
+            "tuned": {"lu_streams": tuned["settings"][1 - 1], "update_kc": tuned["settings"][1],
+                      "form_xpb": tuned["settings"][2], "trials": tuned["trials"],
+                      "ms_per_step_tuned": tuned["ms_per_step"]},
             "device_GB": info.bytes_device / 1e9}
 
 

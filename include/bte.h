@@ -240,14 +240,19 @@ bte_status bte_set_timing(bte_handle* h, int32_t enable);
 bte_status bte_get_timing(bte_handle* h, double* ms_out);
 
 /* Launch-shape tuning; results do not depend on it (every matrix is factored
- * by the same kernels in the same order whatever the grouping).
+ * by the same arithmetic in the same order whatever the shape).
  *   BTE_TUNE_LU_STREAMS: the points are split into this many groups of
- *   consecutive points, factored concurrently on the handle's own side
- *   streams (default priority) and joined back into the caller's stream with
- *   events, so that the latency-bound panel kernels of one group overlap the
- *   MFMA updates of another.  1..4, default 1.
+ *     consecutive points, factored concurrently on the handle's own side
+ *     streams (default priority) and joined back into the caller's stream with
+ *     events, so that the latency-bound panel kernels of one group can overlap
+ *     the MFMA updates of another.  1..4, default 1.
+ *   BTE_TUNE_UPDATE_KC: K chunk of the trailing-update tiles staged per LDS
+ *     buffer: 16 or 32 (FP32 and BF16 factors), 8 or 16 (FP64); 0 = default
+ *     (32 / 16).  The BF16 updates have a fixed chunk of 32.
+ *   BTE_TUNE_FORM_XPB: matrices formed per block of the formation kernel,
+ *     1..64; 0 = default (16).
  * Returns BTE_EINVAL for an unknown key or a value out of range. */
-typedef enum { BTE_TUNE_LU_STREAMS = 0 } bte_tune_key;
+typedef enum { BTE_TUNE_LU_STREAMS = 0, BTE_TUNE_UPDATE_KC = 1, BTE_TUNE_FORM_XPB = 2 } bte_tune_key;
 bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value);
 bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value);
 

@@ -42,6 +42,8 @@ class bte_info(C.Structure):
 
 
 TUNE_LU_STREAMS = 0
+TUNE_UPDATE_KC = 1
+TUNE_FORM_XPB = 2
 
 EXPORTS = {
     "bte_setup_operators": (C.c_int, [C.POINTER(bte_config), C.c_int, C.POINTER(C.c_void_p)]),

@@ -718,21 +718,34 @@ bte_status bte_set_timing(bte_handle* h, int32_t enable) {
 
 bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value) {
   if (!h) return BTE_EINVAL;
-  if (key == BTE_TUNE_LU_STREAMS) {
-    if (value < 1 || value > bte_handle::kMaxLuStreams) return BTE_EINVAL;
-    h->lu_streams = value;
-    return BTE_OK;
+  const bool fp64 = h->cfg.precision == BTE_FP64;
+  switch (key) {
+    case BTE_TUNE_LU_STREAMS:
+      if (value < 1 || value > bte_handle::kMaxLuStreams) return BTE_EINVAL;
+      h->lu_streams = value;
+      return BTE_OK;
+    case BTE_TUNE_UPDATE_KC:
+      if (value != 0 && value != (fp64 ? 8 : 16) && value != (fp64 ? 16 : 32)) return BTE_EINVAL;
+      h->d.update_kc = value;
+      return BTE_OK;
+    case BTE_TUNE_FORM_XPB:
+      if (value < 0 || value > 64) return BTE_EINVAL;
+      h->d.form_xpb = value;
+      return BTE_OK;
+    default:
+      return BTE_EINVAL;
   }
-  return BTE_EINVAL;
 }
 
 bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value) {
   if (!h || !value) return BTE_EINVAL;
-  if (key == BTE_TUNE_LU_STREAMS) {
-    *value = h->lu_streams;
-    return BTE_OK;
+  const bool fp64 = h->cfg.precision == BTE_FP64;
+  switch (key) {
+    case BTE_TUNE_LU_STREAMS: *value = h->lu_streams; return BTE_OK;
+    case BTE_TUNE_UPDATE_KC: *value = h->d.update_kc ? h->d.update_kc : (fp64 ? 16 : 32); return BTE_OK;
+    case BTE_TUNE_FORM_XPB: *value = h->d.form_xpb ? h->d.form_xpb : 16; return BTE_OK;
+    default: return BTE_EINVAL;
   }
-  return BTE_EINVAL;
 }
 
 bte_status bte_get_timing(bte_handle* h, double* ms_out) {

@@ -24,6 +24,8 @@ struct DevOps {
   int nr = 0, nth = 0, n = 0, npad = 0, nh = 0;
   int nd = 0, nx_total = 0, n_params = 0, n_bins = 1, precision = 0;
   int max_nx = 0;
+  int update_kc = 0;           // K chunk of the trailing update (0: default)
+  int form_xpb = 0;            // matrices per formation block (0: default)
   double dt = 0.0;
   // per discharge (device)
   int* x_off = nullptr;        // [nd+1]

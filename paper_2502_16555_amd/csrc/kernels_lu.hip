@@ -142,10 +142,12 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   __shared__ double s_val[2][NW];
   __shared__ int s_idx[2][NW];
-  __shared__ T s_row[2][2][IB];
+  __shared__ T s_row[2][1][IB];
+  __shared__ T s_cand[2][NW][IB];
   __shared__ T s_L11[IB][IB + 1];
   __shared__ T s_U[IB][NB];
   __shared__ int s_sw[IB];
+  __shared__ int s_piv[NB];
   __shared__ int s_R[2 * IB];
   __shared__ int s_src[2 * IB];
   __shared__ int s_lab[kMaxSwapRows];
@@ -186,16 +188,30 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
           bi = oi;
         }
       }
-      // Partials and pivot rows live in buffers of parity j & 1: a buffer is
-      // rewritten two columns later, after every thread has passed both
-      // barriers of the column in between, so two barriers per column suffice.
+      // One barrier per column: every wavefront publishes its partial maximum
+      // together with the row it belongs to, thread j publishes row c; after the
+      // barrier every thread reduces the partials to the same pivot p and finds
+      // both rows of the interchange in LDS.  The buffers alternate with the
+      // column parity: one is rewritten two columns later, when every thread has
+      // passed the barrier of the column in between and finished reading it.
       const int par = j & 1;
       if (lane == 0) {
         s_val[par][wid] = best;
         s_idx[par][wid] = bi;
       }
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        if (c0 + tid + q * NT == bi) {
+#pragma unroll
+          for (int jj = 0; jj < IB; ++jj) s_cand[par][wid][jj] = a[q][jj];
+        }
+      }
+      if (tid == j) {  // row c is owned by thread j (q = 0)
+#pragma unroll
+        for (int jj = 0; jj < IB; ++jj) s_row[par][0][jj] = a[0][jj];
+      }
       __syncthreads();
-      int p = INT_MAX;
+      int p = INT_MAX, pw = 0;
       {
         double v = -1.0;
 #pragma unroll
@@ -205,29 +221,21 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
           if (ov > v || (ov == v && oi < p)) {
             v = ov;
             p = oi;
+            pw = u;
           }
         }
       }
       // a column of NaNs has no candidate: keep row c (every index stays in
       // range whatever the data) and report the non-finite value
-      if (p == INT_MAX) p = c;
-      // row c is owned by thread j (q = 0); publish rows c and p
-      if (tid == j) {
-#pragma unroll
-        for (int jj = 0; jj < IB; ++jj) s_row[par][0][jj] = a[0][jj];
+      const T* prow = s_cand[par][pw];
+      if (p == INT_MAX) {
+        p = c;
+        prow = s_row[par][0];
       }
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        if (c0 + tid + q * NT == p) {
-#pragma unroll
-          for (int jj = 0; jj < IB; ++jj) s_row[par][1][jj] = a[q][jj];
-        }
-      }
-      __syncthreads();
       if (p != c) {
         if (tid == j) {
 #pragma unroll
-          for (int jj = 0; jj < IB; ++jj) a[0][jj] = s_row[par][1][jj];
+          for (int jj = 0; jj < IB; ++jj) a[0][jj] = prow[jj];
         }
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
@@ -237,9 +245,9 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
           }
         }
       }
-      const T pv = s_row[par][1][j];
-      if (tid == 0) {
-        ip[c] = p;
+      const T pv = prow[j];
+      if (tid == 0) {  // pivots stay in LDS until the panel ends: a global store
+        s_piv[c - k0] = p;  // here would make every later barrier wait for it
         s_sw[j] = p;
       }
       if (pv == T(0)) singular = true;
@@ -251,11 +259,13 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
       for (int q = 0; q < RPT; ++q) {
         const int r = c0 + tid + q * NT;
         if (r > c && r < npad && pv != T(0)) {
-          const T l = by_rcp ? a[q][j] * rp : a[q][j] / pv;
-          a[q][j] = l;
+          const T x = a[q][j];
+          const T l = by_rcp ? x * rp : x / pv;
 #pragma unroll
-          for (int jj = 0; jj < IB; ++jj)
-            if (jj > j) a[q][jj] -= l * s_row[par][1][jj];
+          for (int jj = 0; jj < IB; ++jj) {
+            const T upd = a[q][jj] - l * prow[jj];
+            a[q][jj] = (jj > j) ? upd : (jj == j ? l : a[q][jj]);
+          }
         }
       }
     }
@@ -394,7 +404,8 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
   }
   if (singular && tid == 0) atomicOr(status, kStSingular);
   if (nonfinite && tid == 0) atomicOr(status, kStNonFinite);
-  // permutation of the whole panel for the trailing columns
+  // pivots out, then the permutation of the whole panel for the trailing columns
+  for (int t = tid; t < NB; t += NT) ip[k0 + t] = s_piv[t];
   for (int r = k0 + NB + tid; r < npad; r += NT) s_pos[r] = -1;
   __syncthreads();
   if (tid == 0) {
@@ -408,7 +419,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
       lab[t] = t;
     }
     for (int j = 0; j < NB; ++j) {
-      const int p = ip[k0 + j];
+      const int p = s_piv[j];
       int i2;
       if (p < k0 + NB) {
         i2 = p - k0;
@@ -729,9 +740,9 @@ __global__ __launch_bounds__(256, 2) void k_update(T* __restrict__ LU, int npad,
   const int r0 = k0 + NB + ti * 128, c0 = k0 + NB + tj * 128;
   // one LDS block: the two K-chunk buffers of L21 (sA) and U12 (sB), reused by
   // the epilogue (128 columns x (128 + 4) floats or 2 x 64 x (64 + 2) doubles)
-  __shared__ __align__(16) T smem[2 * 2 * KC * LD];
-  static_assert(2 * 2 * KC * LD * sizeof(T) >= 128 * (128 / (sizeof(T) / 4) + 4 / (sizeof(T) / 4)) * sizeof(T),
-                "epilogue staging does not fit");
+  constexpr int OPER = 2 * 2 * KC * LD;
+  constexpr int EPI = 128 * (128 / (sizeof(T) / 4) + 4 / (sizeof(T) / 4));
+  __shared__ __align__(16) T smem[OPER > EPI ? OPER : EPI];
   T (*sA)[KC][LD] = reinterpret_cast<T (*)[KC][LD]>(smem);
   T (*sB)[KC][LD] = reinterpret_cast<T (*)[KC][LD]>(smem + 2 * KC * LD);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -820,6 +831,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
                                                 int npad) {
   if (check_done && status[1]) return;
   __shared__ double sb[kMaxRows];
+  __shared__ int s_ip[kMaxRows];  // the pivots, staged once (the swaps read them serially)
   __shared__ T sD[NB][NB + 1];
   const int mat = blockIdx.x;
   const T* A = LU + (size_t)mat * npad * npad;
@@ -827,7 +839,10 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NWV = 1024 / 64;
   const double* b = Bin + (size_t)mat * npad;
-  for (int i = tid; i < npad; i += 1024) sb[i] = b[i];
+  for (int i = tid; i < npad; i += 1024) {
+    sb[i] = b[i];
+    s_ip[i] = ip[i];
+  }
   const int np = npad / NB;
   auto stage_diag = [&](int k0) {
     for (int e = tid; e < NB * NB; e += 1024) {
@@ -841,7 +856,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       const int k0 = p * NB;
       if (tid == 0) {
         for (int j = 0; j < NB; ++j) {
-          const int q = ip[k0 + j];
+          const int q = s_ip[k0 + j];
           if (q != k0 + j) {
             const double t = sb[k0 + j];
             sb[k0 + j] = sb[q];
@@ -950,7 +965,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       __syncthreads();
       if (tid == 0) {
         for (int j = NB - 1; j >= 0; --j) {
-          const int q = ip[k0 + j];
+          const int q = s_ip[k0 + j];
           if (q != k0 + j) {
             const double t = sb[k0 + j];
             sb[k0 + j] = sb[q];
@@ -973,13 +988,15 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   T* li = static_cast<T*>(d.linv) + (size_t)m0 * 8 * 256;  // diagonal-block inverses
   int* piv = d.piv + (size_t)m0 * d.npad;
   int* perm = d.perm + (size_t)m0 * kPermStride;
-  constexpr int kFormXpb = 16;  // matrices per formation block
-  dim3 gform(d.npad, (nmat + kFormXpb - 1) / kFormXpb);
-  k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, kFormXpb);
+  const int xpb = d.form_xpb > 0 ? d.form_xpb : 16;  // matrices per formation block
+  dim3 gform(d.npad, (nmat + xpb - 1) / xpb);
+  k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, xpb);
   const int np = d.npad / NB;
   if (tm) tm->used = 0;
   constexpr int IB = sizeof(T) == 8 ? 8 : 16;   // register sub-panel width (VGPR budget of 512 threads)
-  constexpr int KC = sizeof(T) == 8 ? 16 : 32;  // K chunk of the trailing update
+  // K chunk of the trailing update (launch shape only: the K order is the same)
+  constexpr int KC = sizeof(T) == 8 ? 16 : 32;
+  const bool half_kc = d.update_kc == KC / 2;
   for (int p = 0; p < np; ++p) {
     const int k0 = p * NB;
     const bool rec = tm && p < tm->max_panels;
@@ -1002,9 +1019,11 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
       if constexpr (sizeof(T) == 4) {
         if (bf16_terms == 1) k_update_bf16<1><<<gu, 256, 0, s>>>(LU, d.npad, k0, mt, nmat);
         else if (bf16_terms == 3) k_update_bf16<3><<<gu, 256, 0, s>>>(LU, d.npad, k0, mt, nmat);
+        else if (half_kc) k_update<T, KC / 2><<<gu, 256, 0, s>>>(LU, d.npad, k0, mt, nmat);
         else k_update<T, KC><<<gu, 256, 0, s>>>(LU, d.npad, k0, mt, nmat);
       } else {
-        k_update<T, KC><<<gu, 256, 0, s>>>(LU, d.npad, k0, mt, nmat);
+        if (half_kc) k_update<T, KC / 2><<<gu, 256, 0, s>>>(LU, d.npad, k0, mt, nmat);
+        else k_update<T, KC><<<gu, 256, 0, s>>>(LU, d.npad, k0, mt, nmat);
       }
       if (rec) (void)hipEventRecord(tm->ev[2 * p + 1], s);
     } else if (rec) {

@@ -510,3 +510,33 @@ def test_graph_replays_match_eager_steps(torch, prec, groups):
         assert s.status()[0] == 0
         assert np.array_equal(Fg.cpu().numpy(), Fe.cpu().numpy()), f"replay {rep}"
     s.close()
+
+
+def test_autotuned_shapes_leave_results_unchanged(torch, tmp_path):
+    """The autotuner picks launch shapes by timing; the steps after tuning equal
+    the default-shape steps bit for bit, for FP64 and mixed precision."""
+    from paper_2502_16555_amd import _lib
+    from paper_2502_16555_amd.autotune import autotune
+    cfg = CASES["panels4"]()
+    ops = oracle.build_operators(cfg)
+    F0 = _state(ops, 8)
+    for prec in ("fp64", "mixed_fp32"):
+        s = solver(cfg, precision=prec)
+        Fa = cuda(torch, F0)
+        for k in range(2):
+            s.step(Fa, k * cfg["dt_s"])
+        r = autotune(s, cuda(torch, F0), prec, steps=1, cache_path=str(tmp_path / "tune.json"))
+        assert set(r["settings"]) == {_lib.TUNE_LU_STREAMS, _lib.TUNE_UPDATE_KC, _lib.TUNE_FORM_XPB}
+        for k, v in r["settings"].items():
+            assert s.get_tuning(k) == v
+        # every candidate shape once more, explicitly
+        for kc in ((16, 8) if prec == "fp64" else (32, 16)):
+            for xpb in (1, 4, 16):
+                s.set_tuning(_lib.TUNE_UPDATE_KC, kc)
+                s.set_tuning(_lib.TUNE_FORM_XPB, xpb)
+                Fb = cuda(torch, F0)
+                for k in range(2):
+                    s.step(Fb, k * cfg["dt_s"])
+                assert s.status()[0] == 0
+                assert np.array_equal(Fb.cpu().numpy(), Fa.cpu().numpy()), (prec, kc, xpb)
+        s.close()
