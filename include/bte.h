@@ -155,6 +155,31 @@ bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle
  * Errors (synchronous): BTE_EINVAL.  Device errors are latched. */
 bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void* stream);
 
+/* Velocity-space solver of bte_step / bte_vstep / bte_graph_capture.
+ *   BTE_VSOLVER_LU (default): batched LU factorization of every point's system
+ *     each step (FP64, or FP32/BF16 factors with FP64 iterative refinement).
+ *   BTE_VSOLVER_GMRES: the paper's Krylov form (velocity space update of the
+ *     semi-implicit scheme; Alg. vspace_action and Alg. vspace_action_precon):
+ *     restarted GMRES per point in FP64, right-preconditioned by
+ *     H_p = (I - dt (n0 C + s_p A))^-1 for the field bin p of the point: the
+ *     n_bins bins split (-E_bound, E_bound) uniformly in u = E (bin_scale = 0)
+ *     or in u = asinh(E / bin_scale) (bin_scale > 0: bins graded towards zero
+ *     field, where the preconditioner no longer damps the speed-advection
+ *     operator), s_p is the bin centre in u mapped back to E, and fields
+ *     outside fall into the end bins.  The H_p are factored
+ *     here, once, by the batched LU in factor_precision (BTE_FP64 or
+ *     BTE_MIXED_FP32), per discharge.  E_bound <= 0 takes max_d |E0_d| (1 + |a1|)
+ *     (CONST and RF fields only).  restart: Krylov vectors per cycle (1..63);
+ *     cycles: restart cycles (1..100); a point stops when
+ *     ||b - M x||_2 <= rtol ||b||_2 (GMRES estimate); points not converged after
+ *     the last cycle latch BTE_ENOCONV, bte_get_status then reports the largest
+ *     iteration count over the points and the largest relative residual estimate.
+ * The adjoint step always factors (it needs the transposed solves).
+ * Synchronous (factors the bins).  Errors: BTE_EINVAL, BTE_ESINGULAR, BTE_ENOMEM, BTE_EHIP. */
+typedef enum { BTE_VSOLVER_LU = 0, BTE_VSOLVER_GMRES = 1 } bte_vsolver;
+bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E_bound, double bin_scale,
+                           int32_t restart, int32_t cycles, double rtol, int32_t factor_precision);
+
 /* Captures n_steps consecutive steps of F (times t0_s + k dt, k = 0..n_steps-1,
  * the same launches as bte_step) into a HIP graph owned by the handle,
  * replacing a previously captured one; nothing runs at capture.  The graph

@@ -41,6 +41,8 @@ class bte_info(C.Structure):
                 ("q_bytes_per_half_step", C.c_double)]
 
 
+VSOLVER_LU = 0
+VSOLVER_GMRES = 1
 TUNE_LU_STREAMS = 0
 TUNE_UPDATE_KC = 1
 TUNE_FORM_XPB = 2
@@ -68,6 +70,8 @@ EXPORTS = {
     "bte_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "bte_graph_capture": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, bte_field]),
     "bte_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "bte_set_vsolver": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                  C.c_double, C.c_int32]),
     "bte_get_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "bte_destroy": (None, [C.c_void_p]),
     "bte_status_string": (C.c_char_p, [C.c_int]),

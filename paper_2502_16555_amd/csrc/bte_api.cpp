@@ -38,6 +38,7 @@ struct bte_handle {
   bte::HostOps host;
   DevOps d;
   std::vector<int> nx_per, x_off;
+  std::vector<double> n0_host, E0_host;   // per discharge
   std::vector<void*> allocs;
   hipStream_t last_stream = nullptr;
   int refine_max_iter = 10;
@@ -56,6 +57,30 @@ struct bte_handle {
   std::vector<hipEvent_t> lu_ev;   // kMaxLuStreams * 4 * max_panels
   bte::LuTimer lu_timer[kMaxLuStreams];
   double ms_acc[6] = {0, 0, 0, 0, 0, 0};
+  // Krylov V solver (bte_set_vsolver): factors of the field-binned
+  // preconditioner (a DevOps over nd * nbins matrices) and the GMRES workspace
+  bool krylov = false;
+  int krylov_cycles = 2;
+  int krylov_prec = 0;         // precision of the bin factors (0 FP64, 1 FP32)
+  DevOps kf;
+  bte::GmresOps kq;
+  std::vector<void*> kallocs;
+  void drop_krylov() {
+    for (void* p : kallocs) (void)hipFree(p);
+    kallocs.clear();
+    krylov = false;
+  }
+  template <typename T>
+  T* kalloc(size_t count) {
+    void* p = nullptr;
+    const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) throw HipError(e, "hipMalloc");
+    kallocs.push_back(p);
+    e = hipMemset(p, 0, b);
+    if (e != hipSuccess) throw HipError(e, "hipMemset");
+    return static_cast<T*>(p);
+  }
   // captured run of steps (bte_graph_capture / bte_graph_launch)
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -99,6 +124,7 @@ struct bte_handle {
     for (auto& q : gs)
       if (q) (void)hipStreamDestroy(q);
     drop_graph();
+    drop_krylov();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocs) (void)hipFree(p);
   }
@@ -198,6 +224,8 @@ void fill_devops(bte_handle* h) {
   std::vector<int> x_disc(d.nx_total);
   std::vector<double> xhat(d.nx_total), n0x(d.nx_total);
   std::vector<double> n0(c.n0_per, c.n0_per + nd), E0(c.E0_per, c.E0_per + nd);
+  h->n0_host = n0;
+  h->E0_host = E0;
   for (int i = 0; i < nd; ++i)
     for (int j = 0; j < h->nx_per[i]; ++j) {
       const int x = h->x_off[i] + j;
@@ -325,10 +353,42 @@ void factor_all(bte_handle* h, hipStream_t s) {
   }
 }
 
+// V(dt) by the batched restarted GMRES with the field-binned preconditioner.
+void v_solve_krylov(bte_handle* h, double* F, hipStream_t s) {
+  DevOps& d = h->d;
+  const bte::GmresOps& q = h->kq;
+  const int nxt = d.nx_total;
+  const size_t vs = static_cast<size_t>(nxt) * d.npad;
+  bte::launch_pad_rows(d, F, d.B, s);
+  bte::launch_bin_map(d, q, s);
+  // initial guess x0 = H b
+  bte::launch_lu_solve_mapped(h->kf, h->krylov_prec, false, q.mat_of, nullptr, nxt, d.B, d.X, false, false, s);
+  for (int cyc = 0; cyc < h->krylov_cycles; ++cyc) {
+    bte::launch_apply(d, 1, d.B, d.X, q.R, s);                  // R = B - M X
+    bte::launch_gmres_init(d, q, cyc == 0, s);
+    for (int j = 0; j < q.m; ++j) {
+      bte::launch_lu_solve_mapped(h->kf, h->krylov_prec, false, q.mat_of, q.conv, nxt, q.V + j * vs, q.Z, false,
+                                  false, s);                      // z = H v_j
+      bte::launch_apply(d, 2, nullptr, q.Z, q.W, s);             // w = M z
+      bte::launch_gmres_arnoldi(d, q, j, s);
+    }
+    bte::launch_gmres_combine(d, q, s);                          // Z = V y
+    bte::launch_lu_solve_mapped(h->kf, h->krylov_prec, false, q.mat_of, q.inact, nxt, q.Z, d.X, true, false, s);
+  }
+  bte::launch_gmres_status(d, q, s);
+  bte::launch_unpad_rows(d, d.X, F, s);
+}
+
 // V(dt) in place on F (field already in d.E).  transpose: solve with A^T.
-void v_solve(bte_handle* h, double* F, bool transpose, hipStream_t s) {
+// The forward step takes the Krylov solver when one is configured; the
+// adjoint (transpose, and its forward recomputation) always factors.
+void v_solve(bte_handle* h, double* F, bool transpose, hipStream_t s, bool allow_krylov = false) {
   DevOps& d = h->d;
   const int prec = h->cfg.precision;
+  if (allow_krylov && h->krylov && !transpose) {
+    v_solve_krylov(h, F, s);
+    return;
+  }
   bte::launch_pad_rows(d, F, d.B, s);
   factor_all(h, s);
   bte::launch_lu_solve(d, prec, transpose, d.B, d.X, false, false, s);
@@ -468,7 +528,7 @@ bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void*
     x_half(h, F, false, s);
     eval_field(h, F, t_s, field, s);
     if (h->timing) HIP_OK(hipEventRecord(h->ev[1], s));
-    v_solve(h, F, false, s);
+    v_solve(h, F, false, s, true);
     if (h->timing) HIP_OK(hipEventRecord(h->ev[2], s));
     x_half(h, F, false, s);
     if (h->timing) {
@@ -518,7 +578,7 @@ bte_status bte_graph_capture(bte_handle* h, double* F, double t0_s, int32_t n_st
         const double t = t0_s + k * h->cfg.dt_s;
         x_half(h, F, false, c);
         eval_field(h, F, t, field, c);
-        v_solve(h, F, false, c);
+        v_solve(h, F, false, c, true);
         x_half(h, F, false, c);
       }
     } catch (...) {
@@ -583,7 +643,7 @@ bte_status bte_vstep(bte_handle* h, double* F, const double* E, void* stream) {
     hipStream_t s = S(stream);
     h->last_stream = s;
     HIP_OK(hipMemcpyAsync(h->d.E, E, sizeof(double) * h->d.nx_total, hipMemcpyDeviceToDevice, s));
-    v_solve(h, F, false, s);
+    v_solve(h, F, false, s, true);
     HIP_OK(hipGetLastError());
     return BTE_OK;
   } catch (const std::exception& e) {
@@ -714,6 +774,101 @@ bte_status bte_set_timing(bte_handle* h, int32_t enable) {
   h->timing = enable != 0;
   std::fill(std::begin(h->ms_acc), std::end(h->ms_acc), 0.0);
   return BTE_OK;
+}
+
+bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E_bound, double bin_scale,
+                           int32_t restart, int32_t cycles, double rtol, int32_t factor_precision) {
+  if (!h) return BTE_EINVAL;
+  if (kind == BTE_VSOLVER_LU) {
+    h->drop_krylov();
+    return BTE_OK;
+  }
+  if (kind != BTE_VSOLVER_GMRES || n_bins < 1 || n_bins > 4096 || restart < 1 || restart > 63 || cycles < 1 ||
+      cycles > 100 || !(rtol > 0.0) || bin_scale < 0.0 ||
+      (factor_precision != BTE_FP64 && factor_precision != BTE_MIXED_FP32))
+    return BTE_EINVAL;
+  const bte_config& c = h->cfg;
+  double bound = E_bound;
+  if (!(bound > 0.0)) {
+    if (c.field_mode != BTE_FIELD_CONST && c.field_mode != BTE_FIELD_RF) return BTE_EINVAL;
+    bound = 0.0;
+    for (double e0 : h->E0_host) bound = std::max(bound, std::fabs(e0) * (1.0 + std::fabs(c.field_a1)));
+    if (!(bound > 0.0)) bound = 1.0;
+  }
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    HIP_OK(hipDeviceSynchronize());
+    h->drop_krylov();
+    const DevOps& d = h->d;
+    const int nd = d.nd, nb = n_bins, nmat = nd * nb;
+    const size_t elt = (factor_precision == BTE_FP64) ? sizeof(double) : sizeof(float);
+    // bin matrices: I - dt (n0_d C + s_p A), s_p the centre of bin p
+    DevOps f = d;
+    f.nx_total = nmat;
+    // bins uniform in u = E, or in u = asinh(E / bin_scale); centres mapped back
+    std::vector<double> Eb(nmat), n0b(nmat);
+    const double ub = bin_scale > 0.0 ? std::asinh(bound / bin_scale) : bound;
+    const double width = 2.0 * ub / nb;
+    for (int di = 0; di < nd; ++di)
+      for (int p = 0; p < nb; ++p) {
+        const double uc = -ub + (p + 0.5) * width;
+        Eb[di * nb + p] = bin_scale > 0.0 ? bin_scale * std::sinh(uc) : uc;
+        n0b[di * nb + p] = h->n0_host[di];
+      }
+    f.E = h->kalloc<double>(nmat);
+    f.n0x = h->kalloc<double>(nmat);
+    HIP_OK(hipMemcpy(f.E, Eb.data(), nmat * sizeof(double), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(f.n0x, n0b.data(), nmat * sizeof(double), hipMemcpyHostToDevice));
+    f.lu = h->kalloc<char>(static_cast<size_t>(nmat) * d.npad * d.npad * elt);
+    f.xscr = h->kalloc<char>(static_cast<size_t>(nmat) * d.npad * bte::kNB * elt);
+    f.linv = h->kalloc<char>(static_cast<size_t>(nmat) * 8 * 256 * elt);
+    f.piv = h->kalloc<int>(static_cast<size_t>(nmat) * d.npad);
+    f.perm = h->kalloc<int>(static_cast<size_t>(nmat) * (2 * bte::kMaxSwapRows + 1));
+    f.precision = factor_precision;
+    f.update_kc = 0;
+    f.form_xpb = 0;
+    bte::launch_lu_factor(f, factor_precision, nullptr);
+    HIP_OK(hipDeviceSynchronize());
+    int st = 0;
+    HIP_OK(hipMemcpy(&st, d.status, sizeof(int), hipMemcpyDeviceToHost));
+    if (st & bte::kStSingular) {
+      const int zero = 0;
+      HIP_OK(hipMemcpy(d.status, &zero, sizeof(int), hipMemcpyHostToDevice));
+      h->drop_krylov();
+      return BTE_ESINGULAR;
+    }
+    bte::GmresOps q;
+    q.m = restart;
+    q.nbins = nb;
+    q.S0 = -ub;
+    q.width = width;
+    q.scale = bin_scale;
+    q.rtol = rtol;
+    const size_t nxt = d.nx_total, np = d.npad;
+    q.mat_of = h->kalloc<int>(nxt);
+    q.V = h->kalloc<double>((restart + 1) * nxt * np);
+    q.W = h->kalloc<double>(nxt * np);
+    q.Z = h->kalloc<double>(nxt * np);
+    q.R = h->kalloc<double>(nxt * np);
+    q.H = h->kalloc<double>(nxt * restart * (restart + 1));
+    q.cs = h->kalloc<double>(nxt * restart);
+    q.sn = h->kalloc<double>(nxt * restart);
+    q.g = h->kalloc<double>(nxt * (restart + 1));
+    q.bnorm = h->kalloc<double>(nxt);
+    q.conv = h->kalloc<int>(nxt);
+    q.inact = h->kalloc<int>(nxt);
+    q.kcount = h->kalloc<int>(nxt);
+    q.ktot = h->kalloc<int>(nxt);
+    h->kf = f;
+    h->kq = q;
+    h->krylov_prec = factor_precision == BTE_FP64 ? 0 : 1;
+    h->krylov_cycles = cycles;
+    h->krylov = true;
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    h->drop_krylov();
+    return map_exc(e);
+  }
 }
 
 bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value) {

@@ -74,6 +74,35 @@ struct DevOps {
   double* scratch3 = nullptr;  // [3*nx_total] moments scratch
 };
 
+// Batched restarted GMRES of the V step (kernels_gmres.hip): workspace of the
+// Krylov solver and the field-binned preconditioner.
+struct GmresOps {
+  int m = 20;                  // restart length (<= 63)
+  int nbins = 0;               // field bins per discharge
+  double S0 = 0.0, width = 1.0;  // bin p covers u in [S0 + p width, S0 + (p+1) width)
+  double scale = 0.0;          // u = E (0) or asinh(E / scale) (bins graded towards E = 0)
+  double rtol = 1e-12;         // ||b - M x||_2 <= rtol ||b||_2 per point
+  int* mat_of = nullptr;       // [nx_total] factor set of the point's bin
+  double* V = nullptr;         // [m+1][nx_total][npad] Krylov basis
+  double* W = nullptr;         // [nx_total][npad]
+  double* Z = nullptr;         // [nx_total][npad]
+  double* R = nullptr;         // [nx_total][npad]
+  double* H = nullptr;         // [nx_total][m][m+1] Hessenberg columns (rotated)
+  double* cs = nullptr;        // [nx_total][m]
+  double* sn = nullptr;        // [nx_total][m]
+  double* g = nullptr;         // [nx_total][m+1]
+  double* bnorm = nullptr;     // [nx_total]
+  int* conv = nullptr;         // [nx_total] converged
+  int* inact = nullptr;        // [nx_total] converged before the current cycle
+  int* kcount = nullptr;       // [nx_total] basis vectors of the current cycle
+  int* ktot = nullptr;         // [nx_total] iterations of the current step
+};
+void launch_bin_map(const DevOps& d, const GmresOps& q, hipStream_t s);
+void launch_gmres_init(const DevOps& d, const GmresOps& q, bool first, hipStream_t s);
+void launch_gmres_arnoldi(const DevOps& d, const GmresOps& q, int j, hipStream_t s);
+void launch_gmres_combine(const DevOps& d, const GmresOps& q, hipStream_t s);
+void launch_gmres_status(const DevOps& d, const GmresOps& q, hipStream_t s);
+
 // ---- X step (kernels_x.hip) -------------------------------------------------
 void launch_x_to_modes(const DevOps& d, const double* F, hipStream_t s);
 void launch_advect(const DevOps& d, bool fp32, bool transpose, hipStream_t s);
@@ -105,11 +134,19 @@ void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* ti
 // X = LU^-1 B (or LU^-T B with transpose), rows of length npad, FP64 right-hand sides.
 void launch_lu_solve(const DevOps& d, int precision, bool transpose, const double* Bin, double* Xout,
                      bool accumulate, bool check_done, hipStream_t s);
+// As launch_lu_solve for nrows right-hand sides, row r solved with the factors
+// of matrix mat_of[r] of f (mat_of NULL: matrix r); rows with skip[r] != 0 are
+// left untouched (skip may be NULL).
+void launch_lu_solve_mapped(const DevOps& f, int precision, bool transpose, const int* mat_of, const int* skip,
+                            int nrows, const double* Bin, double* Xout, bool accumulate, bool check_done,
+                            hipStream_t s);
 // Copy F (rows of n) into padded rows of npad and back.
 void launch_pad_rows(const DevOps& d, const double* F, double* Bp, hipStream_t s);
 void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t s);
 // FP64 residual R = B - (I - dt (n0 C + E A)) X (or with A^T for transpose) + per-x norms.
 void launch_residual(const DevOps& d, bool transpose, hipStream_t s);
+// Operator M = I - dt (n0 C + E A) on padded rows: mode 1: R = B - M X; mode 2: R = M X.
+void launch_apply(const DevOps& d, int mode, const double* B, const double* X, double* R, hipStream_t s);
 void launch_refine_check(const DevOps& d, bool transpose, double rtol, int sweep, bool final_sweep, hipStream_t s);
 void launch_reset_refine(const DevOps& d, hipStream_t s);
 // p[0..n) = v (a kernel, so that captured graphs hold no memset nodes).

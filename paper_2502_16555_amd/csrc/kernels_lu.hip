@@ -828,17 +828,22 @@ template <typename T, int TRANSPOSE>
 __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const int* __restrict__ piv,
                                                 const double* __restrict__ Bin, double* __restrict__ Xout,
                                                 const int* __restrict__ status, int accumulate, int check_done,
-                                                int npad) {
+                                                int npad, const int* __restrict__ mat_of,
+                                                const int* __restrict__ skip) {
   if (check_done && status[1]) return;
+  // right-hand side / solution row: the block; factors: that row's own matrix,
+  // or the one mat_of names (a shared factorization, e.g. a preconditioner bin)
+  const int row = blockIdx.x;
+  if (skip && skip[row]) return;
   __shared__ double sb[kMaxRows];
   __shared__ int s_ip[kMaxRows];  // the pivots, staged once (the swaps read them serially)
   __shared__ T sD[NB][NB + 1];
-  const int mat = blockIdx.x;
+  const int mat = mat_of ? mat_of[row] : row;
   const T* A = LU + (size_t)mat * npad * npad;
   const int* ip = piv + (size_t)mat * npad;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NWV = 1024 / 64;
-  const double* b = Bin + (size_t)mat * npad;
+  const double* b = Bin + (size_t)row * npad;
   for (int i = tid; i < npad; i += 1024) {
     sb[i] = b[i];
     s_ip[i] = ip[i];
@@ -976,7 +981,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       __syncthreads();
     }
   }
-  double* xo = Xout + (size_t)mat * npad;
+  double* xo = Xout + (size_t)row * npad;
   for (int i = tid; i < npad; i += 1024) xo[i] = accumulate ? xo[i] + sb[i] : sb[i];
 }
 
@@ -1047,14 +1052,24 @@ void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* ti
 
 void launch_lu_solve(const DevOps& d, int precision, bool transpose, const double* Bin, double* Xout, bool accumulate,
                      bool check_done, hipStream_t s) {
+  launch_lu_solve_mapped(d, precision, transpose, nullptr, nullptr, d.nx_total, Bin, Xout, accumulate, check_done, s);
+}
+
+void launch_lu_solve_mapped(const DevOps& f, int precision, bool transpose, const int* mat_of, const int* skip,
+                            int nrows, const double* Bin, double* Xout, bool accumulate, bool check_done,
+                            hipStream_t s) {
   if (precision == 0) {
-    const double* LU = static_cast<const double*>(d.lu);
-    if (transpose) k_solve<double, 1><<<d.nx_total, 1024, 0, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
-    else k_solve<double, 0><<<d.nx_total, 1024, 0, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
+    const double* LU = static_cast<const double*>(f.lu);
+    if (transpose)
+      k_solve<double, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+    else
+      k_solve<double, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
   } else {
-    const float* LU = static_cast<const float*>(d.lu);
-    if (transpose) k_solve<float, 1><<<d.nx_total, 1024, 0, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
-    else k_solve<float, 0><<<d.nx_total, 1024, 0, s>>>(LU, d.piv, Bin, Xout, d.status, accumulate, check_done, d.npad);
+    const float* LU = static_cast<const float*>(f.lu);
+    if (transpose)
+      k_solve<float, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+    else
+      k_solve<float, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
   }
 }
 

@@ -38,7 +38,10 @@ __global__ void k_unpad(const double* __restrict__ Bp, double* __restrict__ F, i
 // FP64 residual R = B - X + dt n0_x (X C^T) + dt E_x (X A^T)  (TRANSPOSE: C, A)
 // rows = collocation points, 32 x 64 output tiles, MFMA f64 16x16x4.
 // ---------------------------------------------------------------------------
-template <int TRANSPOSE>
+// MODE 0: the refinement residual above, with the per-point maxima (skipped once
+// the refinement is done); MODE 1: R = B - M X only; MODE 2: R = M X (operator
+// action of Alg. vspace_action, for the Krylov solver).
+template <int TRANSPOSE, int MODE = 0>
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv, const double* __restrict__ Xv,
                                                   double* __restrict__ Rv, const double* __restrict__ C,
                                                   const double* __restrict__ Aop, const double* __restrict__ E,
@@ -46,7 +49,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
                                                   unsigned long long* __restrict__ bmax,
                                                   unsigned long long* __restrict__ xmax, const int* __restrict__ status,
                                                   double dt, int n, int npad, int nx) {
-  if (status[1]) return;
+  if (MODE == 0 && status[1]) return;
   constexpr int BM = 32, BN = 64, BK = 64;
   constexpr int LX = BM * BK / 256, LO = BN * BK / 256;  // loads per thread and tile
   __shared__ double sX[BM][BK + 1];
@@ -131,6 +134,14 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
       const int x = x0 + xl;
       const int i = i0 + w * 16 + li;
       unsigned long long rb = 0ull, bb = 0ull, xb = 0ull;
+      if (MODE != 0) {
+        if (x < nx && i < n) {
+          const size_t o = (size_t)x * npad + i;
+          const double mx = Xv[o] - dt * n0x[x] * accC[b][it] - dt * E[x] * accA[b][it];
+          Rv[o] = (MODE == 1) ? Bv[o] - mx : mx;
+        }
+        continue;
+      }
       if (x < nx && i < n) {
         const size_t o = (size_t)x * npad + i;
         const double bv = Bv[o], xv = Xv[o];
@@ -153,6 +164,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
         s_xm[w][xl] = xb;
       }
     }
+  if (MODE != 0) return;
   __syncthreads();
   if (tid < BM && x0 + tid < nx) {
     unsigned long long rb = 0ull, bb = 0ull, xb = 0ull;
@@ -292,6 +304,16 @@ void launch_pad_rows(const DevOps& d, const double* F, double* Bp, hipStream_t s
 
 void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t s) {
   k_unpad<<<1024, 256, 0, s>>>(Bp, F, d.n, d.npad, d.nx_total);
+}
+
+void launch_apply(const DevOps& d, int mode, const double* B, const double* X, double* R, hipStream_t s) {
+  dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32);
+  if (mode == 1)
+    k_residual<0, 1><<<g, 256, 0, s>>>(B, X, R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
+                                       d.n, d.npad, d.nx_total);
+  else
+    k_residual<0, 2><<<g, 256, 0, s>>>(B, X, R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
+                                       d.n, d.npad, d.nx_total);
 }
 
 void launch_residual(const DevOps& d, bool transpose, hipStream_t s) {

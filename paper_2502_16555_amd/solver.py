@@ -129,6 +129,15 @@ class Solver:
     def step(self, F, t, E_half=None, ni=None, stream=None):
         check(self.lib.bte_step(self.h, _ptr(F), float(t), self._field(E_half, ni), _stream(stream)), "bte_step")
 
+    def set_vsolver(self, kind: str = "lu", n_bins: int = 32, E_bound: float = 0.0, bin_scale: float = 0.0,
+                    restart: int = 20, cycles: int = 2, rtol: float = 1e-12, factor_precision: str = "mixed_fp32"):
+        """Select the velocity-space solver: "lu" (batched factorization) or "gmres"
+        (restarted GMRES with the field-binned preconditioner, factored here)."""
+        k = {"lu": _lib.VSOLVER_LU, "gmres": _lib.VSOLVER_GMRES}[kind]
+        check(self.lib.bte_set_vsolver(self.h, k, int(n_bins), float(E_bound), float(bin_scale), int(restart),
+                                       int(cycles), float(rtol), _lib.PRECISION[factor_precision]),
+              "bte_set_vsolver")
+
     def graph_capture(self, F, t0, n_steps, E_half=None, ni=None):
         """Capture n_steps steps of F from t0 into the handle's HIP graph (nothing runs)."""
         check(self.lib.bte_graph_capture(self.h, _ptr(F), float(t0), int(n_steps), self._field(E_half, ni)),

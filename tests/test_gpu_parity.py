@@ -540,3 +540,54 @@ def test_autotuned_shapes_leave_results_unchanged(torch, tmp_path):
                 assert s.status()[0] == 0
                 assert np.array_equal(Fb.cpu().numpy(), Fa.cpu().numpy()), (prec, kc, xpb)
         s.close()
+
+
+@pytest.mark.parametrize("fprec", ["fp64", "mixed_fp32"])
+@pytest.mark.parametrize("case", ["ragged", "panels", "panels4"])
+def test_krylov_vstep_matches_oracle(torch, case, fprec):
+    """Batched GMRES with the field-binned preconditioner (bin factors in FP64
+    or FP32) against the oracle's direct solves: the GMRES stop at
+    ||r|| <= 1e-13 ||b|| bounds the error by cond * 1e-13."""
+    cfg = CASES[case]()
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg, precision="fp64")
+    s.set_vsolver("gmres", n_bins=32, E_bound=1.5e4, restart=30, cycles=3, rtol=1e-13, factor_precision=fprec)
+    F = _state(ops, 3)
+    rng = np.random.default_rng(4)
+    E = rng.uniform(-1.5e4, 1.5e4, size=ops.nx)
+    E[0] = 1.6e4                       # outside the bound: the end bin
+    Fg = cuda(torch, F)
+    s.vstep(Fg, cuda(torch, E))
+    code, iters, resid = s.status()
+    assert code == 0 and 1 <= iters <= 90 and resid <= 1e-13, (code, iters, resid)
+    close(Fg.cpu().numpy(), S.v_step(ops, F, E), 1e-10, f"{case} gmres {fprec}")
+    s.close()
+
+
+def test_krylov_steps_ensemble_and_graph(torch):
+    """Full RF steps of an uneven ensemble with the Krylov V solver against the
+    oracle per discharge, and a captured run of them against the eager steps."""
+    cfg, members = _ensemble_case()
+    ops = [oracle.build_operators(m) for m in members]
+    F0 = [S.initial_state(o, workloads.density_profile(o.xhat, 1e16), 1.0) for o in ops]
+    s = solver(cfg, precision="mixed_fp32")
+    s.set_vsolver("gmres", n_bins=32, restart=30, cycles=2, rtol=1e-13)
+    t0 = 0.2 * cfg["T_rf_s"]
+    F = cuda(torch, np.concatenate(F0))
+    Fg = cuda(torch, np.concatenate(F0))
+    ref = list(F0)
+    for k in range(3):
+        s.step(F, t0 + k * cfg["dt_s"])
+        ref = [S.step(o, r, t0 + k * cfg["dt_s"]) for o, r in zip(ops, ref)]
+    assert s.status()[0] == 0
+    got = F.cpu().numpy()
+    o = 0
+    for d, r in enumerate(ref):
+        close(got[o:o + r.shape[0]], r, 1e-10, f"discharge {d} gmres")
+        o += r.shape[0]
+    s.graph_capture(Fg, t0, 3)
+    s.graph_launch()
+    torch.cuda.synchronize()
+    assert s.status()[0] == 0
+    assert np.array_equal(Fg.cpu().numpy(), got)
+    s.close()
