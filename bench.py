@@ -36,10 +36,15 @@ def _update_flops(npad: int, nb: int, nmat: int) -> float:
     return tot * nmat
 
 
-def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=False):
+KRYLOV = dict(n_bins=128, bin_scale=100.0, restart=12, cycles=3, rtol=1e-12, factor_precision="mixed_fp32")
+
+
+def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=False, krylov=False):
     from paper_2502_16555_amd import Solver, _lib
     t0 = time.time()
     s = Solver(cfg, precision=precision)
+    if krylov:
+        s.set_vsolver("gmres", **KRYLOV)
     setup_s = time.time() - t0
     if lu_streams is not None:
         s.set_tuning(_lib.TUNE_LU_STREAMS, lu_streams)
@@ -213,6 +218,7 @@ def main():
     ap.add_argument("--lu-streams", type=int, default=None, help="concurrent factorization groups (library default 1)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
     ap.add_argument("--ensemble", action="store_true", help="also time the 64-discharge batching form")
+    ap.add_argument("--no-krylov", action="store_true", help="skip the GMRES V-solver leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hot path is single-GPU in this build",
@@ -271,6 +277,16 @@ def main():
         line["accuracy"] = {
             "mixed_vs_fp64_gpu": dict(moment_errors(main_run["moments"], fp64["moments"]),
                                       steps=main_run["n_end"])}
+    if not args.no_krylov:
+        kr = run_gpu(cfg, "fp64", args.steps, warm, torch, args.lu_streams, krylov=True)
+        line["krylov"] = {"solver": "restarted GMRES per point, FP64, field-binned preconditioner "
+                                    "(Alg. vspace_action_precon) with FP32 bin factors",
+                          "settings": KRYLOV, "steps_per_s": 1000.0 / kr["ms_per_step"],
+                          "ms_per_step": kr["ms_per_step"], "iterations_last_step": kr["refine_sweeps"],
+                          "resid_estimate": kr["refine_resid"]}
+        if fp64 is not None:
+            line["krylov"]["speedup_over_fp64_lu"] = fp64["ms_per_step"] / kr["ms_per_step"]
+            line["krylov"]["vs_fp64_lu"] = dict(moment_errors(kr["moments"], fp64["moments"]), steps=kr["n_end"])
     if not args.no_adjoint:
         line["adjoint"] = run_adjoint(torch)
     if args.ensemble:

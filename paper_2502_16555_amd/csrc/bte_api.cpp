@@ -281,7 +281,7 @@ void fill_devops(bte_handle* h) {
   d.xscr = h->alloc<char>(nxt * d.npad * bte::kNB * elt);
   d.linv = h->alloc<char>(nxt * 8 * 256 * elt);
   d.piv = h->alloc<int>(nxt * d.npad);
-  d.perm = h->alloc<int>(nxt * (2 * bte::kMaxSwapRows + 1));
+  d.perm = h->alloc<int>(nxt * bte::kMaxPanels * bte::kPermStride);
   d.E = h->alloc<double>(nxt);
   d.B = h->alloc<double>(nxt * d.npad);
   d.X = h->alloc<double>(nxt * d.npad);
@@ -364,12 +364,12 @@ void v_solve_krylov(bte_handle* h, double* F, hipStream_t s) {
   // initial guess x0 = H b
   bte::launch_lu_solve_mapped(h->kf, h->krylov_prec, false, q.mat_of, nullptr, nxt, d.B, d.X, false, false, s);
   for (int cyc = 0; cyc < h->krylov_cycles; ++cyc) {
-    bte::launch_apply(d, 1, d.B, d.X, q.R, s);                  // R = B - M X
+    bte::launch_apply(d, 1, d.B, d.X, q.R, cyc == 0 ? nullptr : q.conv, s);   // R = B - M X
     bte::launch_gmres_init(d, q, cyc == 0, s);
     for (int j = 0; j < q.m; ++j) {
       bte::launch_lu_solve_mapped(h->kf, h->krylov_prec, false, q.mat_of, q.conv, nxt, q.V + j * vs, q.Z, false,
                                   false, s);                      // z = H v_j
-      bte::launch_apply(d, 2, nullptr, q.Z, q.W, s);             // w = M z
+      bte::launch_apply(d, 2, nullptr, q.Z, q.W, q.conv, s);     // w = M z
       bte::launch_gmres_arnoldi(d, q, j, s);
     }
     bte::launch_gmres_combine(d, q, s);                          // Z = V y
@@ -823,7 +823,7 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
     f.xscr = h->kalloc<char>(static_cast<size_t>(nmat) * d.npad * bte::kNB * elt);
     f.linv = h->kalloc<char>(static_cast<size_t>(nmat) * 8 * 256 * elt);
     f.piv = h->kalloc<int>(static_cast<size_t>(nmat) * d.npad);
-    f.perm = h->kalloc<int>(static_cast<size_t>(nmat) * (2 * bte::kMaxSwapRows + 1));
+    f.perm = h->kalloc<int>(static_cast<size_t>(nmat) * bte::kMaxPanels * bte::kPermStride);
     f.precision = factor_precision;
     f.update_kc = 0;
     f.form_xpb = 0;
@@ -859,6 +859,7 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
     q.inact = h->kalloc<int>(nxt);
     q.kcount = h->kalloc<int>(nxt);
     q.ktot = h->kalloc<int>(nxt);
+    q.rest = h->kalloc<double>(nxt);
     h->kf = f;
     h->kq = q;
     h->krylov_prec = factor_precision == BTE_FP64 ? 0 : 1;

@@ -16,6 +16,8 @@ constexpr int kNB = 128;
 constexpr int kPanelThreads = 512;
 constexpr int kMaxSwapRows = 2 * kNB;   // rows touched by one panel's interchanges
 constexpr int kMaxRows = 2048;          // largest padded system (n = Nr * Ntheta <= 2048)
+constexpr int kMaxPanels = kMaxRows / kNB;
+constexpr int kPermStride = 1 + 2 * kMaxSwapRows;  // one panel's row permutation: nR, rows, sources
 
 // Device status word bits.
 enum : int { kStSingular = 1, kStNoConv = 2, kStNonFinite = 4 };
@@ -56,7 +58,7 @@ struct DevOps {
   void* xscr = nullptr;        // [nx_total][npad][kNB] of T: interchange staging of extra rows
   void* linv = nullptr;        // [nx_total][8][16][16] of T: inverses of the diagonal blocks of L11
   int* piv = nullptr;          // [nx_total][npad]
-  int* perm = nullptr;         // [nx_total][2*kMaxSwapRows] row list / source list of one panel
+  int* perm = nullptr;         // [nx_total][kMaxPanels][kPermStride] row permutation of every panel
   double* E = nullptr;         // [nx_total]
   double* B = nullptr;         // [nx_total][npad] right-hand side copy
   double* X = nullptr;         // [nx_total][npad] solution (mixed refinement)
@@ -96,6 +98,7 @@ struct GmresOps {
   int* inact = nullptr;        // [nx_total] converged before the current cycle
   int* kcount = nullptr;       // [nx_total] basis vectors of the current cycle
   int* ktot = nullptr;         // [nx_total] iterations of the current step
+  double* rest = nullptr;      // [nx_total] last relative residual estimate
 };
 void launch_bin_map(const DevOps& d, const GmresOps& q, hipStream_t s);
 void launch_gmres_init(const DevOps& d, const GmresOps& q, bool first, hipStream_t s);
@@ -146,7 +149,9 @@ void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t
 // FP64 residual R = B - (I - dt (n0 C + E A)) X (or with A^T for transpose) + per-x norms.
 void launch_residual(const DevOps& d, bool transpose, hipStream_t s);
 // Operator M = I - dt (n0 C + E A) on padded rows: mode 1: R = B - M X; mode 2: R = M X.
-void launch_apply(const DevOps& d, int mode, const double* B, const double* X, double* R, hipStream_t s);
+// Tiles of 32 points that all have skip[x] != 0 are left out (skip may be NULL).
+void launch_apply(const DevOps& d, int mode, const double* B, const double* X, double* R, const int* skip,
+                  hipStream_t s);
 void launch_refine_check(const DevOps& d, bool transpose, double rtol, int sweep, bool final_sweep, hipStream_t s);
 void launch_reset_refine(const DevOps& d, hipStream_t s);
 // p[0..n) = v (a kernel, so that captured graphs hold no memset nodes).

@@ -56,8 +56,8 @@ __global__ __launch_bounds__(kThreads) void k_gmres_init(const double* __restric
                                                          double* __restrict__ V0, double* __restrict__ g,
                                                          double* __restrict__ bnorm, int* __restrict__ conv,
                                                          int* __restrict__ inact, int* __restrict__ kcount,
-                                                         int* __restrict__ ktot, double rtol, int first, int npad,
-                                                         int m) {
+                                                         int* __restrict__ ktot, double* __restrict__ rest,
+                                                         double rtol, int first, int npad, int m) {
   __shared__ double red[kThreads / 64];
   const int x = blockIdx.x, tid = threadIdx.x;
   const double* r = R + (size_t)x * npad;
@@ -79,11 +79,14 @@ __global__ __launch_bounds__(kThreads) void k_gmres_init(const double* __restric
   }
   __syncthreads();
   const double ref = first ? bn : bnorm[x];
-  const bool done = (first ? 0 : conv[x]) || !(beta > rtol * ref);
+  const bool before = first ? false : (conv[x] != 0);   // converged in an earlier cycle
+  const bool done = before || !(beta > rtol * ref);
   if (tid == 0) {
     conv[x] = done ? 1 : 0;
     inact[x] = done ? 1 : 0;
     g[(size_t)x * (m + 1)] = beta;
+    // residual estimate: only points taking part (R is not formed for the others)
+    if (!before) rest[x] = beta / (ref > 0.0 ? ref : 1.0);
   }
   const double inv = (beta > 0.0) ? 1.0 / beta : 0.0;
   double* v = V0 + (size_t)x * npad;
@@ -98,7 +101,8 @@ __global__ __launch_bounds__(kThreads) void k_gmres_arnoldi(double* __restrict__
                                                             double* __restrict__ sn, double* __restrict__ g,
                                                             const double* __restrict__ bnorm, int* __restrict__ conv,
                                                             int* __restrict__ kcount, int* __restrict__ ktot,
-                                                            double rtol, int j, int nxt, int npad, int m) {
+                                                            double* __restrict__ rest, double rtol, int j, int nxt,
+                                                            int npad, int m) {
   const int x = blockIdx.x, tid = threadIdx.x;
   if (conv[x]) return;
   __shared__ double red[kThreads / 64];
@@ -150,6 +154,7 @@ __global__ __launch_bounds__(kThreads) void k_gmres_arnoldi(double* __restrict__
     gx[j + 1] = -sj * gj;
     kcount[x] = j + 1;
     ktot[x] += 1;
+    rest[x] = fabs(gx[j + 1]) / (bnorm[x] > 0.0 ? bnorm[x] : 1.0);
     if (!(fabs(gx[j + 1]) > rtol * bnorm[x]) || hn == 0.0) conv[x] = 1;
   }
 }
@@ -186,13 +191,11 @@ __global__ __launch_bounds__(kThreads) void k_gmres_combine(const double* __rest
 }
 
 // Status: any point not converged after the last cycle -> no convergence (a
-// non-finite estimate -> non-finite); resid[0] = max_x |g_k| / ||b||, the
-// residual estimate of the point's last iteration, status[2] = the largest
-// iteration count over the points.
-__global__ void k_gmres_status(const int* __restrict__ conv, const int* __restrict__ kcount,
-                               const int* __restrict__ ktot, const double* __restrict__ g,
-                               const double* __restrict__ bnorm, int* __restrict__ status, double* __restrict__ resid,
-                               int nx, int m) {
+// non-finite estimate -> non-finite); resid[0] = max_x of the points' last
+// relative residual estimates, status[2] = the largest iteration count.
+__global__ void k_gmres_status(const int* __restrict__ conv, const int* __restrict__ ktot,
+                               const double* __restrict__ rest, int* __restrict__ status, double* __restrict__ resid,
+                               int nx) {
   __shared__ double red[256];
   __shared__ int redi[256];
   __shared__ int bad;
@@ -201,8 +204,7 @@ __global__ void k_gmres_status(const int* __restrict__ conv, const int* __restri
   double worst = 0.0;
   int it = 0;
   for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-    const int k = kcount[x];
-    const double est = fabs(g[(size_t)x * (m + 1) + k]) / (bnorm[x] > 0.0 ? bnorm[x] : 1.0);
+    const double est = rest[x];
     worst = fmax(worst, (est == est) ? est : INFINITY);
     it = max(it, ktot[x]);
     if (!conv[x]) bad = 1;
@@ -234,12 +236,12 @@ void launch_bin_map(const DevOps& d, const GmresOps& q, hipStream_t s) {
 
 void launch_gmres_init(const DevOps& d, const GmresOps& q, bool first, hipStream_t s) {
   k_gmres_init<<<d.nx_total, kThreads, 0, s>>>(q.R, d.B, q.V, q.g, q.bnorm, q.conv, q.inact, q.kcount, q.ktot,
-                                               q.rtol, first ? 1 : 0, d.npad, q.m);
+                                               q.rest, q.rtol, first ? 1 : 0, d.npad, q.m);
 }
 
 void launch_gmres_arnoldi(const DevOps& d, const GmresOps& q, int j, hipStream_t s) {
   k_gmres_arnoldi<<<d.nx_total, kThreads, 0, s>>>(q.W, q.V, q.H, q.cs, q.sn, q.g, q.bnorm, q.conv, q.kcount,
-                                                  q.ktot, q.rtol, j, d.nx_total, d.npad, q.m);
+                                                  q.ktot, q.rest, q.rtol, j, d.nx_total, d.npad, q.m);
 }
 
 void launch_gmres_combine(const DevOps& d, const GmresOps& q, hipStream_t s) {
@@ -247,7 +249,7 @@ void launch_gmres_combine(const DevOps& d, const GmresOps& q, hipStream_t s) {
 }
 
 void launch_gmres_status(const DevOps& d, const GmresOps& q, hipStream_t s) {
-  k_gmres_status<<<1, 256, 0, s>>>(q.conv, q.kcount, q.ktot, q.g, q.bnorm, d.status, d.resid, d.nx_total, q.m);
+  k_gmres_status<<<1, 256, 0, s>>>(q.conv, q.ktot, q.rest, d.status, d.resid, d.nx_total);
 }
 
 }  // namespace bte

@@ -35,7 +35,6 @@ using f64x4 = double __attribute__((ext_vector_type(4)));
 using f32x4 = float __attribute__((ext_vector_type(4)));
 
 constexpr int NB = kNB;
-constexpr int kPermStride = 1 + 2 * kMaxSwapRows;
 constexpr int kXcd = 8;  // XCDs of an MI355X; workgroups are dealt to them round-robin
 
 // MFMA 16x16x4 tiles: operand lanes hold A[i = lane%16][k = lane/16] and
@@ -409,7 +408,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
   for (int r = k0 + NB + tid; r < npad; r += NT) s_pos[r] = -1;
   __syncthreads();
   if (tid == 0) {
-    int* pm = perm + (size_t)mat * kPermStride;
+    int* pm = perm + ((size_t)mat * kMaxPanels + k0 / NB) * kPermStride;
     int* R = pm + 1;
     int* src = pm + 1 + kMaxSwapRows;
     int* lab = s_lab;
@@ -490,7 +489,7 @@ __global__ __launch_bounds__(128) void k_u12(T* __restrict__ LU, const T* __rest
   if (mat >= nmat) return;
   T* A = LU + (size_t)mat * npad * npad;
   const int c0 = k0 + NB + ct * CT;
-  const int* pm = perm + (size_t)mat * kPermStride;
+  const int* pm = perm + ((size_t)mat * kMaxPanels + k0 / NB) * kPermStride;
   const int nR = pm[0];
   const int* R = pm + 1;
   const int* src = pm + 1 + kMaxSwapRows;
@@ -826,7 +825,8 @@ __global__ __launch_bounds__(256, 2) void k_update(T* __restrict__ LU, int npad,
 // ---------------------------------------------------------------------------
 template <typename T, int TRANSPOSE>
 __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const int* __restrict__ piv,
-                                                const double* __restrict__ Bin, double* __restrict__ Xout,
+                                                const int* __restrict__ perm, const double* __restrict__ Bin,
+                                                double* __restrict__ Xout,
                                                 const int* __restrict__ status, int accumulate, int check_done,
                                                 int npad, const int* __restrict__ mat_of,
                                                 const int* __restrict__ skip) {
@@ -836,40 +836,89 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
   const int row = blockIdx.x;
   if (skip && skip[row]) return;
   __shared__ double sb[kMaxRows];
-  __shared__ int s_ip[kMaxRows];  // the pivots, staged once (the swaps read them serially)
   __shared__ T sD[NB][NB + 1];
+  __shared__ double s_part[sizeof(T) == 4 ? 2048 : 1];
   const int mat = mat_of ? mat_of[row] : row;
   const T* A = LU + (size_t)mat * npad * npad;
-  const int* ip = piv + (size_t)mat * npad;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NWV = 1024 / 64;
   const double* b = Bin + (size_t)row * npad;
-  for (int i = tid; i < npad; i += 1024) {
-    sb[i] = b[i];
-    s_ip[i] = ip[i];
-  }
+  for (int i = tid; i < npad; i += 1024) sb[i] = b[i];
   const int np = npad / NB;
-  auto stage_diag = [&](int k0) {
-    for (int e = tid; e < NB * NB; e += 1024) {
-      const int c = e / NB, r = e % NB;
-      sD[r][c] = A[(size_t)(k0 + c) * npad + k0 + r];
+  // sb[r] -= sum_j A[r][k0 + j] sb[k0 + j] for rows r in [r_lo, r_hi): each
+  // thread takes a 16-byte vector of consecutive rows (4 FP32 / 2 FP64) and keeps
+  // JB column loads in flight; FP32 splits the 128 columns between the two
+  // halves of the block and adds the halves through LDS
+  auto strip = [&](int k0, int r_lo, int r_hi) {
+    using V = typename Vec4<T>::type;
+    constexpr int PER = Vec4<T>::per;
+    constexpr int H = sizeof(T) == 4 ? 2 : 1;   // column groups
+    constexpr int CW = NB / H, JB = 8, TPG = 1024 / H;
+    const int grp = tid / TPG, lt = tid % TPG;
+    for (int r0 = r_lo; r0 < r_hi; r0 += TPG * PER) {
+      const int r = r0 + lt * PER;
+      const bool v = r < r_hi;
+      double acc[PER];
+#pragma unroll
+      for (int m = 0; m < PER; ++m) acc[m] = 0.0;
+      for (int jb = 0; jb < CW; jb += JB) {
+        V x[JB];
+#pragma unroll
+        for (int u = 0; u < JB; ++u) {
+          const int c = k0 + grp * CW + jb + u;
+          if (v) x[u] = *reinterpret_cast<const V*>(A + (size_t)c * npad + r);
+        }
+#pragma unroll
+        for (int u = 0; u < JB; ++u) {
+          const double bj = sb[k0 + grp * CW + jb + u];
+          const T* e = reinterpret_cast<const T*>(&x[u]);
+#pragma unroll
+          for (int m = 0; m < PER; ++m) acc[m] += static_cast<double>(e[m]) * bj;
+        }
+      }
+      if (H == 2) {
+        if (grp == 1 && v) {
+#pragma unroll
+          for (int m = 0; m < PER; ++m) s_part[lt * PER + m] = acc[m];
+        }
+        __syncthreads();
+        if (grp == 0 && v) {
+#pragma unroll
+          for (int m = 0; m < PER; ++m) sb[r + m] -= acc[m] + s_part[lt * PER + m];
+        }
+        __syncthreads();
+      } else if (v) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m) sb[r + m] -= acc[m];
+      }
+    }
+  };
+  auto stage_diag = [&](int k0) {  // all loads issued before the LDS stores
+    constexpr int NS = NB * NB / 1024;
+    T v[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + 1024 * u;
+      v[u] = A[(size_t)(k0 + e / NB) * npad + k0 + e % NB];
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + 1024 * u;
+      sD[e % NB][e / NB] = v[u];
     }
   };
   __syncthreads();
   if (!TRANSPOSE) {
     for (int p = 0; p < np; ++p) {
       const int k0 = p * NB;
-      if (tid == 0) {
-        for (int j = 0; j < NB; ++j) {
-          const int q = s_ip[k0 + j];
-          if (q != k0 + j) {
-            const double t = sb[k0 + j];
-            sb[k0 + j] = sb[q];
-            sb[q] = t;
-          }
-        }
-      }
+      // P_p: the panel's interchanges as one gather / scatter over its rows
+      const int* pm = perm + ((size_t)mat * kMaxPanels + p) * kPermStride;
+      const int nR = pm[0];
+      double pv = 0.0;
+      if (tid < nR) pv = sb[pm[1 + kMaxSwapRows + tid]];
       stage_diag(k0);
+      __syncthreads();
+      if (tid < nR) sb[pm[1 + tid]] = pv;
       __syncthreads();
       if (w == 0) {  // unit lower triangular diagonal block
         double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
@@ -882,12 +931,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
         sb[k0 + 64 + lane] = v1;
       }
       __syncthreads();
-      for (int r = k0 + NB + tid; r < npad; r += 1024) {
-        double s = 0.0;
-#pragma unroll 8
-        for (int j = 0; j < NB; ++j) s += static_cast<double>(A[(size_t)(k0 + j) * npad + r]) * sb[k0 + j];
-        sb[r] -= s;
-      }
+      strip(k0, k0 + NB, npad);
       __syncthreads();
     }
     for (int p = np - 1; p >= 0; --p) {
@@ -907,12 +951,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
         sb[k0 + 64 + lane] = v1;
       }
       __syncthreads();
-      for (int r = tid; r < k0; r += 1024) {
-        double s = 0.0;
-#pragma unroll 8
-        for (int j = 0; j < NB; ++j) s += static_cast<double>(A[(size_t)(k0 + j) * npad + r]) * sb[k0 + j];
-        sb[r] -= s;
-      }
+      strip(k0, 0, k0);
       __syncthreads();
     }
   } else {
@@ -968,15 +1007,14 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
         sb[k0 + 64 + lane] = v1;
       }
       __syncthreads();
-      if (tid == 0) {
-        for (int j = NB - 1; j >= 0; --j) {
-          const int q = s_ip[k0 + j];
-          if (q != k0 + j) {
-            const double t = sb[k0 + j];
-            sb[k0 + j] = sb[q];
-            sb[q] = t;
-          }
-        }
+      // P_p^T: inverse of the panel's gather / scatter
+      {
+        const int* pm = perm + ((size_t)mat * kMaxPanels + p) * kPermStride;
+        const int nR = pm[0];
+        double pv = 0.0;
+        if (tid < nR) pv = sb[pm[1 + tid]];
+        __syncthreads();
+        if (tid < nR) sb[pm[1 + kMaxSwapRows + tid]] = pv;
       }
       __syncthreads();
     }
@@ -992,7 +1030,7 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   T* xs = static_cast<T*>(d.xscr) + (size_t)m0 * d.npad * NB;
   T* li = static_cast<T*>(d.linv) + (size_t)m0 * 8 * 256;  // diagonal-block inverses
   int* piv = d.piv + (size_t)m0 * d.npad;
-  int* perm = d.perm + (size_t)m0 * kPermStride;
+  int* perm = d.perm + (size_t)m0 * kMaxPanels * kPermStride;
   const int xpb = d.form_xpb > 0 ? d.form_xpb : 16;  // matrices per formation block
   dim3 gform(d.npad, (nmat + xpb - 1) / xpb);
   k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, xpb);
@@ -1061,15 +1099,15 @@ void launch_lu_solve_mapped(const DevOps& f, int precision, bool transpose, cons
   if (precision == 0) {
     const double* LU = static_cast<const double*>(f.lu);
     if (transpose)
-      k_solve<double, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+      k_solve<double, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
     else
-      k_solve<double, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+      k_solve<double, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
   } else {
     const float* LU = static_cast<const float*>(f.lu);
     if (transpose)
-      k_solve<float, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+      k_solve<float, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
     else
-      k_solve<float, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+      k_solve<float, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
   }
 }
 

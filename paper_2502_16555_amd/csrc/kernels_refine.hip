@@ -48,9 +48,17 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
                                                   const double* __restrict__ n0x, unsigned long long* __restrict__ rmax,
                                                   unsigned long long* __restrict__ bmax,
                                                   unsigned long long* __restrict__ xmax, const int* __restrict__ status,
-                                                  double dt, int n, int npad, int nx) {
+                                                  double dt, int n, int npad, int nx, const int* __restrict__ skip) {
   if (MODE == 0 && status[1]) return;
   constexpr int BM = 32, BN = 64, BK = 64;
+  if (MODE != 0 && skip) {  // points already converged need no operator action
+    bool all = true;
+    for (int u = 0; u < BM; ++u) {
+      const int x = blockIdx.y * BM + u;
+      if (x < nx && !skip[x]) all = false;
+    }
+    if (all) return;
+  }
   constexpr int LX = BM * BK / 256, LO = BN * BK / 256;  // loads per thread and tile
   __shared__ double sX[BM][BK + 1];
   __shared__ double sC[BN][BK + 1];
@@ -306,24 +314,25 @@ void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t
   k_unpad<<<1024, 256, 0, s>>>(Bp, F, d.n, d.npad, d.nx_total);
 }
 
-void launch_apply(const DevOps& d, int mode, const double* B, const double* X, double* R, hipStream_t s) {
+void launch_apply(const DevOps& d, int mode, const double* B, const double* X, double* R, const int* skip,
+                  hipStream_t s) {
   dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32);
   if (mode == 1)
     k_residual<0, 1><<<g, 256, 0, s>>>(B, X, R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
-                                       d.n, d.npad, d.nx_total);
+                                       d.n, d.npad, d.nx_total, skip);
   else
     k_residual<0, 2><<<g, 256, 0, s>>>(B, X, R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
-                                       d.n, d.npad, d.nx_total);
+                                       d.n, d.npad, d.nx_total, skip);
 }
 
 void launch_residual(const DevOps& d, bool transpose, hipStream_t s) {
   dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32);
   if (transpose)
     k_residual<1><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt, d.n,
-                                    d.npad, d.nx_total);
+                                    d.npad, d.nx_total, nullptr);
   else
     k_residual<0><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt, d.n,
-                                    d.npad, d.nx_total);
+                                    d.npad, d.nx_total, nullptr);
 }
 
 namespace {
