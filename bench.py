@@ -25,6 +25,32 @@ sys.path.insert(0, ROOT)
 
 MI355X_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 
+# HBM bytes of the FP32 trailing update (k_update<float, 32>) per launch, averaged
+# over the 15 launches of one factorization at this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters
+# read for a 1 GiB copy (x2.0 and x1.0).  Valid for the kernel source it was taken
+# on (hash of kernels_lu.hip); reported as null once that file has changed.
+KUPDATE_TRAFFIC = {"kernels_lu_sha256_16": "07710f7697af35f8", "fetch_bytes": 1.660e9, "write_bytes": 1.387e9,
+                   "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def _update_traffic():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2502_16555_amd", "csrc", "kernels_lu.hip")
+    try:
+        h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if h != KUPDATE_TRAFFIC["kernels_lu_sha256_16"]:
+        return None
+    return KUPDATE_TRAFFIC["fetch_bytes"] + KUPDATE_TRAFFIC["write_bytes"]
+
+
+def _update_bytes(npad: int, nb: int, nmat: int, elt: int) -> float:
+    """Algorithmic bytes of one average update launch: A22 read and written, L21 and U12 read."""
+    ms = [npad - k0 - nb for k0 in range(0, npad, nb) if npad - k0 - nb > 0]
+    return sum((2 * m * m + 2 * m * nb) * elt for m in ms) * nmat / len(ms)
+
 
 def _update_flops(npad: int, nb: int, nmat: int) -> float:
     """Algorithmic flops of all trailing-update launches of one factorization."""
@@ -219,6 +245,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
     ap.add_argument("--ensemble", action="store_true", help="also time the 64-discharge batching form")
     ap.add_argument("--no-krylov", action="store_true", help="skip the GMRES V-solver leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB buffer 3 times (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hot path is single-GPU in this build",
@@ -229,6 +257,16 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        n = (1 << 30) // 4
+        src = torch.rand(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n,
+                                               "copies": 3}}), flush=True)
+        return
     cfg = workloads.config("C2")
     if args.nx != 256:
         cfg = dict(cfg, nx=args.nx, nx_per=[args.nx])
@@ -258,7 +296,11 @@ def main():
                                f"argon-like sigma, RF E0={cfg['field']['E0']:.1f} V/m, dt=1e-3 T_rf",
                    "precision": args.precision, "nx": cfg["nx"], "nr": 64, "ntheta": 32},
         "roofline": {"bound": "mfma", "kernel": "k_update (LU trailing update)", "achieved": achieved,
-                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": _update_traffic() if args.precision == "mixed_fp32" and npad == 2048 and nx_total == 256
+                     else None,
+                     "algorithmic_bytes_per_launch": _update_bytes(npad, 128, nx_total,
+                                                                   8 if args.precision == "fp64" else 4),
                      "launches_per_step": n_upd_launches,
                      "avg_launch_ms": main_run["ms_update"] / n_upd_launches},
         "breakdown_ms": {"lu_update_launches": main_run["ms_update"], "lu_panel_u12_launches": main_run["ms_panel"],

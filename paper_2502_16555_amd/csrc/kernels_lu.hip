@@ -575,9 +575,22 @@ __global__ __launch_bounds__(128) void k_u12(T* __restrict__ LU, const T* __rest
 // that the read-modify-write of the tile runs down whole columns with 16-byte
 // accesses; FP64 tiles take two passes of 64 rows.
 // ---------------------------------------------------------------------------
-template <typename T, typename Acc>
+// FP32 tiles: the old values of the tile, in the epilogue's layout, loaded
+// before the last K chunk so that their latency hides behind its products.
+constexpr int kPreV = 128 * 128 / 4 / 256;  // float4 per thread
+__device__ inline void tile_prefetch(const float* __restrict__ A, int npad, int r0, int c0, float4 (&pre)[kPreV]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kPreV; ++u) {
+    const int e = tid + u * 256;
+    const int col = e / 32, rr = (e % 32) * 4;
+    pre[u] = *reinterpret_cast<const float4*>(A + (size_t)(c0 + col) * npad + r0 + rr);
+  }
+}
+
+template <typename T, bool HASPRE = false, typename Acc, int NPRE = 1>
 __device__ inline void update_epilogue(T* __restrict__ A, int npad, int r0, int c0, const Acc (&acc)[4][4],
-                                       void* lds) {
+                                       void* lds, const float4 (&pre)[NPRE]) {
   using V = typename Vec4<T>::type;
   constexpr int PER = Vec4<T>::per;
   constexpr int P = sizeof(T) / 4;       // passes
@@ -606,7 +619,9 @@ __device__ inline void update_epilogue(T* __restrict__ A, int npad, int r0, int 
       const int e = tid + u * 256;
       const int col = e / (RP / PER), rr = (e % (RP / PER)) * PER;
       V* p = reinterpret_cast<V*>(A + (size_t)(c0 + col) * npad + r0 + pass * RP + rr);
-      V o = *p;
+      V o;
+      if constexpr (HASPRE) o = pre[u];
+      else o = *p;
       const V a = *reinterpret_cast<const V*>(sC + col * LDC + rr);
       T* po = reinterpret_cast<T*>(&o);
       const T* pa = reinterpret_cast<const T*>(&a);
@@ -688,9 +703,11 @@ __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int
   store(0);
   __syncthreads();
   constexpr int NCH = NB / KC;
+  float4 pre[kPreV];
   for (int ch = 0; ch < NCH; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < NCH) load((ch + 1) * KC);
+    else tile_prefetch(A, npad, r0, c0, pre);
     bf16x8 ah[4], bh[4], al[4], bl[4];
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi) {
@@ -719,7 +736,7 @@ __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int
       __syncthreads();
     }
   }
-  update_epilogue<float>(A, npad, r0, c0, acc, smem);
+  update_epilogue<float, true>(A, npad, r0, c0, acc, smem, pre);
 }
 
 // ---------------------------------------------------------------------------
@@ -792,9 +809,12 @@ __global__ __launch_bounds__(256, 2) void k_update(T* __restrict__ LU, int npad,
   store(0);
   __syncthreads();
   constexpr int NCH = NB / KC;
+  constexpr bool PREF = sizeof(T) == 4;   // register room for the tile's old values
+  float4 pre[PREF ? kPreV : 1];
   for (int ch = 0; ch < NCH; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < NCH) load((ch + 1) * KC);
+    else if constexpr (PREF) tile_prefetch(reinterpret_cast<const float*>(A), npad, r0, c0, pre);
 #pragma unroll
     for (int k = 0; k < KC; k += 4) {
       T av[4], bv[4];
@@ -812,7 +832,7 @@ __global__ __launch_bounds__(256, 2) void k_update(T* __restrict__ LU, int npad,
       __syncthreads();
     }
   }
-  update_epilogue<T>(A, npad, r0, c0, acc, smem);
+  update_epilogue<T, PREF>(A, npad, r0, c0, acc, smem, pre);
 }
 
 // ---------------------------------------------------------------------------
