@@ -29,19 +29,19 @@ MI355X_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 # over the 15 launches of one factorization at this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters
 # read for a 1 GiB copy (x2.0 and x1.0).  Valid for the kernel source it was taken
-# on (hash of kernels_lu.hip); reported as null once that file has changed.
-KUPDATE_TRAFFIC = {"kernels_lu_sha256_16": "07710f7697af35f8", "fetch_bytes": 1.660e9, "write_bytes": 1.387e9,
+# on (hash of kernels_update.hip); reported as null once that file has changed.
+KUPDATE_TRAFFIC = {"source_sha256_16": "c410f3508edaff8d", "fetch_bytes": 1.661e9, "write_bytes": 1.387e9,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def _update_traffic():
     import hashlib
-    path = os.path.join(ROOT, "paper_2502_16555_amd", "csrc", "kernels_lu.hip")
+    path = os.path.join(ROOT, "paper_2502_16555_amd", "csrc", "kernels_update.hip")
     try:
         h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    if h != KUPDATE_TRAFFIC["kernels_lu_sha256_16"]:
+    if h != KUPDATE_TRAFFIC["source_sha256_16"]:
         return None
     return KUPDATE_TRAFFIC["fetch_bytes"] + KUPDATE_TRAFFIC["write_bytes"]
 
@@ -322,7 +322,7 @@ def main():
     if not args.no_krylov:
         kr = run_gpu(cfg, "fp64", args.steps, warm, torch, args.lu_streams, krylov=True)
         line["krylov"] = {"solver": "restarted GMRES per point, FP64, field-binned preconditioner "
-                                    "(Alg. vspace_action_precon) with FP32 bin factors",
+                                    "(Alg. vspace_action_precon), bins factored and stored in FP32",
                           "settings": KRYLOV, "steps_per_s": 1000.0 / kr["ms_per_step"],
                           "ms_per_step": kr["ms_per_step"], "iterations_last_step": kr["refine_sweeps"],
                           "resid_estimate": kr["refine_resid"]}

@@ -63,8 +63,10 @@ typedef enum {
   BTE_MIXED_FP32 = 1,     /* FP32 LU + FP64 iterative refinement of the V-step residual  */
   BTE_MIXED_BF16 = 2,     /* as MIXED_FP32, LU trailing updates with bf16 operands
                            * (MFMA bf16, FP32 accumulation)                           */
-  BTE_MIXED_BF16X3 = 3    /* as MIXED_BF16 with operands split a = hi + lo in bf16 and
+  BTE_MIXED_BF16X3 = 3,   /* as MIXED_BF16 with operands split a = hi + lo in bf16 and
                            * the products hi*hi + hi*lo + lo*hi                       */
+  BTE_FACTORS_FP16 = 4    /* bte_set_vsolver only: preconditioner factored in FP32 and
+                           * stored in FP16                                           */
 } bte_precision;
 
 typedef enum { BTE_ELASTIC = 0, BTE_EXCITATION = 1, BTE_IONIZATION = 2 } bte_process_kind;
@@ -166,9 +168,10 @@ bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void*
  *     or in u = asinh(E / bin_scale) (bin_scale > 0: bins graded towards zero
  *     field, where the preconditioner no longer damps the speed-advection
  *     operator), s_p is the bin centre in u mapped back to E, and fields
- *     outside fall into the end bins.  The H_p are factored
- *     here, once, by the batched LU in factor_precision (BTE_FP64 or
- *     BTE_MIXED_FP32), per discharge.  E_bound <= 0 takes max_d |E0_d| (1 + |a1|)
+ *     outside fall into the end bins.  The H_p are factored here, once, per
+ *     discharge, by the batched LU in factor_precision: BTE_FP64,
+ *     BTE_MIXED_FP32, or BTE_FACTORS_FP16 (FP32 factorization stored in FP16,
+ *     solves accumulate in FP64).  E_bound <= 0 takes max_d |E0_d| (1 + |a1|)
  *     (CONST and RF fields only).  restart: Krylov vectors per cycle (1..63);
  *     cycles: restart cycles (1..100); a point stops when
  *     ||b - M x||_2 <= rtol ||b||_2 (GMRES estimate); points not converged after

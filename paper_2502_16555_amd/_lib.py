@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(_HERE, "libbte.so")
 
 BTE_OK, BTE_EINVAL, BTE_EHIP, BTE_ESINGULAR, BTE_ENOCONV, BTE_ENOMEM, BTE_ENONFINITE, BTE_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
-PRECISION = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2, "mixed_bf16x3": 3}
+PRECISION = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2, "mixed_bf16x3": 3, "fp16_factors": 4}
 FIELD = {"const": 0, "rf": 1, "given": 2, "poisson": 3}
 VBC = {"natural": 0, "zero_vmax": 1}
 KIND = {0: 0, 1: 1, 2: 2}

@@ -785,8 +785,10 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
   }
   if (kind != BTE_VSOLVER_GMRES || n_bins < 1 || n_bins > 4096 || restart < 1 || restart > 63 || cycles < 1 ||
       cycles > 100 || !(rtol > 0.0) || bin_scale < 0.0 ||
-      (factor_precision != BTE_FP64 && factor_precision != BTE_MIXED_FP32))
+      (factor_precision != BTE_FP64 && factor_precision != BTE_MIXED_FP32 && factor_precision != BTE_FACTORS_FP16))
     return BTE_EINVAL;
+  const bool fp16 = factor_precision == BTE_FACTORS_FP16;
+  const int lu_prec = fp16 ? BTE_MIXED_FP32 : factor_precision;   // the factorization itself
   const bte_config& c = h->cfg;
   double bound = E_bound;
   if (!(bound > 0.0)) {
@@ -801,7 +803,7 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
     h->drop_krylov();
     const DevOps& d = h->d;
     const int nd = d.nd, nb = n_bins, nmat = nd * nb;
-    const size_t elt = (factor_precision == BTE_FP64) ? sizeof(double) : sizeof(float);
+    const size_t elt = (lu_prec == BTE_FP64) ? sizeof(double) : sizeof(float);
     // bin matrices: I - dt (n0_d C + s_p A), s_p the centre of bin p
     DevOps f = d;
     f.nx_total = nmat;
@@ -824,11 +826,21 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
     f.linv = h->kalloc<char>(static_cast<size_t>(nmat) * 8 * 256 * elt);
     f.piv = h->kalloc<int>(static_cast<size_t>(nmat) * d.npad);
     f.perm = h->kalloc<int>(static_cast<size_t>(nmat) * bte::kMaxPanels * bte::kPermStride);
-    f.precision = factor_precision;
+    f.precision = lu_prec;
     f.update_kc = 0;
     f.form_xpb = 0;
-    bte::launch_lu_factor(f, factor_precision, nullptr);
+    bte::launch_lu_factor(f, lu_prec, nullptr);
     HIP_OK(hipDeviceSynchronize());
+    if (fp16) {  // keep the factors in FP16 only: half the bytes per preconditioner solve
+      const size_t cnt = static_cast<size_t>(nmat) * d.npad * d.npad;
+      void* h16 = h->kalloc<char>(cnt * 2);
+      bte::launch_to_half(static_cast<const float*>(f.lu), h16, cnt, nullptr);
+      HIP_OK(hipDeviceSynchronize());
+      auto it = std::find(h->kallocs.begin(), h->kallocs.end(), f.lu);
+      if (it != h->kallocs.end()) h->kallocs.erase(it);
+      HIP_OK(hipFree(f.lu));
+      f.lu = h16;
+    }
     int st = 0;
     HIP_OK(hipMemcpy(&st, d.status, sizeof(int), hipMemcpyDeviceToHost));
     if (st & bte::kStSingular) {
@@ -862,7 +874,7 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
     q.rest = h->kalloc<double>(nxt);
     h->kf = f;
     h->kq = q;
-    h->krylov_prec = factor_precision == BTE_FP64 ? 0 : 1;
+    h->krylov_prec = fp16 ? bte::kFactorsFp16 : (factor_precision == BTE_FP64 ? 0 : 1);
     h->krylov_cycles = cycles;
     h->krylov = true;
     return BTE_OK;

@@ -18,6 +18,7 @@ constexpr int kMaxSwapRows = 2 * kNB;   // rows touched by one panel's interchan
 constexpr int kMaxRows = 2048;          // largest padded system (n = Nr * Ntheta <= 2048)
 constexpr int kMaxPanels = kMaxRows / kNB;
 constexpr int kPermStride = 1 + 2 * kMaxSwapRows;  // one panel's row permutation: nR, rows, sources
+constexpr int kFactorsFp16 = 4;   // solve precision code: FP32 factors stored in FP16
 
 // Device status word bits.
 enum : int { kStSingular = 1, kStNoConv = 2, kStNonFinite = 4 };
@@ -134,6 +135,10 @@ struct LuTimer {
 // place, for the points m0 .. m0+count-1 (count < 0: to the last point).
 void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer = nullptr, int m0 = 0,
                       int count = -1);
+// A22 -= L21 U12 of panel k0 for nmat matrices (mt x mt tiles of 128): kind 0
+// FP64, 1 FP32, 2 FP32 with bf16 operands, 3 FP32 with split bf16 operands;
+// half_kc: K chunk 16 (FP32) / 8 (FP64) instead of 32 / 16.
+void launch_update(int kind, void* LU, int npad, int k0, int mt, int nmat, bool half_kc, hipStream_t s);
 // X = LU^-1 B (or LU^-T B with transpose), rows of length npad, FP64 right-hand sides.
 void launch_lu_solve(const DevOps& d, int precision, bool transpose, const double* Bin, double* Xout,
                      bool accumulate, bool check_done, hipStream_t s);
@@ -143,6 +148,8 @@ void launch_lu_solve(const DevOps& d, int precision, bool transpose, const doubl
 void launch_lu_solve_mapped(const DevOps& f, int precision, bool transpose, const int* mat_of, const int* skip,
                             int nrows, const double* Bin, double* Xout, bool accumulate, bool check_done,
                             hipStream_t s);
+// FP32 -> FP16 copy of n elements (factor storage for preconditioning solves).
+void launch_to_half(const float* src, void* dst, size_t n, hipStream_t s);
 // Copy F (rows of n) into padded rows of npad and back.
 void launch_pad_rows(const DevOps& d, const double* F, double* Bp, hipStream_t s);
 void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t s);

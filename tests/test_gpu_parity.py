@@ -542,7 +542,7 @@ def test_autotuned_shapes_leave_results_unchanged(torch, tmp_path):
         s.close()
 
 
-@pytest.mark.parametrize("fprec", ["fp64", "mixed_fp32"])
+@pytest.mark.parametrize("fprec", ["fp64", "mixed_fp32", "fp16_factors"])
 @pytest.mark.parametrize("case", ["ragged", "panels", "panels4"])
 def test_krylov_vstep_matches_oracle(torch, case, fprec):
     """Batched GMRES with the field-binned preconditioner (bin factors in FP64
