@@ -65,12 +65,14 @@ def _update_flops(npad: int, nb: int, nmat: int) -> float:
 KRYLOV = dict(n_bins=128, bin_scale=100.0, restart=12, cycles=3, rtol=1e-12, factor_precision="mixed_fp32")
 
 
-def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=False, krylov=False):
+def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=False, krylov=False, banded=False):
     from paper_2502_16555_amd import Solver, _lib
     t0 = time.time()
     s = Solver(cfg, precision=precision)
     if krylov:
         s.set_vsolver("gmres", **KRYLOV)
+    if banded:
+        s.set_vsolver("banded")
     setup_s = time.time() - t0
     if lu_streams is not None:
         s.set_tuning(_lib.TUNE_LU_STREAMS, lu_streams)
@@ -245,6 +247,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
     ap.add_argument("--ensemble", action="store_true", help="also time the 64-discharge batching form")
     ap.add_argument("--no-krylov", action="store_true", help="skip the GMRES V-solver leg")
+    ap.add_argument("--no-banded", action="store_true", help="skip the banded harmonic-basis V-solver leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
@@ -329,6 +332,15 @@ def main():
         if fp64 is not None:
             line["krylov"]["speedup_over_fp64_lu"] = fp64["ms_per_step"] / kr["ms_per_step"]
             line["krylov"]["vs_fp64_lu"] = dict(moment_errors(kr["moments"], fp64["moments"]), steps=kr["n_end"])
+    if not args.no_banded:
+        bd = run_gpu(cfg, "fp64", args.steps, warm, torch, args.lu_streams, banded=True)
+        line["banded"] = {"solver": "FP64 batched LU of the harmonic-basis systems restricted to their band "
+                                    "(half-bandwidth 2 Nr - 1, eq. f_expansion)",
+                          "steps_per_s": 1000.0 / bd["ms_per_step"], "ms_per_step": bd["ms_per_step"],
+                          "ms_update": bd["ms_update"], "ms_panel": bd["ms_panel"], "ms_vwall": bd["ms_vwall"]}
+        if fp64 is not None:
+            line["banded"]["speedup_over_fp64_lu"] = fp64["ms_per_step"] / bd["ms_per_step"]
+            line["banded"]["vs_fp64_lu"] = dict(moment_errors(bd["moments"], fp64["moments"]), steps=bd["n_end"])
     if not args.no_adjoint:
         line["adjoint"] = run_adjoint(torch)
     if args.ensemble:

@@ -177,9 +177,18 @@ bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void*
  *     ||b - M x||_2 <= rtol ||b||_2 (GMRES estimate); points not converged after
  *     the last cycle latch BTE_ENOCONV, bte_get_status then reports the largest
  *     iteration count over the points and the largest relative residual estimate.
- * The adjoint step always factors (it needs the transposed solves).
+ *   BTE_VSOLVER_BANDED: the systems solved in the spherical-harmonic basis of
+ *     eq. (f_expansion) (with nl == ntheta, P_S = P_O^-1): with the
+ *     unknowns ordered l-major, the collision operator is block diagonal in l
+ *     and the acceleration operator couples l to l +- 1, so
+ *     I - dt (n0 C_h + E A_h) is banded with half-bandwidth 2 Nr - 1; the
+ *     batched LU with partial pivoting runs restricted to that band (fill
+ *     included) in FP64, between F_h = P_S F and F* = P_O F_h*.  The other
+ *     arguments are ignored.  Returns BTE_EUNSUPPORTED when ntheta > 64.
+ * The adjoint step always factors the dense ordinate-space systems (it needs
+ * the transposed solves).
  * Synchronous (factors the bins).  Errors: BTE_EINVAL, BTE_ESINGULAR, BTE_ENOMEM, BTE_EHIP. */
-typedef enum { BTE_VSOLVER_LU = 0, BTE_VSOLVER_GMRES = 1 } bte_vsolver;
+typedef enum { BTE_VSOLVER_LU = 0, BTE_VSOLVER_GMRES = 1, BTE_VSOLVER_BANDED = 2 } bte_vsolver;
 bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E_bound, double bin_scale,
                            int32_t restart, int32_t cycles, double rtol, int32_t factor_precision);
 
@@ -233,11 +242,15 @@ bte_status bte_field_eval(bte_handle* h, const double* F_half, double t_s, bte_f
  * which: 0 C_ord [n][n] (sum_sb scal C^(s,b), per unit n0), 1 A_ord [n][n],
  *        2 M_v [Nr][Nr], 3 G_v [Nr][Nr], 4 eigenvalues Lambda [Nr], 5 U [Nr][Nr],
  *        6 xhat [sum Nx], 7 moment weights [3][n] (number, energy in eV, k_i),
- *        8 C^(s,b) [n_params][n][n], 9 Q of discharge 0 [Nr][Ntheta][Nx][Nx] (row-major Q_ia).
+ *        8 C^(s,b) [n_params][n][n], 9 Q of discharge 0 [Nr][Ntheta][Nx][Nx] (row-major Q_ia),
+ *        10 C_h [n][n], 11 A_h [n][n]: the operators of C_ord and A_ord in the harmonic
+ *        basis, unknowns ordered l-major (l * Nr + k), so that C_ord = P_O C_h P_S,
+ *        12 T_O [Ntheta][nl] (F[k][a] = sum_l T_O[a][l] F_h[l][k]),
+ *        13 T_S [nl][Ntheta] (F_h[l][k] = sum_a T_S[l][a] F[k][a]).
  * host_out must hold the documented number of doubles. */
 bte_status bte_get_operator(bte_handle* h, int32_t which, double* host_out);
 
-/* The same operators (which = 0..9) assembled on the host from a configuration,
+/* The same operators (which = 0..13) assembled on the host from a configuration,
  * without a device or handle (synchronous).  Used to verify the assembly. */
 bte_status bte_host_operator(const bte_config* cfg, int32_t which, double* host_out);
 

@@ -426,12 +426,36 @@ void assemble(const AssemblyInput& in, HostOps* out) {
       }
   };
 
+  // harmonic-space Kronecker accumulate (l-major): Out[(q,k),(l,j)] += R[k][j] * X[q][l]
+  auto kron_h = [&](std::vector<double>& Out, const std::vector<double>& R, const std::vector<double>& X,
+                    double s) {
+    for (int q = 0; q < nl; ++q)
+      for (int l = 0; l < nl; ++l) {
+        const double x = s * X[q * nl + l];
+        if (x == 0.0) continue;
+        for (int k = 0; k < nr; ++k)
+          for (int j = 0; j < nr; ++j) Out[(size_t)(q * nr + k) * n + l * nr + j] += R[k * nr + j] * x;
+      }
+  };
+  H.TO = TO;
+  H.TS = TS;
+
   // --- acceleration operator -------------------------------------------------------
   H.Aord.assign((size_t)n * n, 0.0);
+  H.Ah.assign((size_t)n * n, 0.0);
   {
     std::vector<double> R1 = matmul(Minv, D1, nr, nr, nr), R0 = matmul(Minv, D0, nr, nr, nr);
     kron_add(H.Aord, R1, th_a, kECharge / kMElectron);
     kron_add(H.Aord, R0, th_b, kECharge / kMElectron);
+    // the recurrences of the Legendre polynomials for mu P_l and (1 - mu^2) P_l'
+    // couple l to l +- 1 only; the quadrature leaves rounding noise elsewhere,
+    // which the harmonic operator drops so that it is exactly banded
+    std::vector<double> ab(acpl), bb(bcpl);
+    for (int q = 0; q < nl; ++q)
+      for (int l = 0; l < nl; ++l)
+        if (std::abs(q - l) != 1) ab[q * nl + l] = bb[q * nl + l] = 0.0;
+    kron_h(H.Ah, R1, ab, kECharge / kMElectron);
+    kron_h(H.Ah, R0, bb, kECharge / kMElectron);
   }
 
   // --- collision operators per process and bin -------------------------------------
@@ -439,6 +463,7 @@ void assemble(const AssemblyInput& in, HostOps* out) {
   for (int b = 0; b <= nbins; ++b) edges_v[b] = speed_of(in.bin_edges_eV[b]);
   H.Csb.assign((size_t)H.n_params * n * n, 0.0);
   H.Cord.assign((size_t)n * n, 0.0);
+  H.Ch.assign((size_t)n * n, 0.0);
   std::vector<double> ki(nr, 0.0);
   for (int s = 0; s < nproc; ++s) {
     const Process& P = in.proc[s];
@@ -527,6 +552,8 @@ void assemble(const AssemblyInput& in, HostOps* out) {
       const double sc = in.scal[s * nbins + b];
       double* dst = H.Csb.data() + (size_t)(s * nbins + b) * n * n;
       for (size_t i = 0; i < (size_t)n * n; ++i) { dst[i] = Cb[i]; H.Cord[i] += sc * Cb[i]; }
+      kron_h(H.Ch, Riso, e00, sc);
+      kron_h(H.Ch, Rloss, Il, sc);
       if (P.kind == 2) for (int k = 0; k < nr; ++k) ki[k] += sc * kis[b][k];
     }
   }

@@ -50,6 +50,11 @@ struct HostOps {
   std::vector<double> Cord;           // [n][n] sum_sb scal C^(s,b)_ord (per unit n0)
   std::vector<double> Aord;           // [n][n] per unit field
   std::vector<double> Csb;            // [n_params][n][n]
+  // harmonic-space operators, unknowns ordered l-major (index l * nr + k): the
+  // collision operator is block diagonal in l and the acceleration operator
+  // couples l to l +- 1, so both are banded with half-bandwidth 2 nr - 1
+  std::vector<double> Ch, Ah;         // [n][n]
+  std::vector<double> TO, TS;         // [nth][nl] and [nl][nth] (T_S T_O = I for nl = nth)
   std::vector<double> mom;            // [3][n] number, energy (eV), ionization weights
   std::vector<XOps> xops;             // per discharge
 };

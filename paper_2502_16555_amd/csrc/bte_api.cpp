@@ -60,6 +60,10 @@ struct bte_handle {
   // Krylov V solver (bte_set_vsolver): factors of the field-binned
   // preconditioner (a DevOps over nd * nbins matrices) and the GMRES workspace
   bool krylov = false;
+  bool banded = false;         // V solves in the harmonic basis, banded LU
+  DevOps bd;                   // its factors (FP64) and harmonic operators
+  double* d_TO = nullptr;
+  double* d_TS = nullptr;
   int krylov_cycles = 2;
   int krylov_prec = 0;         // precision of the bin factors (0 FP64, 1 FP32)
   DevOps kf;
@@ -69,6 +73,7 @@ struct bte_handle {
     for (void* p : kallocs) (void)hipFree(p);
     kallocs.clear();
     krylov = false;
+    banded = false;
   }
   template <typename T>
   T* kalloc(size_t count) {
@@ -379,6 +384,18 @@ void v_solve_krylov(bte_handle* h, double* F, hipStream_t s) {
   bte::launch_unpad_rows(d, d.X, F, s);
 }
 
+// V(dt) in the harmonic basis: Fh = P_S F, (I - dt (n0 C_h + E A_h)) Fh* = Fh by
+// the batched LU restricted to the band of the l-major ordering, F* = P_O Fh*.
+void v_solve_banded(bte_handle* h, double* F, hipStream_t s) {
+  DevOps& d = h->d;
+  DevOps& b = h->bd;
+  b.E = d.E;   // the field of this step
+  bte::launch_to_harm(d, F, h->d_TS, d.B, s);
+  bte::launch_lu_factor(b, 0, s, h->timing ? &h->lu_timer[0] : nullptr);
+  bte::launch_lu_solve_mapped(b, 0, false, nullptr, nullptr, d.nx_total, d.B, d.X, false, false, s);
+  bte::launch_from_harm(d, d.X, h->d_TO, F, s);
+}
+
 // V(dt) in place on F (field already in d.E).  transpose: solve with A^T.
 // The forward step takes the Krylov solver when one is configured; the
 // adjoint (transpose, and its forward recomputation) always factors.
@@ -387,6 +404,10 @@ void v_solve(bte_handle* h, double* F, bool transpose, hipStream_t s, bool allow
   const int prec = h->cfg.precision;
   if (allow_krylov && h->krylov && !transpose) {
     v_solve_krylov(h, F, s);
+    return;
+  }
+  if (allow_krylov && h->banded && !transpose) {
+    v_solve_banded(h, F, s);
     return;
   }
   bte::launch_pad_rows(d, F, d.B, s);
@@ -783,6 +804,50 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
     h->drop_krylov();
     return BTE_OK;
   }
+  if (kind == BTE_VSOLVER_BANDED) {
+    // the transforms stage one point and the nl x nl transform in LDS
+    if (h->cfg.nl != h->cfg.ntheta || h->cfg.ntheta > 64) return BTE_EUNSUPPORTED;
+    try {
+      HIP_OK(hipSetDevice(h->device));
+      HIP_OK(hipDeviceSynchronize());
+      h->drop_krylov();
+      const DevOps& d = h->d;
+      const bte::HostOps& H = h->host;
+      const int n = d.n, nxt = d.nx_total, np = d.npad;
+      DevOps b = d;
+      // operators by columns (the formation kernel reads columns contiguously)
+      std::vector<double> T1((size_t)n * n), T2((size_t)n * n);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          T1[(size_t)j * n + i] = H.Ch[(size_t)i * n + j];
+          T2[(size_t)j * n + i] = H.Ah[(size_t)i * n + j];
+        }
+      b.CordT = h->kalloc<double>((size_t)n * n);
+      b.AordT = h->kalloc<double>((size_t)n * n);
+      HIP_OK(hipMemcpy(b.CordT, T1.data(), T1.size() * sizeof(double), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(b.AordT, T2.data(), T2.size() * sizeof(double), hipMemcpyHostToDevice));
+      h->d_TO = h->kalloc<double>(H.TO.size());
+      h->d_TS = h->kalloc<double>(H.TS.size());
+      HIP_OK(hipMemcpy(h->d_TO, H.TO.data(), H.TO.size() * sizeof(double), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(h->d_TS, H.TS.data(), H.TS.size() * sizeof(double), hipMemcpyHostToDevice));
+      b.lu = h->kalloc<char>((size_t)nxt * np * np * sizeof(double));
+      b.xscr = h->kalloc<char>((size_t)nxt * np * bte::kNB * sizeof(double));
+      b.linv = h->kalloc<char>((size_t)nxt * 8 * 256 * sizeof(double));
+      b.piv = h->kalloc<int>((size_t)nxt * np);
+      b.perm = h->kalloc<int>((size_t)nxt * bte::kMaxPanels * bte::kPermStride);
+      b.precision = 0;
+      b.update_kc = 0;
+      b.form_xpb = 0;
+      b.band_kl = 2 * d.nr - 1;
+      b.band_ku = 2 * d.nr - 1;
+      h->bd = b;
+      h->banded = true;
+      return BTE_OK;
+    } catch (const std::exception& e) {
+      h->drop_krylov();
+      return map_exc(e);
+    }
+  }
   if (kind != BTE_VSOLVER_GMRES || n_bins < 1 || n_bins > 4096 || restart < 1 || restart > 63 || cycles < 1 ||
       cycles > 100 || !(rtol > 0.0) || bin_scale < 0.0 ||
       (factor_precision != BTE_FP64 && factor_precision != BTE_MIXED_FP32 && factor_precision != BTE_FACTORS_FP16))
@@ -943,6 +1008,10 @@ bte_status bte_get_operator(bte_handle* h, int32_t which, double* host_out) {
     }
     case 7: put(H.mom); break;
     case 8: put(H.Csb); break;
+    case 10: put(H.Ch); break;
+    case 11: put(H.Ah); break;
+    case 12: put(H.TO); break;
+    case 13: put(H.TS); break;
     case 9: {
       // expand Q of discharge 0 to [nr][ntheta][nx][nx] row-major Q_ia
       const bte::XOps& X = H.xops[0];

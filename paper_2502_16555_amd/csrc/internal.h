@@ -28,6 +28,7 @@ struct DevOps {
   int nd = 0, nx_total = 0, n_params = 0, n_bins = 1, precision = 0;
   int max_nx = 0;
   int update_kc = 0;           // K chunk of the trailing update (0: default)
+  int band_kl = 0, band_ku = 0;  // banded systems: lower / upper bandwidth (0: dense)
   int form_xpb = 0;            // matrices per formation block (0: default)
   double dt = 0.0;
   // per discharge (device)
@@ -135,10 +136,10 @@ struct LuTimer {
 // place, for the points m0 .. m0+count-1 (count < 0: to the last point).
 void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer = nullptr, int m0 = 0,
                       int count = -1);
-// A22 -= L21 U12 of panel k0 for nmat matrices (mt x mt tiles of 128): kind 0
+// A22 -= L21 U12 of panel k0 for nmat matrices (mtr x mtc tiles of 128): kind 0
 // FP64, 1 FP32, 2 FP32 with bf16 operands, 3 FP32 with split bf16 operands;
 // half_kc: K chunk 16 (FP32) / 8 (FP64) instead of 32 / 16.
-void launch_update(int kind, void* LU, int npad, int k0, int mt, int nmat, bool half_kc, hipStream_t s);
+void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int nmat, bool half_kc, hipStream_t s);
 // X = LU^-1 B (or LU^-T B with transpose), rows of length npad, FP64 right-hand sides.
 void launch_lu_solve(const DevOps& d, int precision, bool transpose, const double* Bin, double* Xout,
                      bool accumulate, bool check_done, hipStream_t s);
@@ -150,6 +151,9 @@ void launch_lu_solve_mapped(const DevOps& f, int precision, bool transpose, cons
                             hipStream_t s);
 // FP32 -> FP16 copy of n elements (factor storage for preconditioning solves).
 void launch_to_half(const float* src, void* dst, size_t n, hipStream_t s);
+// Ordinate -> harmonic coefficients (P_S, l-major, padded rows) and back (P_O).
+void launch_to_harm(const DevOps& d, const double* F, const double* TS, double* Bh, hipStream_t s);
+void launch_from_harm(const DevOps& d, const double* Xh, const double* TO, double* F, hipStream_t s);
 // Copy F (rows of n) into padded rows of npad and back.
 void launch_pad_rows(const DevOps& d, const double* F, double* Bp, hipStream_t s);
 void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t s);

@@ -21,6 +21,7 @@
 //   k_update  A22 -= L21 U12: 128 x 128 MFMA tiles, K = 128 in double-buffered
 //             LDS chunks; blocks of one matrix are kept on one XCD so that L21
 //             and U12 stay in that XCD's L2.
+#include <algorithm>
 #include <cfloat>
 #include <climits>
 #include <limits>
@@ -85,7 +86,8 @@ __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* 
 template <typename T, int NT, int RPT, int IB>
 __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restrict__ piv,
                                                          int* __restrict__ perm, int* __restrict__ status, int npad,
-                                                         int k0) {
+                                                         int k0, int rend) {
+  // rows >= rend are zero in the panel columns (banded systems) and take no part
   constexpr int NW = NT / 64;
   const int mat = blockIdx.x;
   T* A = LU + (size_t)mat * npad * npad;
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
     for (int q = 0; q < RPT; ++q) {
       const int r = c0 + tid + q * NT;
 #pragma unroll
-      for (int j = 0; j < IB; ++j) a[q][j] = (r < npad) ? A[(size_t)(c0 + j) * npad + r] : T(0);
+      for (int j = 0; j < IB; ++j) a[q][j] = (r < rend) ? A[(size_t)(c0 + j) * npad + r] : T(0);
     }
 #pragma clang loop unroll(full)
     for (int j = 0; j < IB; ++j) {
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         const int r = c0 + tid + q * NT;
-        if (r >= c && r < npad) {
+        if (r >= c && r < rend) {
           const double v = fabs(static_cast<double>(a[q][j]));
           if (v > best) {
             best = v;
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         const int r = c0 + tid + q * NT;
-        if (r > c && r < npad && pv != T(0)) {
+        if (r > c && r < rend && pv != T(0)) {
           const T x = a[q][j];
           const T l = by_rcp ? x * rp : x / pv;
 #pragma unroll
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int r = c0 + tid + q * NT;
-      if (r < npad) {
+      if (r < rend) {
 #pragma unroll
         for (int j = 0; j < IB; ++j) A[(size_t)(c0 + j) * npad + r] = a[q][j];
       }
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
           const int r = c0 + tid + q * NT;
 #pragma unroll
           for (int u = 0; u < CB; ++u)
-            dst[q][u] = (r >= c0 + IB && r < npad && cb + u < nrest) ? A[(size_t)(c0 + IB + cb + u) * npad + r] : T(0);
+            dst[q][u] = (r >= c0 + IB && r < rend && cb + u < nrest) ? A[(size_t)(c0 + IB + cb + u) * npad + r] : T(0);
         }
       };
       ld(v, 0);
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
           const int r = c0 + tid + q * NT;
 #pragma unroll
           for (int u = 0; u < CB; ++u)
-            if (r >= c0 + IB && r < npad && cb + u < nrest) A[(size_t)(c0 + IB + cb + u) * npad + r] = v[q][u];
+            if (r >= c0 + IB && r < rend && cb + u < nrest) A[(size_t)(c0 + IB + cb + u) * npad + r] = v[q][u];
         }
 #pragma unroll
         for (int q = 0; q < RPT; ++q)
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
   if (nonfinite && tid == 0) atomicOr(status, kStNonFinite);
   // pivots out, then the permutation of the whole panel for the trailing columns
   for (int t = tid; t < NB; t += NT) ip[k0 + t] = s_piv[t];
-  for (int r = k0 + NB + tid; r < npad; r += NT) s_pos[r] = -1;
+  for (int r = k0 + NB + tid; r < rend; r += NT) s_pos[r] = -1;
   __syncthreads();
   if (tid == 0) {
     int* pm = perm + ((size_t)mat * kMaxPanels + k0 / NB) * kPermStride;
@@ -535,7 +537,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
                                                 double* __restrict__ Xout,
                                                 const int* __restrict__ status, int accumulate, int check_done,
                                                 int npad, const int* __restrict__ mat_of,
-                                                const int* __restrict__ skip) {
+                                                const int* __restrict__ skip, int band_lo, int band_up) {
   if (check_done && status[1]) return;
   // right-hand side / solution row: the block; factors: that row's own matrix,
   // or the one mat_of names (a shared factorization, e.g. a preconditioner bin)
@@ -637,7 +639,8 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
         sb[k0 + 64 + lane] = v1;
       }
       __syncthreads();
-      strip(k0, k0 + NB, npad);
+      // banded factors: L below a panel reaches band_lo rows
+      strip(k0, k0 + NB, band_lo > 0 ? min(npad, (k0 + NB + band_lo + NB - 1) / NB * NB) : npad);
       __syncthreads();
     }
     for (int p = np - 1; p >= 0; --p) {
@@ -657,7 +660,9 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
         sb[k0 + 64 + lane] = v1;
       }
       __syncthreads();
-      strip(k0, 0, k0);
+      // banded factors: U has upper bandwidth band_up (kl + ku with the fill of
+      // the interchanges)
+      strip(k0, band_up > 0 ? max(0, (k0 - band_up) / NB * NB) : 0, k0);
       __syncthreads();
     }
   } else {
@@ -747,15 +752,22 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   constexpr int KC = sizeof(T) == 8 ? 16 : 32;
   const bool half_kc = d.update_kc == KC / 2;
   (void)KC;
+  // banded systems (lower / upper bandwidth kl / ku): the rows below a panel end
+  // kl below it; partial pivoting widens the upper band to kl + ku
+  const int kl = d.band_kl, ku = d.band_ku;
+  auto round_up = [](int v) { return (v + NB - 1) / NB * NB; };
   for (int p = 0; p < np; ++p) {
     const int k0 = p * NB;
     const bool rec = tm && p < tm->max_panels;
     if (rec) (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p], s);
-    const int rest = d.npad - k0 - NB;
+    const int rend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl)) : d.npad;
+    const int cend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl + ku)) : d.npad;
+    const int rows = rend - k0;
+    const int rest = cend - k0 - NB;
     constexpr int NT = kPanelThreads;  // 512 threads holding up to 4 rows each
-    if (d.npad <= NT) k_panel<T, NT, 1, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
-    else if (d.npad <= 2 * NT) k_panel<T, NT, 2, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
-    else k_panel<T, NT, 4, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0);
+    if (rows <= NT) k_panel<T, NT, 1, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+    else if (rows <= 2 * NT) k_panel<T, NT, 2, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+    else k_panel<T, NT, 4, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     if (rest > 0) {
       const int nct = rest / 32;  // U12 blocks of 32 columns
       k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);
@@ -764,8 +776,10 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
         (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p + 1], s);
         (void)hipEventRecord(tm->ev[2 * p], s);
       }
-      launch_update(sizeof(T) == 8 ? 0 : (bf16_terms == 1 ? 2 : (bf16_terms == 3 ? 3 : 1)), LU, d.npad, k0,
-                    rest / 128, nmat, half_kc, s);
+      const int mtr = (rend - k0 - NB) / 128, mtc = rest / 128;
+      if (mtr > 0)
+        launch_update(sizeof(T) == 8 ? 0 : (bf16_terms == 1 ? 2 : (bf16_terms == 3 ? 3 : 1)), LU, d.npad, k0, mtr,
+                      mtc, nmat, half_kc, s);
       if (rec) (void)hipEventRecord(tm->ev[2 * p + 1], s);
     } else if (rec) {
       (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p + 1], s);
@@ -808,21 +822,21 @@ void launch_lu_solve_mapped(const DevOps& f, int precision, bool transpose, cons
   if (precision == 0) {
     const double* LU = static_cast<const double*>(f.lu);
     if (transpose)
-      k_solve<double, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+      k_solve<double, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
     else
-      k_solve<double, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+      k_solve<double, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
   } else if (precision == kFactorsFp16) {
     const _Float16* LU = static_cast<const _Float16*>(f.lu);
     if (transpose)
-      k_solve<_Float16, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+      k_solve<_Float16, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
     else
-      k_solve<_Float16, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+      k_solve<_Float16, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
   } else {
     const float* LU = static_cast<const float*>(f.lu);
     if (transpose)
-      k_solve<float, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+      k_solve<float, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
     else
-      k_solve<float, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip);
+      k_solve<float, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
   }
 }
 

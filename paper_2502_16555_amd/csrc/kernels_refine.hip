@@ -34,6 +34,45 @@ __global__ void k_unpad(const double* __restrict__ Bp, double* __restrict__ F, i
   }
 }
 
+// Ordinates <-> harmonics of every point (nl = nth): harmonic coefficients
+// Bh[l * nr + k] = sum_a TS[l][a] F[k][a] (P_S of eq. (proj_ops), l-major, padded
+// rows of npad) and back F[k][a] = sum_l TO[a][l] Xh[l * nr + k] (P_O).
+__global__ __launch_bounds__(256) void k_to_harm(const double* __restrict__ F, const double* __restrict__ TS,
+                                                 double* __restrict__ Bh, int nr, int nth, int npad) {
+  extern __shared__ double sh[];
+  const int n = nr * nth, x = blockIdx.x;
+  double* sF = sh;
+  double* sT = sh + n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sF[i] = F[(size_t)x * n + i];
+  for (int i = threadIdx.x; i < nth * nth; i += blockDim.x) sT[i] = TS[i];
+  __syncthreads();
+  for (int o = threadIdx.x; o < npad; o += blockDim.x) {
+    double v = 0.0;
+    if (o < n) {
+      const int l = o / nr, k = o % nr;
+      for (int a = 0; a < nth; ++a) v += sT[l * nth + a] * sF[k * nth + a];
+    }
+    Bh[(size_t)x * npad + o] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_from_harm(const double* __restrict__ Xh, const double* __restrict__ TO,
+                                                   double* __restrict__ F, int nr, int nth, int npad) {
+  extern __shared__ double sh[];
+  const int n = nr * nth, x = blockIdx.x;
+  double* sX = sh;
+  double* sT = sh + n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sX[i] = Xh[(size_t)x * npad + i];
+  for (int i = threadIdx.x; i < nth * nth; i += blockDim.x) sT[i] = TO[i];
+  __syncthreads();
+  for (int o = threadIdx.x; o < n; o += blockDim.x) {
+    const int k = o / nth, a = o % nth;
+    double v = 0.0;
+    for (int l = 0; l < nth; ++l) v += sT[a * nth + l] * sX[l * nr + k];
+    F[(size_t)x * n + o] = v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // FP64 residual R = B - X + dt n0_x (X C^T) + dt E_x (X A^T)  (TRANSPOSE: C, A)
 // rows = collocation points, 32 x 64 output tiles, MFMA f64 16x16x4.
@@ -305,6 +344,16 @@ __global__ __launch_bounds__(256) void k_adjoint_grads(const double* __restrict_
 }
 
 }  // namespace
+
+void launch_to_harm(const DevOps& d, const double* F, const double* TS, double* Bh, hipStream_t s) {
+  const size_t sh = (size_t)(d.n + d.nth * d.nth) * sizeof(double);
+  k_to_harm<<<d.nx_total, 256, sh, s>>>(F, TS, Bh, d.nr, d.nth, d.npad);
+}
+
+void launch_from_harm(const DevOps& d, const double* Xh, const double* TO, double* F, hipStream_t s) {
+  const size_t sh = (size_t)(d.n + d.nth * d.nth) * sizeof(double);
+  k_from_harm<<<d.nx_total, 256, sh, s>>>(Xh, TO, F, d.nr, d.nth, d.npad);
+}
 
 void launch_pad_rows(const DevOps& d, const double* F, double* Bp, hipStream_t s) {
   k_pad<<<1024, 256, 0, s>>>(F, Bp, d.n, d.npad, d.nx_total);

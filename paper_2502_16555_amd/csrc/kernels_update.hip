@@ -86,14 +86,15 @@ __device__ inline void update_epilogue(T* __restrict__ A, int npad, int r0, int 
 using bf16x8 = __bf16 __attribute__((ext_vector_type(8)));
 
 template <int NTERMS>
-__global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int npad, int k0, int mt, int nmat) {
+__global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int npad, int k0, int mtr, int mtc,
+                                                     int nmat) {
   constexpr int KC = 32;
   constexpr int LDK = KC + 8;               // bf16 per row, padded (80 bytes)
   constexpr int NH = (NTERMS == 1) ? 1 : 2;  // hi (and lo) copies
   int mat, tile;
-  xcd_map(blockIdx.x, mt * mt, nmat, &mat, &tile);
+  xcd_map(blockIdx.x, mtr * mtc, nmat, &mat, &tile);
   if (mat >= nmat) return;
-  const int ti = tile % mt, tj = tile / mt;
+  const int ti = tile % mtr, tj = tile / mtr;
   float* A = LU + (size_t)mat * npad * npad;
   const int r0 = k0 + NB + ti * 128, c0 = k0 + NB + tj * 128;
   // [L21/U12][buffer][hi/lo][row or column][k], or the epilogue's 128 x 132 floats
@@ -186,14 +187,14 @@ __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int
 // through double-buffered LDS, four wavefronts of 64 x 64 (4 x 4 MFMA blocks).
 // ---------------------------------------------------------------------------
 template <typename T, int KC>
-__global__ __launch_bounds__(256, 2) void k_update(T* __restrict__ LU, int npad, int k0, int mt, int nmat) {
+__global__ __launch_bounds__(256, 2) void k_update(T* __restrict__ LU, int npad, int k0, int mtr, int mtc, int nmat) {
   using V = typename Vec4<T>::type;
   constexpr int PER = Vec4<T>::per;
   constexpr int LD = 128 + 4;
   int mat, tile;
-  xcd_map(blockIdx.x, mt * mt, nmat, &mat, &tile);
+  xcd_map(blockIdx.x, mtr * mtc, nmat, &mat, &tile);
   if (mat >= nmat) return;
-  const int ti = tile % mt, tj = tile / mt;
+  const int ti = tile % mtr, tj = tile / mtr;
   T* A = LU + (size_t)mat * npad * npad;
   const int r0 = k0 + NB + ti * 128, c0 = k0 + NB + tj * 128;
   // one LDS block: the two K-chunk buffers of L21 (sA) and U12 (sB), reused by
@@ -279,22 +280,22 @@ __global__ __launch_bounds__(256, 2) void k_update(T* __restrict__ LU, int npad,
 
 }  // namespace
 
-void launch_update(int kind, void* LU, int npad, int k0, int mt, int nmat, bool half_kc, hipStream_t s) {
-  const dim3 gu = xcd_grid(mt * mt, nmat);
+void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int nmat, bool half_kc, hipStream_t s) {
+  const dim3 gu = xcd_grid(mtr * mtc, nmat);
   switch (kind) {
     case 0:
-      if (half_kc) k_update<double, 8><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mt, nmat);
-      else k_update<double, 16><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mt, nmat);
+      if (half_kc) k_update<double, 8><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, nmat);
+      else k_update<double, 16><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, nmat);
       break;
     case 2:
-      k_update_bf16<1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mt, nmat);
+      k_update_bf16<1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
       break;
     case 3:
-      k_update_bf16<3><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mt, nmat);
+      k_update_bf16<3><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
       break;
     default:
-      if (half_kc) k_update<float, 16><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mt, nmat);
-      else k_update<float, 32><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mt, nmat);
+      if (half_kc) k_update<float, 16><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
+      else k_update<float, 32><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
       break;
   }
 }

@@ -108,3 +108,40 @@ def test_host_assembly_matches_oracle(case):
             Qo = np.linalg.inv(B)
             Qo[:, b] = 0.0
             assert rel(Q[i, a], Qo) < 1e-12
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_harmonic_operators_are_banded_and_match_ordinates(case):
+    """The harmonic-basis operators of the banded V solver (eq. f_expansion,
+    eq. proj_ops): P_O C_h P_S reproduces the oracle's C_ord (and A_ord), T_S T_O
+    is the identity, C_h is block diagonal in l and A_h couples l to l +- 1 only,
+    i.e. both vanish outside half-bandwidth 2 Nr - 1 of the l-major ordering."""
+    from paper_2502_16555_amd import host_operator
+    cfg = CASES[case]()
+    ops = oracle.build_operators(cfg)
+    nr, nth = ops.nr, ops.nth
+    n = nr * nth
+    Ch = host_operator(cfg, 10, n * n).reshape(n, n)
+    Ah = host_operator(cfg, 11, n * n).reshape(n, n)
+    TO = host_operator(cfg, 12, nth * nth).reshape(nth, nth)
+    TS = host_operator(cfg, 13, nth * nth).reshape(nth, nth)
+    assert np.abs(TS @ TO - np.eye(nth)).max() < 1e-12
+    # P_S: ordinate index k * nth + a -> harmonic index l * nr + k
+    PS = np.zeros((n, n))
+    PO = np.zeros((n, n))
+    for k in range(nr):
+        for a in range(nth):
+            for l in range(nth):
+                PS[l * nr + k, k * nth + a] = TS[l, a]
+                PO[k * nth + a, l * nr + k] = TO[a, l]
+
+    def rel(a, b):
+        return np.abs(a - b).max() / np.abs(b).max()
+
+    assert rel(PO @ Ch @ PS, ops.Cord) < 5e-12
+    assert rel(PO @ Ah @ PS, ops.Aord) < 1e-12
+    i, j = np.indices((n, n))
+    outside = np.abs(i - j) > 2 * nr - 1
+    assert not Ch[outside].any() and not Ah[outside].any()
+    # C_h does not couple different l at all
+    assert not Ch[(i // nr) != (j // nr)].any()
