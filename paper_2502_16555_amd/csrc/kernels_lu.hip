@@ -10,10 +10,11 @@
 // L_2^-1, ..., U^-1 in that order (A = P_1^T L_1 P_2^T L_2 ... U).
 //
 // Per panel k0:
-//   k_panel   one 512-thread block per matrix: partial pivoting (max |a|, ties
-//             to the lowest row) over register-resident sub-panels of 8 (FP64)
-//             or 16 (FP32) columns, in-panel updates of the remaining columns,
-//             and the panel's row permutation for the trailing columns;
+//   k_panel   one 512-thread block per matrix (256 for panels of at most 256
+//             rows): partial pivoting (max |a|, ties to the lowest row) over
+//             register-resident sub-panels of 8 (FP64) or 16 (FP32) columns,
+//             in-panel updates of the remaining columns, and the panel's row
+//             permutation for the trailing columns;
 //   k_dinv    one block per matrix: inverses of the 16 x 16 diagonal blocks of
 //             the panel's unit lower block L11;
 //   k_u12     per 32 trailing columns: the panel's interchanges and
@@ -45,10 +46,19 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* __restrict__ CT,
                                               const double* __restrict__ AT, const double* __restrict__ E,
                                               const double* __restrict__ n0x, double dt, int n, int npad, int nmat,
-                                              int xpb) {
+                                              int xpb, int kl, int ku) {
   constexpr int CH = kMaxRows / 1024;  // 4-row groups per thread
   const int c = blockIdx.x, tid = threadIdx.x;
   const int x0 = blockIdx.y * xpb, x1 = min(nmat, x0 + xpb);
+  // banded factors (lower / upper bandwidth kl / ku, kl > 0): only rows
+  // [r_lo, r_hi) of column c are ever read, from the U rows of the first panel
+  // whose trailing columns reach c to the last L row of c's own panel
+  int r_lo = 0, r_hi = npad;
+  if (kl > 0) {
+    const int kp = c / NB * NB;
+    r_lo = max(0, (kp - kl - ku) / NB * NB - NB);
+    r_hi = min(npad, (kp + NB + kl + NB - 1) / NB * NB);
+  }
   double cv[CH][4], av[CH][4];
 #pragma unroll
   for (int ch = 0; ch < CH; ++ch)
@@ -65,7 +75,7 @@ __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* 
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
       const int r0 = 4 * tid + 1024 * ch;
-      if (r0 < npad) {
+      if (r0 >= r_lo && r0 < r_hi) {
         T v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) v[u] = static_cast<T>(-dt * (nn * cv[ch][u] + e * av[ch][u]) + (r0 + u == c ? 1.0 : 0.0));
@@ -78,6 +88,45 @@ __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* 
       }
     }
   }
+}
+
+// Wavefront reductions through DPP lane permutations (quad swaps, half-row and
+// row mirrors) inside each row of 16 lanes, then the four row results by lane
+// reads: no LDS round trip on the pivot search's critical path.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(b), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ inline double readlane_f64(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+// maximum over the wavefront of values that are never NaN; uniform result
+__device__ inline double wave_max(double v) {
+  double o = dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]
+  v = o > v ? o : v;
+  o = dpp_f64<0x4E>(v);         // quad_perm [2,3,0,1]
+  v = o > v ? o : v;
+  o = dpp_f64<0x141>(v);        // row_half_mirror
+  v = o > v ? o : v;
+  o = dpp_f64<0x140>(v);        // row_mirror
+  v = o > v ? o : v;
+  const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16), r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+  const double m0 = r1 > r0 ? r1 : r0, m1 = r3 > r2 ? r3 : r2;
+  return m1 > m0 ? m1 : m0;
+}
+__device__ inline int wave_min(int v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // ---------------------------------------------------------------------------
@@ -105,7 +154,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
   __shared__ int s_src[2 * IB];
   __shared__ int s_lab[kMaxSwapRows];
   __shared__ int s_pos[kMaxRows];
-  __shared__ int s_nR, s_any;
+  __shared__ int s_nR, s_any, s_cnt[2];
   bool singular = false, nonfinite = false;
 
   for (int sp = 0; sp < NB / IB; ++sp) {
@@ -133,13 +182,10 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
           }
         }
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > best || (ov == best && oi < bi)) {
-          best = ov;
-          bi = oi;
-        }
+      {
+        const double wm = wave_max(best);
+        bi = wave_min(best == wm ? bi : INT_MAX);
+        best = wm;
       }
       // One barrier per column: every wavefront publishes its partial maximum
       // together with the row it belongs to, thread j publishes row c; after the
@@ -236,39 +282,37 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
 #pragma unroll
       for (int j = 0; j < IB; ++j) s_L11[tid][j] = a[0][j];
     }
-    // permutation of the rows touched by this sub-panel's interchanges
+    // permutation of the rows touched by this sub-panel's interchanges: rows
+    // c0..c0+IB-1 and the distinct pivot rows below, each traced back through
+    // the interchanges (last first) to the row its content comes from
+    __syncthreads();
+    if (wid == 0) {
+      int p = 0;
+      bool own = false;
+      if (lane < IB) {
+        p = s_sw[lane];
+        own = p >= c0 + IB;
+        for (int jj = 0; jj < lane; ++jj)
+          if (s_sw[jj] == p) own = false;
+      }
+      const unsigned long long m = __ballot(own);
+      const int rank = __popcll(m & ((1ull << lane) - 1ull));
+      if (lane < IB) s_R[lane] = c0 + lane;
+      if (own) s_R[IB + rank] = p;
+      if (lane == 0) s_nR = IB + __popcll(m);
+    }
+    __syncthreads();
+    if (tid < s_nR) {
+      int x = s_R[tid];
+      for (int jj = IB - 1; jj >= 0; --jj) {
+        const int pj = s_sw[jj], cj = c0 + jj;
+        x = (x == cj) ? pj : (x == pj ? cj : x);
+      }
+      s_src[tid] = x;
+    }
     if (tid == 0) {
-      int nR = IB, any = 0;
-      int* lab = s_lab;
-      for (int t = 0; t < IB; ++t) {
-        s_R[t] = c0 + t;
-        lab[t] = t;
-      }
-      for (int j = 0; j < IB; ++j) {
-        const int p = s_sw[j];
-        int i2;
-        if (p < c0 + IB) {
-          i2 = p - c0;
-        } else {
-          i2 = -1;
-          for (int t = IB; t < nR; ++t)
-            if (s_R[t] == p) i2 = t;
-          if (i2 < 0) {
-            i2 = nR;
-            s_R[nR] = p;
-            lab[nR] = nR;
-            ++nR;
-          }
-        }
-        if (i2 != j) {
-          any = 1;
-          const int tmp = lab[j];
-          lab[j] = lab[i2];
-          lab[i2] = tmp;
-        }
-      }
-      for (int t = 0; t < nR; ++t) s_src[t] = s_R[lab[t]];
-      s_nR = nR;
+      int any = 0;
+      for (int jj = 0; jj < IB; ++jj) any |= s_sw[jj] != c0 + jj;
       s_any = any;
     }
     __syncthreads();
@@ -316,7 +360,8 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
       // rows >= c0+IB: A[r][rest] -= L[r][c0:c0+IB] U[c0:c0+IB][rest], in batches of
       // CB columns; the next batch is loaded before the current one is stored so
       // that two batches of loads are in flight per thread
-      constexpr int CB = (sizeof(T) == 8 && RPT == 4) ? 2 : 4;
+      // (the batch sizes keep every variant free of register spills)
+      constexpr int CB = sizeof(T) == 8 ? (RPT == 1 ? 8 : 4) : (RPT == 1 ? 16 : (RPT == 2 ? 8 : 4));
       T v[RPT][CB], nv[RPT][CB];
       auto ld = [&](T (&dst)[RPT][CB], int cb) {
 #pragma unroll
@@ -357,42 +402,44 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
   }
   if (singular && tid == 0) atomicOr(status, kStSingular);
   if (nonfinite && tid == 0) atomicOr(status, kStNonFinite);
-  // pivots out, then the permutation of the whole panel for the trailing columns
-  for (int t = tid; t < NB; t += NT) ip[k0 + t] = s_piv[t];
-  for (int r = k0 + NB + tid; r < rend; r += NT) s_pos[r] = -1;
+  // pivots out, then the permutation of the whole panel for the trailing columns:
+  // the panel's rows and the distinct pivot rows below it in the order of their
+  // first selection, with their sources traced back as above
   __syncthreads();
-  if (tid == 0) {
-    int* pm = perm + ((size_t)mat * kMaxPanels + k0 / NB) * kPermStride;
-    int* R = pm + 1;
-    int* src = pm + 1 + kMaxSwapRows;
-    int* lab = s_lab;
-    int nR = NB;
-    for (int t = 0; t < NB; ++t) {
-      R[t] = k0 + t;
-      lab[t] = t;
-    }
-    for (int j = 0; j < NB; ++j) {
-      const int p = s_piv[j];
-      int i2;
-      if (p < k0 + NB) {
-        i2 = p - k0;
-      } else {
-        i2 = s_pos[p];
-        if (i2 < 0) {
-          i2 = nR;
-          s_pos[p] = nR;
-          R[nR] = p;
-          lab[nR] = nR;
-          ++nR;
-        }
-      }
-      const int tmp = lab[j];
-      lab[j] = lab[i2];
-      lab[i2] = tmp;
-    }
-    for (int t = 0; t < nR; ++t) src[t] = R[lab[t]];
-    pm[0] = nR;
+  for (int t = tid; t < NB; t += NT) ip[k0 + t] = s_piv[t];
+  for (int r = k0 + NB + tid; r < rend; r += NT) s_pos[r] = INT_MAX;
+  __syncthreads();
+  if (tid < NB) {
+    const int p = s_piv[tid];
+    if (p >= k0 + NB) atomicMin(&s_pos[p], tid);
   }
+  __syncthreads();
+  unsigned long long om = 0;
+  int orank = 0, pown = 0;
+  bool own = false;
+  if (tid < NB) {
+    pown = s_piv[tid];
+    own = pown >= k0 + NB && s_pos[pown] == tid;
+    om = __ballot(own);
+    orank = __popcll(om & ((1ull << lane) - 1ull));
+    if (lane == 0) s_cnt[wid] = __popcll(om);
+    s_lab[tid] = k0 + tid;
+  }
+  __syncthreads();
+  const int nRf = NB + s_cnt[0] + s_cnt[1];
+  if (own) s_lab[NB + orank + (wid == 1 ? s_cnt[0] : 0)] = pown;
+  __syncthreads();
+  int* pm = perm + ((size_t)mat * kMaxPanels + k0 / NB) * kPermStride;
+  for (int t = tid; t < nRf; t += NT) {
+    int x = s_lab[t];
+    for (int j = NB - 1; j >= 0; --j) {
+      const int pj = s_piv[j], cj = k0 + j;
+      x = (x == cj) ? pj : (x == pj ? cj : x);
+    }
+    pm[1 + t] = s_lab[t];
+    pm[1 + kMaxSwapRows + t] = x;
+  }
+  if (tid == 0) pm[0] = nRf;
 }
 
 // ---------------------------------------------------------------------------
@@ -744,7 +791,8 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   int* perm = d.perm + (size_t)m0 * kMaxPanels * kPermStride;
   const int xpb = d.form_xpb > 0 ? d.form_xpb : 16;  // matrices per formation block
   dim3 gform(d.npad, (nmat + xpb - 1) / xpb);
-  k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, xpb);
+  k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, xpb,
+                                  d.band_kl, d.band_ku);
   const int np = d.npad / NB;
   if (tm) tm->used = 0;
   constexpr int IB = sizeof(T) == 8 ? 8 : 16;   // register sub-panel width (VGPR budget of 512 threads)
@@ -765,7 +813,9 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     const int rows = rend - k0;
     const int rest = cend - k0 - NB;
     constexpr int NT = kPanelThreads;  // 512 threads holding up to 4 rows each
-    if (rows <= NT) k_panel<T, NT, 1, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+    // short panels (the last ones, banded systems): four wavefronts, one row each
+    if (rows <= NT / 2) k_panel<T, NT / 2, 1, IB><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+    else if (rows <= NT) k_panel<T, NT, 1, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     else if (rows <= 2 * NT) k_panel<T, NT, 2, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     else k_panel<T, NT, 4, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     if (rest > 0) {
