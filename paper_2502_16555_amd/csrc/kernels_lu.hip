@@ -132,7 +132,7 @@ __device__ inline int wave_min(int v) {
 // ---------------------------------------------------------------------------
 // Panel factorization: rows k0.., columns k0..k0+NB-1, one block per matrix.
 // ---------------------------------------------------------------------------
-template <typename T, int NT, int RPT, int IB>
+template <typename T, int NT, int RPT, int IB, int CB>
 __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restrict__ piv,
                                                          int* __restrict__ perm, int* __restrict__ status, int npad,
                                                          int k0, int rend) {
@@ -360,8 +360,6 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
       // rows >= c0+IB: A[r][rest] -= L[r][c0:c0+IB] U[c0:c0+IB][rest], in batches of
       // CB columns; the next batch is loaded before the current one is stored so
       // that two batches of loads are in flight per thread
-      // (the batch sizes keep every variant free of register spills)
-      constexpr int CB = sizeof(T) == 8 ? (RPT == 1 ? 8 : 4) : (RPT == 1 ? 16 : (RPT == 2 ? 8 : 4));
       T v[RPT][CB], nv[RPT][CB];
       auto ld = [&](T (&dst)[RPT][CB], int cb) {
 #pragma unroll
@@ -813,11 +811,19 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     const int rows = rend - k0;
     const int rest = cend - k0 - NB;
     constexpr int NT = kPanelThreads;  // 512 threads holding up to 4 rows each
-    // short panels (the last ones, banded systems): four wavefronts, one row each
-    if (rows <= NT / 2) k_panel<T, NT / 2, 1, IB><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
-    else if (rows <= NT) k_panel<T, NT, 1, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
-    else if (rows <= 2 * NT) k_panel<T, NT, 2, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
-    else k_panel<T, NT, 4, IB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+    // block shape and in-panel update batch by panel height (measured): short
+    // panels (the last ones, banded systems) take four wavefronts, which have
+    // the larger register budget for deeper batches
+    if (rows <= NT / 2) {
+      k_panel<T, NT / 2, 1, IB, sizeof(T) == 8 ? 8 : 16><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+    } else if (rows <= NT) {
+      if constexpr (sizeof(T) == 8) k_panel<T, NT, 1, IB, 8><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+      else k_panel<T, NT / 2, 2, IB, 16><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+    } else if (rows <= 2 * NT) {
+      k_panel<T, NT, 2, IB, 4><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+    } else {
+      k_panel<T, NT, 4, IB, 4><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+    }
     if (rest > 0) {
       const int nct = rest / 32;  // U12 blocks of 32 columns
       k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);
