@@ -12,6 +12,7 @@ Tolerances (relative, max-norm over the compared array):
 """
 import math
 import os
+import sys
 
 import numpy as np
 import pytest
@@ -286,15 +287,24 @@ def test_nonfinite_field_is_reported(torch, prec):
     s.close()
 
 
-def test_c1_golden_cycle(torch):
-    """Realistic RF case, one full cycle (1000 steps), FP64 on the GPU against the
-    stored oracle moments (written by tests/golden/make_golden.py)."""
+@pytest.mark.parametrize("mode,tol", [("fp64", 1e-8), ("mixed_fp32", 1e-6), ("banded", 1e-8)])
+def test_c1_golden_cycle(torch, mode, tol):
+    """Realistic RF case (Nx=64, Nr=64, Ntheta=32), one full cycle of 1000 steps on
+    the GPU against the stored oracle moments (written by
+    tests/golden/make_golden.py, which calls only the oracle): n_e, the mean
+    energy and the energy density every 100 steps and the final state, within
+    1e-8 for the FP64 solvers and 1e-6 for the mixed FP32 + FP64 refinement step."""
     path = os.path.join(ROOT, "tests", "golden", "c1_oracle_1000.npz")
     if not os.path.exists(path):
         pytest.skip("golden file not generated")
     g = np.load(path, allow_pickle=False)
     cfg = workloads.config("C1")
-    s = solver(cfg, precision="fp64")
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_golden
+    assert str(g["config_hash"]) == make_golden.config_hash(cfg), "C1 workload changed since the golden run"
+    s = solver(cfg, precision="fp64" if mode == "banded" else mode)
+    if mode == "banded":
+        s.set_vsolver("banded")
     ne = workloads.density_profile(s.xhat(), cfg["ic"]["ne_peak"])
     Fg = s.initial_state(cuda(torch, ne), cfg["ic"]["Te_eV"])
     every = int(g["every"])
@@ -303,9 +313,10 @@ def test_c1_golden_cycle(torch):
         if (n + 1) % every == 0:
             mg = s.moments(Fg).cpu().numpy()
             mo = g["moments"][(n + 1) // every]
-            close(mg[0], mo[0], 1e-8, n)
-            close(mg[0] * mg[1], mo[0] * mo[1], 1e-8, n)
-    close(Fg.cpu().numpy(), g["F"], 1e-8, '')
+            close(mg[0], mo[0], tol, f"{mode} n_e at step {n + 1}")
+            close(mg[1], mo[1], tol, f"{mode} mean energy at step {n + 1}")
+            close(mg[0] * mg[1], mo[0] * mo[1], tol, f"{mode} energy density at step {n + 1}")
+    close(Fg.cpu().numpy(), g["F"], tol, f"{mode} final state")
     assert s.status()[0] == 0
     s.close()
 
