@@ -676,7 +676,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       if (w == 0) {  // unit lower triangular diagonal block
         double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
         for (int i = 0; i < NB - 1; ++i) {
-          const double xi = (i < 64) ? __shfl(v0, i) : __shfl(v1, i - 64);
+          const double xi = (i < 64) ? readlane_f64(v0, i) : readlane_f64(v1, i - 64);
           if (lane > i) v0 -= static_cast<double>(sD[lane][i]) * xi;
           if (64 + lane > i) v1 -= static_cast<double>(sD[64 + lane][i]) * xi;
         }
@@ -694,10 +694,13 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       __syncthreads();
       if (w == 0) {  // upper triangular diagonal block
         double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
+        // reciprocals of the diagonal off the sequential chain
+        const double r0 = 1.0 / static_cast<double>(sD[lane][lane]);
+        const double r1 = 1.0 / static_cast<double>(sD[64 + lane][64 + lane]);
         for (int i = NB - 1; i >= 0; --i) {
-          if (i >= 64 && lane == i - 64) v1 = v1 / static_cast<double>(sD[i][i]);
-          if (i < 64 && lane == i) v0 = v0 / static_cast<double>(sD[i][i]);
-          const double xi = (i < 64) ? __shfl(v0, i) : __shfl(v1, i - 64);
+          if (i >= 64 && lane == i - 64) v1 = v1 * r1;
+          if (i < 64 && lane == i) v0 = v0 * r0;
+          const double xi = (i < 64) ? readlane_f64(v0, i) : readlane_f64(v1, i - 64);
           if (lane < i) v0 -= static_cast<double>(sD[lane][i]) * xi;
           if (64 + lane < i) v1 -= static_cast<double>(sD[64 + lane][i]) * xi;
         }
@@ -718,10 +721,12 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       __syncthreads();
       if (w == 0) {
         double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
+        const double r0 = 1.0 / static_cast<double>(sD[lane][lane]);
+        const double r1 = 1.0 / static_cast<double>(sD[64 + lane][64 + lane]);
         for (int i = 0; i < NB; ++i) {
-          if (i < 64 && lane == i) v0 = v0 / static_cast<double>(sD[i][i]);
-          if (i >= 64 && lane == i - 64) v1 = v1 / static_cast<double>(sD[i][i]);
-          const double xi = (i < 64) ? __shfl(v0, i) : __shfl(v1, i - 64);
+          if (i < 64 && lane == i) v0 = v0 * r0;
+          if (i >= 64 && lane == i - 64) v1 = v1 * r1;
+          const double xi = (i < 64) ? readlane_f64(v0, i) : readlane_f64(v1, i - 64);
           if (lane > i) v0 -= static_cast<double>(sD[i][lane]) * xi;
           if (64 + lane > i) v1 -= static_cast<double>(sD[i][64 + lane]) * xi;
         }
@@ -755,7 +760,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       if (w == 0) {  // L11^T is unit upper triangular
         double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
         for (int i = NB - 1; i >= 0; --i) {
-          const double xi = (i < 64) ? __shfl(v0, i) : __shfl(v1, i - 64);
+          const double xi = (i < 64) ? readlane_f64(v0, i) : readlane_f64(v1, i - 64);
           if (lane < i) v0 -= static_cast<double>(sD[i][lane]) * xi;
           if (64 + lane < i) v1 -= static_cast<double>(sD[i][64 + lane]) * xi;
         }
