@@ -288,8 +288,9 @@ bte_status bte_get_timing(bte_handle* h, double* ms_out);
  *     events, so that the latency-bound panel kernels of one group can overlap
  *     the MFMA updates of another.  1..4, default 1.
  *   BTE_TUNE_UPDATE_KC: K chunk of the trailing-update tiles staged per LDS
- *     buffer: 16 or 32 (FP32 and BF16 factors), 8 or 16 (FP64); 0 = default
- *     (32 / 16).  The BF16 updates have a fixed chunk of 32.
+ *     buffer: 16 or 32 (FP32 factors), 8 or 16 (FP64); 0 = default (16).  The
+ *     16-chunk FP32 form runs four blocks per CU, the 32-chunk form two.  The
+ *     BF16 updates have a fixed chunk of 32 (reported as such).
  *   BTE_TUNE_FORM_XPB: matrices formed per block of the formation kernel,
  *     1..64; 0 = default (16).
  * Returns BTE_EINVAL for an unknown key or a value out of range. */

@@ -975,7 +975,11 @@ bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value) {
   const bool fp64 = h->cfg.precision == BTE_FP64;
   switch (key) {
     case BTE_TUNE_LU_STREAMS: *value = h->lu_streams; return BTE_OK;
-    case BTE_TUNE_UPDATE_KC: *value = h->d.update_kc ? h->d.update_kc : (fp64 ? 16 : 32); return BTE_OK;
+    case BTE_TUNE_UPDATE_KC: {
+      const bool bf16 = h->cfg.precision == BTE_MIXED_BF16 || h->cfg.precision == BTE_MIXED_BF16X3;
+      *value = bf16 ? 32 : (h->d.update_kc ? h->d.update_kc : 16);
+      return BTE_OK;
+    }
     case BTE_TUNE_FORM_XPB: *value = h->d.form_xpb ? h->d.form_xpb : 16; return BTE_OK;
     default: return BTE_EINVAL;
   }

@@ -138,8 +138,8 @@ void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* ti
                       int count = -1);
 // A22 -= L21 U12 of panel k0 for nmat matrices (mtr x mtc tiles of 128): kind 0
 // FP64, 1 FP32, 2 FP32 with bf16 operands, 3 FP32 with split bf16 operands;
-// half_kc: K chunk 16 (FP32) / 8 (FP64) instead of 32 / 16.
-void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int nmat, bool half_kc, hipStream_t s);
+// alt_kc: K chunk 32 (FP32) / 8 (FP64) instead of 16.
+void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int nmat, bool alt_kc, hipStream_t s);
 // X = LU^-1 B (or LU^-T B with transpose), rows of length npad, FP64 right-hand sides.
 void launch_lu_solve(const DevOps& d, int precision, bool transpose, const double* Bin, double* Xout,
                      bool accumulate, bool check_done, hipStream_t s);

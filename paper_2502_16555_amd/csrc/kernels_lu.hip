@@ -799,10 +799,9 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   const int np = d.npad / NB;
   if (tm) tm->used = 0;
   constexpr int IB = sizeof(T) == 8 ? 8 : 16;   // register sub-panel width (VGPR budget of 512 threads)
-  // K chunk of the trailing update (launch shape only: the K order is the same)
-  constexpr int KC = sizeof(T) == 8 ? 16 : 32;
-  const bool half_kc = d.update_kc == KC / 2;
-  (void)KC;
+  // K chunk of the trailing update (launch shape only: the K order is the same):
+  // the default 16, or the alternative 8 (FP64) / 32 (FP32)
+  const bool alt_kc = d.update_kc == (sizeof(T) == 8 ? 8 : 32);
   // banded systems (lower / upper bandwidth kl / ku): the rows below a panel end
   // kl below it; partial pivoting widens the upper band to kl + ku
   const int kl = d.band_kl, ku = d.band_ku;
@@ -840,7 +839,7 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
       const int mtr = (rend - k0 - NB) / 128, mtc = rest / 128;
       if (mtr > 0)
         launch_update(sizeof(T) == 8 ? 0 : (bf16_terms == 1 ? 2 : (bf16_terms == 3 ? 3 : 1)), LU, d.npad, k0, mtr,
-                      mtc, nmat, half_kc, s);
+                      mtc, nmat, alt_kc, s);
       if (rec) (void)hipEventRecord(tm->ev[2 * p + 1], s);
     } else if (rec) {
       (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p + 1], s);

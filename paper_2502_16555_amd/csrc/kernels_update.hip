@@ -185,30 +185,33 @@ __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int
 // ---------------------------------------------------------------------------
 // Trailing update A22 -= L21 U12: 128 x 128 tiles, K = NB in chunks of KC staged
 // through double-buffered LDS, four wavefronts of 64 x 64 (4 x 4 MFMA blocks).
+// The epilogue goes through LDS in P passes of 128 / P rows, which bounds the
+// LDS of a block by the K-chunk buffers and lets MINB blocks share a CU; the
+// old values of the first NPP passes are loaded before the last K chunk, those
+// of every later pass before its accumulators are staged, so that their
+// latency hides behind the products or the staging.
 // ---------------------------------------------------------------------------
-template <typename T, int KC>
-__global__ __launch_bounds__(256, 2) void k_update(T* __restrict__ LU, int npad, int k0, int mtr, int mtc, int nmat) {
+template <typename T, int KC, int P, int MINB, int NPP>
+__global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int npad, int k0, int mtr, int mtc, int nmat) {
   using V = typename Vec4<T>::type;
   constexpr int PER = Vec4<T>::per;
   constexpr int LD = 128 + 4;
+  constexpr int RP = 128 / P;
+  constexpr int LDC = RP + 4 / (sizeof(T) / 4);
   int mat, tile;
   xcd_map(blockIdx.x, mtr * mtc, nmat, &mat, &tile);
   if (mat >= nmat) return;
   const int ti = tile % mtr, tj = tile / mtr;
   T* A = LU + (size_t)mat * npad * npad;
   const int r0 = k0 + NB + ti * 128, c0 = k0 + NB + tj * 128;
-  // one LDS block: the two K-chunk buffers of L21 (sA) and U12 (sB), reused by
-  // the epilogue (128 columns x (128 + 4) floats or 2 x 64 x (64 + 2) doubles)
   constexpr int OPER = 2 * 2 * KC * LD;
-  constexpr int EPI = 128 * (128 / (sizeof(T) / 4) + 4 / (sizeof(T) / 4));
+  constexpr int EPI = 128 * LDC;
   __shared__ __align__(16) T smem[OPER > EPI ? OPER : EPI];
   T (*sA)[KC][LD] = reinterpret_cast<T (*)[KC][LD]>(smem);
   T (*sB)[KC][LD] = reinterpret_cast<T (*)[KC][LD]>(smem + 2 * KC * LD);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
-  // global -> register staging of one K chunk: A part KC columns x 128 rows,
-  // B part 128 columns x KC rows, both as PER-wide vectors down a column
   constexpr int NA = KC * 128 / PER / 256, NBV = KC * 128 / PER / 256;
   V ra[NA], rb[NBV];
   auto load = [&](int kk) {
@@ -252,12 +255,23 @@ __global__ __launch_bounds__(256, 2) void k_update(T* __restrict__ LU, int npad,
   store(0);
   __syncthreads();
   constexpr int NCH = NB / KC;
-  constexpr bool PREF = sizeof(T) == 4;   // register room for the tile's old values
-  float4 pre[PREF ? kPreV : 1];
+  constexpr int NV = 128 * RP / PER / 256;   // vectors per thread per pass
+  V pre[NPP > 0 ? NPP : 1][NV];
+  auto prefetch = [&](int pass, V (&dst)[NV]) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int e = tid + u * 256;
+      const int col = e / (RP / PER), rr = (e % (RP / PER)) * PER;
+      dst[u] = *reinterpret_cast<const V*>(A + (size_t)(c0 + col) * npad + r0 + pass * RP + rr);
+    }
+  };
   for (int ch = 0; ch < NCH; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < NCH) load((ch + 1) * KC);
-    else if constexpr (PREF) tile_prefetch(reinterpret_cast<const float*>(A), npad, r0, c0, pre);
+    else {
+#pragma unroll
+      for (int pp = 0; pp < NPP; ++pp) prefetch(pp, pre[pp]);
+    }
 #pragma unroll
     for (int k = 0; k < KC; k += 4) {
       T av[4], bv[4];
@@ -275,17 +289,50 @@ __global__ __launch_bounds__(256, 2) void k_update(T* __restrict__ LU, int npad,
       __syncthreads();
     }
   }
-  update_epilogue<T, PREF>(A, npad, r0, c0, acc, smem, pre);
+  T* sC = smem;
+#pragma unroll
+  for (int pass = 0; pass < P; ++pass) {
+    V old[NV];
+    if (pass >= NPP) prefetch(pass, old);
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+      if ((wr + bi * 16) / RP == pass) {
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+          for (int it = 0; it < 4; ++it)
+            sC[(wc + bj * 16 + li) * LDC + wr + bi * 16 - pass * RP + Mma<T>::row(lk, it)] = acc[bi][bj][it];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int e = tid + u * 256;
+      const int col = e / (RP / PER), rr = (e % (RP / PER)) * PER;
+      V* p = reinterpret_cast<V*>(A + (size_t)(c0 + col) * npad + r0 + pass * RP + rr);
+      V o;
+      if (pass < NPP) o = pre[pass < NPP ? pass : 0][u];
+      else o = old[u];
+      const V a = *reinterpret_cast<const V*>(sC + col * LDC + rr);
+      T* po = reinterpret_cast<T*>(&o);
+      const T* pa = reinterpret_cast<const T*>(&a);
+#pragma unroll
+      for (int m = 0; m < PER; ++m) po[m] -= pa[m];
+      *p = o;
+    }
+  }
 }
+
 
 }  // namespace
 
-void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int nmat, bool half_kc, hipStream_t s) {
+void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int nmat, bool alt_kc, hipStream_t s) {
   const dim3 gu = xcd_grid(mtr * mtc, nmat);
   switch (kind) {
     case 0:
-      if (half_kc) k_update<double, 8><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, nmat);
-      else k_update<double, 16><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, nmat);
+      if (alt_kc) k_update<double, 8, 4, 2, 1><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, nmat);
+      else k_update<double, 16, 4, 2, 1><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, nmat);
       break;
     case 2:
       k_update_bf16<1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
@@ -294,8 +341,8 @@ void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int n
       k_update_bf16<3><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
       break;
     default:
-      if (half_kc) k_update<float, 16><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
-      else k_update<float, 32><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
+      if (alt_kc) k_update<float, 32, 1, 2, 1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
+      else k_update<float, 16, 4, 4, 1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
       break;
   }
 }
