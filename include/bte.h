@@ -157,6 +157,28 @@ bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle
  * Errors (synchronous): BTE_EINVAL.  Device errors are latched. */
 bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void* stream);
 
+/* Heavies' update of the hybrid model (operator split of eq. glow_hybrid,
+ * eq. fluid_step), POISSON field mode only:
+ *   (n_i^{n+1} - n_i^n)/dt + D_x J_i(E^n, n_i^{n+1}) = (k_i^T F^n) n0 (u^T F^n),
+ *   J_i = mu_i n_i E - D_i D_x n_i (eq. hybrid_cnt_a_flux),
+ * with E^n = L (n_i^n - u^T F^n) at t_s (eq. hybrid_cnt_c with the voltage of
+ * eq. voltage_bc at t_s) frozen, per discharge on its CGL points.  The walls take
+ * the drift outflow condition of eq. fl_ion_bc with the outward normal,
+ * J_i . n = n_i max(0, mu_i E . n) (no inflow), in place of the equation at the
+ * wall nodes.  Ion coefficients from the table of modeling parameters:
+ * n0 mu_i = 4.65e21 /(V m s), n0 D_i = 2.07e20 /(m s), n0 per discharge.
+ * F is device [sum Nx][Nr][Ntheta] (read), ni_in / ni_out device [sum Nx]
+ * (distinct).  Each discharge's Nx x Nx system is solved by Gaussian
+ * elimination with partial pivoting on the device; a zero pivot latches
+ * BTE_ESINGULAR, a non-finite one BTE_ENONFINITE in the status word.
+ * Errors: BTE_EINVAL (null pointers), BTE_EUNSUPPORTED (other field modes). */
+bte_status bte_ion_step(bte_handle* h, const double* F, const double* ni_in, double* ni_out, double t_s,
+                        void* stream);
+/* One step of the hybrid model: n_i <- n_i^{n+1} by bte_ion_step, then
+ * F <- bte_step(F, t_s) with the Poisson field of n_i^{n+1}.  ni is device
+ * [sum Nx], updated in place.  POISSON field mode only (else BTE_EUNSUPPORTED). */
+bte_status bte_hybrid_step(bte_handle* h, double* F, double* ni, double t_s, void* stream);
+
 /* Velocity-space solver of bte_step / bte_vstep / bte_graph_capture.
  *   BTE_VSOLVER_LU (default): batched LU factorization of every point's system
  *     each step (FP64, or FP32/BF16 factors with FP64 iterative refinement).

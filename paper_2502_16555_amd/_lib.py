@@ -59,6 +59,8 @@ EXPORTS = {
     "bte_xstep": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "bte_xstep_T": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "bte_vstep": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bte_ion_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "bte_hybrid_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "bte_field_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, bte_field, C.c_void_p, C.c_void_p]),
     "bte_get_operator": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "bte_host_operator": (C.c_int, [C.POINTER(bte_config), C.c_int32, C.POINTER(C.c_double)]),

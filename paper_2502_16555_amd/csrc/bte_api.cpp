@@ -280,6 +280,28 @@ void fill_devops(bte_handle* h) {
     }
   }
   const size_t nxt = d.nx_total;
+  if (c.field_mode == BTE_FIELD_POISSON) {
+    // the heavies' update of the hybrid step: D_x and D_x^2 per discharge
+    std::vector<double> Dx, D2;
+    Dx.reserve(ptot);
+    D2.reserve(ptot);
+    for (auto& X : H.xops) {
+      const int nx = X.nx;
+      Dx.insert(Dx.end(), X.Dx.begin(), X.Dx.end());
+      for (int r = 0; r < nx; ++r)
+        for (int cc = 0; cc < nx; ++cc) {
+          double acc = 0.0;
+          for (int k = 0; k < nx; ++k) acc += X.Dx[(size_t)r * nx + k] * X.Dx[(size_t)k * nx + cc];
+          D2.push_back(acc);
+        }
+    }
+    d.dx = h->upload(Dx);
+    d.dx2 = h->upload(D2);
+    d.ion_M = h->alloc<double>(ptot);
+    d.ion_b = h->alloc<double>(nxt);
+    d.ion_E = h->alloc<double>(nxt);
+    d.ni1 = h->alloc<double>(nxt);
+  }
   d.Y = h->alloc<double>(nxt * d.n);
   const size_t elt = (c.precision == BTE_FP64) ? sizeof(double) : sizeof(float);
   d.lu = h->alloc<char>(nxt * d.npad * d.npad * elt);
@@ -455,6 +477,14 @@ void eval_field(bte_handle* h, const double* Fh, double t_s, const bte_field& f,
   const bte_config& c = h->cfg;
   bte::launch_field(h->d, c.field_mode, t_s + 0.5 * c.dt_s, c.field_freq_hz, c.field_a1, c.poisson_V0, Fh, f.E_half,
                     f.ni, h->d.E, s);
+}
+
+// Heavies' update (eq. fluid_step) with E^n = L (n_i^n - u^T F^n) at t_s.
+void ion_update(bte_handle* h, const double* F, const double* ni_in, double* ni_out, double t_s, hipStream_t s) {
+  const bte_config& c = h->cfg;
+  bte::launch_field(h->d, BTE_FIELD_POISSON, t_s, c.field_freq_hz, c.field_a1, c.poisson_V0, F, nullptr, ni_in,
+                    h->d.ion_E, s);
+  bte::launch_ion_update(h->d, F, ni_in, ni_out, s);
 }
 
 }  // namespace
@@ -651,6 +681,39 @@ bte_status bte_xstep_T(bte_handle* h, double* F, void* stream) {
     h->last_stream = S(stream);
     x_half(h, F, true, S(stream));
     HIP_OK(hipGetLastError());
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_ion_step(bte_handle* h, const double* F, const double* ni_in, double* ni_out, double t_s,
+                        void* stream) {
+  if (!h || !F || !ni_in || !ni_out) return BTE_EINVAL;
+  if (h->cfg.field_mode != BTE_FIELD_POISSON) return BTE_EUNSUPPORTED;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    hipStream_t s = S(stream);
+    h->last_stream = s;
+    ion_update(h, F, ni_in, ni_out, t_s, s);
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_hybrid_step(bte_handle* h, double* F, double* ni, double t_s, void* stream) {
+  if (!h || !F || !ni) return BTE_EINVAL;
+  if (h->cfg.field_mode != BTE_FIELD_POISSON) return BTE_EUNSUPPORTED;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    hipStream_t s = S(stream);
+    h->last_stream = s;
+    ion_update(h, F, ni, h->d.ni1, t_s, s);
+    bte_field f{nullptr, h->d.ni1};
+    const bte_status st = bte_step(h, F, t_s, f, stream);
+    if (st != BTE_OK) return st;
+    HIP_OK(hipMemcpyAsync(ni, h->d.ni1, sizeof(double) * h->d.nx_total, hipMemcpyDeviceToDevice, s));
     return BTE_OK;
   } catch (const std::exception& e) {
     return map_exc(e);

@@ -76,6 +76,13 @@ struct DevOps {
   int* status = nullptr;       // [4]: status bits, done flag, sweeps, spare
   double* resid = nullptr;     // [1] final max_x |r|/|b|
   double* scratch3 = nullptr;  // [3*nx_total] moments scratch
+  // heavies' update of the hybrid model (Poisson field mode only)
+  double* dx = nullptr;        // concatenated [nx_d][nx_d] CGL derivative (physical), offsets p_off
+  double* dx2 = nullptr;       // concatenated D_x D_x
+  double* ion_M = nullptr;     // concatenated [nx_d][nx_d] ion systems (column-major)
+  double* ion_b = nullptr;     // [nx_total] right-hand sides
+  double* ion_E = nullptr;     // [nx_total] E^n
+  double* ni1 = nullptr;       // [nx_total] n_i^{n+1} of the hybrid step
 };
 
 // Batched restarted GMRES of the V step (kernels_gmres.hip): workspace of the
@@ -107,6 +114,10 @@ void launch_gmres_init(const DevOps& d, const GmresOps& q, bool first, hipStream
 void launch_gmres_arnoldi(const DevOps& d, const GmresOps& q, int j, hipStream_t s);
 void launch_gmres_combine(const DevOps& d, const GmresOps& q, hipStream_t s);
 void launch_gmres_status(const DevOps& d, const GmresOps& q, hipStream_t s);
+
+// ---- heavies' update (kernels_ion.hip) ----------------------------------------
+// n_i^{n+1} of eq. fluid_step for every discharge, with E^n already in d.ion_E.
+void launch_ion_update(const DevOps& d, const double* F, const double* ni_in, double* ni_out, hipStream_t s);
 
 // ---- X step (kernels_x.hip) -------------------------------------------------
 void launch_x_to_modes(const DevOps& d, const double* F, hipStream_t s);

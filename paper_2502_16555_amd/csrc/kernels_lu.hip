@@ -90,45 +90,6 @@ __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* 
   }
 }
 
-// Wavefront reductions through DPP lane permutations (quad swaps, half-row and
-// row mirrors) inside each row of 16 lanes, then the four row results by lane
-// reads: no LDS round trip on the pivot search's critical path.
-template <int CTRL>
-__device__ inline double dpp_f64(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(b), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
-__device__ inline double readlane_f64(double v, int l) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
-  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
-  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
-// maximum over the wavefront of values that are never NaN; uniform result
-__device__ inline double wave_max(double v) {
-  double o = dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]
-  v = o > v ? o : v;
-  o = dpp_f64<0x4E>(v);         // quad_perm [2,3,0,1]
-  v = o > v ? o : v;
-  o = dpp_f64<0x141>(v);        // row_half_mirror
-  v = o > v ? o : v;
-  o = dpp_f64<0x140>(v);        // row_mirror
-  v = o > v ? o : v;
-  const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16), r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
-  const double m0 = r1 > r0 ? r1 : r0, m1 = r3 > r2 ? r3 : r2;
-  return m1 > m0 ? m1 : m0;
-}
-__device__ inline int wave_min(int v) {
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false));
-  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-}
-
 // ---------------------------------------------------------------------------
 // Panel factorization: rows k0.., columns k0..k0+NB-1, one block per matrix.
 // ---------------------------------------------------------------------------

@@ -153,6 +153,15 @@ class Solver:
     def xstep_T(self, F, stream=None):
         check(self.lib.bte_xstep_T(self.h, _ptr(F), _stream(stream)), "bte_xstep_T")
 
+    def ion_step(self, F, ni_in, ni_out, t, stream=None):
+        """Heavies' update of the hybrid model (bte_ion_step): ni_out <- n_i^{n+1}."""
+        check(self.lib.bte_ion_step(self.h, _ptr(F), _ptr(ni_in), _ptr(ni_out), float(t), _stream(stream)),
+              "bte_ion_step")
+
+    def hybrid_step(self, F, ni, t, stream=None):
+        """One hybrid step (bte_hybrid_step): ions, then electrons; F and ni in place."""
+        check(self.lib.bte_hybrid_step(self.h, _ptr(F), _ptr(ni), float(t), _stream(stream)), "bte_hybrid_step")
+
     def vstep(self, F, E, stream=None):
         check(self.lib.bte_vstep(self.h, _ptr(F), _ptr(E), _stream(stream)), "bte_vstep")
 

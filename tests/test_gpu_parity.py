@@ -235,6 +235,83 @@ def test_poisson_field_matches_oracle(torch):
     s.close()
 
 
+def _hybrid_cfg(nx=9, V0=150.0):
+    cfg = workloads.small_config(nx=nx, nr=10, nth=6, kinds=("elastic", "excitation", "ionization"), E=5e3,
+                                 field_kind="rf", n_bins=2)
+    cfg["field"] = {"kind": "poisson", "V0": V0, "freq_hz": workloads.RF_FREQ_HZ}
+    return cfg
+
+
+@pytest.mark.parametrize("nx", [9, 37, 130])
+def test_ion_step_matches_oracle(torch, nx):
+    """Heavies' update of the hybrid model (eq. fluid_step) against the oracle's
+    dense solve: ragged Nx (130 spans more than two 64-row wavefronts)."""
+    from oracle import hybrid as H
+    cfg = _hybrid_cfg(nx)
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg)
+    F = S.initial_state(ops, workloads.density_profile(ops.xhat, 1e16), 2.0)
+    ni = 0.8 * S.moments(ops, F)[0] + 3e14 * (1.0 + ops.xhat)
+    t = 0.3 * cfg["T_rf_s"]
+    out = torch.empty(s.nx_total, dtype=torch.float64, device="cuda:0")
+    s.ion_step(cuda(torch, F), cuda(torch, ni), out, t)
+    assert s.status()[0] == 0
+    close(out.cpu().numpy(), H.ion_step(ops, ni, F, t), 1e-10, f"ion step nx={nx}")
+    s.close()
+
+
+def test_hybrid_steps_match_oracle(torch):
+    """Five hybrid steps (ions, then electrons with the Poisson field of the new
+    ion density) against the oracle, F and n_i."""
+    from oracle import hybrid as H
+    cfg = _hybrid_cfg(9)
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg)
+    F0 = S.initial_state(ops, workloads.density_profile(ops.xhat, 1e16), 2.0)
+    ni0 = S.moments(ops, F0)[0] * 1.05
+    F = cuda(torch, F0)
+    ni = cuda(torch, ni0)
+    Fo, nio = F0, ni0
+    t0 = 0.15 * cfg["T_rf_s"]
+    for k in range(5):
+        s.hybrid_step(F, ni, t0 + k * ops.dt)
+        Fo, nio = H.hybrid_step(ops, Fo, nio, t0 + k * ops.dt)
+    assert s.status()[0] == 0
+    close(ni.cpu().numpy(), nio, 1e-10, "n_i")
+    close(F.cpu().numpy(), Fo, 1e-10, "F")
+    s.close()
+
+
+def test_hybrid_ensemble_per_discharge(torch):
+    """The hybrid step of an uneven ensemble (Nx = 5, 9, 7; three pressures)
+    against the oracle per discharge."""
+    from oracle import hybrid as H
+    cfg, members = _ensemble_case()
+    fld = {"kind": "poisson", "V0": 120.0, "freq_hz": workloads.RF_FREQ_HZ}
+    cfg["field"] = fld
+    for m in members:
+        m["field"] = dict(fld)
+    ops = [oracle.build_operators(m) for m in members]
+    F0 = [S.initial_state(o, workloads.density_profile(o.xhat, 1e16), 1.0) for o in ops]
+    ni0 = [S.moments(o, f)[0] * 0.9 for o, f in zip(ops, F0)]
+    s = solver(cfg)
+    F = cuda(torch, np.concatenate(F0))
+    ni = cuda(torch, np.concatenate(ni0))
+    t0 = 0.4 * cfg["T_rf_s"]
+    ref = list(zip(F0, ni0))
+    for k in range(3):
+        s.hybrid_step(F, ni, t0 + k * cfg["dt_s"])
+        ref = [H.hybrid_step(o, f, n, t0 + k * cfg["dt_s"]) for o, (f, n) in zip(ops, ref)]
+    assert s.status()[0] == 0
+    got_F, got_n = F.cpu().numpy(), ni.cpu().numpy()
+    o = 0
+    for d, (f, n) in enumerate(ref):
+        close(got_n[o:o + n.shape[0]], n, 1e-10, f"discharge {d} n_i")
+        close(got_F[o:o + f.shape[0]], f, 1e-10, f"discharge {d} F")
+        o += n.shape[0]
+    s.close()
+
+
 def test_adjoint_step_matches_oracle(torch):
     cfg = CASES["ragged"]()
     ops = oracle.build_operators(cfg)
