@@ -143,6 +143,53 @@ def moment_errors(got, ref):
             "k_i_n_e": rel_err(got[0] * got[2], ref[0] * ref[2])}
 
 
+def run_hybrid(cfg, steps, warmup, torch):
+    """The hybrid model's step at the bench grid: heavies' update (eq. fluid_step)
+    with E^n from the Poisson field (V0 = 100 V), then the electron step with the
+    Poisson field of the new ion density; mixed precision.  Times the whole step
+    and, separately, the ion update alone."""
+    import copy
+    import workloads
+    from paper_2502_16555_amd import Solver
+    hc = copy.deepcopy(cfg)
+    hc["field"] = {"kind": "poisson", "V0": 100.0, "freq_hz": workloads.RF_FREQ_HZ}
+    s = Solver(hc, precision="mixed_fp32")
+    ne = workloads.density_profile(s.xhat(), hc["ic"]["ne_peak"])
+    F = s.initial_state(torch.as_tensor(ne, device="cuda:0"), hc["ic"]["Te_eV"])
+    ni = torch.as_tensor(ne, device="cuda:0").clone()
+    dt = hc["dt_s"]
+    for k in range(warmup):
+        s.hybrid_step(F, ni, k * dt)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        s.hybrid_step(F, ni, (warmup + k) * dt)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out = torch.empty_like(ni)
+    n_ion = 20
+    e0.record()
+    for k in range(n_ion):
+        s.ion_step(F, ni, out, 0.0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_ion = e0.elapsed_time(e1) / n_ion
+    code = s.status()[0]
+    if code != 0:
+        raise RuntimeError(f"hybrid: device status {code}")
+    mom = s.moments(F).cpu().numpy()
+    res = {"workload": f"Nx={hc['nx']}, Nr={hc['nr']}, Ntheta={hc['ntheta']}, Poisson field V0=100 V, "
+                       "ions: n0 mu_i = 4.65e21, n0 D_i = 2.07e20, mixed precision",
+           "steps_per_s": 1000.0 / ms, "ms_per_step": ms, "ms_ion_update": ms_ion,
+           "ni_range": [float(ni.min()), float(ni.max())], "ne_max": float(mom[0].max()),
+           "finite": bool(np.isfinite(mom).all() and torch.isfinite(ni).all())}
+    s.close()
+    return res
+
+
 def run_adjoint(torch, n_steps=100, every=50):
     """Adjoint cost on the differentiation workload (Nx=128, Nr=64, Ntheta=32,
     8 bins x 3 processes + E0, FP64): time of the checkpointed forward pass vs
@@ -248,6 +295,7 @@ def main():
     ap.add_argument("--ensemble", action="store_true", help="also time the 64-discharge batching form")
     ap.add_argument("--no-krylov", action="store_true", help="skip the GMRES V-solver leg")
     ap.add_argument("--no-banded", action="store_true", help="skip the banded harmonic-basis V-solver leg")
+    ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid-model (ions + electrons) leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
@@ -341,6 +389,8 @@ def main():
         if fp64 is not None:
             line["banded"]["speedup_over_fp64_lu"] = fp64["ms_per_step"] / bd["ms_per_step"]
             line["banded"]["vs_fp64_lu"] = dict(moment_errors(bd["moments"], fp64["moments"]), steps=bd["n_end"])
+    if not args.no_hybrid:
+        line["hybrid"] = run_hybrid(cfg, min(args.steps, 20), 2, torch)
     if not args.no_adjoint:
         line["adjoint"] = run_adjoint(torch)
     if args.ensemble:

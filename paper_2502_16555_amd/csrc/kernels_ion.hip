@@ -72,25 +72,33 @@ __global__ __launch_bounds__(kIonThreads) void k_ion_form(const double* __restri
 }
 
 // Gaussian elimination with partial pivoting (max |a|, ties to the lowest row)
-// on [M | b] of one discharge, then back substitution; out = n_i^{n+1}.
-__global__ __launch_bounds__(kIonThreads) void k_ion_solve(double* __restrict__ M, double* __restrict__ b,
-                                                           double* __restrict__ out, const int* __restrict__ x_off,
-                                                           const int* __restrict__ nx_of,
-                                                           const size_t* __restrict__ m_off, int* __restrict__ status) {
-  constexpr int NW = kIonThreads / 64;
+// on [M | b] of one discharge, then back substitution; out = n_i^{n+1}.  Per
+// column: the pivot by wavefront reductions, the interchange, the multipliers
+// and the pivot row staged in LDS, and the trailing update by a 64-row x
+// 16-column thread grid (coalesced down the columns); four barriers.
+constexpr int kIonSolveThreads = 1024;
+__global__ __launch_bounds__(kIonSolveThreads) void k_ion_solve(double* __restrict__ M, double* __restrict__ b,
+                                                                double* __restrict__ out,
+                                                                const int* __restrict__ x_off,
+                                                                const int* __restrict__ nx_of,
+                                                                const size_t* __restrict__ m_off,
+                                                                int* __restrict__ status) {
+  constexpr int NT = kIonSolveThreads, NW = NT / 64;
   const int d = blockIdx.x, N = nx_of[d], x0 = x_off[d];
   double* A = M + m_off[d];
   double* r = b + x0;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  extern __shared__ double s_dyn[];
+  double* s_l = s_dyn;        // [N] multipliers of the current column
+  double* s_u = s_dyn + N;    // [N + 1] pivot row (and its right-hand side)
   __shared__ double s_val[NW];
   __shared__ int s_idx[NW];
-  __shared__ int s_p;
-  __shared__ double s_x;
   bool singular = false, nonfinite = false;
   for (int k = 0; k < N; ++k) {
+    // (a) pivot
     double best = -1.0;
     int bi = INT_MAX;
-    for (int i = k + tid; i < N; i += kIonThreads) {
+    for (int i = k + tid; i < N; i += NT) {
       const double v = fabs(A[(size_t)k * N + i]);
       if (v > best) {
         best = v;
@@ -104,59 +112,58 @@ __global__ __launch_bounds__(kIonThreads) void k_ion_solve(double* __restrict__ 
       s_idx[w] = wr;
     }
     __syncthreads();
-    if (tid == 0) {
+    int p = INT_MAX;
+    {
       double v = -1.0;
-      int p = INT_MAX;
       for (int u = 0; u < NW; ++u)
         if (s_val[u] > v || (s_val[u] == v && s_idx[u] < p)) {
           v = s_val[u];
           p = s_idx[u];
         }
-      s_p = (p == INT_MAX) ? k : p;  // a column of NaNs keeps row k
+    }
+    if (p == INT_MAX) p = k;  // a column of NaNs keeps row k
+    // (b) interchange of rows k and p over columns k.. and the right-hand side
+    if (p != k) {
+      for (int j = k + tid; j <= N; j += NT) {
+        double* x = (j < N) ? A + (size_t)j * N : r;
+        const double t = x[k];
+        x[k] = x[p];
+        x[p] = t;
+      }
     }
     __syncthreads();
-    const int p = s_p;
-    if (p != k) {
-      for (int j = k + tid; j < N; j += kIonThreads) {
-        const double t = A[(size_t)j * N + k];
-        A[(size_t)j * N + k] = A[(size_t)j * N + p];
-        A[(size_t)j * N + p] = t;
-      }
-      if (tid == 0) {
-        const double t = r[k];
-        r[k] = r[p];
-        r[p] = t;
-      }
-      __syncthreads();
-    }
+    // (c) multipliers and the pivot row into LDS
     const double pv = A[(size_t)k * N + k];
     if (pv == 0.0) singular = true;
     if (!(fabs(pv) <= DBL_MAX)) nonfinite = true;
-    if (pv != 0.0) {
-      for (int i = k + 1 + tid; i < N; i += kIonThreads) A[(size_t)k * N + i] /= pv;
-    }
-    __syncthreads();
-    // trailing update of [M | b]: column N stands for b
     const int m = N - k - 1;
-    if (pv != 0.0 && m > 0) {
-      for (int e = tid; e < m * (m + 1); e += kIonThreads) {
-        const int i = k + 1 + e % m, j = k + 1 + e / m;
-        const double l = A[(size_t)k * N + i];
-        if (j < N) A[(size_t)j * N + i] -= l * A[(size_t)j * N + k];
-        else r[i] -= l * r[k];
+    for (int i = tid; i < m; i += NT) {
+      const double l = (pv != 0.0) ? A[(size_t)k * N + k + 1 + i] / pv : 0.0;
+      A[(size_t)k * N + k + 1 + i] = l;
+      s_l[i] = l;
+    }
+    for (int j = tid; j <= m; j += NT) s_u[j] = (j < m) ? A[(size_t)(k + 1 + j) * N + k] : r[k];
+    __syncthreads();
+    // (d) trailing update of [M | b] (column m of the grid is b)
+    {
+      const int ti = tid & 63, tj = tid >> 6;
+      for (int j = tj; j <= m; j += NW) {
+        double* x = (j < m) ? A + (size_t)(k + 1 + j) * N + k + 1 : r + k + 1;
+        const double u = s_u[j];
+        for (int i = ti; i < m; i += 64) x[i] -= s_l[i] * u;
       }
     }
     __syncthreads();
   }
+  // back substitution U x = b
   for (int k = N - 1; k >= 0; --k) {
-    if (tid == 0) s_x = r[k] / A[(size_t)k * N + k];
+    const double xk = r[k] / A[(size_t)k * N + k];
+    for (int i = tid; i < k; i += NT) r[i] -= A[(size_t)k * N + i] * xk;
     __syncthreads();
-    const double xk = s_x;
-    for (int i = tid; i < k; i += kIonThreads) r[i] -= A[(size_t)k * N + i] * xk;
     if (tid == 0) r[k] = xk;
-    __syncthreads();
   }
-  for (int i = tid; i < N; i += kIonThreads) out[x0 + i] = r[i];
+  __syncthreads();
+  for (int i = tid; i < N; i += NT) out[x0 + i] = r[i];
   if (singular && tid == 0) atomicOr(status, kStSingular);
   if (nonfinite && tid == 0) atomicOr(status, kStNonFinite);
 }
@@ -166,7 +173,8 @@ __global__ __launch_bounds__(kIonThreads) void k_ion_solve(double* __restrict__ 
 void launch_ion_update(const DevOps& d, const double* F, const double* ni_in, double* ni_out, hipStream_t s) {
   k_ion_form<<<d.nd, kIonThreads, 0, s>>>(F, ni_in, d.ion_E, d.dx, d.dx2, d.mom + 2 * (size_t)d.n, d.n0_of,
                                           d.x_off, d.nx_of, d.p_off, d.ion_M, d.ion_b, d.dt, d.n);
-  k_ion_solve<<<d.nd, kIonThreads, 0, s>>>(d.ion_M, d.ion_b, ni_out, d.x_off, d.nx_of, d.p_off, d.status);
+  const size_t sh = (size_t)(2 * d.max_nx + 1) * sizeof(double);
+  k_ion_solve<<<d.nd, kIonSolveThreads, sh, s>>>(d.ion_M, d.ion_b, ni_out, d.x_off, d.nx_of, d.p_off, d.status);
 }
 
 }  // namespace bte
