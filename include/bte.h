@@ -157,6 +157,38 @@ bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle
  * Errors (synchronous): BTE_EINVAL.  Device errors are latched. */
 bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void* stream);
 
+/* Fully implicit electron step (eq. bte_fully_implicit): F^{n+1} solves
+ *   F^{n+1} - F^n = dt [-A_x F^{n+1} D_x^T + P_O C P_S F^{n+1} + P_O A_v P_S (E(F^{n+1}) . F^{n+1})]
+ * with E(F) = L (n_i - u^T F) at t_s + dt (POISSON mode; ni device [sum Nx])
+ * or the specified field at t_s + dt (CONST, RF: the equation is then linear),
+ * and F = 0 at the inflow entries of the walls (eq. hybrid_cnt_b_bdy).
+ * Newton's method with a backtracking line search on ||R||_2; each Newton
+ * system J_F dlt = -R (Jacobian action of eq. 1dbte_jac_action, matrix free)
+ * by restarted GMRES, right-preconditioned by the semi-implicit step as a
+ * linear map with the field frozen at E(F) (X(dt/2), the factored V systems,
+ * X(dt/2)), classical Gram-Schmidt twice.  F (device [sum Nx][Nr][Ntheta]) is
+ * replaced by F^{n+1}.  Synchronous on the stream (the host drives the
+ * iterations).  Defaults for zero fields of opts: newton_rtol 1e-12 (relative
+ * to ||F^n||_2), max_newton 20, gmres_rtol 1e-6, restart 30 (<= 200), max_gmres
+ * 200 per Newton step.  stats (may be NULL) receives the counts and the final
+ * and initial ||R||_2.  Errors: BTE_EINVAL, BTE_EUNSUPPORTED (GIVEN field),
+ * BTE_ENOCONV (Newton did not reach newton_rtol; F holds the last iterate). */
+typedef struct {
+  double newton_rtol;
+  int32_t max_newton;
+  double gmres_rtol;
+  int32_t restart;
+  int32_t max_gmres;
+} bte_implicit_opts;
+typedef struct {
+  int32_t newton_iters;
+  int32_t gmres_iters;
+  double residual;
+  double residual0;
+} bte_implicit_stats;
+bte_status bte_implicit_step(bte_handle* h, double* F, const double* ni, double t_s, bte_implicit_opts opts,
+                             bte_implicit_stats* stats, void* stream);
+
 /* Heavies' update of the hybrid model (operator split of eq. glow_hybrid,
  * eq. fluid_step), POISSON field mode only:
  *   (n_i^{n+1} - n_i^n)/dt + D_x J_i(E^n, n_i^{n+1}) = (k_i^T F^n) n0 (u^T F^n),

@@ -35,6 +35,16 @@ class bte_field(C.Structure):
     _fields_ = [("E_half", C.c_void_p), ("ni", C.c_void_p)]
 
 
+class bte_implicit_opts(C.Structure):
+    _fields_ = [("newton_rtol", C.c_double), ("max_newton", C.c_int32), ("gmres_rtol", C.c_double),
+                ("restart", C.c_int32), ("max_gmres", C.c_int32)]
+
+
+class bte_implicit_stats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("gmres_iters", C.c_int32), ("residual", C.c_double),
+                ("residual0", C.c_double)]
+
+
 class bte_info(C.Structure):
     _fields_ = [("nx_total", C.c_int32), ("n", C.c_int32), ("n_params", C.c_int32), ("n_discharges", C.c_int32),
                 ("vmax", C.c_double), ("bytes_device", C.c_double), ("lu_flops_per_step", C.c_double),
@@ -61,6 +71,8 @@ EXPORTS = {
     "bte_vstep": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bte_ion_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "bte_hybrid_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "bte_implicit_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, bte_implicit_opts,
+                                    C.POINTER(bte_implicit_stats), C.c_void_p]),
     "bte_field_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, bte_field, C.c_void_p, C.c_void_p]),
     "bte_get_operator": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "bte_host_operator": (C.c_int, [C.POINTER(bte_config), C.c_int32, C.POINTER(C.c_double)]),

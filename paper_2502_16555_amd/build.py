@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libbte.so")
 SOURCES = ["assemble.cpp", "bte_api.cpp", "kernels_x.hip", "kernels_lu.hip", "kernels_update.hip",
-           "kernels_refine.hip", "kernels_gmres.hip", "kernels_ion.hip"]
+           "kernels_refine.hip", "kernels_gmres.hip", "kernels_ion.hip", "kernels_implicit.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -32,6 +32,18 @@ struct HipError : std::runtime_error {
 
 }  // namespace
 
+// Workspace of the fully implicit step (allocated at its first call).
+struct ImplicitWs {
+  int m = 0;                    // Krylov vectors per cycle the basis holds
+  size_t N = 0;                 // unknowns (sum Nx * n)
+  double *Fn = nullptr, *R = nullptr, *Rt = nullptr, *dlt = nullptr, *tmp = nullptr, *z = nullptr, *u = nullptr;
+  double *V = nullptr;          // [m + 1][N]
+  double *Pa = nullptr, *Pb = nullptr, *Pc = nullptr;   // padded rows
+  double *El = nullptr, *zeros = nullptr;               // [sum Nx]
+  double *partial = nullptr, *coef = nullptr;
+  std::vector<double> hpart, hcoef;
+};
+
 struct bte_handle {
   int device = 0;
   bte_config cfg{};
@@ -61,6 +73,7 @@ struct bte_handle {
   // preconditioner (a DevOps over nd * nbins matrices) and the GMRES workspace
   bool krylov = false;
   bool banded = false;         // V solves in the harmonic basis, banded LU
+  ImplicitWs iw;               // fully implicit step
   DevOps bd;                   // its factors (FP64) and harmonic operators
   double* d_TO = nullptr;
   double* d_TS = nullptr;
@@ -280,14 +293,21 @@ void fill_devops(bte_handle* h) {
     }
   }
   const size_t nxt = d.nx_total;
-  if (c.field_mode == BTE_FIELD_POISSON) {
-    // the heavies' update of the hybrid step: D_x and D_x^2 per discharge
-    std::vector<double> Dx, D2;
+  {
+    // D_x per discharge (the forward spatial operator of the fully implicit step)
+    std::vector<double> Dx;
     Dx.reserve(ptot);
+    for (auto& X : H.xops) Dx.insert(Dx.end(), X.Dx.begin(), X.Dx.end());
+    d.dx = h->upload(Dx);
+    d.lam = h->upload(H.lam);
+    d.mu_th = h->upload(H.mu);
+  }
+  if (c.field_mode == BTE_FIELD_POISSON) {
+    // the heavies' update of the hybrid step: D_x^2 per discharge
+    std::vector<double> D2;
     D2.reserve(ptot);
     for (auto& X : H.xops) {
       const int nx = X.nx;
-      Dx.insert(Dx.end(), X.Dx.begin(), X.Dx.end());
       for (int r = 0; r < nx; ++r)
         for (int cc = 0; cc < nx; ++cc) {
           double acc = 0.0;
@@ -295,7 +315,6 @@ void fill_devops(bte_handle* h) {
           D2.push_back(acc);
         }
     }
-    d.dx = h->upload(Dx);
     d.dx2 = h->upload(D2);
     d.ion_M = h->alloc<double>(ptot);
     d.ion_b = h->alloc<double>(nxt);
@@ -477,6 +496,192 @@ void eval_field(bte_handle* h, const double* Fh, double t_s, const bte_field& f,
   const bte_config& c = h->cfg;
   bte::launch_field(h->d, c.field_mode, t_s + 0.5 * c.dt_s, c.field_freq_hz, c.field_a1, c.poisson_V0, Fh, f.E_half,
                     f.ni, h->d.E, s);
+}
+
+
+// ---- fully implicit step (eq. bte_fully_implicit) ------------------------------
+void implicit_alloc(bte_handle* h, int m) {
+  ImplicitWs& w = h->iw;
+  const DevOps& d = h->d;
+  const size_t N = (size_t)d.nx_total * d.n, P = (size_t)d.nx_total * d.npad;
+  if (w.N == 0) {
+    w.N = N;
+    w.Fn = h->alloc<double>(N);
+    w.R = h->alloc<double>(N);
+    w.Rt = h->alloc<double>(N);
+    w.dlt = h->alloc<double>(N);
+    w.tmp = h->alloc<double>(N);
+    w.z = h->alloc<double>(N);
+    w.u = h->alloc<double>(N);
+    w.Pa = h->alloc<double>(P);
+    w.Pb = h->alloc<double>(P);
+    w.Pc = h->alloc<double>(P);
+    HIP_OK(hipMemset(w.Pa, 0, P * sizeof(double)));
+    HIP_OK(hipMemset(w.Pb, 0, P * sizeof(double)));
+    HIP_OK(hipMemset(w.Pc, 0, P * sizeof(double)));
+    w.El = h->alloc<double>(d.nx_total);
+    w.zeros = h->alloc<double>(d.nx_total);
+    HIP_OK(hipMemset(w.zeros, 0, d.nx_total * sizeof(double)));
+  }
+  if (w.m < m) {
+    w.m = m;
+    w.V = h->alloc<double>((size_t)(m + 1) * N);
+    w.partial = h->alloc<double>((size_t)bte::dot_blocks() * (m + 1));
+    w.coef = h->alloc<double>((size_t)m + 1);
+    w.hpart.assign((size_t)bte::dot_blocks() * (m + 1), 0.0);
+    w.hcoef.assign((size_t)m + 1, 0.0);
+  }
+}
+
+// out[v] = w . V_v (v < nvec), partial sums added in a fixed order
+void imp_dots(bte_handle* h, const double* w, const double* V, int nvec, double* out, hipStream_t s) {
+  ImplicitWs& iw = h->iw;
+  const int nb = bte::dot_blocks();
+  bte::launch_dots(w, V, nvec, iw.N, iw.N, iw.partial, s);
+  HIP_OK(hipMemcpyAsync(iw.hpart.data(), iw.partial, sizeof(double) * nb * nvec, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  for (int v = 0; v < nvec; ++v) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += iw.hpart[(size_t)b * nvec + v];
+    out[v] = t;
+  }
+}
+
+double imp_norm(bte_handle* h, const double* x, hipStream_t s) {
+  double v = 0.0;
+  imp_dots(h, x, x, 1, &v, s);
+  return std::sqrt(v);
+}
+
+// y = beta y + sum_v c[v] V_v
+void imp_comb(bte_handle* h, double* y, double beta, const double* V, const double* c, int nvec, hipStream_t s) {
+  ImplicitWs& iw = h->iw;
+  for (int v = 0; v < nvec; ++v) iw.hcoef[v] = c[v];
+  HIP_OK(hipMemcpyAsync(iw.coef, iw.hcoef.data(), sizeof(double) * nvec, hipMemcpyHostToDevice, s));
+  bte::launch_comb(y, beta, V, iw.coef, nvec, iw.N, iw.N, s);
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+// E(F) at t1 (specified field, or the Poisson field of n_i - u^T F)
+void imp_field(bte_handle* h, const double* F, double t1, const double* ni, double* E, hipStream_t s) {
+  const bte_config& c = h->cfg;
+  bte::launch_field(h->d, c.field_mode, t1, c.field_freq_hz, c.field_a1, c.poisson_V0, F, nullptr, ni, E, s);
+}
+
+// out = A_x X D_x^T
+void imp_xop(bte_handle* h, const double* X, double* out, hipStream_t s) {
+  bte::launch_x_to_modes(h->d, X, s);
+  bte::launch_x_forward(h->d, s);
+  bte::launch_modes_to_x(h->d, out, s);
+}
+
+// R = F - F^n + dt A_x F D_x^T - dt (n0 C + E(F) A) F, R = F at the inflow entries; d.E <- E(F)
+void imp_residual(bte_handle* h, const double* F, const double* ni, double t1, double* R, hipStream_t s) {
+  DevOps& d = h->d;
+  ImplicitWs& iw = h->iw;
+  imp_field(h, F, t1, ni, d.E, s);
+  bte::launch_pad_rows(d, F, iw.Pa, s);
+  bte::launch_apply_field(d, 2, nullptr, iw.Pa, iw.Pb, d.E, s);
+  bte::launch_unpad_rows(d, iw.Pb, R, s);
+  imp_xop(h, F, iw.tmp, s);
+  bte::launch_axpby(R, iw.tmp, 1.0, d.dt, iw.N, s);
+  bte::launch_axpby(R, iw.Fn, 1.0, -1.0, iw.N, s);
+  bte::launch_wall_rows(d, R, F, s);
+}
+
+// out = J_F X (eq. 1dbte_jac_action in residual form), with d.E = E(F)
+void imp_jac(bte_handle* h, const double* F, const double* X, double* out, hipStream_t s) {
+  DevOps& d = h->d;
+  ImplicitWs& iw = h->iw;
+  const bte_config& c = h->cfg;
+  bte::launch_pad_rows(d, X, iw.Pa, s);
+  bte::launch_apply_field(d, 2, nullptr, iw.Pa, iw.Pb, d.E, s);
+  if (c.field_mode == BTE_FIELD_POISSON) {
+    // E_lin(X) = L (0 - u^T X): the derivative of the affine field map
+    bte::launch_field(d, BTE_FIELD_POISSON, 0.0, c.field_freq_hz, c.field_a1, 0.0, X, nullptr, iw.zeros, iw.El, s);
+    bte::launch_pad_rows(d, F, iw.Pc, s);
+    bte::launch_apply_field(d, 3, iw.Pb, iw.Pc, iw.Pb, iw.El, s);
+  }
+  bte::launch_unpad_rows(d, iw.Pb, out, s);
+  imp_xop(h, X, iw.tmp, s);
+  bte::launch_axpby(out, iw.tmp, 1.0, d.dt, iw.N, s);
+  bte::launch_wall_rows(d, out, X, s);
+}
+
+// z = S v: the semi-implicit step as a linear map with the field frozen (factors of d.E)
+void imp_precond(bte_handle* h, const double* v, double* z, hipStream_t s) {
+  HIP_OK(hipMemcpyAsync(z, v, sizeof(double) * h->iw.N, hipMemcpyDeviceToDevice, s));
+  x_half(h, z, false, s);
+  v_solve_again(h, z, false, s);
+  x_half(h, z, false, s);
+}
+
+// Right-preconditioned restarted GMRES for J_F dlt = b (b in iw.Rt); classical
+// Gram-Schmidt twice; returns the iterations.
+int imp_gmres(bte_handle* h, const double* F, double rtol, int m, int maxit, hipStream_t s) {
+  ImplicitWs& iw = h->iw;
+  const size_t N = iw.N;
+  double* V = iw.V;
+  bte::launch_comb(iw.dlt, 0.0, V, iw.coef, 0, N, N, s);   // dlt = 0
+  HIP_OK(hipMemcpyAsync(V, iw.Rt, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  const double beta0 = imp_norm(h, iw.Rt, s);
+  if (!(beta0 > 0.0)) return 0;
+  int total = 0;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hc(m + 1), h2(m + 1), y(m);
+  while (total < maxit) {
+    const double beta = imp_norm(h, V, s);
+    if (!(beta > rtol * beta0)) break;
+    bte::launch_axpby(V, V, 1.0 / beta, 0.0, N, s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + (size_t)j * N;
+      double* w = V + (size_t)(j + 1) * N;
+      imp_precond(h, vj, iw.z, s);
+      imp_jac(h, F, iw.z, w, s);
+      imp_dots(h, w, V, j + 1, hc.data(), s);
+      for (int i = 0; i <= j; ++i) h2[i] = -hc[i];
+      imp_comb(h, w, 1.0, V, h2.data(), j + 1, s);
+      imp_dots(h, w, V, j + 1, h2.data(), s);
+      for (int i = 0; i <= j; ++i) {
+        hc[i] += h2[i];
+        h2[i] = -h2[i];
+      }
+      imp_comb(h, w, 1.0, V, h2.data(), j + 1, s);
+      const double hn = imp_norm(h, w, s);
+      if (hn > 0.0) bte::launch_axpby(w, w, 1.0 / hn, 0.0, N, s);
+      // Givens rotations on column j
+      for (int i = 0; i < j; ++i) {
+        const double a = cs[i] * hc[i] + sn[i] * hc[i + 1];
+        hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+        hc[i] = a;
+      }
+      const double r = std::hypot(hc[j], hn);
+      cs[j] = (r > 0.0) ? hc[j] / r : 1.0;
+      sn[j] = (r > 0.0) ? hn / r : 0.0;
+      hc[j] = r;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i];
+      ++total;
+      k = j + 1;
+      if (std::fabs(g[j + 1]) <= rtol * beta0 || !(hn > 0.0) || total >= maxit) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int c = i + 1; c < k; ++c) t -= H[(size_t)i * m + c] * y[c];
+      y[i] = t / H[(size_t)i * m + i];
+    }
+    imp_comb(h, iw.u, 0.0, V, y.data(), k, s);
+    imp_precond(h, iw.u, iw.z, s);
+    bte::launch_axpby(iw.dlt, iw.z, 1.0, 1.0, N, s);
+    // true residual of the accumulated correction into V_0
+    imp_jac(h, F, iw.dlt, iw.u, s);
+    HIP_OK(hipMemcpyAsync(V, iw.Rt, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    bte::launch_axpby(V, iw.u, 1.0, -1.0, N, s);
+  }
+  return total;
 }
 
 // Heavies' update (eq. fluid_step) with E^n = L (n_i^n - u^T F^n) at t_s.
@@ -682,6 +887,70 @@ bte_status bte_xstep_T(bte_handle* h, double* F, void* stream) {
     x_half(h, F, true, S(stream));
     HIP_OK(hipGetLastError());
     return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_implicit_step(bte_handle* h, double* F, const double* ni, double t_s, bte_implicit_opts opts,
+                             bte_implicit_stats* stats, void* stream) {
+  if (!h || !F) return BTE_EINVAL;
+  const int fm = h->cfg.field_mode;
+  if (fm == BTE_FIELD_GIVEN) return BTE_EUNSUPPORTED;
+  if (fm == BTE_FIELD_POISSON && !ni) return BTE_EINVAL;
+  const double nrtol = opts.newton_rtol > 0.0 ? opts.newton_rtol : 1e-12;
+  const int max_newton = opts.max_newton > 0 ? opts.max_newton : 20;
+  const double grtol = opts.gmres_rtol > 0.0 ? opts.gmres_rtol : 1e-6;
+  const int m = opts.restart > 0 ? std::min(opts.restart, 200) : 30;
+  const int max_gmres = opts.max_gmres > 0 ? opts.max_gmres : 200;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    hipStream_t s = S(stream);
+    h->last_stream = s;
+    implicit_alloc(h, m);
+    ImplicitWs& iw = h->iw;
+    const size_t N = iw.N;
+    const double t1 = t_s + h->cfg.dt_s;
+    HIP_OK(hipMemcpyAsync(iw.Fn, F, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    imp_residual(h, F, ni, t1, iw.R, s);
+    double rn = imp_norm(h, iw.R, s);
+    const double r0 = rn;
+    const double tol = nrtol * std::max(imp_norm(h, iw.Fn, s), 1e-300);
+    int it = 0, gits = 0;
+    bool ok = rn <= tol;
+    for (; it < max_newton && !ok; ++it) {
+      factor_all(h, s);                               // V factors for E(F), d.E from the residual
+      HIP_OK(hipMemcpyAsync(iw.Rt, iw.R, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+      bte::launch_axpby(iw.Rt, iw.Rt, -1.0, 0.0, N, s);
+      gits += imp_gmres(h, F, grtol, m, max_gmres, s);
+      // line search on ||R||: full step first, then halvings
+      double alpha = 1.0;
+      bool acc = false;
+      for (int ls = 0; ls < 10 && !acc; ++ls) {
+        HIP_OK(hipMemcpyAsync(iw.z, F, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        bte::launch_axpby(iw.z, iw.dlt, 1.0, alpha, N, s);
+        imp_residual(h, iw.z, ni, t1, iw.Rt, s);
+        const double rt = imp_norm(h, iw.Rt, s);
+        if (rt <= (1.0 - 1e-4 * alpha) * rn) {
+          HIP_OK(hipMemcpyAsync(F, iw.z, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+          HIP_OK(hipMemcpyAsync(iw.R, iw.Rt, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+          rn = rt;
+          acc = true;
+        } else {
+          alpha *= 0.5;
+        }
+      }
+      if (!acc) break;
+      ok = rn <= tol;
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    if (stats) {
+      stats->newton_iters = it;
+      stats->gmres_iters = gits;
+      stats->residual = rn;
+      stats->residual0 = r0;
+    }
+    return ok ? BTE_OK : BTE_ENOCONV;
   } catch (const std::exception& e) {
     return map_exc(e);
   }

@@ -77,12 +77,14 @@ struct DevOps {
   double* resid = nullptr;     // [1] final max_x |r|/|b|
   double* scratch3 = nullptr;  // [3*nx_total] moments scratch
   // heavies' update of the hybrid model (Poisson field mode only)
-  double* dx = nullptr;        // concatenated [nx_d][nx_d] CGL derivative (physical), offsets p_off
+  double* dx = nullptr;        // concatenated [nx_d][nx_d] CGL derivative (physical), offsets p_off (all modes)
   double* dx2 = nullptr;       // concatenated D_x D_x
   double* ion_M = nullptr;     // concatenated [nx_d][nx_d] ion systems (column-major)
   double* ion_b = nullptr;     // [nx_total] right-hand sides
   double* ion_E = nullptr;     // [nx_total] E^n
   double* ni1 = nullptr;       // [nx_total] n_i^{n+1} of the hybrid step
+  double* lam = nullptr;       // [nr] eigenvalues of M^-1 G (speed advection)
+  double* mu_th = nullptr;     // [nth] cos theta of the ordinates
 };
 
 // Batched restarted GMRES of the V step (kernels_gmres.hip): workspace of the
@@ -118,6 +120,24 @@ void launch_gmres_status(const DevOps& d, const GmresOps& q, hipStream_t s);
 // ---- heavies' update (kernels_ion.hip) ----------------------------------------
 // n_i^{n+1} of eq. fluid_step for every discharge, with E^n already in d.ion_E.
 void launch_ion_update(const DevOps& d, const double* F, const double* ni_in, double* ni_out, hipStream_t s);
+
+// ---- fully implicit step (kernels_implicit.hip) -------------------------------
+// d.Y <- A_x applied mode by mode (lambda_i cos theta_a D_x) to the modes in d.Y.
+void launch_x_forward(const DevOps& d, hipStream_t s);
+// out = X at the inflow entries of every discharge's walls.
+void launch_wall_rows(const DevOps& d, double* out, const double* X, hipStream_t s);
+int dot_blocks();
+// partial[b][v] (b < dot_blocks()) = partial sums of w . V_v, v < nvec.
+void launch_dots(const double* w, const double* V, int nvec, size_t stride, size_t N, double* partial,
+                 hipStream_t s);
+// y = beta y + sum_v coef[v] V_v (coef on the device).
+void launch_comb(double* y, double beta, const double* V, const double* coef, int nvec, size_t stride, size_t N,
+                 hipStream_t s);
+void launch_axpby(double* y, const double* x, double a, double b, size_t N, hipStream_t s);
+// Operator action on padded rows with a given field: mode 2: R = (I - dt (n0 C + E A)) X;
+// mode 3: R = B - dt E (X A^T).
+void launch_apply_field(const DevOps& d, int mode, const double* B, const double* X, double* R, const double* E,
+                        hipStream_t s);
 
 // ---- X step (kernels_x.hip) -------------------------------------------------
 void launch_x_to_modes(const DevOps& d, const double* F, hipStream_t s);

@@ -1,0 +1,118 @@
+// Pieces of the fully implicit electron step (eq. bte_fully_implicit) that the
+// semi-implicit kernels do not already provide: the forward spatial operator
+// A_x F D_x^T in the speed eigenbasis, the wall rows of the implicit system,
+// and the vector kernels of the Newton-Krylov driver (batched dot products with
+// deterministic two-stage sums, linear combinations).
+#include "internal.h"
+
+namespace bte {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kDotBlocks = 256;
+
+// Y_ia <- lambda_i cos(theta_a) D_x Y_ia for every mode of every discharge
+// (mode-major Y of the X step: the modes of discharge d at Y + x_off[d] n, one
+// row of nx_d per mode); A_x = U Lambda U^-1 (x) diag(cos theta).
+__global__ __launch_bounds__(kThreads) void k_x_fwd(double* __restrict__ Y, const double* __restrict__ Dx,
+                                                    const size_t* __restrict__ dx_off, const double* __restrict__ lam,
+                                                    const double* __restrict__ mu, const int* __restrict__ x_off,
+                                                    const int* __restrict__ nx_of, int nth, int n) {
+  extern __shared__ double sy[];
+  const int o = blockIdx.x, d = blockIdx.y;
+  const int i = o / nth, a = o % nth, nx = nx_of[d];
+  double* y = Y + (size_t)x_off[d] * n + (size_t)o * nx;
+  for (int j = threadIdx.x; j < nx; j += blockDim.x) sy[j] = y[j];
+  __syncthreads();
+  const double c = lam[i] * mu[a];
+  const double* D = Dx + dx_off[d];
+  for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nx; ++k) s += D[(size_t)x * nx + k] * sy[k];
+    y[x] = c * s;
+  }
+}
+
+// out = X at the inflow entries (x = 0 for cos theta > 0, x = L for cos theta < 0)
+__global__ __launch_bounds__(kThreads) void k_wall_rows(double* __restrict__ out, const double* __restrict__ X,
+                                                        const int* __restrict__ x_disc, const int* __restrict__ x_off,
+                                                        const int* __restrict__ nx_of, const double* __restrict__ mu,
+                                                        int nth, int n) {
+  const int x = blockIdx.x, d = x_disc[x];
+  const int xl = x - x_off[d], nx = nx_of[d];
+  if (xl != 0 && xl != nx - 1) return;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const double m = mu[e % nth];
+    if ((xl == 0 && m > 0.0) || (xl == nx - 1 && m < 0.0)) out[(size_t)x * n + e] = X[(size_t)x * n + e];
+  }
+}
+
+// partial[b][v] = sum over block b's slice of w . V_v   (v < nvec, V_v = V + v stride)
+__global__ __launch_bounds__(kThreads) void k_dots(const double* __restrict__ w, const double* __restrict__ V,
+                                                   int nvec, size_t stride, size_t N, double* __restrict__ partial) {
+  __shared__ double red[kThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int v = 0; v < nvec; ++v) {
+    const double* vv = V + (size_t)v * stride;
+    double s = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x)
+      s += w[i] * vv[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) red[wid] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int u = 0; u < kThreads / 64; ++u) t += red[u];
+      partial[(size_t)blockIdx.x * nvec + v] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// y = beta y + sum_v coef[v] V_v
+__global__ __launch_bounds__(kThreads) void k_comb(double* __restrict__ y, double beta, const double* __restrict__ V,
+                                                   const double* __restrict__ coef, int nvec, size_t stride,
+                                                   size_t N) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+    double s = (beta == 0.0) ? 0.0 : beta * y[i];
+    for (int v = 0; v < nvec; ++v) s += coef[v] * V[(size_t)v * stride + i];
+    y[i] = s;
+  }
+}
+
+// y = a y + b x
+__global__ __launch_bounds__(kThreads) void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a,
+                                                    double b, size_t N) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = a * y[i] + b * x[i];
+}
+
+}  // namespace
+
+void launch_x_forward(const DevOps& d, hipStream_t s) {
+  dim3 g(d.n, d.nd);
+  k_x_fwd<<<g, kThreads, sizeof(double) * d.max_nx, s>>>(d.Y, d.dx, d.p_off, d.lam, d.mu_th, d.x_off, d.nx_of,
+                                                         d.nth, d.n);
+}
+
+void launch_wall_rows(const DevOps& d, double* out, const double* X, hipStream_t s) {
+  k_wall_rows<<<d.nx_total, kThreads, 0, s>>>(out, X, d.x_disc, d.x_off, d.nx_of, d.mu_th, d.nth, d.n);
+}
+
+int dot_blocks() { return kDotBlocks; }
+
+void launch_dots(const double* w, const double* V, int nvec, size_t stride, size_t N, double* partial,
+                 hipStream_t s) {
+  k_dots<<<kDotBlocks, kThreads, 0, s>>>(w, V, nvec, stride, N, partial);
+}
+
+void launch_comb(double* y, double beta, const double* V, const double* coef, int nvec, size_t stride, size_t N,
+                 hipStream_t s) {
+  k_comb<<<1024, kThreads, 0, s>>>(y, beta, V, coef, nvec, stride, N);
+}
+
+void launch_axpby(double* y, const double* x, double a, double b, size_t N, hipStream_t s) {
+  k_axpby<<<1024, kThreads, 0, s>>>(y, x, a, b, N);
+}
+
+}  // namespace bte

@@ -79,7 +79,8 @@ __global__ __launch_bounds__(256) void k_from_harm(const double* __restrict__ Xh
 // ---------------------------------------------------------------------------
 // MODE 0: the refinement residual above, with the per-point maxima (skipped once
 // the refinement is done); MODE 1: R = B - M X only; MODE 2: R = M X (operator
-// action of Alg. vspace_action, for the Krylov solver).
+// action of Alg. vspace_action, for the Krylov solver); MODE 3: R = B - dt E (X A^T)
+// (the field-coupling term of the fully implicit Jacobian, eq. 1dbte_jac_action).
 template <int TRANSPOSE, int MODE = 0>
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv, const double* __restrict__ Xv,
                                                   double* __restrict__ Rv, const double* __restrict__ C,
@@ -184,8 +185,12 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
       if (MODE != 0) {
         if (x < nx && i < n) {
           const size_t o = (size_t)x * npad + i;
-          const double mx = Xv[o] - dt * n0x[x] * accC[b][it] - dt * E[x] * accA[b][it];
-          Rv[o] = (MODE == 1) ? Bv[o] - mx : mx;
+          if (MODE == 3) {
+            Rv[o] = Bv[o] - dt * E[x] * accA[b][it];
+          } else {
+            const double mx = Xv[o] - dt * n0x[x] * accC[b][it] - dt * E[x] * accA[b][it];
+            Rv[o] = (MODE == 1) ? Bv[o] - mx : mx;
+          }
         }
         continue;
       }
@@ -372,6 +377,17 @@ void launch_apply(const DevOps& d, int mode, const double* B, const double* X, d
   else
     k_residual<0, 2><<<g, 256, 0, s>>>(B, X, R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
                                        d.n, d.npad, d.nx_total, skip);
+}
+
+void launch_apply_field(const DevOps& d, int mode, const double* B, const double* X, double* R, const double* E,
+                        hipStream_t s) {
+  dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32);
+  if (mode == 3)
+    k_residual<0, 3><<<g, 256, 0, s>>>(B, X, R, d.Cord, d.Aord, E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
+                                       d.n, d.npad, d.nx_total, nullptr);
+  else
+    k_residual<0, 2><<<g, 256, 0, s>>>(B, X, R, d.Cord, d.Aord, E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
+                                       d.n, d.npad, d.nx_total, nullptr);
 }
 
 void launch_residual(const DevOps& d, bool transpose, hipStream_t s) {

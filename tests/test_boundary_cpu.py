@@ -47,6 +47,7 @@ def test_status_strings_and_argument_errors():
     assert lib.bte_set_vsolver(None, L.VSOLVER_GMRES, 8, 1e4, 0.0, 20, 2, 1e-12, 1) == L.BTE_EINVAL
     assert lib.bte_ion_step(None, None, None, None, 0.0, None) == L.BTE_EINVAL
     assert lib.bte_hybrid_step(None, None, None, 0.0, None) == L.BTE_EINVAL
+    assert lib.bte_implicit_step(None, None, None, 0.0, L.bte_implicit_opts(), None, None) == L.BTE_EINVAL
     v = ctypes.c_int32()
     assert lib.bte_get_tuning(None, L.TUNE_LU_STREAMS, ctypes.byref(v)) == L.BTE_EINVAL
 
