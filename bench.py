@@ -190,6 +190,38 @@ def run_hybrid(cfg, steps, warmup, torch):
     return res
 
 
+def run_implicit(cfg, torch, mults=(1.0,)):
+    """The fully implicit step at the bench grid (RF field, mixed-precision
+    preconditioner): wall time per step, Newton and GMRES iterations, and the
+    simulated time advanced per wall second against the semi-implicit step's."""
+    import copy
+    import workloads
+    from paper_2502_16555_amd import Solver
+    opts = dict(newton_rtol=1e-8, gmres_rtol=1e-4, restart=60, max_gmres=1500, max_newton=8)
+    out = {"workload": f"Nx={cfg['nx']}, Nr={cfg['nr']}, Ntheta={cfg['ntheta']}, RF field, Newton-GMRES "
+                       "preconditioned by the semi-implicit step (mixed precision), one step from the "
+                       "initial state", "options": opts, "steps": []}
+    for q, mult in enumerate(mults):
+        c = copy.deepcopy(cfg)
+        c["dt_s"] = cfg["dt_s"] * mult
+        s = Solver(c, precision="mixed_fp32")
+        ne = workloads.density_profile(s.xhat(), c["ic"]["ne_peak"])
+        F = s.initial_state(torch.as_tensor(ne, device="cuda:0"), c["ic"]["Te_eV"])
+        if q == 0:   # first use: kernels loaded, workspace allocated
+            s.implicit_step(F.clone(), 0.0, max_newton=1, max_gmres=2, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.implicit_step(F, 0.0, raise_on_noconv=False, **opts)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out["steps"].append({"dt_over_T_rf": c["dt_s"] / c["T_rf_s"], "ms_per_step": wall * 1e3,
+                             "newton_iters": st["newton_iters"], "gmres_iters": st["gmres_iters"],
+                             "converged": st["status"] == 0, "residual_rel": st["residual"] / st["residual0"],
+                             "simulated_s_per_wall_s": c["dt_s"] / wall})
+        s.close()
+    return out
+
+
 def run_adjoint(torch, n_steps=100, every=50):
     """Adjoint cost on the differentiation workload (Nx=128, Nr=64, Ntheta=32,
     8 bins x 3 processes + E0, FP64): time of the checkpointed forward pass vs
@@ -296,6 +328,7 @@ def main():
     ap.add_argument("--no-krylov", action="store_true", help="skip the GMRES V-solver leg")
     ap.add_argument("--no-banded", action="store_true", help="skip the banded harmonic-basis V-solver leg")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid-model (ions + electrons) leg")
+    ap.add_argument("--no-implicit", action="store_true", help="skip the fully implicit step leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
@@ -391,6 +424,9 @@ def main():
             line["banded"]["vs_fp64_lu"] = dict(moment_errors(bd["moments"], fp64["moments"]), steps=bd["n_end"])
     if not args.no_hybrid:
         line["hybrid"] = run_hybrid(cfg, min(args.steps, 20), 2, torch)
+    if not args.no_implicit:
+        line["implicit"] = run_implicit(cfg, torch)
+        line["implicit"]["semi_implicit_simulated_s_per_wall_s"] = cfg["dt_s"] / (main_run["ms_per_step"] * 1e-3)
     if not args.no_adjoint:
         line["adjoint"] = run_adjoint(torch)
     if args.ensemble:
