@@ -567,7 +567,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
     using V = typename Vec4<T>::type;
     constexpr int PER = Vec4<T>::per;
     constexpr int H = sizeof(T) < 8 ? 2 : 1;    // column groups
-    constexpr int CW = NB / H, JB = 8, TPG = 1024 / H;
+    constexpr int CW = NB / H, JB = sizeof(T) == 2 ? 8 : 16, TPG = 1024 / H;
     const int grp = tid / TPG, lt = tid % TPG;
     for (int r0 = r_lo; r0 < r_hi; r0 += TPG * PER) {
       const int r = r0 + lt * PER;
