@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+MI355X_PEAK_HBM_GBS = 8000.0
 
 # HBM bytes of the FP32 trailing update (k_update<float, 32>) per launch, averaged
 # over the 15 launches of one factorization at this workload, from two
@@ -329,6 +330,7 @@ def main():
     ap.add_argument("--no-banded", action="store_true", help="skip the banded harmonic-basis V-solver leg")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid-model (ions + electrons) leg")
     ap.add_argument("--no-implicit", action="store_true", help="skip the fully implicit step leg")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 (split-operand) variant of the mixed step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
@@ -413,6 +415,20 @@ def main():
         if fp64 is not None:
             line["krylov"]["speedup_over_fp64_lu"] = fp64["ms_per_step"] / kr["ms_per_step"]
             line["krylov"]["vs_fp64_lu"] = dict(moment_errors(kr["moments"], fp64["moments"]), steps=kr["n_end"])
+    bf = None
+    if not args.no_bf16 and args.precision != "mixed_bf16x3":
+        # the BF16 variant of the precision form: trailing updates with split bf16
+        # operands (three products), same FP64 refinement
+        bf = run_gpu(cfg, "mixed_bf16x3", args.steps, warm, torch, args.lu_streams, one_step=True)
+        nup = bf["update_launches"]
+        line["bf16x3"] = {"steps_per_s": 1000.0 / bf["ms_per_step"], "ms_per_step": bf["ms_per_step"],
+                          "ms_update": bf["ms_update"], "ms_panel": bf["ms_panel"],
+                          "update_hbm_frac": (_update_bytes(npad, 128, nx_total, 4) / (bf["ms_update"] / nup * 1e-3))
+                          / (MI355X_PEAK_HBM_GBS * 1e9),
+                          "refine": {"sweeps": bf["refine_sweeps"], "resid": bf["refine_resid"]}}
+        if fp64 is not None:
+            line["bf16x3"]["speedup_over_fp64"] = fp64["ms_per_step"] / bf["ms_per_step"]
+            line["bf16x3"]["vs_fp64_gpu"] = dict(moment_errors(bf["moments"], fp64["moments"]), steps=bf["n_end"])
     if not args.no_banded:
         bd = run_gpu(cfg, "fp64", args.steps, warm, torch, args.lu_streams, banded=True)
         line["banded"] = {"solver": "FP64 batched LU of the harmonic-basis systems restricted to their band "
@@ -439,6 +455,8 @@ def main():
         acc["vs_oracle_one_step"] = {args.precision: moment_errors(main_run["first_step_moments"], mom1)}
         if fp64 is not None:
             acc["vs_oracle_one_step"]["fp64"] = moment_errors(fp64["first_step_moments"], mom1)
+        if bf is not None:
+            acc["vs_oracle_one_step"]["mixed_bf16x3"] = moment_errors(bf["first_step_moments"], mom1)
     print(json.dumps(line), flush=True)
 
 
