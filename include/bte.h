@@ -347,8 +347,20 @@ bte_status bte_get_timing(bte_handle* h, double* ms_out);
  *     BF16 updates have a fixed chunk of 32 (reported as such).
  *   BTE_TUNE_FORM_XPB: matrices formed per block of the formation kernel,
  *     1..64; 0 = default (16).
+ *   BTE_TUNE_LOOKAHEAD: 0 (default) or 1.  With one group, each panel's
+ *     trailing update is split: the next panel's 128 columns are updated on
+ *     the caller's stream, the remaining columns on the handle's side stream
+ *     (default priority), where they may overlap the next panel factorization;
+ *     events order the two.  Ignored with more than one group.  A panel block
+ *     occupies a whole compute unit's registers, so the two kernels share the
+ *     GPU by compute units rather than overlap within them.
  * Returns BTE_EINVAL for an unknown key or a value out of range. */
-typedef enum { BTE_TUNE_LU_STREAMS = 0, BTE_TUNE_UPDATE_KC = 1, BTE_TUNE_FORM_XPB = 2 } bte_tune_key;
+typedef enum {
+  BTE_TUNE_LU_STREAMS = 0,
+  BTE_TUNE_UPDATE_KC = 1,
+  BTE_TUNE_FORM_XPB = 2,
+  BTE_TUNE_LOOKAHEAD = 3
+} bte_tune_key;
 bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value);
 bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value);
 

@@ -66,7 +66,12 @@ struct bte_handle {
   hipStream_t gs[kMaxLuStreams] = {};
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kMaxLuStreams] = {};
-  std::vector<hipEvent_t> lu_ev;   // kMaxLuStreams * 4 * max_panels
+  std::vector<hipEvent_t> lu_ev;   // kMaxLuStreams * 8 * max_panels
+  // look-ahead schedule of a one-group factorization (side stream, default
+  // priority, and its two events); off by default: a panel block holds a whole
+  // CU's register file, so the side-stream update and the panel do not share CUs
+  bool lookahead = false;
+  bte::LuLookahead la;
   bte::LuTimer lu_timer[kMaxLuStreams];
   double ms_acc[6] = {0, 0, 0, 0, 0, 0};
   // Krylov V solver (bte_set_vsolver): factors of the field-binned
@@ -141,6 +146,9 @@ struct bte_handle {
       if (e) (void)hipEventDestroy(e);
     for (auto& q : gs)
       if (q) (void)hipStreamDestroy(q);
+    if (la.u12_done) (void)hipEventDestroy(la.u12_done);
+    if (la.rest_done) (void)hipEventDestroy(la.rest_done);
+    if (la.side) (void)hipStreamDestroy(la.side);
     drop_graph();
     drop_krylov();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -325,7 +333,7 @@ void fill_devops(bte_handle* h) {
   const size_t elt = (c.precision == BTE_FP64) ? sizeof(double) : sizeof(float);
   d.lu = h->alloc<char>(nxt * d.npad * d.npad * elt);
   d.xscr = h->alloc<char>(nxt * d.npad * bte::kNB * elt);
-  d.linv = h->alloc<char>(nxt * 8 * 256 * elt);
+  d.linv = h->alloc<char>(nxt * bte::kLinvElems * elt);
   d.piv = h->alloc<int>(nxt * d.npad);
   d.perm = h->alloc<int>(nxt * bte::kMaxPanels * bte::kPermStride);
   d.E = h->alloc<double>(nxt);
@@ -385,7 +393,7 @@ void factor_all(bte_handle* h, hipStream_t s) {
   const int prec = h->cfg.precision;
   const int G = std::max(1, std::min(h->lu_streams, d.nx_total));
   if (G == 1) {
-    bte::launch_lu_factor(d, prec, s, h->timing ? &h->lu_timer[0] : nullptr);
+    bte::launch_lu_factor(d, prec, s, h->timing ? &h->lu_timer[0] : nullptr, 0, -1, h->lookahead ? &h->la : nullptr);
     return;
   }
   HIP_OK(hipEventRecord(h->fork_ev, s));
@@ -726,15 +734,18 @@ bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle
     fill_devops(h);
     for (auto& e : h->ev) HIP_OK(hipEventCreate(&e));
     const int P = h->d.npad / bte::kNB;
-    h->lu_ev.assign(static_cast<size_t>(bte_handle::kMaxLuStreams) * 4 * P, nullptr);
+    h->lu_ev.assign(static_cast<size_t>(bte_handle::kMaxLuStreams) * 8 * P, nullptr);
     for (auto& e : h->lu_ev) HIP_OK(hipEventCreate(&e));
     for (int g = 0; g < bte_handle::kMaxLuStreams; ++g) {
       h->lu_timer[g].max_panels = P;
-      h->lu_timer[g].ev = h->lu_ev.data() + static_cast<size_t>(g) * 4 * P;
+      h->lu_timer[g].ev = h->lu_ev.data() + static_cast<size_t>(g) * 8 * P;
       HIP_OK(hipStreamCreateWithFlags(&h->gs[g], hipStreamNonBlocking));
       HIP_OK(hipEventCreateWithFlags(&h->join_ev[g], hipEventDisableTiming));
     }
     HIP_OK(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+    HIP_OK(hipStreamCreateWithFlags(&h->la.side, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&h->la.u12_done, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&h->la.rest_done, hipEventDisableTiming));
     HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     // pointers inside cfg are not retained
     h->cfg.proc = nullptr;
@@ -799,15 +810,18 @@ bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void*
       for (const auto& tm : h->lu_timer) {
         const int P = tm.max_panels;
         for (int p = 0; p < tm.used; ++p) {
-          float t1 = 0.f, t2 = 0.f;
-          HIP_OK(hipEventElapsedTime(&t1, tm.ev[2 * p], tm.ev[2 * p + 1]));
-          HIP_OK(hipEventElapsedTime(&t2, tm.ev[2 * P + 2 * p], tm.ev[2 * P + 2 * p + 1]));
-          upd += t1;
-          pan += t2;
-          if (p + 1 < P) ++n_upd;
+          float t[4] = {0.f, 0.f, 0.f, 0.f};
+          for (int slot = 0; slot < 4; ++slot)
+            HIP_OK(hipEventElapsedTime(&t[slot], tm.ev[2 * P * slot + 2 * p], tm.ev[2 * P * slot + 2 * p + 1]));
+          upd += t[0] + t[2];
+          pan += t[1] + t[3];
         }
+        if (tm.used > 0) n_upd += tm.launches;
       }
-      for (auto& tm : h->lu_timer) tm.used = 0;
+      for (auto& tm : h->lu_timer) {
+        tm.used = 0;
+        tm.launches = 0;
+      }
       h->ms_acc[0] += upd;        // LU trailing-update launches (summed over streams)
       h->ms_acc[1] += pan;        // LU panel + U12 launches (summed over streams)
       h->ms_acc[2] += b;          // V step, wall
@@ -1164,7 +1178,7 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
       HIP_OK(hipMemcpy(h->d_TS, H.TS.data(), H.TS.size() * sizeof(double), hipMemcpyHostToDevice));
       b.lu = h->kalloc<char>((size_t)nxt * np * np * sizeof(double));
       b.xscr = h->kalloc<char>((size_t)nxt * np * bte::kNB * sizeof(double));
-      b.linv = h->kalloc<char>((size_t)nxt * 8 * 256 * sizeof(double));
+      b.linv = h->kalloc<char>((size_t)nxt * bte::kLinvElems * sizeof(double));
       b.piv = h->kalloc<int>((size_t)nxt * np);
       b.perm = h->kalloc<int>((size_t)nxt * bte::kMaxPanels * bte::kPermStride);
       b.precision = 0;
@@ -1220,7 +1234,7 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
     HIP_OK(hipMemcpy(f.n0x, n0b.data(), nmat * sizeof(double), hipMemcpyHostToDevice));
     f.lu = h->kalloc<char>(static_cast<size_t>(nmat) * d.npad * d.npad * elt);
     f.xscr = h->kalloc<char>(static_cast<size_t>(nmat) * d.npad * bte::kNB * elt);
-    f.linv = h->kalloc<char>(static_cast<size_t>(nmat) * 8 * 256 * elt);
+    f.linv = h->kalloc<char>(static_cast<size_t>(nmat) * bte::kLinvElems * elt);
     f.piv = h->kalloc<int>(static_cast<size_t>(nmat) * d.npad);
     f.perm = h->kalloc<int>(static_cast<size_t>(nmat) * bte::kMaxPanels * bte::kPermStride);
     f.precision = lu_prec;
@@ -1297,6 +1311,10 @@ bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value) {
       if (value < 0 || value > 64) return BTE_EINVAL;
       h->d.form_xpb = value;
       return BTE_OK;
+    case BTE_TUNE_LOOKAHEAD:
+      if (value != 0 && value != 1) return BTE_EINVAL;
+      h->lookahead = value != 0;
+      return BTE_OK;
     default:
       return BTE_EINVAL;
   }
@@ -1313,6 +1331,7 @@ bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value) {
       return BTE_OK;
     }
     case BTE_TUNE_FORM_XPB: *value = h->d.form_xpb ? h->d.form_xpb : 16; return BTE_OK;
+    case BTE_TUNE_LOOKAHEAD: *value = h->lookahead ? 1 : 0; return BTE_OK;
     default: return BTE_EINVAL;
   }
 }

@@ -17,11 +17,19 @@
 //             permutation for the trailing columns;
 //   k_dinv    one block per matrix: inverses of the 16 x 16 diagonal blocks of
 //             the panel's unit lower block L11;
-//   k_u12     per 32 trailing columns: the panel's interchanges and
-//             U12 = L11^-1 P A12 by 16-row blocks, each two MFMA products;
+//   k_l11inv  four blocks per matrix: L11^-1 by blocked substitution on the
+//             identity (16-row blocks, each two MFMA products);
+//   k_u12     per 128 trailing columns: the panel's interchanges and
+//             U12 = L11^-1 P A12 as one MFMA product (K = 128) -- the
+//             substitution's sequential 16-row steps are paid once per panel
+//             in k_l11inv instead of once per column block;
 //   k_update  A22 -= L21 U12: 128 x 128 MFMA tiles, K = 128 in double-buffered
 //             LDS chunks; blocks of one matrix are kept on one XCD so that L21
 //             and U12 stay in that XCD's L2.
+// With look-ahead, the update of the next panel's 128 columns goes first, on
+// the factor stream, and the update of the columns after it on a side stream,
+// where it overlaps the next (latency-bound) panel factorization; the next
+// U12 waits for it.  Every tile is computed by the same arithmetic either way.
 #include <algorithm>
 #include <cfloat>
 #include <climits>
@@ -404,7 +412,8 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
 // ---------------------------------------------------------------------------
 // Inverses of the eight 16 x 16 unit lower diagonal blocks of the panel's L11
 // (one block of 128 threads per matrix; thread = one column of one block, by
-// forward substitution in registers).  Output dinv[mat][b][r][c], row-major.
+// forward substitution in registers).  Output: the first 8 x 256 elements of
+// the matrix's kLinvElems slot, [b][r][c] row-major.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(128) void k_dinv(const T* __restrict__ LU, T* __restrict__ dinv, int npad, int k0) {
@@ -424,41 +433,34 @@ __global__ __launch_bounds__(128) void k_dinv(const T* __restrict__ LU, T* __res
   for (int r = 1; r < 16; ++r)
 #pragma unroll
     for (int k = 0; k < r; ++k) x[r] -= sD[b][r][k] * x[k];
-  T* out = dinv + ((size_t)mat * 8 + b) * 256;
+  T* out = dinv + (size_t)mat * kLinvElems + b * 256;
 #pragma unroll
   for (int r = 0; r < 16; ++r) out[r * 16 + c] = x[r];
 }
 
 // ---------------------------------------------------------------------------
-// Interchanges and U12 = L11^-1 P A12 for 32 trailing columns per block (two
-// wavefronts, one 16-column MFMA block each; small LDS so that several blocks
-// share a CU).  The block owns its columns, so all original rows are read
-// (gathered into LDS, rows outside the panel staged through a global scratch)
-// before any of them is written back.  The solve goes by 16-row blocks I:
-//   T_I = B_I - sum_{J<I} L_IJ U_J,   U_I = X_II T_I   (two MFMA products),
-// with X_II the inverse of the diagonal block and the next block row of L11
-// prefetched into registers while the current one is in use.
+// L11^-1 by blocked forward substitution on the identity, 32 columns per block
+// (two wavefronts, one 16-column MFMA block each): by 16-row blocks I,
+//   T_I = E_I - sum_{J<I} L_IJ Y_J,   Y_I = X_II T_I   (two MFMA products),
+// with X_II the inverse of the diagonal block (k_dinv) and the next block row
+// of L11 prefetched into registers while the current one is in use.  The four
+// blocks of a matrix write L11^-1 column-major after the diagonal-block
+// inverses in the matrix's kLinvElems slot.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(128) void k_u12(T* __restrict__ LU, const T* __restrict__ dinv,
-                                             const int* __restrict__ perm, T* __restrict__ xscr, int npad, int k0,
-                                             int nct, int nmat) {
+__global__ __launch_bounds__(128) void k_l11inv(const T* __restrict__ LU, T* __restrict__ linv, int npad, int k0,
+                                                int nmat) {
   constexpr int CT = 32, LDB = CT + 4, LDL = NB + 4;
   int mat, ct;
-  xcd_map(blockIdx.x, nct, nmat, &mat, &ct);
+  xcd_map(blockIdx.x, NB / CT, nmat, &mat, &ct);
   if (mat >= nmat) return;
-  T* A = LU + (size_t)mat * npad * npad;
-  const int c0 = k0 + NB + ct * CT;
-  const int* pm = perm + ((size_t)mat * kMaxPanels + k0 / NB) * kPermStride;
-  const int nR = pm[0];
-  const int* R = pm + 1;
-  const int* src = pm + 1 + kMaxSwapRows;
+  const T* A = LU + (size_t)mat * npad * npad;
   __shared__ T sB[NB][LDB];
   __shared__ T sLr[16][LDL];   // block row I of L11: rows 16I.., columns 0..16I+15
   __shared__ T sX[16][17];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const T* Xg = dinv + (size_t)mat * 8 * 256;
+  const T* Xg = linv + (size_t)mat * kLinvElems;
   // register prefetch of one block row of L11 (16 x up to 128) and its X_II
   T pl[16], px[2];
   auto fetch = [&](int I) {
@@ -486,23 +488,10 @@ __global__ __launch_bounds__(128) void k_u12(T* __restrict__ LU, const T* __rest
   fetch(0);
   for (int e = tid; e < NB * CT; e += 128) {
     const int k = e % NB, j = e / NB;
-    sB[k][j] = A[(size_t)(c0 + j) * npad + src[k]];
-  }
-  const int nx = nR - NB;
-  if (nx > 0) {
-    for (int e = tid; e < nx * CT; e += 128) {
-      const int t = NB + e % nx, j = e / nx;
-      xscr[((size_t)mat * npad + c0 + j) * NB + (t - NB)] = A[(size_t)(c0 + j) * npad + src[t]];
-    }
+    sB[k][j] = (k == ct * CT + j) ? T(1) : T(0);
   }
   put();
   __syncthreads();
-  if (nx > 0) {
-    for (int e = tid; e < nx * CT; e += 128) {
-      const int t = NB + e % nx, j = e / nx;
-      if (src[t] != R[t]) A[(size_t)(c0 + j) * npad + R[t]] = xscr[((size_t)mat * npad + c0 + j) * NB + (t - NB)];
-    }
-  }
   const int col = 16 * w + li;
   for (int I = 0; I < NB / 16; ++I) {
     const int r0 = 16 * I;
@@ -523,9 +512,128 @@ __global__ __launch_bounds__(128) void k_u12(T* __restrict__ LU, const T* __rest
     if (I + 1 < NB / 16) put();
     __syncthreads();
   }
+  T* out = linv + (size_t)mat * kLinvElems + 8 * 256;
   for (int e = tid; e < NB * CT; e += 128) {
     const int k = e % NB, j = e / NB;
-    A[(size_t)(c0 + j) * npad + k0 + k] = sB[k][j];
+    out[(size_t)(ct * CT + j) * NB + k] = sB[k][j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The panel's interchanges and U12 = L11^-1 P A12 as one MFMA product per
+// 128-column tile, with the explicit L11^-1 of k_l11inv: the tile of
+// P A12 is gathered (rows src[k] of the original columns) chunk by chunk into
+// double-buffered LDS as the K operand, L11^-1 (column-major, read by all tiles
+// of the matrix from L2) as the row operand; four wavefronts of 64 x 64.  The
+// rows that the interchanges move below the panel are read first (each thread
+// stages its own elements) and written after the last chunk, when every read
+// of the tile's columns has been made.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __restrict__ linv,
+                                               const int* __restrict__ perm, T* __restrict__ xscr, int npad, int k0,
+                                               int nct, int nmat) {
+  using V = typename Vec4<T>::type;
+  constexpr int PER = Vec4<T>::per;
+  constexpr int KC = 16, LD = 128 + 4;
+  int mat, ct;
+  xcd_map(blockIdx.x, nct, nmat, &mat, &ct);
+  if (mat >= nmat) return;
+  T* A = LU + (size_t)mat * npad * npad;
+  const T* Li = linv + (size_t)mat * kLinvElems + 8 * 256;
+  const int c0 = k0 + NB + ct * 128;
+  const int* pm = perm + ((size_t)mat * kMaxPanels + k0 / NB) * kPermStride;
+  const int nR = pm[0];
+  const int* R = pm + 1;
+  const int* src = pm + 1 + kMaxSwapRows;
+  __shared__ __align__(16) T sA[2][KC][LD];
+  __shared__ __align__(16) T sB[2][KC][LD];
+  __shared__ int s_src[NB];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  if (tid < NB) s_src[tid] = src[tid];
+  const int nx = nR - NB;
+  T* xs = xscr + ((size_t)mat * npad + c0) * NB;
+  for (int e = tid; e < nx * 128; e += 256) {
+    const int t = NB + e % nx, j = e / nx;
+    xs[(size_t)j * NB + (t - NB)] = A[(size_t)(c0 + j) * npad + src[t]];
+  }
+  __syncthreads();
+  constexpr int NA = KC * 128 / PER / 256;   // vectors of L11^-1 per thread and chunk
+  constexpr int NBS = KC * 128 / 256;        // gathered elements per thread and chunk
+  V ra[NA];
+  T rb[NBS];
+  auto load = [&](int kk) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + u * 256;
+      const int k = e / (128 / PER), i = (e % (128 / PER)) * PER;
+      ra[u] = *reinterpret_cast<const V*>(Li + (size_t)(kk + k) * NB + i);
+    }
+#pragma unroll
+    for (int u = 0; u < NBS; ++u) {
+      const int e = tid + u * 256;
+      const int k = e % KC, j = e / KC;
+      rb[u] = A[(size_t)(c0 + j) * npad + s_src[kk + k]];
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + u * 256;
+      const int k = e / (128 / PER), i = (e % (128 / PER)) * PER;
+      const T* v = reinterpret_cast<const T*>(&ra[u]);
+#pragma unroll
+      for (int m = 0; m < PER; ++m) sA[buf][k][i + m] = v[m];
+    }
+#pragma unroll
+    for (int u = 0; u < NBS; ++u) {
+      const int e = tid + u * 256;
+      sB[buf][e % KC][e / KC] = rb[u];
+    }
+  };
+  typename Mma<T>::acc acc[4][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = typename Mma<T>::acc{0, 0, 0, 0};
+  load(0);
+  store(0);
+  __syncthreads();
+  constexpr int NCH = NB / KC;
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < NCH) load((ch + 1) * KC);
+#pragma unroll
+    for (int k = 0; k < KC; k += 4) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][k + lk][wr + bi * 16 + li];
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][k + lk][wc + bj * 16 + li];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mma<T>::step(av[bi], bv[bj], acc[bi][bj]);
+    }
+    if (ch + 1 < NCH) {
+      store(buf ^ 1);
+      __syncthreads();
+    }
+  }
+  // every gather of the tile's columns was consumed before the last barrier
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      T* cp = A + (size_t)(c0 + wc + bj * 16 + li) * npad + k0 + wr + bi * 16;
+#pragma unroll
+      for (int it = 0; it < 4; ++it) cp[Mma<T>::row(lk, it)] = acc[bi][bj][it];
+    }
+  for (int e = tid; e < nx * 128; e += 256) {
+    const int t = NB + e % nx, j = e / nx;
+    if (src[t] != R[t]) A[(size_t)(c0 + j) * npad + R[t]] = xs[(size_t)j * NB + (t - NB)];
   }
 }
 
@@ -746,11 +854,12 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
 }
 
 template <typename T>
-void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, int bf16_terms) {
+void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, int bf16_terms,
+                 const LuLookahead* la) {
   const size_t np2 = (size_t)d.npad * d.npad;
   T* LU = static_cast<T*>(d.lu) + (size_t)m0 * np2;
   T* xs = static_cast<T*>(d.xscr) + (size_t)m0 * d.npad * NB;
-  T* li = static_cast<T*>(d.linv) + (size_t)m0 * 8 * 256;  // diagonal-block inverses
+  T* li = static_cast<T*>(d.linv) + (size_t)m0 * kLinvElems;  // inverses of L11 and its diagonal blocks
   int* piv = d.piv + (size_t)m0 * d.npad;
   int* perm = d.perm + (size_t)m0 * kMaxPanels * kPermStride;
   const int xpb = d.form_xpb > 0 ? d.form_xpb : 16;  // matrices per formation block
@@ -758,8 +867,17 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, xpb,
                                   d.band_kl, d.band_ku);
   const int np = d.npad / NB;
-  if (tm) tm->used = 0;
+  const int P = tm ? tm->max_panels : 0;
+  if (tm) {
+    tm->used = 0;
+    tm->launches = 0;
+  }
+  // timer event pair `slot` of panel p (slots: update, panel, remaining update, U12)
+  auto mark = [&](int slot, int p, int end, hipStream_t st) {
+    (void)hipEventRecord(tm->ev[2 * P * slot + 2 * p + end], st);
+  };
   constexpr int IB = sizeof(T) == 8 ? 8 : 16;   // register sub-panel width (VGPR budget of 512 threads)
+  const int kind = sizeof(T) == 8 ? 0 : (bf16_terms == 1 ? 2 : (bf16_terms == 3 ? 3 : 1));
   // K chunk of the trailing update (launch shape only: the K order is the same):
   // the default 16, or the alternative 8 (FP64) / 32 (FP32)
   const bool alt_kc = d.update_kc == (sizeof(T) == 8 ? 8 : 32);
@@ -767,10 +885,11 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   // kl below it; partial pivoting widens the upper band to kl + ku
   const int kl = d.band_kl, ku = d.band_ku;
   auto round_up = [](int v) { return (v + NB - 1) / NB * NB; };
+  bool rest_pending = false;   // a remaining update on the side stream not yet waited for
   for (int p = 0; p < np; ++p) {
     const int k0 = p * NB;
-    const bool rec = tm && p < tm->max_panels;
-    if (rec) (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p], s);
+    const bool rec = tm && p < P;
+    if (rec) mark(1, p, 0, s);
     const int rend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl)) : d.npad;
     const int cend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl + ku)) : d.npad;
     const int rows = rend - k0;
@@ -789,36 +908,60 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     } else {
       k_panel<T, NT, 4, IB, 4><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     }
+    if (rest > 0) k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);
+    if (rec) mark(1, p, 1, s);
+    const int mtr = rest > 0 ? (rend - k0 - NB) / 128 : 0, mtc = rest / 128;
+    // look-ahead: the first column tile (the next panel) here, the others on the side stream
+    const bool split = la && mtr > 0 && mtc > 1;
     if (rest > 0) {
-      const int nct = rest / 32;  // U12 blocks of 32 columns
-      k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);
-      k_u12<T><<<xcd_grid(nct, nmat), 128, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
-      if (rec) {
-        (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p + 1], s);
-        (void)hipEventRecord(tm->ev[2 * p], s);
+      // U12 reads and writes every trailing column, so the previous panel's
+      // remaining update must have finished
+      if (rest_pending) {
+        (void)hipStreamWaitEvent(s, la->rest_done, 0);
+        rest_pending = false;
       }
-      const int mtr = (rend - k0 - NB) / 128, mtc = rest / 128;
-      if (mtr > 0)
-        launch_update(sizeof(T) == 8 ? 0 : (bf16_terms == 1 ? 2 : (bf16_terms == 3 ? 3 : 1)), LU, d.npad, k0, mtr,
-                      mtc, nmat, alt_kc, s);
-      if (rec) (void)hipEventRecord(tm->ev[2 * p + 1], s);
+      const int nct = rest / 128;  // U12 tiles of 128 columns
+      if (rec) mark(3, p, 0, s);
+      k_l11inv<T><<<xcd_grid(NB / 32, nmat), 128, 0, s>>>(LU, li, d.npad, k0, nmat);
+      k_u12<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
+      if (rec) mark(3, p, 1, s);
+      if (split) (void)hipEventRecord(la->u12_done, s);
     } else if (rec) {
-      (void)hipEventRecord(tm->ev[2 * tm->max_panels + 2 * p + 1], s);
-      (void)hipEventRecord(tm->ev[2 * p], s);
-      (void)hipEventRecord(tm->ev[2 * p + 1], s);
+      mark(3, p, 0, s);
+      mark(3, p, 1, s);
+    }
+    if (rec) mark(0, p, 0, s);
+    if (mtr > 0) {
+      launch_update(kind, LU, d.npad, k0, mtr, split ? 1 : mtc, 0, nmat, alt_kc, s);
+      if (tm) ++tm->launches;
+    }
+    if (rec) mark(0, p, 1, s);
+    if (split) {
+      (void)hipStreamWaitEvent(la->side, la->u12_done, 0);
+      if (rec) mark(2, p, 0, la->side);
+      launch_update(kind, LU, d.npad, k0, mtr, mtc - 1, 1, nmat, alt_kc, la->side);
+      if (tm) ++tm->launches;
+      if (rec) mark(2, p, 1, la->side);
+      (void)hipEventRecord(la->rest_done, la->side);
+      rest_pending = true;
+    } else if (rec) {
+      mark(2, p, 0, s);
+      mark(2, p, 1, s);
     }
     if (rec) tm->used = p + 1;
   }
+  if (rest_pending) (void)hipStreamWaitEvent(s, la->rest_done, 0);
 }
 
 }  // namespace
 
-void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer, int m0, int count) {
+void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer, int m0, int count,
+                      const LuLookahead* la) {
   if (count < 0) count = d.nx_total - m0;
   if (count <= 0) return;
   // precision: 0 FP64, 1 FP32, 2 FP32 with a bf16 update, 3 FP32 with a split (3-term) bf16 update
-  if (precision == 0) factor_impl<double>(d, s, timer, m0, count, 0);
-  else factor_impl<float>(d, s, timer, m0, count, precision == 2 ? 1 : (precision == 3 ? 3 : 0));
+  if (precision == 0) factor_impl<double>(d, s, timer, m0, count, 0, la);
+  else factor_impl<float>(d, s, timer, m0, count, precision == 2 ? 1 : (precision == 3 ? 3 : 0), la);
 }
 
 namespace {

@@ -87,7 +87,7 @@ using bf16x8 = __bf16 __attribute__((ext_vector_type(8)));
 
 template <int NTERMS>
 __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int npad, int k0, int mtr, int mtc,
-                                                     int nmat) {
+                                                     int tj0, int nmat) {
   constexpr int KC = 32;
   constexpr int LDK = KC + 8;               // bf16 per row, padded (80 bytes)
   constexpr int NH = (NTERMS == 1) ? 1 : 2;  // hi (and lo) copies
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int
   if (mat >= nmat) return;
   const int ti = tile % mtr, tj = tile / mtr;
   float* A = LU + (size_t)mat * npad * npad;
-  const int r0 = k0 + NB + ti * 128, c0 = k0 + NB + tj * 128;
+  const int r0 = k0 + NB + ti * 128, c0 = k0 + NB + (tj0 + tj) * 128;
   // [L21/U12][buffer][hi/lo][row or column][k], or the epilogue's 128 x 132 floats
   constexpr int OPER_BYTES = 2 * 2 * NH * 128 * LDK * 2;
   constexpr int EPI_BYTES = 128 * 132 * 4;
@@ -192,7 +192,8 @@ __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int
 // latency hides behind the products or the staging.
 // ---------------------------------------------------------------------------
 template <typename T, int KC, int P, int MINB, int NPP>
-__global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int npad, int k0, int mtr, int mtc, int nmat) {
+__global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int npad, int k0, int mtr, int mtc, int tj0,
+                                                      int nmat) {
   using V = typename Vec4<T>::type;
   constexpr int PER = Vec4<T>::per;
   constexpr int LD = 128 + 4;
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int np
   if (mat >= nmat) return;
   const int ti = tile % mtr, tj = tile / mtr;
   T* A = LU + (size_t)mat * npad * npad;
-  const int r0 = k0 + NB + ti * 128, c0 = k0 + NB + tj * 128;
+  const int r0 = k0 + NB + ti * 128, c0 = k0 + NB + (tj0 + tj) * 128;
   constexpr int OPER = 2 * 2 * KC * LD;
   constexpr int EPI = 128 * LDC;
   __shared__ __align__(16) T smem[OPER > EPI ? OPER : EPI];
@@ -327,22 +328,23 @@ __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int np
 
 }  // namespace
 
-void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int nmat, bool alt_kc, hipStream_t s) {
+void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int tj0, int nmat, bool alt_kc,
+                   hipStream_t s) {
   const dim3 gu = xcd_grid(mtr * mtc, nmat);
   switch (kind) {
     case 0:
-      if (alt_kc) k_update<double, 8, 4, 2, 1><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, nmat);
-      else k_update<double, 16, 4, 2, 1><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, nmat);
+      if (alt_kc) k_update<double, 8, 4, 2, 1><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      else k_update<double, 16, 4, 2, 1><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, tj0, nmat);
       break;
     case 2:
-      k_update_bf16<1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
+      k_update_bf16<1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
       break;
     case 3:
-      k_update_bf16<3><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
+      k_update_bf16<3><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
       break;
     default:
-      if (alt_kc) k_update<float, 32, 1, 2, 1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
-      else k_update<float, 16, 4, 4, 1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, nmat);
+      if (alt_kc) k_update<float, 32, 1, 2, 1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      else k_update<float, 16, 4, 4, 1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
       break;
   }
 }

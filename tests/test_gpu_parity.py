@@ -458,26 +458,31 @@ def test_device_factors_match_blocked_restatement(torch, prec):
     s.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
-def test_factorization_grouping_does_not_change_results(torch, prec):
-    """Factoring the points in 1..4 concurrent groups gives bit-identical steps."""
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_factorization_schedule_does_not_change_results(torch, prec):
+    """Factoring the points in 1..4 concurrent groups, with or without the
+    look-ahead split of the trailing updates, gives bit-identical steps (four
+    panels, so that two updates are split)."""
     from paper_2502_16555_amd import _lib
-    cfg = CASES["panels"]()
+    cfg = CASES["panels4"]()
     ops = oracle.build_operators(cfg)
     F0 = _state(ops, 11)
     outs = []
-    for g in (1, 2, 3, 4):
+    schedules = [(1, 0), (1, 1), (2, 1), (3, 1), (4, 1)]
+    for g, la in schedules:
         s = solver(cfg, precision=prec)
         s.set_tuning(_lib.TUNE_LU_STREAMS, g)
+        s.set_tuning(_lib.TUNE_LOOKAHEAD, la)
         assert s.get_tuning(_lib.TUNE_LU_STREAMS) == g
+        assert s.get_tuning(_lib.TUNE_LOOKAHEAD) == la
         F = cuda(torch, F0)
         for n in range(3):
             s.step(F, n * cfg["dt_s"])
         assert s.status()[0] == 0
         outs.append(F.cpu().numpy())
         s.close()
-    for g, o in enumerate(outs[1:], start=2):
-        assert np.array_equal(o, outs[0]), f"{g} groups differ from 1"
+    for sch, o in zip(schedules[1:], outs[1:]):
+        assert np.array_equal(o, outs[0]), f"schedule {sch} differs from one group without look-ahead"
 
 
 def _grad_case():
