@@ -10,11 +10,11 @@
 // L_2^-1, ..., U^-1 in that order (A = P_1^T L_1 P_2^T L_2 ... U).
 //
 // Per panel k0:
-//   k_panel   one 512-thread block per matrix (256 for panels of at most 256
-//             rows): partial pivoting (max |a|, ties to the lowest row) over
-//             register-resident sub-panels of 8 (FP64) or 16 (FP32) columns,
-//             in-panel updates of the remaining columns, and the panel's row
-//             permutation for the trailing columns;
+//   k_panel   one 512-thread block per matrix (256 for short panels): partial
+//             pivoting (max |a|, ties to the lowest row) over register-resident
+//             sub-panels of 8 (FP64) or 16 (FP32) columns, left-looking across
+//             the sub-panels, and the panel's row permutation for the
+//             trailing columns;
 //   k_dinv    one block per matrix: inverses of the 16 x 16 diagonal blocks of
 //             the panel's unit lower block L11;
 //   k_l11inv  four blocks per matrix: L11^-1 by blocked substitution on the
@@ -99,13 +99,22 @@ __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* 
 }
 
 // ---------------------------------------------------------------------------
-// Panel factorization: rows k0.., columns k0..k0+NB-1, one block per matrix.
+// Panel factorization: rows k0.., columns k0..k0+NB-1, one block per matrix,
+// left-looking over sub-panels of IB columns: a sub-panel's columns receive
+// the updates of all earlier sub-panels when they are loaded (their L read in
+// chunks of CB columns with the next chunk in flight, the sub-panel's U rows
+// from LDS), are factored in registers, and then only their U rows of the rest
+// of the panel are formed.  The tall part of the panel is read once per
+// sub-panel as L rather than read and written by a right-looking update, which
+// halves the traffic of a 2048-row panel (1.4x faster FP32, 1.6x FP64, with the
+// same products in the same order, hence the same bits).
 // ---------------------------------------------------------------------------
 template <typename T, int NT, int RPT, int IB, int CB>
 __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restrict__ piv,
                                                          int* __restrict__ perm, int* __restrict__ status, int npad,
                                                          int k0, int rend) {
   // rows >= rend are zero in the panel columns (banded systems) and take no part
+  static_assert(IB % CB == 0, "the L chunks must tile the sub-panel width");
   constexpr int NW = NT / 64;
   const int mat = blockIdx.x;
   T* A = LU + (size_t)mat * npad * npad;
@@ -124,6 +133,8 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
   __shared__ int s_lab[kMaxSwapRows];
   __shared__ int s_pos[kMaxRows];
   __shared__ int s_nR, s_any, s_cnt[2];
+  __shared__ T s_Ut[NB][IB];       // U rows (k0..c0) of the sub-panel's columns
+  __shared__ T s_Lr[IB][NB + 1];   // L of the sub-panel's top rows, earlier columns
   bool singular = false, nonfinite = false;
 
   for (int sp = 0; sp < NB / IB; ++sp) {
@@ -134,6 +145,45 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
       const int r = c0 + tid + q * NT;
 #pragma unroll
       for (int j = 0; j < IB; ++j) a[q][j] = (r < rend) ? A[(size_t)(c0 + j) * npad + r] : T(0);
+    }
+    {
+      // a -= L[rows, k0:c0] U[k0:c0, sub-panel]: L in chunks of CB columns with
+      // the next chunk's loads in flight
+      const int nk = c0 - k0;
+      if (nk > 0) {
+        for (int e = tid; e < nk * IB; e += NT) {
+          const int m = e % nk, j = e / nk;
+          s_Ut[m][j] = A[(size_t)(c0 + j) * npad + k0 + m];
+        }
+        __syncthreads();
+        T lv[RPT][CB], ln[RPT][CB];
+        auto ldl = [&](T (&dst)[RPT][CB], int m0) {
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) {
+            const int r = c0 + tid + q * NT;
+#pragma unroll
+            for (int u = 0; u < CB; ++u) dst[q][u] = (r < rend) ? A[(size_t)(k0 + m0 + u) * npad + r] : T(0);
+          }
+        };
+        ldl(lv, 0);
+        for (int m0 = 0; m0 < nk; m0 += CB) {
+          if (m0 + CB < nk) ldl(ln, m0 + CB);
+#pragma unroll
+          for (int u = 0; u < CB; ++u) {
+            T uj[IB];
+#pragma unroll
+            for (int j = 0; j < IB; ++j) uj[j] = s_Ut[m0 + u][j];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q)
+#pragma unroll
+              for (int j = 0; j < IB; ++j) a[q][j] -= lv[q][u] * uj[j];
+          }
+#pragma unroll
+          for (int q = 0; q < RPT; ++q)
+#pragma unroll
+            for (int u = 0; u < CB; ++u) lv[q][u] = ln[q][u];
+        }
+      }
     }
 #pragma clang loop unroll(full)
     for (int j = 0; j < IB; ++j) {
@@ -312,57 +362,40 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
       }
       __syncthreads();
     }
-    // update the remaining columns of the panel
+    // the sub-panel's U rows of the remaining columns of the panel
     const int nrest = k0 + NB - c0 - IB;
     if (nrest > 0) {
+      // U rows c0..c0+IB-1 of the rest: first the updates of the earlier
+      // sub-panels (their L rows staged in LDS, U read down each column in
+      // chunks of 8), then the sub-panel's own unit lower block
+      const int nk = c0 - k0;
+      for (int e = tid; e < IB * nk; e += NT) {
+        const int i = e % IB, m = e / IB;
+        s_Lr[i][m] = A[(size_t)(k0 + m) * npad + c0 + i];
+      }
+      __syncthreads();
+      for (int e = tid; e < IB * nrest; e += NT) {
+        const int i = e % IB, cc = e / IB;
+        const T* colp = A + (size_t)(c0 + IB + cc) * npad;
+        T v = colp[c0 + i];
+        for (int m0 = 0; m0 < nk; m0 += 8) {
+          T uv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) uv[u] = colp[k0 + m0 + u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v -= s_Lr[i][m0 + u] * uv[u];
+        }
+        s_U[i][cc] = v;
+      }
+      __syncthreads();
       if (tid < nrest) {
         T* colp = A + (size_t)(c0 + IB + tid) * npad;
-        for (int j = 0; j < IB; ++j) s_U[j][tid] = colp[c0 + j];
         for (int j = 1; j < IB; ++j) {
           T v = s_U[j][tid];
           for (int i = 0; i < j; ++i) v -= s_L11[j][i] * s_U[i][tid];
           s_U[j][tid] = v;
         }
         for (int j = 0; j < IB; ++j) colp[c0 + j] = s_U[j][tid];
-      }
-      __syncthreads();
-      // rows >= c0+IB: A[r][rest] -= L[r][c0:c0+IB] U[c0:c0+IB][rest], in batches of
-      // CB columns; the next batch is loaded before the current one is stored so
-      // that two batches of loads are in flight per thread
-      T v[RPT][CB], nv[RPT][CB];
-      auto ld = [&](T (&dst)[RPT][CB], int cb) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int r = c0 + tid + q * NT;
-#pragma unroll
-          for (int u = 0; u < CB; ++u)
-            dst[q][u] = (r >= c0 + IB && r < rend && cb + u < nrest) ? A[(size_t)(c0 + IB + cb + u) * npad + r] : T(0);
-        }
-      };
-      ld(v, 0);
-      for (int cb = 0; cb < nrest; cb += CB) {
-        if (cb + CB < nrest) ld(nv, cb + CB);
-#pragma unroll
-        for (int u = 0; u < CB; ++u) {
-          T uj[IB];
-#pragma unroll
-          for (int j = 0; j < IB; ++j) uj[j] = s_U[j][(cb + u) & (NB - 1)];
-#pragma unroll
-          for (int q = 0; q < RPT; ++q)
-#pragma unroll
-            for (int j = 0; j < IB; ++j) v[q][u] -= a[q][j] * uj[j];
-        }
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int r = c0 + tid + q * NT;
-#pragma unroll
-          for (int u = 0; u < CB; ++u)
-            if (r >= c0 + IB && r < rend && cb + u < nrest) A[(size_t)(c0 + IB + cb + u) * npad + r] = v[q][u];
-        }
-#pragma unroll
-        for (int q = 0; q < RPT; ++q)
-#pragma unroll
-          for (int u = 0; u < CB; ++u) v[q][u] = nv[q][u];
       }
       __syncthreads();
     }
@@ -895,18 +928,19 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     const int rows = rend - k0;
     const int rest = cend - k0 - NB;
     constexpr int NT = kPanelThreads;  // 512 threads holding up to 4 rows each
-    // block shape and in-panel update batch by panel height (measured): short
-    // panels (the last ones, banded systems) take four wavefronts, which have
-    // the larger register budget for deeper batches
+    // block shape and L chunk by panel height (measured): short panels (the
+    // last ones, banded systems) take four wavefronts, which have the larger
+    // register budget
+    constexpr int CB = sizeof(T) == 8 ? 4 : 8;
     if (rows <= NT / 2) {
-      k_panel<T, NT / 2, 1, IB, sizeof(T) == 8 ? 8 : 16><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+      k_panel<T, NT / 2, 1, IB, 8><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     } else if (rows <= NT) {
       if constexpr (sizeof(T) == 8) k_panel<T, NT, 1, IB, 8><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
-      else k_panel<T, NT / 2, 2, IB, 16><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+      else k_panel<T, NT / 2, 2, IB, 8><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     } else if (rows <= 2 * NT) {
-      k_panel<T, NT, 2, IB, 4><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+      k_panel<T, NT, 2, IB, CB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     } else {
-      k_panel<T, NT, 4, IB, 4><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+      k_panel<T, NT, 4, IB, CB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     }
     if (rest > 0) k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);
     if (rec) mark(1, p, 1, s);
