@@ -671,6 +671,89 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
 }
 
 // ---------------------------------------------------------------------------
+// One wavefront's triangular solve with a 128 x 128 diagonal block staged in
+// LDS; v0 / v1 hold rows lane / 64 + lane and each solved value is passed on by
+// a lane read.  FWD: ascending (lower triangular), else descending (upper);
+// SCALE: a value is multiplied by the reciprocal of its diagonal entry before
+// it is passed on (non-unit diagonal); TR: the block is used transposed.  For
+// FP32 and FP16 factors the entries the chain needs are read from LDS in chunks
+// of 4 pivots with the next chunk in flight, so that the sequential chain does
+// not wait on an LDS read at every step (4x shorter chains at n = 2048); the
+// two halves of the block are separate loops, so that the register holding
+// the current pivot is known at compile time.
+// ---------------------------------------------------------------------------
+template <typename T, bool FWD, bool SCALE, bool TR, int H>
+__device__ __attribute__((always_inline)) inline void diag_half(const T (*sD)[NB + 1], int lane, double& v0,
+                                                                double& v1, double r0, double r1) {
+  // pivots 64 H .. 64 H + 63, whose values live in v0 (H = 0) or v1 (H = 1);
+  // the entries of 4 pivots are in registers while those of the next 4 load
+  constexpr int CH = 4;
+  constexpr int base = 64 * H;
+  T c0[CH], c1[CH], n0[CH], n1[CH];
+  auto ld = [&](T (&a)[CH], T (&b)[CH], int i0) {
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      a[u] = TR ? sD[i0 + u][lane] : sD[lane][i0 + u];
+      b[u] = TR ? sD[i0 + u][64 + lane] : sD[64 + lane][i0 + u];
+    }
+  };
+  ld(c0, c1, base + (FWD ? 0 : 64 - CH));
+  for (int k = 0; k < 64 / CH; ++k) {
+    const int i0 = base + (FWD ? k * CH : 64 - CH - k * CH);
+    if (k + 1 < 64 / CH) ld(n0, n1, FWD ? i0 + CH : i0 - CH);
+#pragma unroll
+    for (int uu = 0; uu < CH; ++uu) {
+      const int u = FWD ? uu : CH - 1 - uu;
+      const int i = i0 + u;
+      double& vp = H ? v1 : v0;
+      if constexpr (SCALE) {
+        if (lane == i - base) vp = vp * (H ? r1 : r0);
+      }
+      const double xi = readlane_f64(vp, i - base);
+      if (FWD ? lane > i : lane < i) v0 -= static_cast<double>(c0[u]) * xi;
+      if (FWD ? 64 + lane > i : 64 + lane < i) v1 -= static_cast<double>(c1[u]) * xi;
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      c0[u] = n0[u];
+      c1[u] = n1[u];
+    }
+  }
+}
+
+template <typename T, bool FWD, bool SCALE, bool TR>
+__device__ __attribute__((always_inline)) inline void diag_chain(const T (*sD)[NB + 1], int lane, double& v0,
+                                                                 double& v1) {
+  double r0 = 1.0, r1 = 1.0;
+  if constexpr (SCALE) {
+    r0 = 1.0 / static_cast<double>(sD[lane][lane]);
+    r1 = 1.0 / static_cast<double>(sD[64 + lane][64 + lane]);
+  }
+  if constexpr (sizeof(T) == 8) {
+    // FP64: one loop, unrolled by 4 (prefetched chunks spill next to the strip)
+#pragma unroll 4
+    for (int k = 0; k < NB; ++k) {
+      const int i = FWD ? k : NB - 1 - k;
+      const double l0 = TR ? sD[i][lane] : sD[lane][i];
+      const double l1 = TR ? sD[i][64 + lane] : sD[64 + lane][i];
+      if constexpr (SCALE) {
+        if (i < 64 && lane == i) v0 = v0 * r0;
+        if (i >= 64 && lane == i - 64) v1 = v1 * r1;
+      }
+      const double xi = (i < 64) ? readlane_f64(v0, i) : readlane_f64(v1, i - 64);
+      if (FWD ? lane > i : lane < i) v0 -= l0 * xi;
+      if (FWD ? 64 + lane > i : 64 + lane < i) v1 -= l1 * xi;
+    }
+  } else if constexpr (FWD) {
+    diag_half<T, FWD, SCALE, TR, 0>(sD, lane, v0, v1, r0, r1);
+    diag_half<T, FWD, SCALE, TR, 1>(sD, lane, v0, v1, r0, r1);
+  } else {
+    diag_half<T, FWD, SCALE, TR, 1>(sD, lane, v0, v1, r0, r1);
+    diag_half<T, FWD, SCALE, TR, 0>(sD, lane, v0, v1, r0, r1);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Solve with the factors (one 1024-thread block per matrix), FP64 right-hand side.
 // transpose = 0: x = U^-1 L_m^-1 P_m ... L_1^-1 P_1 b
 // transpose = 1: y = P_1^T L_1^-T ... P_m^T L_m^-T U^-T c
@@ -777,11 +860,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       __syncthreads();
       if (w == 0) {  // unit lower triangular diagonal block
         double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
-        for (int i = 0; i < NB - 1; ++i) {
-          const double xi = (i < 64) ? readlane_f64(v0, i) : readlane_f64(v1, i - 64);
-          if (lane > i) v0 -= static_cast<double>(sD[lane][i]) * xi;
-          if (64 + lane > i) v1 -= static_cast<double>(sD[64 + lane][i]) * xi;
-        }
+        diag_chain<T, true, false, false>(sD, lane, v0, v1);
         sb[k0 + lane] = v0;
         sb[k0 + 64 + lane] = v1;
       }
@@ -794,18 +873,9 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       const int k0 = p * NB;
       stage_diag(k0);
       __syncthreads();
-      if (w == 0) {  // upper triangular diagonal block
+      if (w == 0) {  // upper triangular diagonal block (reciprocals of the diagonal off the chain)
         double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
-        // reciprocals of the diagonal off the sequential chain
-        const double r0 = 1.0 / static_cast<double>(sD[lane][lane]);
-        const double r1 = 1.0 / static_cast<double>(sD[64 + lane][64 + lane]);
-        for (int i = NB - 1; i >= 0; --i) {
-          if (i >= 64 && lane == i - 64) v1 = v1 * r1;
-          if (i < 64 && lane == i) v0 = v0 * r0;
-          const double xi = (i < 64) ? readlane_f64(v0, i) : readlane_f64(v1, i - 64);
-          if (lane < i) v0 -= static_cast<double>(sD[lane][i]) * xi;
-          if (64 + lane < i) v1 -= static_cast<double>(sD[64 + lane][i]) * xi;
-        }
+        diag_chain<T, false, true, false>(sD, lane, v0, v1);
         sb[k0 + lane] = v0;
         sb[k0 + 64 + lane] = v1;
       }
@@ -821,17 +891,9 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       const int k0 = p * NB;
       stage_diag(k0);
       __syncthreads();
-      if (w == 0) {
+      if (w == 0) {  // U^T: lower triangular
         double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
-        const double r0 = 1.0 / static_cast<double>(sD[lane][lane]);
-        const double r1 = 1.0 / static_cast<double>(sD[64 + lane][64 + lane]);
-        for (int i = 0; i < NB; ++i) {
-          if (i < 64 && lane == i) v0 = v0 * r0;
-          if (i >= 64 && lane == i - 64) v1 = v1 * r1;
-          const double xi = (i < 64) ? readlane_f64(v0, i) : readlane_f64(v1, i - 64);
-          if (lane > i) v0 -= static_cast<double>(sD[i][lane]) * xi;
-          if (64 + lane > i) v1 -= static_cast<double>(sD[i][64 + lane]) * xi;
-        }
+        diag_chain<T, true, true, true>(sD, lane, v0, v1);
         sb[k0 + lane] = v0;
         sb[k0 + 64 + lane] = v1;
       }
@@ -861,11 +923,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       __syncthreads();
       if (w == 0) {  // L11^T is unit upper triangular
         double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
-        for (int i = NB - 1; i >= 0; --i) {
-          const double xi = (i < 64) ? readlane_f64(v0, i) : readlane_f64(v1, i - 64);
-          if (lane < i) v0 -= static_cast<double>(sD[i][lane]) * xi;
-          if (64 + lane < i) v1 -= static_cast<double>(sD[i][64 + lane]) * xi;
-        }
+        diag_chain<T, false, false, true>(sD, lane, v0, v1);
         sb[k0 + lane] = v0;
         sb[k0 + 64 + lane] = v1;
       }
