@@ -114,7 +114,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
                                                          int* __restrict__ perm, int* __restrict__ status, int npad,
                                                          int k0, int rend) {
   // rows >= rend are zero in the panel columns (banded systems) and take no part
-  static_assert(IB % CB == 0, "the L chunks must tile the sub-panel width");
+  static_assert(IB % CB == 0 || CB % IB == 0, "the L chunk and the sub-panel width must nest");
   constexpr int NW = NT / 64;
   const int mat = blockIdx.x;
   T* A = LU + (size_t)mat * npad * npad;
@@ -148,7 +148,8 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
     }
     {
       // a -= L[rows, k0:c0] U[k0:c0, sub-panel]: L in chunks of CB columns with
-      // the next chunk's loads in flight
+      // the next chunk's loads in flight (a chunk wider than the sub-panel may
+      // end past column c0: those loads and products are skipped)
       const int nk = c0 - k0;
       if (nk > 0) {
         for (int e = tid; e < nk * IB; e += NT) {
@@ -162,7 +163,8 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
           for (int q = 0; q < RPT; ++q) {
             const int r = c0 + tid + q * NT;
 #pragma unroll
-            for (int u = 0; u < CB; ++u) dst[q][u] = (r < rend) ? A[(size_t)(k0 + m0 + u) * npad + r] : T(0);
+            for (int u = 0; u < CB; ++u)
+              dst[q][u] = (r < rend && (IB % CB == 0 || m0 + u < nk)) ? A[(size_t)(k0 + m0 + u) * npad + r] : T(0);
           }
         };
         ldl(lv, 0);
@@ -170,6 +172,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
           if (m0 + CB < nk) ldl(ln, m0 + CB);
 #pragma unroll
           for (int u = 0; u < CB; ++u) {
+            if (CB % IB == 0 && CB > IB && m0 + u >= nk) break;   // last chunk of a wide CB
             T uj[IB];
 #pragma unroll
             for (int j = 0; j < IB; ++j) uj[j] = s_Ut[m0 + u][j];
@@ -989,16 +992,17 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     // block shape and L chunk by panel height (measured): short panels (the
     // last ones, banded systems) take four wavefronts, which have the larger
     // register budget
-    constexpr int CB = sizeof(T) == 8 ? 4 : 8;
+    // (FP64 short panels: chunks of 16 L columns, two sub-panels, keep the
+    // latency-bound left-looking update to half as many round trips)
+    constexpr bool F64 = sizeof(T) == 8;
     if (rows <= NT / 2) {
-      k_panel<T, NT / 2, 1, IB, 8><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+      k_panel<T, NT / 2, 1, IB, F64 ? 16 : 8><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     } else if (rows <= NT) {
-      if constexpr (sizeof(T) == 8) k_panel<T, NT, 1, IB, 8><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
-      else k_panel<T, NT / 2, 2, IB, 8><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+      k_panel<T, NT / 2, 2, IB, F64 ? 16 : 8><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     } else if (rows <= 2 * NT) {
-      k_panel<T, NT, 2, IB, CB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+      k_panel<T, NT, 2, IB, 8><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     } else {
-      k_panel<T, NT, 4, IB, CB><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+      k_panel<T, NT, 4, IB, F64 ? 4 : 8><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     }
     if (rest > 0) k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);
     if (rec) mark(1, p, 1, s);
