@@ -122,6 +122,7 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   __shared__ double s_val[2][NW];
   __shared__ int s_idx[2][NW];
+  __shared__ unsigned long long s_key[2][NW];
   __shared__ T s_row[2][1][IB];
   __shared__ T s_cand[2][NW][IB];
   __shared__ T s_L11[IB][IB + 1];
@@ -193,18 +194,36 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
       const int c = c0 + j;
       double best = -1.0;
       int bi = INT_MAX;
+      // FP32: one 64-bit key per candidate, the bits of |a| (monotone for
+      // non-negative floats) over ~row, so that a single maximum picks the
+      // largest |a| and, among equal ones, the lowest row; 0 = no candidate
+      // (NaN or outside the panel's rows)
+      unsigned long long key = 0;
+      if constexpr (sizeof(T) == 4) {
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int r = c0 + tid + q * NT;
-        if (r >= c && r < rend) {
-          const double v = fabs(static_cast<double>(a[q][j]));
-          if (v > best) {
-            best = v;
-            bi = r;
+        for (int q = 0; q < RPT; ++q) {
+          const int r = c0 + tid + q * NT;
+          const float av = fabsf(a[q][j]);
+          if (r >= c && r < rend && av == av) {
+            const unsigned long long k =
+                (static_cast<unsigned long long>(__float_as_uint(av)) << 32) | static_cast<unsigned>(~r);
+            key = k > key ? k : key;
           }
         }
-      }
-      {
+        key = wave_max_u64(key);
+        bi = key ? static_cast<int>(~static_cast<unsigned>(key)) : INT_MAX;
+      } else {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int r = c0 + tid + q * NT;
+          if (r >= c && r < rend) {
+            const double v = fabs(static_cast<double>(a[q][j]));
+            if (v > best) {
+              best = v;
+              bi = r;
+            }
+          }
+        }
         const double wm = wave_max(best);
         bi = wave_min(best == wm ? bi : INT_MAX);
         best = wm;
@@ -217,8 +236,12 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
       // passed the barrier of the column in between and finished reading it.
       const int par = j & 1;
       if (lane == 0) {
-        s_val[par][wid] = best;
-        s_idx[par][wid] = bi;
+        if constexpr (sizeof(T) == 4) {
+          s_key[par][wid] = key;
+        } else {
+          s_val[par][wid] = best;
+          s_idx[par][wid] = bi;
+        }
       }
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
@@ -233,7 +256,18 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
       }
       __syncthreads();
       int p = INT_MAX, pw = 0;
-      {
+      if constexpr (sizeof(T) == 4) {
+        unsigned long long km = 0;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+          const unsigned long long ok = s_key[par][u];
+          if (ok > km) {
+            km = ok;
+            pw = u;
+          }
+        }
+        if (km) p = static_cast<int>(~static_cast<unsigned>(km));
+      } else {
         double v = -1.0;
 #pragma unroll
         for (int u = 0; u < NW; ++u) {

@@ -76,6 +76,32 @@ __device__ inline double wave_max(double v) {
   const double m0 = r1 > r0 ? r1 : r0, m1 = r3 > r2 ? r3 : r2;
   return m1 > m0 ? m1 : m0;
 }
+// maximum over the wavefront of 64-bit unsigned keys; uniform result
+template <int CTRL>
+__device__ inline unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(v >> 32), CTRL, 0xF, 0xF, false);
+  return (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) | static_cast<unsigned>(lo);
+}
+__device__ inline unsigned long long readlane_u64(unsigned long long v, int l) {
+  const unsigned lo = __builtin_amdgcn_readlane(static_cast<int>(v), l);
+  const unsigned hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), l);
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+  unsigned long long o = dpp_u64<0xB1>(v);
+  v = o > v ? o : v;
+  o = dpp_u64<0x4E>(v);
+  v = o > v ? o : v;
+  o = dpp_u64<0x141>(v);
+  v = o > v ? o : v;
+  o = dpp_u64<0x140>(v);
+  v = o > v ? o : v;
+  const unsigned long long r0 = readlane_u64(v, 0), r1 = readlane_u64(v, 16), r2 = readlane_u64(v, 32),
+                           r3 = readlane_u64(v, 48);
+  const unsigned long long m0 = r1 > r0 ? r1 : r0, m1 = r3 > r2 ? r3 : r2;
+  return m1 > m0 ? m1 : m0;
+}
 __device__ inline int wave_min(int v) {
   v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
   v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
