@@ -34,6 +34,7 @@
 #include <cfloat>
 #include <climits>
 #include <limits>
+#include <type_traits>
 #include <cmath>
 
 #include "internal.h"
@@ -307,22 +308,28 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
       }
       if (pv == T(0)) singular = true;
       if (!(fabs(static_cast<double>(pv)) <= DBL_MAX)) nonfinite = true;
-      // multipliers by the reciprocal of the pivot (division for subnormal pivots)
+      // multipliers by the reciprocal of the pivot (division for subnormal
+      // pivots); the pivot is the same in every lane, so a scalar branch keeps
+      // the divisions off the common path
       const bool by_rcp = fabs(pv) >= std::numeric_limits<T>::min();
       const T rp = T(1) / pv;
+      auto rank1 = [&](auto use_rcp) {
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int r = c0 + tid + q * NT;
-        if (r > c && r < rend && pv != T(0)) {
-          const T x = a[q][j];
-          const T l = by_rcp ? x * rp : x / pv;
+        for (int q = 0; q < RPT; ++q) {
+          const int r = c0 + tid + q * NT;
+          if (r > c && r < rend && pv != T(0)) {
+            const T x = a[q][j];
+            const T l = decltype(use_rcp)::value ? x * rp : x / pv;
 #pragma unroll
-          for (int jj = 0; jj < IB; ++jj) {
-            const T upd = a[q][jj] - l * prow[jj];
-            a[q][jj] = (jj > j) ? upd : (jj == j ? l : a[q][jj]);
+            for (int jj = 0; jj < IB; ++jj) {
+              const T upd = a[q][jj] - l * prow[jj];
+              a[q][jj] = (jj > j) ? upd : (jj == j ? l : a[q][jj]);
+            }
           }
         }
-      }
+      };
+      if (__builtin_amdgcn_readfirstlane(static_cast<int>(by_rcp))) rank1(std::true_type{});
+      else rank1(std::false_type{});
     }
     __syncthreads();
     // write the factored sub-panel back (coalesced: consecutive threads, consecutive rows)
