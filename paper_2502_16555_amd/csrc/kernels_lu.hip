@@ -1033,15 +1033,18 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     // block shape and L chunk by panel height (measured): short panels (the
     // last ones, banded systems) take four wavefronts, which have the larger
     // register budget
-    // (FP64 short panels: chunks of 16 L columns, two sub-panels, keep the
-    // latency-bound left-looking update to half as many round trips)
+    // (FP64: chunks of 16 L columns on the shortest panels, which keeps the
+    // latency-bound left-looking update to half as many round trips, and
+    // 16-column sub-panels where the registers allow, which halves the L
+    // re-reads; the sub-panel width does not change the result, every element
+    // takes its products in column order either way)
     constexpr bool F64 = sizeof(T) == 8;
     if (rows <= NT / 2) {
       k_panel<T, NT / 2, 1, IB, F64 ? 16 : 8><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     } else if (rows <= NT) {
-      k_panel<T, NT / 2, 2, IB, F64 ? 16 : 8><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+      k_panel<T, NT / 2, 2, 16, 8><<<nmat, NT / 2, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     } else if (rows <= 2 * NT) {
-      k_panel<T, NT, 2, IB, 8><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
+      k_panel<T, NT, 2, 16, F64 ? 4 : 8><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     } else {
       k_panel<T, NT, 4, IB, F64 ? 4 : 8><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     }
