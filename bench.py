@@ -67,7 +67,7 @@ KRYLOV = dict(n_bins=128, bin_scale=100.0, restart=12, cycles=3, rtol=1e-12, fac
 
 
 def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=False, krylov=False, banded=False,
-            lookahead=None):
+            pairs=None):
     from paper_2502_16555_amd import Solver, _lib
     t0 = time.time()
     s = Solver(cfg, precision=precision)
@@ -78,8 +78,8 @@ def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=Fals
     setup_s = time.time() - t0
     if lu_streams is not None:
         s.set_tuning(_lib.TUNE_LU_STREAMS, lu_streams)
-    if lookahead is not None:
-        s.set_tuning(_lib.TUNE_LOOKAHEAD, lookahead)
+    if pairs is not None:
+        s.set_tuning(_lib.TUNE_PANEL_PAIRS, pairs)
     import workloads
     ne = workloads.density_profile(s.xhat(), cfg["ic"]["ne_peak"])
     F = s.initial_state(torch.as_tensor(ne, device="cuda:0"), cfg["ic"]["Te_eV"])
@@ -125,7 +125,7 @@ def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=Fals
            "moments": mom, "n_end": n_end, "first_step_moments": first,
            "ms_update": tm[0] / nt, "ms_panel": tm[1] / nt, "ms_vwall": tm[2] / nt, "ms_x": tm[4] / nt,
            "update_launches": tm[3] / nt, "lu_streams": s.get_tuning(_lib.TUNE_LU_STREAMS),
-           "lookahead": s.get_tuning(_lib.TUNE_LOOKAHEAD),
+           "panel_pairs": s.get_tuning(_lib.TUNE_PANEL_PAIRS),
            "info": s.info}
     s.close()
     return out

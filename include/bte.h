@@ -334,8 +334,9 @@ bte_status bte_get_status(bte_handle* h, int32_t* refine_iters, double* final_re
 bte_status bte_set_timing(bte_handle* h, int32_t enable);
 bte_status bte_get_timing(bte_handle* h, double* ms_out);
 
-/* Launch-shape tuning; results do not depend on it (every matrix is factored
- * by the same arithmetic in the same order whatever the shape).
+/* Launch-shape tuning; apart from BTE_TUNE_PANEL_PAIRS, results do not depend
+ * on it (every matrix is factored by the same arithmetic in the same order
+ * whatever the shape).
  *   BTE_TUNE_LU_STREAMS: the points are split into this many groups of
  *     consecutive points, factored concurrently on the handle's own side
  *     streams (default priority) and joined back into the caller's stream with
@@ -347,19 +348,20 @@ bte_status bte_get_timing(bte_handle* h, double* ms_out);
  *     BF16 updates have a fixed chunk of 32 (reported as such).
  *   BTE_TUNE_FORM_XPB: matrices formed per block of the formation kernel,
  *     1..64; 0 = default (16).
- *   BTE_TUNE_LOOKAHEAD: 0 (default) or 1.  With one group, each panel's
- *     trailing update is split: the next panel's 128 columns are updated on
- *     the caller's stream, the remaining columns on the handle's side stream
- *     (default priority), where they may overlap the next panel factorization;
- *     events order the two.  Ignored with more than one group.  A panel block
- *     occupies a whole compute unit's registers, so the two kernels share the
- *     GPU by compute units rather than overlap within them.
+ *   BTE_TUNE_PANEL_PAIRS: 1 (default) or 0.  Dense factors take the panels in
+ *     pairs: a panel's update of the columns beyond the next panel is deferred
+ *     and applied together with the next panel's in one update of depth 256,
+ *     which reads and writes the trailing matrix half as often.  The factors
+ *     then store each pair's second interchanges in the first panel's L rows
+ *     as well (the solves follow).  Unlike the other keys this one changes the
+ *     rounding of the trailing updates (not the pivots of a well-separated
+ *     column); it only takes effect at the next factorization.
  * Returns BTE_EINVAL for an unknown key or a value out of range. */
 typedef enum {
   BTE_TUNE_LU_STREAMS = 0,
   BTE_TUNE_UPDATE_KC = 1,
   BTE_TUNE_FORM_XPB = 2,
-  BTE_TUNE_LOOKAHEAD = 3
+  BTE_TUNE_PANEL_PAIRS = 3
 } bte_tune_key;
 bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value);
 bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value);

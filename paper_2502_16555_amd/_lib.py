@@ -57,7 +57,7 @@ VSOLVER_BANDED = 2
 TUNE_LU_STREAMS = 0
 TUNE_UPDATE_KC = 1
 TUNE_FORM_XPB = 2
-TUNE_LOOKAHEAD = 3
+TUNE_PANEL_PAIRS = 3
 
 EXPORTS = {
     "bte_setup_operators": (C.c_int, [C.POINTER(bte_config), C.c_int, C.POINTER(C.c_void_p)]),

@@ -67,11 +67,6 @@ struct bte_handle {
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kMaxLuStreams] = {};
   std::vector<hipEvent_t> lu_ev;   // kMaxLuStreams * 8 * max_panels
-  // look-ahead schedule of a one-group factorization (side stream, default
-  // priority, and its two events); off by default: a panel block holds a whole
-  // CU's register file, so the side-stream update and the panel do not share CUs
-  bool lookahead = false;
-  bte::LuLookahead la;
   bte::LuTimer lu_timer[kMaxLuStreams];
   double ms_acc[6] = {0, 0, 0, 0, 0, 0};
   // Krylov V solver (bte_set_vsolver): factors of the field-binned
@@ -146,9 +141,6 @@ struct bte_handle {
       if (e) (void)hipEventDestroy(e);
     for (auto& q : gs)
       if (q) (void)hipStreamDestroy(q);
-    if (la.u12_done) (void)hipEventDestroy(la.u12_done);
-    if (la.rest_done) (void)hipEventDestroy(la.rest_done);
-    if (la.side) (void)hipStreamDestroy(la.side);
     drop_graph();
     drop_krylov();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -393,7 +385,7 @@ void factor_all(bte_handle* h, hipStream_t s) {
   const int prec = h->cfg.precision;
   const int G = std::max(1, std::min(h->lu_streams, d.nx_total));
   if (G == 1) {
-    bte::launch_lu_factor(d, prec, s, h->timing ? &h->lu_timer[0] : nullptr, 0, -1, h->lookahead ? &h->la : nullptr);
+    bte::launch_lu_factor(d, prec, s, h->timing ? &h->lu_timer[0] : nullptr);
     return;
   }
   HIP_OK(hipEventRecord(h->fork_ev, s));
@@ -743,9 +735,6 @@ bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle
       HIP_OK(hipEventCreateWithFlags(&h->join_ev[g], hipEventDisableTiming));
     }
     HIP_OK(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
-    HIP_OK(hipStreamCreateWithFlags(&h->la.side, hipStreamNonBlocking));
-    HIP_OK(hipEventCreateWithFlags(&h->la.u12_done, hipEventDisableTiming));
-    HIP_OK(hipEventCreateWithFlags(&h->la.rest_done, hipEventDisableTiming));
     HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     // pointers inside cfg are not retained
     h->cfg.proc = nullptr;
@@ -1311,9 +1300,9 @@ bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value) {
       if (value < 0 || value > 64) return BTE_EINVAL;
       h->d.form_xpb = value;
       return BTE_OK;
-    case BTE_TUNE_LOOKAHEAD:
+    case BTE_TUNE_PANEL_PAIRS:
       if (value != 0 && value != 1) return BTE_EINVAL;
-      h->lookahead = value != 0;
+      h->d.lu_pairs = value;
       return BTE_OK;
     default:
       return BTE_EINVAL;
@@ -1331,7 +1320,7 @@ bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value) {
       return BTE_OK;
     }
     case BTE_TUNE_FORM_XPB: *value = h->d.form_xpb ? h->d.form_xpb : 16; return BTE_OK;
-    case BTE_TUNE_LOOKAHEAD: *value = h->lookahead ? 1 : 0; return BTE_OK;
+    case BTE_TUNE_PANEL_PAIRS: *value = h->d.lu_pairs; return BTE_OK;
     default: return BTE_EINVAL;
   }
 }

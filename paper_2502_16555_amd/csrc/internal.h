@@ -61,6 +61,7 @@ struct DevOps {
   double* Y = nullptr;         // [nx_total*n] mode-major scratch of the X step
   void* lu = nullptr;          // [nx_total][npad][npad] of T (double or float), column-major
   void* xscr = nullptr;        // [nx_total][npad][kNB] of T: interchange staging of extra rows
+  int lu_pairs = 1;             // dense factors: panels in pairs (K = 256 trailing updates)
   void* linv = nullptr;        // [nx_total][kLinvElems] of T: inverses of L11's diagonal blocks, then of L11
   int* piv = nullptr;          // [nx_total][npad]
   int* perm = nullptr;         // [nx_total][kMaxPanels][kPermStride] row permutation of every panel
@@ -160,37 +161,30 @@ void launch_maxwellian(const DevOps& d, const double* ne, const double* coeff, d
 // pairs [0, n_panels) bracket the trailing updates, [n_panels, 2 n_panels) the
 // panel + interchange/TRSM launches of each panel step.
 struct LuTimer {
-  // 8 * max_panels events, one pair per panel each: [0, 2P) trailing update (on
-  // the factor stream), [2P, 4P) panel and diagonal-block inverses, [4P, 6P)
-  // the look-ahead's remaining update (on the side stream), [6P, 8P) U12
+  // 8 * max_panels events, one pair per panel each: [0, 2P) trailing update,
+  // [2P, 4P) panel and diagonal-block inverses, [4P, 6P) unused (kept empty),
+  // [6P, 8P) L11 inverse and U12
   hipEvent_t* ev = nullptr;
   int max_panels = 0;
   int used = 0;               // panel steps recorded
   int launches = 0;           // trailing-update launches recorded
 };
 
-// Look-ahead schedule of the factorization: the trailing update of panel p is
-// split into the next panel's columns, updated on the factor stream, and the
-// remaining columns, updated on the side stream while panel p+1 is factored;
-// U12 of panel p+1 waits for the remaining update (it reads those columns).
-struct LuLookahead {
-  hipStream_t side = nullptr;
-  hipEvent_t u12_done = nullptr;    // factor stream: U12 of the current panel written
-  hipEvent_t rest_done = nullptr;   // side stream: remaining update finished
-};
+// Dense factors are formed with the panels in pairs (the solve must know).
+inline bool lu_paired(const DevOps& d) { return d.lu_pairs != 0 && d.band_kl == 0; }
 
 // ---- V step (kernels_lu.hip) ------------------------------------------------
 // Forms I - dt (n0 C + E A) (padded to npad with identity) and factors it in
 // place, for the points m0 .. m0+count-1 (count < 0: to the last point).
-// la (optional): the look-ahead schedule, with its side stream and events.
 void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer = nullptr, int m0 = 0,
-                      int count = -1, const LuLookahead* la = nullptr);
-// A22 -= L21 U12 of panel k0 for nmat matrices (mtr x mtc tiles of 128, column
-// tiles tj0 .. tj0 + mtc - 1 of the trailing matrix): kind 0 FP64, 1 FP32, 2
-// FP32 with bf16 operands, 3 FP32 with split bf16 operands; alt_kc: K chunk 32
-// (FP32) / 8 (FP64) instead of 16.
+                      int count = -1);
+// A22 -= L21 U12 of the kd = 128 (one panel) or 256 (two panels) columns from
+// k0 for nmat matrices (mtr x mtc tiles of 128, column tiles tj0 .. tj0 + mtc - 1
+// of the trailing matrix from k0 + kd): kind 0 FP64, 1 FP32, 2 FP32 with bf16
+// operands, 3 FP32 with split bf16 operands; alt_kc: K chunk 32 (FP32) / 8
+// (FP64) instead of 16.
 void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int tj0, int nmat, bool alt_kc,
-                   hipStream_t s);
+                   hipStream_t s, int kd = kNB);
 // X = LU^-1 B (or LU^-T B with transpose), rows of length npad, FP64 right-hand sides.
 void launch_lu_solve(const DevOps& d, int precision, bool transpose, const double* Bin, double* Xout,
                      bool accumulate, bool check_done, hipStream_t s);

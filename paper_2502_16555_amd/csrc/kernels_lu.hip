@@ -26,10 +26,11 @@
 //   k_update  A22 -= L21 U12: 128 x 128 MFMA tiles, K = 128 in double-buffered
 //             LDS chunks; blocks of one matrix are kept on one XCD so that L21
 //             and U12 stay in that XCD's L2.
-// With look-ahead, the update of the next panel's 128 columns goes first, on
-// the factor stream, and the update of the columns after it on a side stream,
-// where it overlaps the next (latency-bound) panel factorization; the next
-// U12 waits for it.  Every tile is computed by the same arithmetic either way.
+// Dense systems take the panels in pairs: panel p updates panel p+1's columns
+// at once, its update of the columns beyond is deferred, and after panel p+1
+// one K = 256 update applies both (A22 read and written once per two panels).
+// Panel p+1's interchanges then also reach panel p's L columns, so the solve
+// applies P_p P_{p+1} before L_p and L_{p+1} (A = ... P_p^T P_{p+1}^T L' ...).
 #include <algorithm>
 #include <cfloat>
 #include <climits>
@@ -606,7 +607,7 @@ __global__ __launch_bounds__(128) void k_l11inv(const T* __restrict__ LU, T* __r
 // stages its own elements) and written after the last chunk, when every read
 // of the tile's columns has been made.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool FROM_W = false>
 __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __restrict__ linv,
                                                const int* __restrict__ perm, T* __restrict__ xscr, int npad, int k0,
                                                int nct, int nmat) {
@@ -630,7 +631,9 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
   const int li = lane & 15, lk = lane >> 4;
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
   if (tid < NB) s_src[tid] = src[tid];
-  const int nx = nR - NB;
+  // FROM_W: the tile of P A12 is already gathered (and updated) in xscr as
+  // W[col][k], and the interchanges' other rows are already moved
+  const int nx = FROM_W ? 0 : nR - NB;
   T* xs = xscr + ((size_t)mat * npad + c0) * NB;
   for (int e = tid; e < nx * 128; e += 256) {
     const int t = NB + e % nx, j = e / nx;
@@ -652,7 +655,7 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
     for (int u = 0; u < NBS; ++u) {
       const int e = tid + u * 256;
       const int k = e % KC, j = e / KC;
-      rb[u] = A[(size_t)(c0 + j) * npad + s_src[kk + k]];
+      rb[u] = FROM_W ? xs[(size_t)j * NB + kk + k] : A[(size_t)(c0 + j) * npad + s_src[kk + k]];
     }
   };
   auto store = [&](int buf) {
@@ -711,6 +714,183 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
   for (int e = tid; e < nx * 128; e += 256) {
     const int t = NB + e % nx, j = e / nx;
     if (src[t] != R[t]) A[(size_t)(c0 + j) * npad + R[t]] = xs[(size_t)j * NB + (t - NB)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Panels in pairs (p at kp, p+1 at k1 = kp + NB): panel p's update reaches panel
+// p+1's columns at once, and is deferred for the columns beyond, where one
+// K = 256 update then applies both panels.  Panel p+1's U12 needs its top rows
+// (after the interchanges of panel p+1) with panel p's update applied; these
+// kernels form them and keep the deferred update consistent:
+//   k_u12pre     W[col][k] = A[src[k]][col] - sum_i L_p[src[k]][i] U_p[i][col]
+//                for the 128 rows src[k] that the interchanges of panel p+1
+//                bring to its top block: one MFMA product per 128-column tile,
+//                the gathered rows of L_p as the row operand; into xscr, which
+//                k_u12<T, true> then takes in place of its gather;
+//   k_move_down  the interchanges' other rows, A[R[t]] = A[src[t]] (t >= 128):
+//                contents only ever leave the top block downwards, so every
+//                source is a top-block row, not yet overwritten by U12;
+//   k_perm_lp    the interchanges applied to panel p's L columns as well, so
+//                that each row's deferred update moves with it; the solve then
+//                applies P_{p+1} before L_p (A = P_p^T P_{p+1}^T L' U per pair).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_u12pre(T* __restrict__ LU, const int* __restrict__ perm,
+                                                T* __restrict__ xscr, int npad, int k1, int nct, int nmat) {
+  using V = typename Vec4<T>::type;
+  constexpr int PER = Vec4<T>::per;
+  constexpr int KC = 16, LD = 128 + 4;
+  int mat, ct;
+  xcd_map(blockIdx.x, nct, nmat, &mat, &ct);
+  if (mat >= nmat) return;
+  T* A = LU + (size_t)mat * npad * npad;
+  const int kp = k1 - NB;
+  const int c0 = k1 + NB + ct * 128;
+  const int* src = perm + ((size_t)mat * kMaxPanels + k1 / NB) * kPermStride + 1 + kMaxSwapRows;
+  __shared__ __align__(16) T smem[4 * KC * LD];   // the operand chunks, then the passes of W
+  T (*sA)[KC][LD] = reinterpret_cast<T (*)[KC][LD]>(smem);
+  T (*sB)[KC][LD] = reinterpret_cast<T (*)[KC][LD]>(smem + 2 * KC * LD);
+  __shared__ int s_src[NB];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  if (tid < NB) s_src[tid] = src[tid];
+  __syncthreads();
+  constexpr int NAS = KC * 128 / 256;         // gathered L_p elements per thread and chunk
+  constexpr int NBV = KC * 128 / PER / 256;   // U_p vectors per thread and chunk
+  T ra[NAS];
+  V rb[NBV];
+  auto load = [&](int kk) {
+#pragma unroll
+    for (int u = 0; u < NAS; ++u) {
+      const int e = tid + u * 256;
+      ra[u] = A[(size_t)(kp + kk + e / 128) * npad + s_src[e % 128]];
+    }
+#pragma unroll
+    for (int u = 0; u < NBV; ++u) {
+      const int e = tid + u * 256;
+      const int j = e / (KC / PER), k = (e % (KC / PER)) * PER;
+      rb[u] = *reinterpret_cast<const V*>(A + (size_t)(c0 + j) * npad + kp + kk + k);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NAS; ++u) {
+      const int e = tid + u * 256;
+      sA[buf][e / 128][e % 128] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NBV; ++u) {
+      const int e = tid + u * 256;
+      const int j = e / (KC / PER), k = (e % (KC / PER)) * PER;
+      const T* v = reinterpret_cast<const T*>(&rb[u]);
+#pragma unroll
+      for (int m = 0; m < PER; ++m) sB[buf][k + m][j] = v[m];
+    }
+  };
+  typename Mma<T>::acc acc[4][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = typename Mma<T>::acc{0, 0, 0, 0};
+  load(0);
+  store(0);
+  __syncthreads();
+  constexpr int NCH = NB / KC;
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < NCH) load((ch + 1) * KC);
+#pragma unroll
+    for (int k = 0; k < KC; k += 4) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][k + lk][wr + bi * 16 + li];
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][k + lk][wc + bj * 16 + li];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mma<T>::step(av[bi], bv[bj], acc[bi][bj]);
+    }
+    if (ch + 1 < NCH) {
+      store(buf ^ 1);
+      __syncthreads();
+    }
+  }
+  // W = A[src rows] - acc, through LDS in four passes of 32 rows so that the
+  // gathered reads and the stores of W run down the columns
+  T* xs = xscr + ((size_t)mat * npad + c0) * NB;
+  constexpr int RP = 32, LDC = RP + 4;
+  static_assert(128 * LDC <= 4 * KC * LD, "a pass of the tile fits in the operand buffers");
+  T* sC = smem;
+#pragma unroll
+  for (int pass = 0; pass < 128 / RP; ++pass) {
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+      if ((wr + bi * 16) / RP == pass) {
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+          for (int it = 0; it < 4; ++it)
+            sC[(wc + bj * 16 + li) * LDC + wr + bi * 16 - pass * RP + Mma<T>::row(lk, it)] = acc[bi][bj][it];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 128 * RP / 256; ++u) {
+      const int e = tid + u * 256;
+      const int n = e / RP, rr = e % RP, m = pass * RP + rr;
+      xs[(size_t)n * NB + m] = A[(size_t)(c0 + n) * npad + s_src[m]] - sC[n * LDC + rr];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_move_down(T* __restrict__ LU, const int* __restrict__ perm, int npad,
+                                                   int k1, int nct, int nmat) {
+  int mat, ct;
+  xcd_map(blockIdx.x, nct, nmat, &mat, &ct);
+  if (mat >= nmat) return;
+  T* A = LU + (size_t)mat * npad * npad;
+  const int c0 = k1 + NB + ct * 128;
+  const int* pm = perm + ((size_t)mat * kMaxPanels + k1 / NB) * kPermStride;
+  const int nx = pm[0] - NB;
+  const int* R = pm + 1;
+  const int* src = pm + 1 + kMaxSwapRows;
+  for (int e = threadIdx.x; e < nx * 128; e += 256) {
+    const int t = NB + e % nx, j = e / nx;
+    if (src[t] != R[t]) A[(size_t)(c0 + j) * npad + R[t]] = A[(size_t)(c0 + j) * npad + src[t]];
+  }
+}
+
+// panel p's L columns, rows R[t] <- src[t] for every t (16 columns per block:
+// all reads before the block's writes)
+template <typename T>
+__global__ __launch_bounds__(256) void k_perm_lp(T* __restrict__ LU, const int* __restrict__ perm, int npad, int k1,
+                                                 int nmat) {
+  int mat, cg;
+  xcd_map(blockIdx.x, NB / 16, nmat, &mat, &cg);
+  if (mat >= nmat) return;
+  T* A = LU + (size_t)mat * npad * npad;
+  const int kp = k1 - NB;
+  const int* pm = perm + ((size_t)mat * kMaxPanels + k1 / NB) * kPermStride;
+  const int nR = pm[0];
+  const int* R = pm + 1;
+  const int* src = pm + 1 + kMaxSwapRows;
+  constexpr int NV = kMaxSwapRows * 16 / 256;
+  T v[NV];
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int e = threadIdx.x + u * 256;
+    if (e < nR * 16) v[u] = A[(size_t)(kp + 16 * cg + e / nR) * npad + src[e % nR]];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int e = threadIdx.x + u * 256;
+    if (e < nR * 16 && src[e % nR] != R[e % nR]) A[(size_t)(kp + 16 * cg + e / nR) * npad + R[e % nR]] = v[u];
   }
 }
 
@@ -811,7 +991,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
                                                 double* __restrict__ Xout,
                                                 const int* __restrict__ status, int accumulate, int check_done,
                                                 int npad, const int* __restrict__ mat_of,
-                                                const int* __restrict__ skip, int band_lo, int band_up) {
+                                                const int* __restrict__ skip, int band_lo, int band_up, int paired) {
   if (check_done && status[1]) return;
   // right-hand side / solution row: the block; factors: that row's own matrix,
   // or the one mat_of names (a shared factorization, e.g. a preconditioner bin)
@@ -893,14 +1073,22 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
   if (!TRANSPOSE) {
     for (int p = 0; p < np; ++p) {
       const int k0 = p * NB;
-      // P_p: the panel's interchanges as one gather / scatter over its rows
-      const int* pm = perm + ((size_t)mat * kMaxPanels + p) * kPermStride;
-      const int nR = pm[0];
-      double pv = 0.0;
-      if (tid < nR) pv = sb[pm[1 + kMaxSwapRows + tid]];
+      // P_p: the panel's interchanges as one gather / scatter over its rows;
+      // the first panel of a pair applies P_{p+1} too, the second none
+      const bool first = paired && p % 2 == 0 && p + 2 < np;
+      const bool second = paired && p % 2 == 1 && p + 1 < np;
+      auto gather = [&](int q) {
+        const int* pm = perm + ((size_t)mat * kMaxPanels + q) * kPermStride;
+        const int nR = pm[0];
+        double pv = 0.0;
+        if (tid < nR) pv = sb[pm[1 + kMaxSwapRows + tid]];
+        __syncthreads();
+        if (tid < nR) sb[pm[1 + tid]] = pv;
+        __syncthreads();
+      };
       stage_diag(k0);
-      __syncthreads();
-      if (tid < nR) sb[pm[1 + tid]] = pv;
+      if (!second) gather(p);
+      if (first) gather(p + 1);
       __syncthreads();
       if (w == 0) {  // unit lower triangular diagonal block
         double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
@@ -972,14 +1160,20 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
         sb[k0 + 64 + lane] = v1;
       }
       __syncthreads();
-      // P_p^T: inverse of the panel's gather / scatter
-      {
-        const int* pm = perm + ((size_t)mat * kMaxPanels + p) * kPermStride;
-        const int nR = pm[0];
-        double pv = 0.0;
-        if (tid < nR) pv = sb[pm[1 + tid]];
-        __syncthreads();
-        if (tid < nR) sb[pm[1 + kMaxSwapRows + tid]] = pv;
+      // P_p^T: inverse of the panel's gather / scatter (a pair's first panel
+      // applies P_{p+1}^T then P_p^T, its second none)
+      const bool first = paired && p % 2 == 0 && p + 2 < np;
+      const bool second = paired && p % 2 == 1 && p + 1 < np;
+      if (!second) {
+        for (int q = first ? p + 1 : p; q >= p; --q) {
+          const int* pm = perm + ((size_t)mat * kMaxPanels + q) * kPermStride;
+          const int nR = pm[0];
+          double pv = 0.0;
+          if (tid < nR) pv = sb[pm[1 + tid]];
+          __syncthreads();
+          if (tid < nR) sb[pm[1 + kMaxSwapRows + tid]] = pv;
+          __syncthreads();
+        }
       }
       __syncthreads();
     }
@@ -989,8 +1183,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
 }
 
 template <typename T>
-void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, int bf16_terms,
-                 const LuLookahead* la) {
+void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, int bf16_terms) {
   const size_t np2 = (size_t)d.npad * d.npad;
   T* LU = static_cast<T*>(d.lu) + (size_t)m0 * np2;
   T* xs = static_cast<T*>(d.xscr) + (size_t)m0 * d.npad * NB;
@@ -1020,15 +1213,12 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   // kl below it; partial pivoting widens the upper band to kl + ku
   const int kl = d.band_kl, ku = d.band_ku;
   auto round_up = [](int v) { return (v + NB - 1) / NB * NB; };
-  bool rest_pending = false;   // a remaining update on the side stream not yet waited for
-  for (int p = 0; p < np; ++p) {
-    const int k0 = p * NB;
-    const bool rec = tm && p < P;
-    if (rec) mark(1, p, 0, s);
-    const int rend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl)) : d.npad;
-    const int cend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl + ku)) : d.npad;
+  // panels in pairs (dense systems): panel p's update of the columns beyond
+  // panel p+1 is deferred and applied with panel p+1's in one K = 256 update,
+  // which reads and writes A22 half as often; the last two panels go singly
+  const bool pairs = lu_paired(d);
+  auto panel = [&](int k0, int rend) {
     const int rows = rend - k0;
-    const int rest = cend - k0 - NB;
     constexpr int NT = kPanelThreads;  // 512 threads holding up to 4 rows each
     // block shape and L chunk by panel height (measured): short panels (the
     // last ones, banded systems) take four wavefronts, which have the larger
@@ -1048,60 +1238,67 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     } else {
       k_panel<T, NT, 4, IB, F64 ? 4 : 8><<<nmat, NT, 0, s>>>(LU, piv, perm, d.status, d.npad, k0, rend);
     }
+  };
+  auto update = [&](int k0, int mtr, int mtc, int kd) {
+    launch_update(kind, LU, d.npad, k0, mtr, mtc, 0, nmat, alt_kc, s, kd);
+    if (tm) ++tm->launches;
+  };
+  for (int p = 0; p < np; ++p) {
+    const int k0 = p * NB;
+    const bool rec = tm && p < P;
+    const bool first = pairs && p % 2 == 0 && p + 2 < np;   // first panel of a pair
+    const bool second = pairs && p % 2 == 1 && p + 1 < np;  // second panel of a pair
+    if (rec) mark(1, p, 0, s);
+    const int rend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl)) : d.npad;
+    const int cend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl + ku)) : d.npad;
+    const int rest = cend - k0 - NB;
+    panel(k0, rend);
     if (rest > 0) k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);
-    if (rec) mark(1, p, 1, s);
-    const int mtr = rest > 0 ? (rend - k0 - NB) / 128 : 0, mtc = rest / 128;
-    // look-ahead: the first column tile (the next panel) here, the others on the side stream
-    const bool split = la && mtr > 0 && mtc > 1;
-    if (rest > 0) {
-      // U12 reads and writes every trailing column, so the previous panel's
-      // remaining update must have finished
-      if (rest_pending) {
-        (void)hipStreamWaitEvent(s, la->rest_done, 0);
-        rest_pending = false;
-      }
-      const int nct = rest / 128;  // U12 tiles of 128 columns
-      if (rec) mark(3, p, 0, s);
-      k_l11inv<T><<<xcd_grid(NB / 32, nmat), 128, 0, s>>>(LU, li, d.npad, k0, nmat);
-      k_u12<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
-      if (rec) mark(3, p, 1, s);
-      if (split) (void)hipEventRecord(la->u12_done, s);
-    } else if (rec) {
-      mark(3, p, 0, s);
-      mark(3, p, 1, s);
-    }
-    if (rec) mark(0, p, 0, s);
-    if (mtr > 0) {
-      launch_update(kind, LU, d.npad, k0, mtr, split ? 1 : mtc, 0, nmat, alt_kc, s);
-      if (tm) ++tm->launches;
-    }
-    if (rec) mark(0, p, 1, s);
-    if (split) {
-      (void)hipStreamWaitEvent(la->side, la->u12_done, 0);
-      if (rec) mark(2, p, 0, la->side);
-      launch_update(kind, LU, d.npad, k0, mtr, mtc - 1, 1, nmat, alt_kc, la->side);
-      if (tm) ++tm->launches;
-      if (rec) mark(2, p, 1, la->side);
-      (void)hipEventRecord(la->rest_done, la->side);
-      rest_pending = true;
-    } else if (rec) {
+    if (rec) {
+      mark(1, p, 1, s);
       mark(2, p, 0, s);
       mark(2, p, 1, s);
+      mark(3, p, 0, s);
     }
-    if (rec) tm->used = p + 1;
+    const int nct = rest / 128;  // U12 tiles of 128 columns
+    if (rest > 0) k_l11inv<T><<<xcd_grid(NB / 32, nmat), 128, 0, s>>>(LU, li, d.npad, k0, nmat);
+    if (second) {
+      // this panel's U12 from its top rows with panel p-1's deferred update,
+      // the interchanges' other rows moved down, panel p-1's L rows permuted
+      k_u12pre<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, xs, d.npad, k0, nct, nmat);
+      k_move_down<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, d.npad, k0, nct, nmat);
+      k_u12<T, true><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
+      k_perm_lp<T><<<xcd_grid(NB / 16, nmat), 256, 0, s>>>(LU, perm, d.npad, k0, nmat);
+    } else if (rest > 0) {
+      k_u12<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
+    }
+    if (rec) {
+      mark(3, p, 1, s);
+      mark(0, p, 0, s);
+    }
+    const int mtr = rest > 0 ? (rend - k0 - NB) / 128 : 0;
+    if (first) {
+      update(k0, mtr, 1, NB);                    // the next panel's columns only
+    } else if (second) {
+      update(k0 - NB, mtr, nct, 2 * NB);         // both panels, the columns beyond
+    } else if (mtr > 0) {
+      update(k0, mtr, nct, NB);
+    }
+    if (rec) {
+      mark(0, p, 1, s);
+      tm->used = p + 1;
+    }
   }
-  if (rest_pending) (void)hipStreamWaitEvent(s, la->rest_done, 0);
 }
 
 }  // namespace
 
-void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer, int m0, int count,
-                      const LuLookahead* la) {
+void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer, int m0, int count) {
   if (count < 0) count = d.nx_total - m0;
   if (count <= 0) return;
   // precision: 0 FP64, 1 FP32, 2 FP32 with a bf16 update, 3 FP32 with a split (3-term) bf16 update
-  if (precision == 0) factor_impl<double>(d, s, timer, m0, count, 0, la);
-  else factor_impl<float>(d, s, timer, m0, count, precision == 2 ? 1 : (precision == 3 ? 3 : 0), la);
+  if (precision == 0) factor_impl<double>(d, s, timer, m0, count, 0);
+  else factor_impl<float>(d, s, timer, m0, count, precision == 2 ? 1 : (precision == 3 ? 3 : 0));
 }
 
 namespace {
@@ -1126,21 +1323,21 @@ void launch_lu_solve_mapped(const DevOps& f, int precision, bool transpose, cons
   if (precision == 0) {
     const double* LU = static_cast<const double*>(f.lu);
     if (transpose)
-      k_solve<double, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
+      k_solve<double, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
     else
-      k_solve<double, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
+      k_solve<double, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
   } else if (precision == kFactorsFp16) {
     const _Float16* LU = static_cast<const _Float16*>(f.lu);
     if (transpose)
-      k_solve<_Float16, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
+      k_solve<_Float16, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
     else
-      k_solve<_Float16, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
+      k_solve<_Float16, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
   } else {
     const float* LU = static_cast<const float*>(f.lu);
     if (transpose)
-      k_solve<float, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
+      k_solve<float, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
     else
-      k_solve<float, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0);
+      k_solve<float, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
   }
 }
 

@@ -85,7 +85,7 @@ __device__ inline void update_epilogue(T* __restrict__ A, int npad, int r0, int 
 // ---------------------------------------------------------------------------
 using bf16x8 = __bf16 __attribute__((ext_vector_type(8)));
 
-template <int NTERMS>
+template <int NTERMS, int KD>
 __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int npad, int k0, int mtr, int mtc,
                                                      int tj0, int nmat) {
   constexpr int KC = 32;
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int
   if (mat >= nmat) return;
   const int ti = tile % mtr, tj = tile / mtr;
   float* A = LU + (size_t)mat * npad * npad;
-  const int r0 = k0 + NB + ti * 128, c0 = k0 + NB + (tj0 + tj) * 128;
+  const int r0 = k0 + KD + ti * 128, c0 = k0 + KD + (tj0 + tj) * 128;
   // [L21/U12][buffer][hi/lo][row or column][k], or the epilogue's 128 x 132 floats
   constexpr int OPER_BYTES = 2 * 2 * NH * 128 * LDK * 2;
   constexpr int EPI_BYTES = 128 * 132 * 4;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int
   load(0);
   store(0);
   __syncthreads();
-  constexpr int NCH = NB / KC;
+  constexpr int NCH = KD / KC;
   float4 pre[kPreV];
   for (int ch = 0; ch < NCH; ++ch) {
     const int buf = ch & 1;
@@ -183,7 +183,8 @@ __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int
 }
 
 // ---------------------------------------------------------------------------
-// Trailing update A22 -= L21 U12: 128 x 128 tiles, K = NB in chunks of KC staged
+// Trailing update A22 -= L21 U12: 128 x 128 tiles, K = KD (one panel, 128, or
+// two, 256) in chunks of KC staged
 // through double-buffered LDS, four wavefronts of 64 x 64 (4 x 4 MFMA blocks).
 // The epilogue goes through LDS in P passes of 128 / P rows, which bounds the
 // LDS of a block by the K-chunk buffers and lets MINB blocks share a CU; the
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int
 // of every later pass before its accumulators are staged, so that their
 // latency hides behind the products or the staging.
 // ---------------------------------------------------------------------------
-template <typename T, int KC, int P, int MINB, int NPP>
+template <typename T, int KC, int P, int MINB, int NPP, int KD>
 __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int npad, int k0, int mtr, int mtc, int tj0,
                                                       int nmat) {
   using V = typename Vec4<T>::type;
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int np
   if (mat >= nmat) return;
   const int ti = tile % mtr, tj = tile / mtr;
   T* A = LU + (size_t)mat * npad * npad;
-  const int r0 = k0 + NB + ti * 128, c0 = k0 + NB + (tj0 + tj) * 128;
+  const int r0 = k0 + KD + ti * 128, c0 = k0 + KD + (tj0 + tj) * 128;
   constexpr int OPER = 2 * 2 * KC * LD;
   constexpr int EPI = 128 * LDC;
   __shared__ __align__(16) T smem[OPER > EPI ? OPER : EPI];
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int np
   load(0);
   store(0);
   __syncthreads();
-  constexpr int NCH = NB / KC;
+  constexpr int NCH = KD / KC;
   constexpr int NV = 128 * RP / PER / 256;   // vectors per thread per pass
   V pre[NPP > 0 ? NPP : 1][NV];
   auto prefetch = [&](int pass, V (&dst)[NV]) {
@@ -325,28 +326,34 @@ __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int np
   }
 }
 
+template <int KD>
+void launch_update_k(int kind, void* LU, int npad, int k0, int mtr, int mtc, int tj0, int nmat, bool alt_kc,
+                     hipStream_t s) {
+  const dim3 gu = xcd_grid(mtr * mtc, nmat);
+  switch (kind) {
+    case 0:
+      if (alt_kc) k_update<double, 8, 4, 2, 1, KD><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      else k_update<double, 16, 4, 2, 1, KD><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      break;
+    case 2:
+      k_update_bf16<1, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      break;
+    case 3:
+      k_update_bf16<3, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      break;
+    default:
+      if (alt_kc) k_update<float, 32, 1, 2, 1, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      else k_update<float, 16, 4, 4, 1, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      break;
+  }
+}
 
 }  // namespace
 
 void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int tj0, int nmat, bool alt_kc,
-                   hipStream_t s) {
-  const dim3 gu = xcd_grid(mtr * mtc, nmat);
-  switch (kind) {
-    case 0:
-      if (alt_kc) k_update<double, 8, 4, 2, 1><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, tj0, nmat);
-      else k_update<double, 16, 4, 2, 1><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, tj0, nmat);
-      break;
-    case 2:
-      k_update_bf16<1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
-      break;
-    case 3:
-      k_update_bf16<3><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
-      break;
-    default:
-      if (alt_kc) k_update<float, 32, 1, 2, 1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
-      else k_update<float, 16, 4, 4, 1><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
-      break;
-  }
+                   hipStream_t s, int kd) {
+  if (kd == 2 * NB) launch_update_k<2 * NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s);
+  else launch_update_k<NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s);
 }
 
 }  // namespace bte

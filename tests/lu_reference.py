@@ -33,7 +33,11 @@ def pad(M):
     return P
 
 
-def factor(A, IB):
+def factor(A, IB, pairs=False):
+    """pairs: the convention of dense factors formed with the panels in pairs
+    (a pair's second interchanges also applied to the first panel's L rows;
+    panels 2m and 2m+1 for 2m + 2 < n / NB).  The arithmetic here stays one
+    update per panel, so values agree with the device's to rounding."""
     A = A.copy()
     n = len(A)
     ip = np.zeros(n, dtype=np.int64)
@@ -68,6 +72,12 @@ def factor(A, IB):
                     U[j] -= a[j, :j] @ U[:j]
                 A[c0:c0 + IB, rest] = U
                 A[c0 + IB:, rest] -= a[IB:, :IB] @ U
+        p = k0 // NB
+        second = pairs and p % 2 == 1 and k0 + NB < n
+        if second:
+            R, src = _perm(k0, NB, ip[k0:k0 + NB])
+            prev = list(range(k0 - NB, k0))
+            A[np.ix_(R, prev)] = A[src][:, prev].copy()
         if k0 + NB < n:
             R, src = _perm(k0, NB, ip[k0:k0 + NB])
             cols = list(range(k0 + NB, n))
@@ -80,14 +90,25 @@ def factor(A, IB):
     return A, ip
 
 
-def solve(A, ip, b):
+def solve(A, ip, b, pairs=False):
     b = b.copy()
     n = len(A)
-    for k0 in range(0, n, NB):
+    npan = n // NB
+
+    def interchange(k0):
         for j in range(NB):
             q = ip[k0 + j]
             if q != k0 + j:
                 b[[k0 + j, q]] = b[[q, k0 + j]]
+
+    for k0 in range(0, n, NB):
+        p = k0 // NB
+        if pairs and p % 2 == 1 and p + 1 < npan:
+            pass                       # applied with the pair's first panel
+        else:
+            interchange(k0)
+            if pairs and p % 2 == 0 and p + 2 < npan:
+                interchange(k0 + NB)
         for j in range(NB):
             b[k0 + j] -= A[k0 + j, k0:k0 + j] @ b[k0:k0 + j]
         b[k0 + NB:] -= A[k0 + NB:, k0:k0 + NB] @ b[k0:k0 + NB]

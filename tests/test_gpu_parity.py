@@ -444,7 +444,7 @@ def test_device_factors_match_blocked_restatement(torch, prec):
         M = LR.pad(S.v_matrix(ops, E[x]))
         if prec != "fp64":
             M = M.astype(np.float32).astype(np.float64)
-        ref, ip = LR.factor(M, IB)
+        ref, ip = LR.factor(M, IB, pairs=True)   # dense factors take the panels in pairs
         nb = LR.NB
         # FP32 factors: 1e-4; bf16 products split in three terms keep ~16 bits of
         # each operand (2e-3 after the updates); plain bf16 operands keep 8 bits
@@ -460,29 +460,34 @@ def test_device_factors_match_blocked_restatement(torch, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
 def test_factorization_schedule_does_not_change_results(torch, prec):
-    """Factoring the points in 1..4 concurrent groups, with or without the
-    look-ahead split of the trailing updates, gives bit-identical steps (four
-    panels, so that two updates are split)."""
+    """Factoring the points in 1..4 concurrent groups gives bit-identical steps,
+    with the panels in pairs (K = 256 trailing updates) and singly; the two
+    forms round the trailing updates differently and agree to rounding (four
+    panels: one pair, then two single panels)."""
     from paper_2502_16555_amd import _lib
     cfg = CASES["panels4"]()
     ops = oracle.build_operators(cfg)
     F0 = _state(ops, 11)
-    outs = []
-    schedules = [(1, 0), (1, 1), (2, 1), (3, 1), (4, 1)]
-    for g, la in schedules:
-        s = solver(cfg, precision=prec)
-        s.set_tuning(_lib.TUNE_LU_STREAMS, g)
-        s.set_tuning(_lib.TUNE_LOOKAHEAD, la)
-        assert s.get_tuning(_lib.TUNE_LU_STREAMS) == g
-        assert s.get_tuning(_lib.TUNE_LOOKAHEAD) == la
-        F = cuda(torch, F0)
-        for n in range(3):
-            s.step(F, n * cfg["dt_s"])
-        assert s.status()[0] == 0
-        outs.append(F.cpu().numpy())
-        s.close()
-    for sch, o in zip(schedules[1:], outs[1:]):
-        assert np.array_equal(o, outs[0]), f"schedule {sch} differs from one group without look-ahead"
+    res = {}
+    for pairs in (1, 0):
+        outs = []
+        for g in (1, 2, 3, 4):
+            s = solver(cfg, precision=prec)
+            s.set_tuning(_lib.TUNE_LU_STREAMS, g)
+            s.set_tuning(_lib.TUNE_PANEL_PAIRS, pairs)
+            assert s.get_tuning(_lib.TUNE_LU_STREAMS) == g
+            assert s.get_tuning(_lib.TUNE_PANEL_PAIRS) == pairs
+            F = cuda(torch, F0)
+            for n in range(3):
+                s.step(F, n * cfg["dt_s"])
+            assert s.status()[0] == 0
+            outs.append(F.cpu().numpy())
+            s.close()
+        for g, o in enumerate(outs[1:], start=2):
+            assert np.array_equal(o, outs[0]), f"pairs={pairs}: {g} groups differ from 1"
+        res[pairs] = outs[0]
+    tol = 1e-12 if prec == "fp64" else 1e-13   # mixed: refined to the FP64 backward error
+    close(res[1], res[0], tol, "pairs vs single panels")
 
 
 def _grad_case():

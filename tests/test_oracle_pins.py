@@ -431,15 +431,28 @@ def test_poisson_field_closed_form():
 
 def test_blocked_lu_restatement_matches_lapack():
     """The NumPy restatement of the device's blocked LU (used to localize device
-    errors) solves the V systems like LAPACK, with and without interchanges."""
+    errors) solves the V systems like LAPACK, with and without interchanges, in
+    both storage conventions (single panels, and panels in pairs whose second
+    interchanges also reach the first panel's L rows); a random matrix makes
+    interchanges in every panel, including the rows across a pair."""
     import lu_reference as LR
     cfg = workloads.small_config(nx=3, nr=20, nth=20, kinds=("elastic", "ionization"))
     ops = oracle.build_operators(cfg)
     rng = np.random.default_rng(0)
-    for E in (0.0, 1.2e4, -1.4e4):
-        M = LR.pad(S.v_matrix(ops, E))
+    mats = [LR.pad(S.v_matrix(ops, E)) for E in (0.0, 1.2e4, -1.4e4)]
+    mats.append(rng.standard_normal((512, 512)) + 0.1 * np.eye(512))
+    for M in mats:
         b = rng.standard_normal(len(M))
+        want = np.linalg.solve(M, b)
         for IB in (8, 16):
-            LU, ip = LR.factor(M, IB)
-            x = LR.solve(LU, ip, b)
-            assert np.abs(x - np.linalg.solve(M, b)).max() < 1e-12 * np.abs(x).max()
+            for pairs in (False, True):
+                LU, ip = LR.factor(M, IB, pairs=pairs)
+                x = LR.solve(LU, ip, b, pairs=pairs)
+                assert np.abs(x - want).max() < 1e-10 * np.abs(want).max(), (IB, pairs)
+    # the conventions differ exactly in the first panel's L rows of a pair
+    M = mats[-1]
+    a, ip_a = LR.factor(M, 16)
+    b_, ip_b = LR.factor(M, 16, pairs=True)
+    assert np.array_equal(ip_a, ip_b)
+    assert not np.array_equal(a[128:, :128], b_[128:, :128])
+    assert np.allclose(a[:, 128:], b_[:, 128:], rtol=0, atol=1e-12 * np.abs(a).max())
