@@ -26,12 +26,13 @@ sys.path.insert(0, ROOT)
 MI355X_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 MI355X_PEAK_HBM_GBS = 8000.0
 
-# HBM bytes of the FP32 trailing update (k_update<float, 32>) per launch, averaged
-# over the 15 launches of one factorization at this workload, from two
+# HBM bytes of the FP32 trailing update (k_update<float, 16, ...>, K = 128 and 256)
+# per launch, averaged over the 15 launches of one factorization at this workload
+# (panels in pairs), from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters
 # read for a 1 GiB copy (x2.0 and x1.0).  Valid for the kernel source it was taken
 # on (hash of kernels_update.hip); reported as null once that file has changed.
-KUPDATE_TRAFFIC = {"source_sha256_16": "7f39d8006dbb02d7", "fetch_bytes": 1.662e9, "write_bytes": 1.387e9,
+KUPDATE_TRAFFIC = {"source_sha256_16": "d5cfcc103aa95365", "fetch_bytes": 1.155e9, "write_bytes": 6.979e8,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -47,20 +48,36 @@ def _update_traffic():
     return KUPDATE_TRAFFIC["fetch_bytes"] + KUPDATE_TRAFFIC["write_bytes"]
 
 
-def _update_bytes(npad: int, nb: int, nmat: int, elt: int) -> float:
-    """Algorithmic bytes of one average update launch: A22 read and written, L21 and U12 read."""
-    ms = [npad - k0 - nb for k0 in range(0, npad, nb) if npad - k0 - nb > 0]
-    return sum((2 * m * m + 2 * m * nb) * elt for m in ms) * nmat / len(ms)
+def _update_launches(npad: int, nb: int, pairs: bool = True):
+    """(flops, elements moved) of each trailing-update launch of one
+    factorization.  With the panels in pairs (dense factors), the first panel
+    of a pair updates only the next panel's columns (that column block read and
+    written, L21 and U12 read) and the second applies both panels to the
+    columns beyond (K = 2 nb, A22 read and written once); the last panels go
+    singly (K = nb).  The first panel's update of the second's row block is
+    part of the second's U12 kernel, not of these launches."""
+    npan = npad // nb
+    out = []
+    for p in range(npan):
+        m = npad - p * nb - nb
+        if pairs and p % 2 == 0 and p + 2 < npan:
+            out.append((2.0 * m * nb * nb, 3 * m * nb + nb * nb))
+        elif pairs and p % 2 == 1 and p + 1 < npan:
+            out.append((4.0 * m * m * nb, 2 * m * m + 4 * m * nb))
+        elif m > 0:
+            out.append((2.0 * m * m * nb, 2 * m * m + 2 * m * nb))
+    return out
 
 
-def _update_flops(npad: int, nb: int, nmat: int) -> float:
+def _update_bytes(npad: int, nb: int, nmat: int, elt: int, pairs: bool = True) -> float:
+    """Algorithmic bytes of one average update launch (see _update_launches)."""
+    ls = _update_launches(npad, nb, pairs)
+    return sum(b for _, b in ls) * elt * nmat / len(ls)
+
+
+def _update_flops(npad: int, nb: int, nmat: int, pairs: bool = True) -> float:
     """Algorithmic flops of all trailing-update launches of one factorization."""
-    tot = 0.0
-    for k0 in range(0, npad, nb):
-        m = npad - k0 - nb
-        if m > 0:
-            tot += 2.0 * m * m * nb
-    return tot * nmat
+    return sum(f for f, _ in _update_launches(npad, nb, pairs)) * nmat
 
 
 KRYLOV = dict(n_bins=128, bin_scale=100.0, restart=12, cycles=3, rtol=1e-12, factor_precision="mixed_fp32")
@@ -372,7 +389,8 @@ def main():
     dtype = {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64", "mixed_bf16x3": "bf16x3+f32+f64"}[args.precision]
     mfma = {"fp64": "fp64", "mixed_fp32": "fp32", "mixed_bf16": "bf16", "mixed_bf16x3": "bf16"}[args.precision]
     # update flops of one step over the summed durations of its update launches
-    upd_flops = _update_flops(npad, 128, nx_total)
+    pairs = bool(main_run["panel_pairs"])
+    upd_flops = _update_flops(npad, 128, nx_total, pairs)
     n_upd_launches = main_run["update_launches"]
     achieved = upd_flops / (main_run["ms_update"] * 1e-3) / 1e12
     peak = MI355X_PEAK_TFLOPS[mfma]
@@ -390,7 +408,8 @@ def main():
                      "traffic": _update_traffic() if args.precision == "mixed_fp32" and npad == 2048 and nx_total == 256
                      else None,
                      "algorithmic_bytes_per_launch": _update_bytes(npad, 128, nx_total,
-                                                                   8 if args.precision == "fp64" else 4),
+                                                                   8 if args.precision == "fp64" else 4, pairs),
+                     "panel_pairs": pairs,
                      "launches_per_step": n_upd_launches,
                      "avg_launch_ms": main_run["ms_update"] / n_upd_launches},
         "breakdown_ms": {"lu_update_launches": main_run["ms_update"], "lu_panel_u12_launches": main_run["ms_panel"],
@@ -403,8 +422,10 @@ def main():
         line["fp64"] = {"steps_per_s": 1000.0 / fp64["ms_per_step"], "ms_per_step": fp64["ms_per_step"],
                         "speedup_mixed_over_fp64": fp64["ms_per_step"] / main_run["ms_per_step"],
                         "ms_update": fp64["ms_update"], "ms_panel": fp64["ms_panel"],
-                        "update_tflops": _update_flops(npad, 128, nx_total) / (fp64["ms_update"] * 1e-3) / 1e12,
-                        "update_frac_fp64_peak": _update_flops(npad, 128, nx_total) / (fp64["ms_update"] * 1e-3)
+                        "update_tflops": _update_flops(npad, 128, nx_total, bool(fp64["panel_pairs"]))
+                        / (fp64["ms_update"] * 1e-3) / 1e12,
+                        "update_frac_fp64_peak": _update_flops(npad, 128, nx_total, bool(fp64["panel_pairs"]))
+                        / (fp64["ms_update"] * 1e-3)
                         / 1e12 / MI355X_PEAK_TFLOPS["fp64"]}
         line["accuracy"] = {
             "mixed_vs_fp64_gpu": dict(moment_errors(main_run["moments"], fp64["moments"]),
@@ -427,7 +448,8 @@ def main():
         nup = bf["update_launches"]
         line["bf16x3"] = {"steps_per_s": 1000.0 / bf["ms_per_step"], "ms_per_step": bf["ms_per_step"],
                           "ms_update": bf["ms_update"], "ms_panel": bf["ms_panel"],
-                          "update_hbm_frac": (_update_bytes(npad, 128, nx_total, 4) / (bf["ms_update"] / nup * 1e-3))
+                          "update_hbm_frac": (_update_bytes(npad, 128, nx_total, 4, bool(bf["panel_pairs"]))
+                                              / (bf["ms_update"] / nup * 1e-3))
                           / (MI355X_PEAK_HBM_GBS * 1e9),
                           "refine": {"sweeps": bf["refine_sweeps"], "resid": bf["refine_resid"]}}
         if fp64 is not None:
