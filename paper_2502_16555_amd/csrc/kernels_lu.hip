@@ -12,7 +12,7 @@
 // Per panel k0:
 //   k_panel   one 512-thread block per matrix (256 for short panels): partial
 //             pivoting (max |a|, ties to the lowest row) over register-resident
-//             sub-panels of 8 (FP64) or 16 (FP32) columns, left-looking across
+//             sub-panels of 8 or 16 columns, left-looking across
 //             the sub-panels, and the panel's row permutation for the
 //             trailing columns;
 //   k_dinv    one block per matrix: inverses of the 16 x 16 diagonal blocks of
@@ -23,14 +23,16 @@
 //             U12 = L11^-1 P A12 as one MFMA product (K = 128) -- the
 //             substitution's sequential 16-row steps are paid once per panel
 //             in k_l11inv instead of once per column block;
-//   k_update  A22 -= L21 U12: 128 x 128 MFMA tiles, K = 128 in double-buffered
-//             LDS chunks; blocks of one matrix are kept on one XCD so that L21
-//             and U12 stay in that XCD's L2.
+//   k_update  A22 -= L21 U12: 128 x 128 MFMA tiles, K = 128 (or 256, two
+//             panels) in double-buffered LDS chunks; blocks of one matrix are
+//             kept on one XCD so that L21 and U12 stay in that XCD's L2.
 // Dense systems take the panels in pairs: panel p updates panel p+1's columns
 // at once, its update of the columns beyond is deferred, and after panel p+1
 // one K = 256 update applies both (A22 read and written once per two panels).
-// Panel p+1's interchanges then also reach panel p's L columns, so the solve
-// applies P_p P_{p+1} before L_p and L_{p+1} (A = ... P_p^T P_{p+1}^T L' ...).
+// For panel p+1, k_u12pre, k_move_down and k_perm_lp (below) take the place of
+// k_u12's gather.  Panel p+1's interchanges then also reach panel p's L
+// columns, so the solve applies P_p P_{p+1} before L_p and L_{p+1}
+// (A = ... P_p^T P_{p+1}^T L' ...).
 #include <algorithm>
 #include <cfloat>
 #include <climits>
