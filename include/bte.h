@@ -165,8 +165,9 @@ bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void*
  * Newton's method with a backtracking line search on ||R||_2; each Newton
  * system J_F dlt = -R (Jacobian action of eq. 1dbte_jac_action, matrix free)
  * by restarted GMRES, right-preconditioned by the semi-implicit step as a
- * linear map with the field frozen at E(F) (X(dt/2), the factored V systems,
- * X(dt/2)), classical Gram-Schmidt twice.  F (device [sum Nx][Nr][Ntheta]) is
+ * linear map with the field frozen at E(F) (X(dt/2), one solve with the V
+ * factors of the handle's precision, without refinement, X(dt/2)), classical
+ * Gram-Schmidt twice.  F (device [sum Nx][Nr][Ntheta]) is
  * replaced by F^{n+1}.  Synchronous on the stream (the host drives the
  * iterations).  Defaults for zero fields of opts: newton_rtol 1e-12 (relative
  * to ||F^n||_2), max_newton 20, gmres_rtol 1e-6, restart 30 (<= 200), max_gmres

@@ -468,12 +468,15 @@ void v_solve(bte_handle* h, double* F, bool transpose, hipStream_t s, bool allow
 }
 
 // Solve with existing factors (no refactorization), used by the adjoint.
-void v_solve_again(bte_handle* h, double* F, bool transpose, hipStream_t s) {
+// refine = false: one solve with the stored (possibly FP32) factors, no
+// refinement -- a fixed linear map, as a preconditioner needs, accurate to the
+// factors' precision.
+void v_solve_again(bte_handle* h, double* F, bool transpose, hipStream_t s, bool refine = true) {
   DevOps& d = h->d;
   const int prec = h->cfg.precision;
   bte::launch_pad_rows(d, F, d.B, s);
   bte::launch_lu_solve(d, prec, transpose, d.B, d.X, false, false, s);
-  if (prec != BTE_FP64) {
+  if (prec != BTE_FP64 && refine) {
     bte::launch_reset_refine(d, s);
     for (int it = 1; it <= h->refine_max_iter; ++it) {
       bte::launch_residual(d, transpose, s);
@@ -612,7 +615,7 @@ void imp_jac(bte_handle* h, const double* F, const double* X, double* out, hipSt
 void imp_precond(bte_handle* h, const double* v, double* z, hipStream_t s) {
   HIP_OK(hipMemcpyAsync(z, v, sizeof(double) * h->iw.N, hipMemcpyDeviceToDevice, s));
   x_half(h, z, false, s);
-  v_solve_again(h, z, false, s);
+  v_solve_again(h, z, false, s, false);
   x_half(h, z, false, s);
 }
 
