@@ -303,18 +303,22 @@ void fill_devops(bte_handle* h) {
     d.mu_th = h->upload(H.mu);
   }
   if (c.field_mode == BTE_FIELD_POISSON) {
-    // the heavies' update of the hybrid step: D_x^2 per discharge
-    std::vector<double> D2;
+    // the heavies' update of the hybrid step: D_x and D_x^2 per discharge,
+    // column-major (entry (r, c) at c nx + r)
+    std::vector<double> DT, D2;
+    DT.reserve(ptot);
     D2.reserve(ptot);
     for (auto& X : H.xops) {
       const int nx = X.nx;
-      for (int r = 0; r < nx; ++r)
-        for (int cc = 0; cc < nx; ++cc) {
+      for (int cc = 0; cc < nx; ++cc)
+        for (int r = 0; r < nx; ++r) {
           double acc = 0.0;
           for (int k = 0; k < nx; ++k) acc += X.Dx[(size_t)r * nx + k] * X.Dx[(size_t)k * nx + cc];
           D2.push_back(acc);
+          DT.push_back(X.Dx[(size_t)r * nx + cc]);
         }
     }
+    d.dxT = h->upload(DT);
     d.dx2 = h->upload(D2);
     d.ion_M = h->alloc<double>(ptot);
     d.ion_b = h->alloc<double>(nxt);
