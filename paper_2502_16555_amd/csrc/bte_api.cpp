@@ -333,6 +333,7 @@ void fill_devops(bte_handle* h) {
   d.piv = h->alloc<int>(nxt * d.npad);
   d.perm = h->alloc<int>(nxt * bte::kMaxPanels * bte::kPermStride);
   d.E = h->alloc<double>(nxt);
+  d.field_rhs = h->alloc<double>(nxt);
   d.B = h->alloc<double>(nxt * d.npad);
   d.X = h->alloc<double>(nxt * d.npad);
   d.R = h->alloc<double>(nxt * d.npad);

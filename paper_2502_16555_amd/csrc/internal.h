@@ -66,6 +66,7 @@ struct DevOps {
   int* piv = nullptr;          // [nx_total][npad]
   int* perm = nullptr;         // [nx_total][kMaxPanels][kPermStride] row permutation of every panel
   double* E = nullptr;         // [nx_total]
+  double* field_rhs = nullptr; // [nx_total] right-hand side of the Poisson field solve
   double* B = nullptr;         // [nx_total][npad] right-hand side copy
   double* X = nullptr;         // [nx_total][npad] solution (mixed refinement)
   double* R = nullptr;         // [nx_total][npad] residual / correction

@@ -138,7 +138,46 @@ __global__ __launch_bounds__(kThreads) void k_advect(double* __restrict__ Y, con
   }
 }
 
-// E^{1/2} for the specified modes and for Poisson (one block per discharge).
+// Poisson field over all points: rhs[x] = -(e/eps0)(n_i - u^T F) at interior
+// points, the electrode voltage / 0 at the walls (one wavefront per point);
+// then E[x] = (P_d rhs_d)[x] (one wavefront per point, lanes along P's row).
+__global__ __launch_bounds__(kThreads) void k_field_rhs(double t_half, double freq, double V0,
+                                                        const double* __restrict__ Fh, const double* __restrict__ ni,
+                                                        double* __restrict__ rhs, const int* __restrict__ x_disc,
+                                                        const int* __restrict__ x_off, const int* __restrict__ nx_of,
+                                                        const double* __restrict__ mom, int nx_total, int n) {
+  const int x = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (x >= nx_total) return;
+  const int d = x_disc[x], xl = x - x_off[d];
+  const double kE = 1.602176634e-19, kEps0 = 8.8541878128e-12, kPi = 3.14159265358979323846;
+  const double* f = Fh + (size_t)x * n;
+  double s = 0.0;
+  for (int c = lane; c < n; c += 64) s += mom[c] * f[c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) {
+    double v = -(kE / kEps0) * (ni[x] - s);
+    if (xl == 0) v = V0 * sin(2.0 * kPi * freq * t_half);
+    if (xl == nx_of[d] - 1) v = 0.0;
+    rhs[x] = v;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_field_apply(const double* __restrict__ rhs, double* __restrict__ E,
+                                                          const int* __restrict__ x_disc,
+                                                          const int* __restrict__ x_off, const int* __restrict__ nx_of,
+                                                          const double* __restrict__ P,
+                                                          const size_t* __restrict__ p_off, int nx_total) {
+  const int x = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (x >= nx_total) return;
+  const int d = x_disc[x], x0 = x_off[d], nx = nx_of[d], j = x - x0;
+  const double* row = P + p_off[d] + (size_t)j * nx;
+  double s = 0.0;
+  for (int c = lane; c < nx; c += 64) s += row[c] * rhs[x0 + c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) E[x] = s;
+}
+
+// E^{1/2} for the specified modes (one block per discharge).
 __global__ __launch_bounds__(kThreads) void k_field(int mode, double t_half, double freq, double a1, double V0,
                                                     const double* __restrict__ Fh, const double* __restrict__ Eg,
                                                     const double* __restrict__ ni, double* __restrict__ E,
@@ -155,31 +194,8 @@ __global__ __launch_bounds__(kThreads) void k_field(int mode, double t_half, dou
       const int x = x0 + j;
       E[x] = (mode == 2) ? Eg[x] : (mode == 0 ? E0_of[d] : E0_of[d] * s * (1.0 + a1 * xhat[x]));
     }
-    return;
   }
-  // Poisson: rhs = [V_left, -(e/eps0)(ni - ne) interior, 0], E = P rhs
-  extern __shared__ double rhs[];
-  const double kE = 1.602176634e-19, kEps0 = 8.8541878128e-12;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int j = wid; j < nx; j += nw) {
-    const double* f = Fh + (size_t)(x0 + j) * n;
-    double s = 0.0;
-    for (int c = lane; c < n; c += 64) s += mom[c] * f[c];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) rhs[j] = -(kE / kEps0) * (ni[x0 + j] - s);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    rhs[0] = V0 * sin(2.0 * kPi * freq * t_half);
-    rhs[nx - 1] = 0.0;
-  }
-  __syncthreads();
-  const double* Pd = P + p_off[d];
-  for (int j = threadIdx.x; j < nx; j += blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < nx; ++c) s += Pd[(size_t)j * nx + c] * rhs[c];
-    E[x0 + j] = s;
-  }
+  // Poisson (mode 3) runs as k_field_rhs and k_field_apply
 }
 
 // gE0[d] += sum_{x in d} gE[x] dE_x/dE0_d
@@ -318,9 +334,16 @@ void launch_advect(const DevOps& d, bool fp32, bool transpose, hipStream_t s) {
 
 void launch_field(const DevOps& d, int mode, double t_half, double freq, double a1, double V0, const double* Fh,
                   const double* E_given, const double* ni, double* E, hipStream_t s) {
-  const size_t sh = (mode == 3) ? sizeof(double) * d.max_nx : 0;
-  k_field<<<d.nd, kThreads, sh, s>>>(mode, t_half, freq, a1, V0, Fh, E_given, ni, E, d.x_off, d.nx_of, d.E0_of,
-                                     d.xhat, d.mom, d.poisson, d.p_off, d.n);
+  if (mode == 3) {
+    const int gb = (d.nx_total + kThreads / 64 - 1) / (kThreads / 64);
+    k_field_rhs<<<gb, kThreads, 0, s>>>(t_half, freq, V0, Fh, ni, d.field_rhs, d.x_disc, d.x_off, d.nx_of, d.mom,
+                                        d.nx_total, d.n);
+    k_field_apply<<<gb, kThreads, 0, s>>>(d.field_rhs, E, d.x_disc, d.x_off, d.nx_of, d.poisson, d.p_off,
+                                          d.nx_total);
+    return;
+  }
+  k_field<<<d.nd, kThreads, 0, s>>>(mode, t_half, freq, a1, V0, Fh, E_given, ni, E, d.x_off, d.nx_of, d.E0_of,
+                                    d.xhat, d.mom, d.poisson, d.p_off, d.n);
 }
 
 void launch_field_dE0(const DevOps& d, int mode, double t_half, double freq, double a1, const double* gE, double* gE0,
