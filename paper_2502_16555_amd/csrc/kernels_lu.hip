@@ -601,7 +601,8 @@ __global__ __launch_bounds__(128) void k_l11inv(const T* __restrict__ LU, T* __r
 
 // ---------------------------------------------------------------------------
 // The panel's interchanges and U12 = L11^-1 P A12 as one MFMA product per
-// 128-column tile, with the explicit L11^-1 of k_l11inv: the tile of
+// 128-column tile, with the explicit L11^-1 of k_l11inv (the blocks of its
+// zero upper triangle skipped): the tile of
 // P A12 is gathered (rows src[k] of the original columns) chunk by chunk into
 // double-buffered LDS as the K operand, L11^-1 (column-major, read by all tiles
 // of the matrix from L2) as the row operand; four wavefronts of 64 x 64.  The
@@ -631,7 +632,14 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
   __shared__ int s_src[NB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  const int wc = (w & 1) * 64;
+  // L11^-1 is lower triangular: row block b (rows 16 b .. 16 b + 15) takes the
+  // K chunks 0..b only.  The two wave rows own the row blocks {0, 3, 4, 7} and
+  // {1, 2, 5, 6}, 18 of the 36 nonzero block products each.
+  const int rsel = __builtin_amdgcn_readfirstlane(tid >> 7);
+  int rowb[4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi) rowb[bi] = 4 * (bi >> 1) + ((bi & 1) ? 3 - rsel : rsel);
   if (tid < NB) s_src[tid] = src[tid];
   // FROM_W: the tile of P A12 is already gathered (and updated) in xscr as
   // W[col][k], and the interchanges' other rows are already moved
@@ -691,13 +699,16 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
     for (int k = 0; k < KC; k += 4) {
       T av[4], bv[4];
 #pragma unroll
-      for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][k + lk][wr + bi * 16 + li];
+      for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][k + lk][rowb[bi] * 16 + li];
 #pragma unroll
       for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][k + lk][wc + bj * 16 + li];
 #pragma unroll
-      for (int bi = 0; bi < 4; ++bi)
+      for (int bi = 0; bi < 4; ++bi) {
+        if (ch <= rowb[bi]) {  // KC = 16: chunk ch is row block ch of the K range
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mma<T>::step(av[bi], bv[bj], acc[bi][bj]);
+          for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mma<T>::step(av[bi], bv[bj], acc[bi][bj]);
+        }
+      }
     }
     if (ch + 1 < NCH) {
       store(buf ^ 1);
@@ -709,7 +720,7 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
-      T* cp = A + (size_t)(c0 + wc + bj * 16 + li) * npad + k0 + wr + bi * 16;
+      T* cp = A + (size_t)(c0 + wc + bj * 16 + li) * npad + k0 + rowb[bi] * 16;
 #pragma unroll
       for (int it = 0; it < 4; ++it) cp[Mma<T>::row(lk, it)] = acc[bi][bj][it];
     }
