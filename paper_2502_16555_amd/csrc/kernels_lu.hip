@@ -604,14 +604,16 @@ __global__ __launch_bounds__(128) void k_l11inv(const T* __restrict__ LU, T* __r
 // 128-column tile, with the explicit L11^-1 of k_l11inv (the blocks of its
 // zero upper triangle skipped): the tile of
 // P A12 is gathered (rows src[k] of the original columns) chunk by chunk into
-// double-buffered LDS as the K operand, L11^-1 (column-major, read by all tiles
-// of the matrix from L2) as the row operand; four wavefronts of 64 x 64.  The
+// double-buffered LDS as the K operand (or read as vectors from W, below),
+// L11^-1 (column-major, read by all tiles of the matrix from L2)
+// as the row operand; four wavefronts of 64 x 64, the result written through
+// LDS down whole columns.  The
 // rows that the interchanges move below the panel are read first (each thread
 // stages its own elements) and written after the last chunk, when every read
 // of the tile's columns has been made.
 // ---------------------------------------------------------------------------
 template <typename T, bool FROM_W = false>
-__global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __restrict__ linv,
+__global__ __launch_bounds__(256, 2) void k_u12(T* __restrict__ LU, const T* __restrict__ linv,
                                                const int* __restrict__ perm, T* __restrict__ xscr, int npad, int k0,
                                                int nct, int nmat) {
   using V = typename Vec4<T>::type;
@@ -627,8 +629,12 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
   const int nR = pm[0];
   const int* R = pm + 1;
   const int* src = pm + 1 + kMaxSwapRows;
-  __shared__ __align__(16) T sA[2][KC][LD];
-  __shared__ __align__(16) T sB[2][KC][LD];
+  constexpr int LE = 64 + 1;                      // epilogue: a pass of 64 rows, column-major
+  static_assert(128 * LE <= 4 * KC * LD, "an epilogue pass fits in the operand buffers");
+  static_assert(PER == 2 || PER == 4, "4 rows of W are one or two vectors");
+  __shared__ __align__(16) T smem[4 * KC * LD];   // the operand chunks, then the epilogue passes
+  T (*sA)[KC][LD] = reinterpret_cast<T (*)[KC][LD]>(smem);
+  T (*sB)[KC][LD] = reinterpret_cast<T (*)[KC][LD]>(smem + 2 * KC * LD);
   __shared__ int s_src[NB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -651,7 +657,7 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
   }
   __syncthreads();
   constexpr int NA = KC * 128 / PER / 256;   // vectors of L11^-1 per thread and chunk
-  constexpr int NBS = KC * 128 / 256;        // gathered elements per thread and chunk
+  constexpr int NBS = KC * 128 / 256;        // B elements per thread and chunk
   V ra[NA];
   T rb[NBS];
   auto load = [&](int kk) {
@@ -661,11 +667,28 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
       const int k = e / (128 / PER), i = (e % (128 / PER)) * PER;
       ra[u] = *reinterpret_cast<const V*>(Li + (size_t)(kk + k) * NB + i);
     }
+    if constexpr (FROM_W) {
+      // W is k-contiguous: rows kk + 4 q .. + 3 of column j as one or two vectors
 #pragma unroll
-    for (int u = 0; u < NBS; ++u) {
-      const int e = tid + u * 256;
-      const int k = e % KC, j = e / KC;
-      rb[u] = FROM_W ? xs[(size_t)j * NB + kk + k] : A[(size_t)(c0 + j) * npad + s_src[kk + k]];
+      for (int u = 0; u < NBS / 4; ++u) {
+        const int e = tid + u * 256;
+        const int q = e % (KC / 4), j = e / (KC / 4);
+#pragma unroll
+        for (int h = 0; h < 4 / PER; ++h) {
+          const V v = *reinterpret_cast<const V*>(xs + (size_t)j * NB + kk + 4 * q + h * PER);
+          const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+          for (int m = 0; m < PER; ++m) rb[4 * u + h * PER + m] = pv[m];
+        }
+      }
+    } else {
+      // the gather: 16 lanes read rows src[kk..kk+15] of one column
+#pragma unroll
+      for (int u = 0; u < NBS; ++u) {
+        const int e = tid + u * 256;
+        const int k = e % KC, j = e / KC;
+        rb[u] = A[(size_t)(c0 + j) * npad + s_src[kk + k]];
+      }
     }
   };
   auto store = [&](int buf) {
@@ -677,10 +700,20 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
 #pragma unroll
       for (int m = 0; m < PER; ++m) sA[buf][k][i + m] = v[m];
     }
+    if constexpr (FROM_W) {
 #pragma unroll
-    for (int u = 0; u < NBS; ++u) {
-      const int e = tid + u * 256;
-      sB[buf][e % KC][e / KC] = rb[u];
+      for (int u = 0; u < NBS / 4; ++u) {
+        const int e = tid + u * 256;
+        const int q = e % (KC / 4), j = e / (KC / 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sB[buf][4 * q + i][j] = rb[4 * u + i];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < NBS; ++u) {
+        const int e = tid + u * 256;
+        sB[buf][e % KC][e / KC] = rb[u];
+      }
     }
   };
   typename Mma<T>::acc acc[4][4];
@@ -715,15 +748,36 @@ __global__ __launch_bounds__(256) void k_u12(T* __restrict__ LU, const T* __rest
       __syncthreads();
     }
   }
-  // every gather of the tile's columns was consumed before the last barrier
+  // every gather of the tile's columns was consumed before the last barrier.
+  // The tile goes out through LDS in two passes of 64 rows (row blocks 4 h ..
+  // 4 h + 3, which are bi = 2 h, 2 h + 1 of both wave rows), so that each
+  // thread writes whole vectors down a column.
 #pragma unroll
-  for (int bi = 0; bi < 4; ++bi)
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    T(*sE)[LE] = reinterpret_cast<T(*)[LE]>(smem);
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
-      T* cp = A + (size_t)(c0 + wc + bj * 16 + li) * npad + k0 + rowb[bi] * 16;
+    for (int bb = 0; bb < 2; ++bb) {
+      const int bi = 2 * h + bb;
 #pragma unroll
-      for (int it = 0; it < 4; ++it) cp[Mma<T>::row(lk, it)] = acc[bi][bj][it];
+      for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+        for (int it = 0; it < 4; ++it)
+          sE[wc + bj * 16 + li][rowb[bi] * 16 - 64 * h + Mma<T>::row(lk, it)] = acc[bi][bj][it];
     }
+    __syncthreads();
+    constexpr int VPC = 64 / PER;   // vectors per column of a pass
+#pragma unroll
+    for (int u = 0; u < 128 * VPC / 256; ++u) {
+      const int e = tid + u * 256;
+      const int col = e / VPC, r = (e % VPC) * PER;
+      V v;
+      T* pv = reinterpret_cast<T*>(&v);
+#pragma unroll
+      for (int m = 0; m < PER; ++m) pv[m] = sE[col][r + m];
+      *reinterpret_cast<V*>(A + (size_t)(c0 + col) * npad + k0 + 64 * h + r) = v;
+    }
+  }
   for (int e = tid; e < nx * 128; e += 256) {
     const int t = NB + e % nx, j = e / nx;
     if (src[t] != R[t]) A[(size_t)(c0 + j) * npad + R[t]] = xs[(size_t)j * NB + (t - NB)];
