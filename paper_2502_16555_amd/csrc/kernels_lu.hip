@@ -885,31 +885,41 @@ __global__ __launch_bounds__(256, 2) void k_u12pre(T* __restrict__ LU, const int
       __syncthreads();
     }
   }
-  // W = A[src rows] - acc, through LDS in four passes of 32 rows so that the
-  // gathered reads and the stores of W run down the columns
+  // W = A[src rows] - acc, through LDS in two passes of 64 rows (a wave row's
+  // tile each), so that the gathered reads and the vector stores of W run down
+  // the columns
   T* xs = xscr + ((size_t)mat * npad + c0) * NB;
-  constexpr int RP = 32, LDC = RP + 4;
-  static_assert(128 * LDC <= 4 * KC * LD, "a pass of the tile fits in the operand buffers");
-  T* sC = smem;
+  constexpr int LE = 64 + 1;
+  static_assert(128 * LE <= 4 * KC * LD, "a pass of the tile fits in the operand buffers");
+  T(*sC)[LE] = reinterpret_cast<T(*)[LE]>(smem);
 #pragma unroll
-  for (int pass = 0; pass < 128 / RP; ++pass) {
+  for (int pass = 0; pass < 2; ++pass) {
     __syncthreads();
+    if (wr == 64 * pass) {
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
-      if ((wr + bi * 16) / RP == pass) {
+      for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-          for (int it = 0; it < 4; ++it)
-            sC[(wc + bj * 16 + li) * LDC + wr + bi * 16 - pass * RP + Mma<T>::row(lk, it)] = acc[bi][bj][it];
-      }
+          for (int it = 0; it < 4; ++it) sC[wc + bj * 16 + li][bi * 16 + Mma<T>::row(lk, it)] = acc[bi][bj][it];
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 128 * RP / 256; ++u) {
+    for (int u = 0; u < 128 * 64 / 4 / 256; ++u) {
       const int e = tid + u * 256;
-      const int n = e / RP, rr = e % RP, m = pass * RP + rr;
-      xs[(size_t)n * NB + m] = A[(size_t)(c0 + n) * npad + s_src[m]] - sC[n * LDC + rr];
+      const int n = e / 16, rr = (e % 16) * 4, m = pass * 64 + rr;
+      const T* cp = A + (size_t)(c0 + n) * npad;
+      T v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = cp[s_src[m + i]] - sC[n][rr + i];
+#pragma unroll
+      for (int h = 0; h < 4 / PER; ++h) {
+        V o;
+        T* po = reinterpret_cast<T*>(&o);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) po[q] = v[h * PER + q];
+        *reinterpret_cast<V*>(xs + (size_t)n * NB + m + h * PER) = o;
+      }
     }
   }
 }
