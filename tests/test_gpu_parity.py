@@ -136,6 +136,45 @@ def test_vstep_matches_oracle(torch, case, prec):
     s.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("mixed_fp32", 1e-10), ("fp64", 1e-11)])
+def test_full_size_substeps_at_sampled_points(torch, prec, tol):
+    """The benchmark's workload at full size (Nx = 256, Nr = 64, Ntheta = 32:
+    256 systems of order 2048, sixteen panels in pairs) in the launch
+    configuration the benchmark times.  X(dt/2) and the field are checked at
+    every point; V(dt), whose oracle costs one dense solve per point, at points
+    spread over the domain (both walls included), each solved by the oracle on
+    its own.  The field is taken near its RF peak, where the systems are least
+    diagonally dominant."""
+    cfg = workloads.config("C2")
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg, precision=prec)
+    ne = workloads.density_profile(ops.xhat, cfg["ic"]["ne_peak"])
+    rng = np.random.default_rng(21)
+    F = S.initial_state(ops, ne, cfg["ic"]["Te_eV"]) * (1.0 + 0.1 * rng.standard_normal((ops.nx, ops.nr, ops.nth)))
+    t = 0.25 / workloads.RF_FREQ_HZ - 0.5 * ops.dt
+    Fg = cuda(torch, F)
+    s.xstep(Fg)
+    Fh = S.x_half_step(ops, F)
+    close(Fg.cpu().numpy(), Fh, 1e-11, 'X(dt/2)')
+    E = torch.empty(s.nx_total, dtype=torch.float64, device="cuda:0")
+    s.field(cuda(torch, Fh), t, E)
+    Eo = S.field_half(ops, t, Fh)
+    close(E.cpu().numpy(), Eo, 1e-12, 'field')
+    assert np.abs(Eo).max() > 0.9 * cfg["field"]["E0"]
+    Fv = cuda(torch, Fh)
+    s.vstep(Fv, cuda(torch, Eo))
+    code, sweeps, resid = s.status()
+    assert code == 0, (code, sweeps, resid)
+    if prec != "fp64":
+        assert resid <= 1e-14 and sweeps >= 1
+    xs = [0, 1, 37, 128, 200, 254, 255]
+    ref = S.v_step(ops, Fh, Eo, xs=xs)
+    got = Fv.cpu().numpy()
+    for x in xs:
+        close(got[x], ref[x], tol, f'V(dt) at x = {x}')
+    s.close()
+
+
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_initial_state_and_moments(torch, case):
     cfg = CASES[case]()
