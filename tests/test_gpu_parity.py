@@ -136,18 +136,35 @@ def test_vstep_matches_oracle(torch, case, prec):
     s.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("mixed_fp32", 1e-10), ("fp64", 1e-11)])
-def test_full_size_substeps_at_sampled_points(torch, prec, tol):
+# the V solvers as the benchmark runs them: (precision, solver settings, tolerance)
+FULL_SIZE = {
+    "mixed_fp32": ("mixed_fp32", None, 1e-10),
+    "fp64": ("fp64", None, 1e-11),
+    # GMRES stops at 1e-12 ||b||: the error is bounded by cond * 1e-12
+    "krylov": ("fp64", dict(n_bins=128, bin_scale=100.0, restart=12, cycles=3, rtol=1e-12,
+                            factor_precision="mixed_fp32"), 1e-9),
+    "banded": ("fp64", "banded", 1e-10),
+}
+
+
+@pytest.mark.parametrize("variant", sorted(FULL_SIZE))
+def test_full_size_substeps_at_sampled_points(torch, variant):
     """The benchmark's workload at full size (Nx = 256, Nr = 64, Ntheta = 32:
     256 systems of order 2048, sixteen panels in pairs) in the launch
-    configuration the benchmark times.  X(dt/2) and the field are checked at
-    every point; V(dt), whose oracle costs one dense solve per point, at points
+    configuration the benchmark times (the mixed and FP64 LU, and the Krylov and
+    banded V solvers with the benchmark's settings).  X(dt/2) and the field are
+    checked at every point; V(dt), whose oracle costs one dense solve per point, at points
     spread over the domain (both walls included), each solved by the oracle on
     its own.  The field is taken near its RF peak, where the systems are least
     diagonally dominant."""
+    prec, vsolver, tol = FULL_SIZE[variant]
     cfg = workloads.config("C2")
     ops = oracle.build_operators(cfg)
     s = solver(cfg, precision=prec)
+    if vsolver == "banded":
+        s.set_vsolver("banded")
+    elif vsolver is not None:
+        s.set_vsolver("gmres", **vsolver)
     ne = workloads.density_profile(ops.xhat, cfg["ic"]["ne_peak"])
     rng = np.random.default_rng(21)
     F = S.initial_state(ops, ne, cfg["ic"]["Te_eV"]) * (1.0 + 0.1 * rng.standard_normal((ops.nx, ops.nr, ops.nth)))
@@ -165,8 +182,10 @@ def test_full_size_substeps_at_sampled_points(torch, prec, tol):
     s.vstep(Fv, cuda(torch, Eo))
     code, sweeps, resid = s.status()
     assert code == 0, (code, sweeps, resid)
-    if prec != "fp64":
+    if variant == "mixed_fp32":
         assert resid <= 1e-14 and sweeps >= 1
+    if variant == "krylov":
+        assert resid <= 1e-12, (sweeps, resid)
     xs = [0, 1, 37, 128, 200, 254, 255]
     ref = S.v_step(ops, Fh, Eo, xs=xs)
     got = Fv.cpu().numpy()
