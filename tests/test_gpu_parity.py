@@ -293,6 +293,28 @@ def test_poisson_field_matches_oracle(torch):
     s.close()
 
 
+@pytest.mark.parametrize("nx,tol", [(130, 1e-11), (256, 1e-11), (700, 1e-10), (1024, 1e-10)])
+def test_poisson_field_large_nx_matches_oracle(torch, nx, tol):
+    """The Poisson field at large Nx, in a state where n_i - n_e changes sign
+    across the gap.  Its operator (D_x^2 with Dirichlet rows) has a condition
+    number of order Nx^4: the library forms and inverts it in 80-bit arithmetic,
+    the oracle inverts it in double (LAPACK), whose rounding sets the
+    agreement: measured 2e-13 (Nx = 130), 2e-12 (256), 8e-12 (700), 3e-11
+    (1024).  An inverse by Gauss-Jordan in double was 1000x further off."""
+    cfg = _hybrid_cfg(nx)
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg)
+    F = S.initial_state(ops, workloads.density_profile(ops.xhat, 1e16), 2.0)
+    ni = 0.8 * S.moments(ops, F)[0] + 3e14 * (1.0 + ops.xhat)
+    t = 0.3 * cfg["T_rf_s"]
+    E = torch.empty(s.nx_total, dtype=torch.float64, device="cuda:0")
+    s.field(cuda(torch, F), t, E, ni=cuda(torch, ni))
+    V_left = 150.0 * math.sin(2 * math.pi * workloads.RF_FREQ_HZ * (t + 0.5 * ops.dt))
+    Eo = S.field_half(ops, t, F, ni=ni, V_left=V_left)
+    close(E.cpu().numpy(), Eo, tol, f"Poisson field nx={nx}")
+    s.close()
+
+
 def _hybrid_cfg(nx=9, V0=150.0):
     cfg = workloads.small_config(nx=nx, nr=10, nth=6, kinds=("elastic", "excitation", "ionization"), E=5e3,
                                  field_kind="rf", n_bins=2)
@@ -300,10 +322,13 @@ def _hybrid_cfg(nx=9, V0=150.0):
     return cfg
 
 
-@pytest.mark.parametrize("nx", [9, 37, 130])
+@pytest.mark.parametrize("nx", [9, 37, 130, 256, 700, 1024])
 def test_ion_step_matches_oracle(torch, nx):
     """Heavies' update of the hybrid model (eq. fluid_step) against the oracle's
-    dense solve: ragged Nx (130 spans more than two 64-row wavefronts)."""
+    dense solve: ragged Nx (130 spans more than two 64-row wavefronts), the
+    benchmark's Nx = 256, and the 8-column panels above Nx = 512 (700, ragged,
+    and the largest Nx, 1024).  With its wall rows equilibrated the system's
+    condition number stays below 100 up to Nx = 1024."""
     from oracle import hybrid as H
     cfg = _hybrid_cfg(nx)
     ops = oracle.build_operators(cfg)
