@@ -1086,13 +1086,13 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
   const int np = npad / NB;
   // sb[r] -= sum_j A[r][k0 + j] sb[k0 + j] for rows r in [r_lo, r_hi): each
   // thread takes a 16-byte vector of consecutive rows (4 FP32 / 2 FP64) and keeps
-  // JB column loads in flight; FP32 and FP16 split the 128 columns between the
+  // JB column loads in flight (16 FP32, 8 FP64 and FP16: 16 FP64 loads spilled); FP32 and FP16 split the 128 columns between the
   // two halves of the block and add the halves through LDS
   auto strip = [&](int k0, int r_lo, int r_hi) {
     using V = typename Vec4<T>::type;
     constexpr int PER = Vec4<T>::per;
     constexpr int H = sizeof(T) < 8 ? 2 : 1;    // column groups
-    constexpr int CW = NB / H, JB = sizeof(T) == 2 ? 8 : 16, TPG = 1024 / H;
+    constexpr int CW = NB / H, JB = sizeof(T) == 4 ? 16 : 8, TPG = 1024 / H;
     const int grp = tid / TPG, lt = tid % TPG;
     for (int r0 = r_lo; r0 < r_hi; r0 += TPG * PER) {
       const int r = r0 + lt * PER;
