@@ -32,7 +32,7 @@ def torch():
     if not _t.cuda.is_available():
         pytest.skip("no GPU visible")
     from paper_2502_16555_amd import _lib
-    _lib.load()          # must exist on a GPU machine: no fallback
+    _lib.load()          # the built library is required: no fallback
     return _t
 
 
