@@ -356,7 +356,7 @@ def main():
                     help="only copy a 1 GiB buffer 3 times (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hot path is single-GPU in this build",
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step is measured on a single GPU",
               file=sys.stderr)
         sys.exit(2)
     import torch
