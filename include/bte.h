@@ -55,7 +55,7 @@ typedef enum {
   BTE_ENOCONV = -4,       /* mixed-precision refinement did not reach refine_rtol       */
   BTE_ENOMEM = -5,        /* device allocation failed                                   */
   BTE_ENONFINITE = -6,    /* NaN/Inf found in the state                                 */
-  BTE_EUNSUPPORTED = -7   /* valid request that this build does not implement           */
+  BTE_EUNSUPPORTED = -7   /* valid request that the library does not implement          */
 } bte_status;
 
 typedef enum {
