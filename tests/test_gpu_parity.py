@@ -365,11 +365,13 @@ def test_hybrid_steps_match_oracle(torch):
     s.close()
 
 
-def test_hybrid_ensemble_per_discharge(torch):
-    """The hybrid step of an uneven ensemble (Nx = 5, 9, 7; three pressures)
-    against the oracle per discharge."""
+@pytest.mark.parametrize("nx_per", [(5, 9, 7), (5, 600, 9)])
+def test_hybrid_ensemble_per_discharge(torch, nx_per):
+    """The hybrid step of an uneven ensemble (three sizes and pressures) against
+    the oracle per discharge; with Nx = 600 in it, every discharge of the launch
+    takes the ion elimination's 8-column panels."""
     from oracle import hybrid as H
-    cfg, members = _ensemble_case()
+    cfg, members = _ensemble_case(nx_per)
     fld = {"kind": "poisson", "V0": 120.0, "freq_hz": workloads.RF_FREQ_HZ}
     cfg["field"] = fld
     for m in members:
@@ -637,12 +639,13 @@ def test_cycle_gradient_matches_central_differences(torch):
     assert np.abs(grad - fd).max() < 1e-5 * scale, (grad, fd)
 
 
-def _ensemble_case():
+def _ensemble_case(nx_per=(5, 9, 7)):
     """Three discharges of different size, pressure and amplitude (the batching
-    form at test size): Nx = 5, 9, 7; 0.3, 1, 2 Torr; E0 = 3e3, 8e3, 1.2e4 V/m."""
-    base = workloads.small_config(nx=5, nr=10, nth=6, kinds=("elastic", "excitation", "ionization"), E=3e3,
-                                  field_kind="rf", n_bins=2)
-    nx_per = [5, 9, 7]
+    form at test size): Nx = 5, 9, 7 by default; 0.3, 1, 2 Torr; E0 = 3e3, 8e3,
+    1.2e4 V/m."""
+    base = workloads.small_config(nx=nx_per[0], nr=10, nth=6, kinds=("elastic", "excitation", "ionization"),
+                                  E=3e3, field_kind="rf", n_bins=2)
+    nx_per = list(nx_per)
     p = [0.3, 1.0, 2.0]
     E0 = [3e3, 8e3, 1.2e4]
     ens = dict(base, n_discharges=3, nx_per=nx_per, n0_per=[workloads.n0_ideal_gas(q) for q in p], E0_per=E0)
