@@ -315,6 +315,30 @@ def test_poisson_field_large_nx_matches_oracle(torch, nx, tol):
     s.close()
 
 
+@pytest.mark.parametrize("nx", [9, 256, 1024])
+def test_poisson_field_exact_for_a_quadratic_potential(torch, nx):
+    """A closed form, independent of the oracle: with no electrons and a uniform
+    ion density n_i, eq. (voltage_bc) with V(0) = V_left, V(L) = 0 has the
+    quadratic solution V = V_left (1 - s) + a s (1 - s), s = x / L, with
+    a = e n_i L^2 / (2 eps0), so E = -V' = (V_left - a (1 - 2 s)) / L.
+    Collocation on the CGL nodes is exact for it, which leaves rounding: the
+    field must hold to 1e-11 of its largest value even at Nx = 1024."""
+    cfg = _hybrid_cfg(nx, V0=100.0)
+    s = solver(cfg)
+    xhat = s.xhat()
+    L = cfg["L_m"]
+    ni = np.full(nx, 1e15)
+    t = 0.1 * cfg["T_rf_s"]
+    E = torch.empty(s.nx_total, dtype=torch.float64, device="cuda:0")
+    F = torch.zeros((nx, cfg["nr"], cfg["ntheta"]), dtype=torch.float64, device="cuda:0")
+    s.field(F, t, E, ni=cuda(torch, ni))
+    V_left = 100.0 * math.sin(2 * math.pi * workloads.RF_FREQ_HZ * (t + 0.5 * cfg["dt_s"]))
+    a = 1.602176634e-19 * 1e15 * L * L / (2 * 8.8541878128e-12)
+    sx = 0.5 * (np.asarray(xhat) + 1.0)
+    close(E.cpu().numpy(), (V_left - a * (1.0 - 2.0 * sx)) / L, 1e-11, f"quadratic potential nx={nx}")
+    s.close()
+
+
 def _hybrid_cfg(nx=9, V0=150.0):
     cfg = workloads.small_config(nx=nx, nr=10, nth=6, kinds=("elastic", "excitation", "ionization"), E=5e3,
                                  field_kind="rf", n_bins=2)
