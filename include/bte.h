@@ -318,6 +318,15 @@ bte_status bte_factor_export(bte_handle* h, const double* E, int32_t x, double* 
 
 bte_status bte_get_info(bte_handle* h, bte_info* out);
 
+/* Refinement of the mixed-precision V step (bte_config.refine_max_iter and
+ * refine_rtol set it at setup): at most max_iter sweeps (1..100; <= 0: 10),
+ * stopping once the normwise backward error of every point is <= rtol
+ * (<= 0: 1e-14).  A V step that ends above rtol latches BTE_ENOCONV and leaves
+ * its last iterate in F; the handle stays usable.  Applies from the next call
+ * (a captured graph keeps the settings it was captured with).
+ * Errors: BTE_EINVAL (max_iter > 100 or rtol not finite). */
+bte_status bte_set_refine(bte_handle* h, int32_t max_iter, double rtol);
+
 /* Synchronizes the handle's last stream and returns the latched device status
  * (then clears it), the refinement sweeps used by the last mixed V-step and the
  * final max|r|/max|b|.  Any pointer may be NULL. */

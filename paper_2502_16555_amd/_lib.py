@@ -82,6 +82,7 @@ EXPORTS = {
                                     C.POINTER(C.c_int32)]),
     "bte_get_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "bte_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "bte_set_refine": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
     "bte_get_timing": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "bte_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "bte_graph_capture": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, bte_field]),

@@ -339,6 +339,10 @@ void fill_devops(bte_handle* h) {
   d.R = h->alloc<double>(nxt * d.npad);
   d.Fs = h->alloc<double>(nxt * d.n);
   d.mu = h->alloc<double>(nxt * d.n);
+  {
+    const size_t gx = (d.n + 63) / 64, gy = (nxt + 31) / 32;
+    d.adj_part = h->alloc<double>(static_cast<size_t>(d.n_params) * gx * gy + nxt * gx);
+  }
   d.rmax = h->alloc<unsigned long long>(nxt);
   d.bmax = h->alloc<unsigned long long>(nxt);
   d.xmax = h->alloc<unsigned long long>(nxt);
@@ -1095,7 +1099,6 @@ bte_status bte_adjoint_step(bte_handle* h, const double* F_n, double t_s, bte_fi
     x_half(h, d.mu, true, s);
     v_solve_again(h, d.mu, true, s);
     // gradients
-    bte::launch_fill(h->d_gE, 0.0, d.nx_total, s);
     bte::launch_adjoint_grads(d, grad_scal, h->d_gE, s);
     if (grad_E) HIP_OK(hipMemcpyAsync(grad_E, h->d_gE, sizeof(double) * d.nx_total, hipMemcpyDeviceToDevice, s));
     if (grad_E0 && h->cfg.field_mode != BTE_FIELD_GIVEN)
@@ -1131,6 +1134,13 @@ bte_status bte_get_status(bte_handle* h, int32_t* refine_iters, double* final_re
   } catch (const std::exception& e) {
     return map_exc(e);
   }
+}
+
+bte_status bte_set_refine(bte_handle* h, int32_t max_iter, double rtol) {
+  if (!h || max_iter > 100 || !std::isfinite(rtol)) return BTE_EINVAL;
+  h->refine_max_iter = max_iter > 0 ? max_iter : 10;
+  h->refine_rtol = rtol > 0 ? rtol : 1e-14;
+  return BTE_OK;
 }
 
 bte_status bte_set_timing(bte_handle* h, int32_t enable) {

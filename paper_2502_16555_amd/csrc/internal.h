@@ -72,6 +72,8 @@ struct DevOps {
   double* R = nullptr;         // [nx_total][npad] residual / correction
   double* Fs = nullptr;        // [nx_total][n] adjoint: post-V state
   double* mu = nullptr;        // [nx_total][n] adjoint: A^-T X^T lambda
+  double* adj_part = nullptr;  // adjoint gradient partial sums, one slot per block:
+                               // [n_params][ceil(nx/32)][ceil(n/64)] then [nx_total][ceil(n/64)]
   unsigned long long* rmax = nullptr;  // [nx_total] max|r| (as ordered bits)
   unsigned long long* bmax = nullptr;  // [nx_total] max|b|
   unsigned long long* xmax = nullptr;  // [nx_total] max|x|
@@ -214,7 +216,8 @@ void launch_refine_check(const DevOps& d, bool transpose, double rtol, int sweep
 void launch_reset_refine(const DevOps& d, hipStream_t s);
 // p[0..n) = v (a kernel, so that captured graphs hold no memset nodes).
 void launch_fill(double* p, double v, size_t n, hipStream_t s);
-// Adjoint gradient contractions.
+// Adjoint gradient contractions (fixed-order two-pass sums; grad_E overwritten,
+// grad_scal accumulated).
 void launch_adjoint_grads(const DevOps& d, double* grad_scal, double* grad_E, hipStream_t s);
 
 }  // namespace bte

@@ -288,21 +288,25 @@ __global__ void k_reset_refine(unsigned long long* rmax, unsigned long long* bma
 
 // grad_scal[op] += dt sum_x n0_x mu_x^T C^(op) F*_x  and  grad_E[x] = dt mu_x^T A F*_x.
 // Tiled like the residual: out[x][i] = sum_k F*[x][k] M[i][k] (MFMA f64), then the
-// epilogue contracts with mu[x][i].  Grid: (n/64, ceil(nx/32), n_params + 1).
+// epilogue contracts with mu[x][i].  Grid: (gx = n/64, gy = ceil(nx/32), n_params + 1).
+// Every block writes its partial sums to slots of its own (no atomics), and
+// k_adjoint_reduce adds the slots in a fixed order, so the gradients are the same
+// bit for bit from run to run:
+//   pscal[(op * gy + by) * gx + bx]  = dt sum_{x in block} n0_x (mu_x . out_x)   (op < n_params)
+//   pE[x * gx + bx]                  = dt (mu_x . out_x) over the block's i range  (op = n_params)
 __global__ __launch_bounds__(256) void k_adjoint_grads(const double* __restrict__ Mu, const double* __restrict__ Fs,
                                                        const double* __restrict__ Csb, const double* __restrict__ Aop,
-                                                       const double* __restrict__ n0x, double* __restrict__ gscal,
-                                                       double* __restrict__ gE, double dt, int n, int nx, int nparams) {
+                                                       const double* __restrict__ n0x, double* __restrict__ pscal,
+                                                       double* __restrict__ pE, double dt, int n, int nx, int nparams) {
   constexpr int BM = 32, BN = 64, BK = 64;
   const int op = blockIdx.z;
   const double* M = (op < nparams) ? Csb + (size_t)op * n * n : Aop;
   __shared__ double sX[BM][BK + 1];
   __shared__ double sM[BN][BK + 1];
-  __shared__ double sRed[BM];
+  __shared__ double sRed[4][BM];
   const int x0 = blockIdx.y * BM, i0 = blockIdx.x * BN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  if (tid < BM) sRed[tid] = 0.0;
   f64x4 acc[2] = {f64x4{0, 0, 0, 0}, f64x4{0, 0, 0, 0}};
   for (int k0 = 0; k0 < n; k0 += BK) {
     for (int e = tid; e < BM * BK; e += 256) {
@@ -322,7 +326,8 @@ __global__ __launch_bounds__(256) void k_adjoint_grads(const double* __restrict_
     }
     __syncthreads();
   }
-  // contract with mu and reduce over i within the block
+  // contract with mu: each wave reduces its 16 rows i for each of the 32 points
+  // (lanes of the same lk hold one point) and writes one slot per point
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -331,20 +336,41 @@ __global__ __launch_bounds__(256) void k_adjoint_grads(const double* __restrict_
       const int x = x0 + xl;
       const int i = i0 + w * 16 + li;
       double v = (x < nx && i < n) ? Mu[(size_t)x * n + i] * acc[b][it] : 0.0;
-      // reduce over the 16 lanes sharing this x (same lk)
       for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      if (li == 0 && x < nx) atomicAdd(&sRed[xl], v);
+      if (li == 0) sRed[w][xl] = v;
     }
   __syncthreads();
-  if (tid == 0) {
-    double total = 0.0;
-    for (int xl = 0; xl < BM; ++xl) {
-      const int x = x0 + xl;
-      if (x >= nx) break;
-      if (op < nparams) total += dt * n0x[x] * sRed[xl];
-      else atomicAdd(&gE[x], dt * sRed[xl]);
+  const size_t gx = gridDim.x, gy = gridDim.y;
+  if (op < nparams) {
+    if (tid == 0) {
+      double total = 0.0;
+      for (int xl = 0; xl < BM && x0 + xl < nx; ++xl)
+        total += dt * n0x[x0 + xl] * (((sRed[0][xl] + sRed[1][xl]) + sRed[2][xl]) + sRed[3][xl]);
+      pscal[((size_t)op * gy + blockIdx.y) * gx + blockIdx.x] = total;
     }
-    if (op < nparams) atomicAdd(&gscal[op], total);
+  } else if (tid < BM && x0 + tid < nx) {
+    pE[(size_t)(x0 + tid) * gx + blockIdx.x] =
+        dt * (((sRed[0][tid] + sRed[1][tid]) + sRed[2][tid]) + sRed[3][tid]);
+  }
+}
+
+// Second pass: gscal[op] += sum over the (by, bx) slots, gE[x] = sum over bx,
+// both in ascending slot order.
+__global__ void k_adjoint_reduce(const double* __restrict__ pscal, const double* __restrict__ pE,
+                                 double* __restrict__ gscal, double* __restrict__ gE, int nparams, int nx, int gx,
+                                 int gy) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nparams) {
+    const double* p = pscal + (size_t)t * gy * gx;
+    double s = 0.0;
+    for (int q = 0; q < gx * gy; ++q) s += p[q];
+    gscal[t] += s;
+  } else if (t < nparams + nx) {
+    const int x = t - nparams;
+    const double* p = pE + (size_t)x * gx;
+    double s = 0.0;
+    for (int q = 0; q < gx; ++q) s += p[q];
+    gE[x] = s;
   }
 }
 
@@ -423,9 +449,14 @@ void launch_reset_refine(const DevOps& d, hipStream_t s) {
 }
 
 void launch_adjoint_grads(const DevOps& d, double* grad_scal, double* grad_E, hipStream_t s) {
-  dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32, d.n_params + 1);
-  k_adjoint_grads<<<g, 256, 0, s>>>(d.mu, d.Fs, d.Csb, d.Aord, d.n0x, grad_scal, grad_E, d.dt, d.n, d.nx_total,
+  const int gx = (d.n + 63) / 64, gy = (d.nx_total + 31) / 32;
+  dim3 g(gx, gy, d.n_params + 1);
+  double* pE = d.adj_part + (size_t)d.n_params * gx * gy;
+  k_adjoint_grads<<<g, 256, 0, s>>>(d.mu, d.Fs, d.Csb, d.Aord, d.n0x, d.adj_part, pE, d.dt, d.n, d.nx_total,
                                     d.n_params);
+  const int tot = d.n_params + d.nx_total;
+  k_adjoint_reduce<<<(tot + 255) / 256, 256, 0, s>>>(d.adj_part, pE, grad_scal, grad_E, d.n_params, d.nx_total, gx,
+                                                     gy);
 }
 
 }  // namespace bte

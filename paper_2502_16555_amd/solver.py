@@ -219,6 +219,10 @@ class Solver:
         code = self.lib.bte_get_status(self.h, C.byref(it), C.byref(r))
         return code, it.value, r.value
 
+    def set_refine(self, max_iter: int = 0, rtol: float = 0.0):
+        """Refinement sweeps and stop of the mixed-precision V step (bte_set_refine)."""
+        check(self.lib.bte_set_refine(self.h, int(max_iter), float(rtol)), "bte_set_refine")
+
     def set_timing(self, on: bool):
         check(self.lib.bte_set_timing(self.h, 1 if on else 0), "bte_set_timing")
 

@@ -44,6 +44,7 @@ def test_status_strings_and_argument_errors():
     assert lib.bte_step(None, None, 0.0, L.bte_field(None, None), None) == L.BTE_EINVAL
     assert lib.bte_moments(None, None, None, None) == L.BTE_EINVAL
     assert lib.bte_set_tuning(None, L.TUNE_LU_STREAMS, 2) == L.BTE_EINVAL
+    assert lib.bte_set_refine(None, 1, 1e-14) == L.BTE_EINVAL
     assert lib.bte_set_vsolver(None, L.VSOLVER_GMRES, 8, 1e4, 0.0, 20, 2, 1e-12, 1) == L.BTE_EINVAL
     assert lib.bte_ion_step(None, None, None, None, 0.0, None) == L.BTE_EINVAL
     assert lib.bte_hybrid_step(None, None, None, 0.0, None) == L.BTE_EINVAL

@@ -470,6 +470,32 @@ def test_adjoint_step_matches_oracle(torch):
     s.close()
 
 
+def test_adjoint_step_is_bitwise_reproducible(torch):
+    """The gradient contractions sum their per-block partials in a fixed order
+    (no floating-point atomics), so repeated adjoint steps from the same inputs
+    give the same bits: lambda, the scaling gradients, dL/dE0 and dL/dE, on an
+    ensemble whose points span several 32-point blocks."""
+    cfg, _ = _ensemble_case((37, 41, 29))
+    rng = np.random.default_rng(17)
+    Fn = rng.standard_normal((sum(cfg["nx_per"]), cfg["nr"], cfg["ntheta"]))
+    lam0 = rng.standard_normal(Fn.shape)
+    t = 0.3 * cfg["T_rf_s"]
+    s = solver(cfg)
+    outs = []
+    for rep in range(3):
+        lam = cuda(torch, lam0)
+        gs = torch.zeros(s.n_params, dtype=torch.float64, device="cuda:0")
+        gE0 = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+        gE = torch.zeros(s.nx_total, dtype=torch.float64, device="cuda:0")
+        s.adjoint_step(cuda(torch, Fn), t, lam, gs, gE0, gE)
+        outs.append([a.cpu().numpy() for a in (lam, gs, gE0, gE)])
+    assert s.status()[0] == 0
+    for rep in (1, 2):
+        for a, b in zip(outs[rep], outs[0]):
+            assert np.array_equal(a, b), rep
+    s.close()
+
+
 def test_nonfinite_state_is_reported(torch):
     from paper_2502_16555_amd import _lib
     cfg = workloads.config("C0")
@@ -502,38 +528,107 @@ def test_nonfinite_field_is_reported(torch, prec):
     s.close()
 
 
-@pytest.mark.parametrize("mode,tol", [("fp64", 1e-8), ("mixed_fp32", 1e-6), ("mixed_bf16x3", 1e-6), ("banded", 1e-8)])
-def test_c1_golden_cycle(torch, mode, tol):
-    """Realistic RF case (Nx=64, Nr=64, Ntheta=32), one full cycle of 1000 steps on
-    the GPU against the stored oracle moments (written by
-    tests/golden/make_golden.py, which calls only the oracle): n_e, the mean
-    energy and the energy density every 100 steps and the final state, within
-    1e-8 for the FP64 solvers and 1e-6 for the mixed steps (FP32, or split-bf16
-    trailing updates, with FP64 refinement)."""
-    path = os.path.join(ROOT, "tests", "golden", "c1_oracle_1000.npz")
+def _golden_run(torch, name, n_file_steps, mode, tol):
+    """Run the stored oracle workload ``name`` on the GPU from its initial state
+    and compare n_e, the mean energy (everywhere, and on points with n_e above
+    1e-3 of its peak), the energy density and k_i n_e at every stored step, and
+    the final state."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name.lower()}_oracle_{n_file_steps}.npz")
     if not os.path.exists(path):
-        pytest.skip("golden file not generated")
+        pytest.skip(f"golden file {os.path.basename(path)} not generated")
     g = np.load(path, allow_pickle=False)
-    cfg = workloads.config("C1")
+    cfg = workloads.config(name)
     sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
     import make_golden
-    assert str(g["config_hash"]) == make_golden.config_hash(cfg), "C1 workload changed since the golden run"
+    assert str(g["config_hash"]) == make_golden.config_hash(cfg), f"{name} workload changed since the golden run"
     s = solver(cfg, precision="fp64" if mode == "banded" else mode)
     if mode == "banded":
         s.set_vsolver("banded")
     ne = workloads.density_profile(s.xhat(), cfg["ic"]["ne_peak"])
     Fg = s.initial_state(cuda(torch, ne), cfg["ic"]["Te_eV"])
     every = int(g["every"])
-    for n in range(cfg["n_steps"]):
+    worst = {}
+    for n in range(int(g["n_steps"])):
         s.step(Fg, n * cfg["dt_s"])
         if (n + 1) % every == 0:
             mg = s.moments(Fg).cpu().numpy()
             mo = g["moments"][(n + 1) // every]
-            close(mg[0], mo[0], tol, f"{mode} n_e at step {n + 1}")
-            close(mg[1], mo[1], tol, f"{mode} mean energy at step {n + 1}")
-            close(mg[0] * mg[1], mo[0] * mo[1], tol, f"{mode} energy density at step {n + 1}")
+            inner = mo[0] > 1e-3 * mo[0].max()
+            for what, a, b in (("n_e", mg[0], mo[0]), ("mean energy", mg[1], mo[1]),
+                               ("mean energy (n_e > 1e-3 max)", mg[1][inner], mo[1][inner]),
+                               ("energy density", mg[0] * mg[1], mo[0] * mo[1]),
+                               ("k_i n_e", mg[0] * mg[2], mo[0] * mo[2])):
+                worst[what] = max(worst.get(what, 0.0), rel(a, b))
+                close(a, b, tol, f"{mode} {what} at step {n + 1}")
+    worst["final state"] = rel(Fg.cpu().numpy(), g["F"])
+    print(f"{name} {mode}: " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()))
     close(Fg.cpu().numpy(), g["F"], tol, f"{mode} final state")
     assert s.status()[0] == 0
+    s.close()
+
+
+GOLDEN_MODES = ["fp64", "mixed_fp32", "mixed_bf16x3", "mixed_bf16", "banded"]
+
+
+@pytest.mark.parametrize("mode", GOLDEN_MODES)
+def test_c1_golden_cycle(torch, mode):
+    """Realistic RF case (Nx=64, Nr=64, Ntheta=32), one full cycle of 1000 steps on
+    the GPU against the stored oracle (written by tests/golden/make_golden.py,
+    which calls only the oracle), every 100 steps and at the end, for every
+    V solver and precision: FP64 LU, FP32 / split-bf16 / bf16 factors with FP64
+    refinement, and the banded harmonic-basis LU.
+
+    Tolerance 2e-10 for all of them, n_e, mean energy and k_i alike: the
+    refinement brings the mixed steps to the FP64 backward error, so every
+    path carries the FP64 rounding of the X step (Chebyshev systems of
+    condition ~1e4) and of the V solve, which adds up about linearly over the
+    steps: measured 1.6e-12 per 100 steps, 1.8e-11 after the cycle for every
+    mode and result.  (One step from the initial Maxwellian, k_i n_e agrees to
+    only ~1e-8, see test_ionization_rate_is_sensitive_to_speed_mode_rounding; by
+    step 100 the field has filled the tail and the gap is gone.)"""
+    _golden_run(torch, "C1", 1000, mode, 2e-10)
+
+
+@pytest.mark.parametrize("mode", [m for m in GOLDEN_MODES if m != "banded"])
+def test_c2_golden_run(torch, mode):
+    """The benchmark workload itself (Nx=256, Nr=64, Ntheta=32: 256 systems of
+    order 2048 per step) for the first 100 steps of the RF cycle against the
+    stored oracle run (every 10 steps and the final state), in FP64 and in the
+    three mixed forms of the precision workload (FP32, split-bf16 and bf16
+    trailing updates, each with FP64 refinement).  The target for the mixed
+    step is 1e-6 relative on n_e and the mean energy; the test holds every
+    result to 1e-9 (the FP64 rounding of the steps, as for C1)."""
+    _golden_run(torch, "C2", 100, mode, 1e-9)
+
+
+def test_refinement_nonconvergence_is_latched_and_the_handle_recovers(torch):
+    """With one refinement sweep and an unreachable stop (rtol 1e-30) the mixed
+    V step latches BTE_ENOCONV; the state holds the last iterate (finite, and
+    one sweep from the FP32 factors already agrees with the oracle to 1e-9).
+    After restoring the default stop the same handle steps cleanly and matches
+    the oracle to the mixed tolerance."""
+    from paper_2502_16555_amd import _lib
+    cfg = CASES["panels"]()
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg, precision="mixed_fp32")
+    F0 = _state(ops, 13)
+    t = 0.3 * cfg["T_rf_s"]
+    ref = S.step(ops, F0, t)
+    s.set_refine(1, 1e-30)
+    Fg = cuda(torch, F0)
+    s.step(Fg, t)
+    code, sweeps, resid = s.status()
+    assert code == _lib.BTE_ENOCONV and sweeps == 1 and resid > 0, (code, sweeps, resid)
+    assert s.status()[0] == 0                  # read once, then cleared
+    got = Fg.cpu().numpy()
+    assert np.isfinite(got).all()
+    close(got, ref, 1e-9, "last iterate after one sweep")
+    s.set_refine(0, 0.0)                       # defaults: 10 sweeps, 1e-14
+    Fg = cuda(torch, F0)
+    s.step(Fg, t)
+    code, sweeps, resid = s.status()
+    assert code == 0 and 1 <= sweeps <= 10 and resid <= 1e-14, (code, sweeps, resid)
+    close(Fg.cpu().numpy(), ref, 1e-10, "after recovery")
     s.close()
 
 
@@ -890,4 +985,75 @@ def test_krylov_steps_ensemble_and_graph(torch):
     torch.cuda.synchronize()
     assert s.status()[0] == 0
     assert np.array_equal(Fg.cpu().numpy(), got)
+    s.close()
+
+
+def test_c3_ensemble_at_size(torch):
+    """The batching workload at its full size: 64 discharges (Nx ~ U{32..200},
+    7255 points, 0.1-2 Torr, E0 ~ U[1e3, 1e4] V/m, seed 1) in the same
+    launches, mixed precision, as the benchmark runs it.  Inputs are built on
+    the oracle side (CGL nodes and the projected Maxwellian of every
+    discharge).  Checked against the oracle per discharge:
+    * the smallest discharge over two full steps, every point;
+    * a median-size and the largest discharge: X(dt/2) and the field at every
+      point, V(dt) at three points (both walls and the middle), each solved by
+      the oracle alone, from the oracle's own half-step and field."""
+    from oracle import basis as OB
+    cfg = workloads.config("C3")
+    nx_per = list(cfg["nx_per"])
+    nd = len(nx_per)
+    offs = np.concatenate([[0], np.cumsum(nx_per)]).astype(int)
+    order = np.argsort(nx_per, kind="stable")
+    d_small, d_mid, d_big = int(order[0]), int(order[nd // 2]), int(order[-1])
+
+    def member(d):
+        return dict(cfg, n_discharges=1, nx=nx_per[d], nx_per=[nx_per[d]], n0_m3=cfg["n0_per"][d],
+                    n0_per=[cfg["n0_per"][d]], E0_per=[cfg["E0_per"][d]], field=dict(cfg["field"], E0=cfg["E0_per"][d]))
+
+    ops = {d: oracle.build_operators(member(d)) for d in (d_small, d_mid, d_big)}
+    ne = np.concatenate([workloads.density_profile(OB.cgl_nodes(nx_per[d]), cfg["ic"]["ne_peak"]) for d in range(nd)])
+    F0 = S.initial_state(ops[d_small], ne, cfg["ic"]["Te_eV"])       # same speed basis for every discharge
+    s = solver(cfg, precision="mixed_fp32")
+    assert s.nx_total == offs[-1] == 7255 and s.n_discharges == 64
+    close(s.xhat()[offs[d_big]:offs[d_big + 1]], ops[d_big].xhat, 1e-15, "grid of the largest discharge")
+    dt, t0 = cfg["dt_s"], 0.2 * cfg["T_rf_s"]
+    Fg = cuda(torch, F0)
+    for k in range(2):
+        s.step(Fg, t0 + k * dt)
+    code, sweeps, resid = s.status()
+    assert code == 0 and resid <= 1e-14, (code, sweeps, resid)
+    got = Fg.cpu().numpy()
+    assert np.isfinite(got).all()
+    sl = slice(offs[d_small], offs[d_small + 1])
+    ref = F0[sl]
+    for k in range(2):
+        ref = S.step(ops[d_small], ref, t0 + k * dt)
+    close(got[sl], ref, 1e-10, f"discharge {d_small} (Nx={nx_per[d_small]}) after two steps")
+    # sub-steps of the larger discharges
+    Fx = cuda(torch, F0)
+    s.xstep(Fx)
+    gx = Fx.cpu().numpy()
+    E = torch.empty(s.nx_total, dtype=torch.float64, device="cuda:0")
+    t = 0.25 * cfg["T_rf_s"] - 0.5 * dt                               # field at its RF peak
+    s.field(Fx, t, E)
+    gE = E.cpu().numpy()
+    Fv_in, E_in = gx.copy(), gE.copy()
+    refs = {}
+    for d in (d_mid, d_big):
+        sl = slice(offs[d], offs[d + 1])
+        Fh = S.x_half_step(ops[d], F0[sl])
+        close(gx[sl], Fh, 1e-11, f"X(dt/2) of discharge {d} (Nx={nx_per[d]})")
+        Eo = S.field_half(ops[d], t, Fh)
+        close(gE[sl], Eo, 1e-13, f"field of discharge {d}")
+        Fv_in[sl], E_in[sl] = Fh, Eo
+        xs = [0, nx_per[d] // 2, nx_per[d] - 1]
+        refs[d] = (xs, S.v_step(ops[d], Fh, Eo, xs=xs))
+    Fv = cuda(torch, Fv_in)
+    s.vstep(Fv, cuda(torch, E_in))
+    code, sweeps, resid = s.status()
+    assert code == 0 and resid <= 1e-14, (code, sweeps, resid)
+    gv = Fv.cpu().numpy()
+    for d, (xs, rv) in refs.items():
+        for x in xs:
+            close(gv[offs[d] + x], rv[x], 1e-10, f"V(dt) of discharge {d} at x = {x}")
     s.close()

@@ -456,3 +456,29 @@ def test_blocked_lu_restatement_matches_lapack():
     assert np.array_equal(ip_a, ip_b)
     assert not np.array_equal(a[128:, :128], b_[128:, :128])
     assert np.allclose(a[:, 128:], b_[:, 128:], rtol=0, atol=1e-12 * np.abs(a).max())
+
+
+def test_ionization_rate_is_sensitive_to_speed_mode_rounding():
+    """Why k_i agrees less closely than n_e between two FP64 evaluations of a
+    step.  k_i weights only the splines above the 15.76 eV threshold, where the
+    1 eV initial Maxwellian is below 5e-7 of its bulk.  The X half-step changes
+    basis through the eigenvectors U of (G_v, M_v) (Alg. bte_spatial_adv),
+    which are global in speed (cond(U) ~ 1e3), so rounding of order eps times
+    the bulk lands on the tail coefficients.  An exact identity, U (U^-1 F) = F,
+    evaluated in FP64 already moves k_i n_e by about 4e-9 while n_e moves by
+    rounding only.  Two correct FP64 implementations of the step (different
+    summation orders) therefore differ by this much in k_i n_e after one step
+    from the initial state, and the parity bar for k_i is set from it."""
+    cfg = workloads.config("C1")
+    ops = oracle.build_operators(cfg)
+    F = S.initial_state(ops, workloads.density_profile(ops.xhat, cfg["ic"]["ne_peak"]), cfg["ic"]["Te_eV"])
+    c = F[ops.nx // 2, :, 0]
+    assert np.abs(c[np.flatnonzero(ops.ki_ord.reshape(ops.nr, ops.nth)[:, 0])]).max() < 1e-6 * np.abs(c).max()
+    Fr = np.einsum("ki,xia->xka", ops.U, np.einsum("ik,xka->xia", ops.Uinv, F))
+    m0, mr = S.moments(ops, F), S.moments(ops, Fr)
+    rel = lambda a, b: np.abs(a - b).max() / np.abs(b).max()
+    d_ne = rel(mr[0], m0[0])
+    d_ki = rel(mr[0] * mr[2], m0[0] * m0[2])
+    assert d_ne < 1e-14
+    assert 1e-10 < d_ki < 1e-7, d_ki
+
