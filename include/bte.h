@@ -207,6 +207,22 @@ bte_status bte_implicit_step(bte_handle* h, double* F, const double* ni, double 
  * Errors: BTE_EINVAL (null pointers), BTE_EUNSUPPORTED (other field modes). */
 bte_status bte_ion_step(bte_handle* h, const double* F, const double* ni_in, double* ni_out, double t_s,
                         void* stream);
+/* bte_ion_step for callers that cannot allocate device memory or call the
+ * allocator (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, same kernels and the same result bit for
+ * bit, but its scratch -- the formed ion systems (sum_d Nx_d^2 doubles), their
+ * right-hand sides, E^n and the Poisson right-hand side (sum_d Nx_d doubles
+ * each) -- lives in a fixed device array of the library of
+ * BTE_ION_SCRATCH_DOUBLES doubles (16 MiB), one copy on every GPU the library
+ * runs on, held until the process ends, instead of in the handle's buffers.  Calls no allocator.  Every entry of the
+ * scratch is written before it is read, so nothing has to start at zero.  All
+ * calls on one GPU share the array: calls that overlap on one GPU (two streams,
+ * or two handles) race and must be ordered by the caller.
+ * Errors: as bte_ion_step; BTE_EINVAL when sum_d Nx_d^2 + 3 sum_d Nx_d >
+ * BTE_ION_SCRATCH_DOUBLES. */
+#define BTE_ION_SCRATCH_DOUBLES 2097152
+bte_status bte_ion_step_noalloc(bte_handle* h, const double* F, const double* ni_in, double* ni_out, double t_s,
+                                void* stream);
 /* One step of the hybrid model: n_i <- n_i^{n+1} by bte_ion_step, then
  * F <- bte_step(F, t_s) with the Poisson field of n_i^{n+1}.  ni is device
  * [sum Nx], updated in place.  POISSON field mode only (else BTE_EUNSUPPORTED). */

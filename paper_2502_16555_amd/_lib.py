@@ -58,6 +58,7 @@ TUNE_LU_STREAMS = 0
 TUNE_UPDATE_KC = 1
 TUNE_FORM_XPB = 2
 TUNE_PANEL_PAIRS = 3
+ION_SCRATCH_DOUBLES = 2097152   # BTE_ION_SCRATCH_DOUBLES
 
 EXPORTS = {
     "bte_setup_operators": (C.c_int, [C.POINTER(bte_config), C.c_int, C.POINTER(C.c_void_p)]),
@@ -71,6 +72,7 @@ EXPORTS = {
     "bte_xstep_T": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "bte_vstep": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bte_ion_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "bte_ion_step_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "bte_hybrid_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "bte_implicit_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, bte_implicit_opts,
                                     C.POINTER(bte_implicit_stats), C.c_void_p]),

@@ -15,6 +15,8 @@
 #include "assemble.h"
 #include "internal.h"
 
+static_assert(bte::kIonScratchDoubles == BTE_ION_SCRATCH_DOUBLES, "ion scratch size");
+
 namespace {
 
 using bte::DevOps;
@@ -736,6 +738,10 @@ bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle
     HIP_OK(hipSetDevice(hip_device));
     bte::assemble(in, &h->host);
     fill_devops(h);
+    if (cfg->field_mode == BTE_FIELD_POISSON) {   // this GPU's copy of the ion step's fixed scratch
+      double* ws = nullptr;
+      HIP_OK(bte::ion_scratch(&ws));
+    }
     for (auto& e : h->ev) HIP_OK(hipEventCreate(&e));
     const int P = h->d.npad / bte::kNB;
     h->lu_ev.assign(static_cast<size_t>(bte_handle::kMaxLuStreams) * 8 * P, nullptr);
@@ -980,6 +986,35 @@ bte_status bte_ion_step(bte_handle* h, const double* F, const double* ni_in, dou
     hipStream_t s = S(stream);
     h->last_stream = s;
     ion_update(h, F, ni_in, ni_out, t_s, s);
+    return BTE_OK;
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+}
+
+bte_status bte_ion_step_noalloc(bte_handle* h, const double* F, const double* ni_in, double* ni_out, double t_s,
+                                void* stream) {
+  if (!h || !F || !ni_in || !ni_out) return BTE_EINVAL;
+  if (h->cfg.field_mode != BTE_FIELD_POISSON) return BTE_EUNSUPPORTED;
+  const size_t nxt = static_cast<size_t>(h->d.nx_total);
+  size_t m = 0;
+  for (int nx : h->nx_per) m += static_cast<size_t>(nx) * nx;
+  if (m + 3 * nxt > bte::kIonScratchDoubles) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    double* ws = nullptr;
+    HIP_OK(bte::ion_scratch(&ws));
+    double* M = ws;            // [sum Nx_d^2] the formed systems
+    double* b = M + m;         // [sum Nx] right-hand sides
+    double* E = b + nxt;       // [sum Nx] E^n
+    double* rhs = E + nxt;     // [sum Nx] Poisson right-hand side
+    hipStream_t s = S(stream);
+    h->last_stream = s;
+    const bte_config& c = h->cfg;
+    bte::launch_field(h->d, BTE_FIELD_POISSON, t_s, c.field_freq_hz, c.field_a1, c.poisson_V0, F, nullptr, ni_in, E,
+                      s, rhs);
+    bte::launch_ion_update_ws(h->d, F, ni_in, ni_out, M, b, E, s);
+    HIP_OK(hipGetLastError());
     return BTE_OK;
   } catch (const std::exception& e) {
     return map_exc(e);

@@ -128,6 +128,14 @@ void launch_gmres_status(const DevOps& d, const GmresOps& q, hipStream_t s);
 // ---- heavies' update (kernels_ion.hip) ----------------------------------------
 // n_i^{n+1} of eq. fluid_step for every discharge, with E^n already in d.ion_E.
 void launch_ion_update(const DevOps& d, const double* F, const double* ni_in, double* ni_out, hipStream_t s);
+// The same with the ion systems, right-hand sides and E^n in caller-given
+// buffers (M: sum Nx_d^2 at the offsets p_off, b and E: [nx_total]).
+void launch_ion_update_ws(const DevOps& d, const double* F, const double* ni_in, double* ni_out, double* M, double* b,
+                          const double* E, hipStream_t s);
+// Fixed device scratch of the allocation-free ion step: the address of this
+// GPU's copy (looked up once per device, with that device current).
+constexpr size_t kIonScratchDoubles = size_t(1) << 21;
+hipError_t ion_scratch(double** out);
 
 // ---- fully implicit step (kernels_implicit.hip) -------------------------------
 // d.Y <- A_x applied mode by mode (lambda_i cos theta_a D_x) to the modes in d.Y.
@@ -154,7 +162,8 @@ void launch_modes_to_x(const DevOps& d, double* F, hipStream_t s);
 void launch_x_to_modes_T(const DevOps& d, const double* F, hipStream_t s);   // U^T contraction
 void launch_modes_to_x_T(const DevOps& d, double* F, hipStream_t s);         // Uinv^T contraction
 void launch_field(const DevOps& d, int mode, double t_half, double freq, double a1, double V0,
-                  const double* Fh, const double* E_given, const double* ni, double* E, hipStream_t s);
+                  const double* Fh, const double* E_given, const double* ni, double* E, hipStream_t s,
+                  double* rhs = nullptr);   // Poisson right-hand side scratch (NULL: d.field_rhs)
 void launch_field_dE0(const DevOps& d, int mode, double t_half, double freq, double a1, const double* gE,
                       double* gE0, hipStream_t s);
 void launch_moments(const DevOps& d, const double* F, double* out, hipStream_t s);

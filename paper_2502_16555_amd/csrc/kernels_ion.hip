@@ -9,6 +9,7 @@
 // Gaussian elimination with partial pivoting in one block per discharge.
 #include <cfloat>
 #include <climits>
+#include <mutex>
 #include <type_traits>
 
 #include "internal.h"
@@ -304,20 +305,52 @@ __global__ __launch_bounds__(kIonSolveThreads) void k_ion_solve_blk(double* __re
 
 }  // namespace
 
-void launch_ion_update(const DevOps& d, const double* F, const double* ni_in, double* ni_out, hipStream_t s) {
+void launch_ion_update_ws(const DevOps& d, const double* F, const double* ni_in, double* ni_out, double* M, double* b,
+                          const double* E, hipStream_t s) {
   const dim3 gf((d.max_nx + kIonFormCols - 1) / kIonFormCols, d.nd);
-  k_ion_form<<<gf, kIonThreads, 0, s>>>(F, ni_in, d.ion_E, d.dxT, d.dx2, d.mom + 2 * (size_t)d.n, d.n0_of, d.x_off,
-                                        d.nx_of, d.p_off, d.ion_M, d.ion_b, d.dt, d.n);
+  k_ion_form<<<gf, kIonThreads, 0, s>>>(F, ni_in, E, d.dxT, d.dx2, d.mom + 2 * (size_t)d.n, d.n0_of, d.x_off,
+                                        d.nx_of, d.p_off, M, b, d.dt, d.n);
   // blocked elimination, panel width by the largest Nx (two W x Nx tiles of LDS)
   const int ldp = d.max_nx + 1;
   auto blk = [&](auto wc) {
     constexpr int W = decltype(wc)::value;
     const size_t sh = (size_t)(W * ldp + (ldp + 1) * W) * sizeof(double);
-    k_ion_solve_blk<W><<<d.nd, kIonSolveThreads, sh, s>>>(d.ion_M, d.ion_b, ni_out, d.x_off, d.nx_of, d.p_off,
-                                                         d.status, ldp, d.dt);
+    k_ion_solve_blk<W><<<d.nd, kIonSolveThreads, sh, s>>>(M, b, ni_out, d.x_off, d.nx_of, d.p_off, d.status, ldp,
+                                                         d.dt);
   };
   if (d.max_nx <= 512) blk(std::integral_constant<int, 16>{});
   else blk(std::integral_constant<int, 8>{});
+}
+
+void launch_ion_update(const DevOps& d, const double* F, const double* ni_in, double* ni_out, hipStream_t s) {
+  launch_ion_update_ws(d, F, ni_in, ni_out, d.ion_M, d.ion_b, d.ion_E, s);
+}
+
+// Scratch of the allocation-free ion step: one copy per GPU, alive until the
+// process ends.  Host code never uses the array's name as an address; it takes
+// the device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[kIonScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t ion_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    double* p = nullptr;
+    e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace bte

@@ -333,12 +333,13 @@ void launch_advect(const DevOps& d, bool fp32, bool transpose, hipStream_t s) {
 }
 
 void launch_field(const DevOps& d, int mode, double t_half, double freq, double a1, double V0, const double* Fh,
-                  const double* E_given, const double* ni, double* E, hipStream_t s) {
+                  const double* E_given, const double* ni, double* E, hipStream_t s, double* rhs) {
   if (mode == 3) {
+    if (!rhs) rhs = d.field_rhs;
     const int gb = (d.nx_total + kThreads / 64 - 1) / (kThreads / 64);
-    k_field_rhs<<<gb, kThreads, 0, s>>>(t_half, freq, V0, Fh, ni, d.field_rhs, d.x_disc, d.x_off, d.nx_of, d.mom,
+    k_field_rhs<<<gb, kThreads, 0, s>>>(t_half, freq, V0, Fh, ni, rhs, d.x_disc, d.x_off, d.nx_of, d.mom,
                                         d.nx_total, d.n);
-    k_field_apply<<<gb, kThreads, 0, s>>>(d.field_rhs, E, d.x_disc, d.x_off, d.nx_of, d.poisson, d.p_off,
+    k_field_apply<<<gb, kThreads, 0, s>>>(rhs, E, d.x_disc, d.x_off, d.nx_of, d.poisson, d.p_off,
                                           d.nx_total);
     return;
   }

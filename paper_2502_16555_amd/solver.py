@@ -158,6 +158,11 @@ class Solver:
         check(self.lib.bte_ion_step(self.h, _ptr(F), _ptr(ni_in), _ptr(ni_out), float(t), _stream(stream)),
               "bte_ion_step")
 
+    def ion_step_noalloc(self, F, ni_in, ni_out, t, stream=None):
+        """bte_ion_step with its scratch in the library's fixed device array (no allocation)."""
+        check(self.lib.bte_ion_step_noalloc(self.h, _ptr(F), _ptr(ni_in), _ptr(ni_out), float(t), _stream(stream)),
+              "bte_ion_step_noalloc")
+
     def hybrid_step(self, F, ni, t, stream=None):
         """One hybrid step (bte_hybrid_step): ions, then electrons; F and ni in place."""
         check(self.lib.bte_hybrid_step(self.h, _ptr(F), _ptr(ni), float(t), _stream(stream)), "bte_hybrid_step")
