@@ -84,7 +84,7 @@ KRYLOV = dict(n_bins=128, bin_scale=100.0, restart=12, cycles=3, rtol=1e-12, fac
 
 
 def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=False, krylov=False, banded=False,
-            pairs=None):
+            pairs=None, vsolver=None):
     from paper_2502_16555_amd import Solver, _lib
     t0 = time.time()
     s = Solver(cfg, precision=precision)
@@ -92,6 +92,8 @@ def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=Fals
         s.set_vsolver("gmres", **KRYLOV)
     if banded:
         s.set_vsolver("banded")
+    if vsolver is not None:
+        s.set_vsolver(vsolver)
     setup_s = time.time() - t0
     if lu_streams is not None:
         s.set_tuning(_lib.TUNE_LU_STREAMS, lu_streams)
@@ -163,6 +165,42 @@ def moment_errors(got, ref):
     return {"n_e": rel_err(got[0], ref[0]), "mean_energy": rel_err(got[1], ref[1], mask),
             "energy_density": rel_err(got[0] * got[1], ref[0] * ref[1]),
             "k_i_n_e": rel_err(got[0] * got[2], ref[0] * ref[2])}
+
+
+def golden_check(cfg, precision, torch, name="C2", n_steps=100):
+    """Untimed: the first n_steps steps of the RF cycle from the initial state,
+    compared every stored step with the stored FP64 oracle run of the same
+    workload (tests/golden/<name>_oracle_<n_steps>.npz, written by the oracle
+    alone); returns the largest relative error per result over the stored steps,
+    or None when the file is absent or belongs to another workload."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name.lower()}_oracle_{n_steps}.npz")
+    if not os.path.exists(path):
+        return None
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_golden
+    import workloads
+    from paper_2502_16555_amd import Solver
+    g = np.load(path, allow_pickle=False)
+    if str(g["config_hash"]) != make_golden.config_hash(cfg):
+        return None
+    s = Solver(cfg, precision=precision)
+    ne = workloads.density_profile(s.xhat(), cfg["ic"]["ne_peak"])
+    F = s.initial_state(torch.as_tensor(ne, device="cuda:0"), cfg["ic"]["Te_eV"])
+    every = int(g["every"])
+    worst = {}
+    for n in range(n_steps):
+        s.step(F, n * cfg["dt_s"])
+        if (n + 1) % every == 0:
+            e = moment_errors(s.moments(F).cpu().numpy(), g["moments"][(n + 1) // every])
+            for k, v in e.items():
+                worst[k] = max(worst.get(k, 0.0), v)
+    worst["final_state"] = rel_err(F.cpu().numpy(), g["F"])
+    worst["steps"] = n_steps
+    code = s.status()[0]
+    s.close()
+    if code != 0:
+        raise RuntimeError(f"{precision}: device status {code} in the stored-run comparison")
+    return worst
 
 
 def run_hybrid(cfg, steps, warmup, torch):
@@ -317,10 +355,44 @@ def run_ensemble(torch, steps=3):
             "device_GB": info.bytes_device / 1e9}
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def paper_grid(torch, steps):
+    """The grid of the paper's timed semi-implicit runs (table of the hybrid
+    solver's performance: Nr = 64, Ntheta = 16, Nl = 3, Nx = 100, dt f = 5e-5),
+    with this repository's synthetic RF physics, by every V solver here.  The
+    paper's own time for that grid (GMRES V solver, 1 A100 + 1 CPU core, its
+    LXCat physics) is quoted as context only."""
+    import workloads
+    cfg = dict(workloads.config("C1"), nx=100, nx_per=[100], ntheta=16, nl=3)
+    cfg["dt_s"] = 5e-5 * cfg["T_rf_s"]
+    out = {"workload": "Nx=100 CGL, Nr=64, Ntheta=16, Nl=3, dt = 5e-5 T_rf, RF E0=6732.7 V/m",
+           "paper_context": {"s_per_step": 3.53e-2, "hardware": "1x A100 + 1 EPYC 7763 core",
+                             "solver": "semi-implicit step, GMRES V solver (table of the hybrid solver's performance)"},
+           "solvers": {}}
+    for name, prec, vs in (("lu_fp64", "fp64", None), ("lu_mixed_fp32", "mixed_fp32", None),
+                           ("banded_fp64", "fp64", "banded"), ("hessenberg_fp64", "fp64", "hessenberg")):
+        r = run_gpu(cfg, prec, steps, 3, torch, vsolver=vs)
+        out["solvers"][name] = {"ms_per_step": r["ms_per_step"], "steps_per_s": 1000.0 / r["ms_per_step"],
+                                "setup_s": r["setup_s"]}
+    return out
+
+
 def cpu_baseline(cfg):
     """The FP64 oracle on the host cores: one full step from the initial state
     (both X half-steps and all Nx velocity-space solves).  Returns the timing and
-    the moments after the step (the reference of the one-step accuracy check)."""
+    the moments after the step (the reference of the one-step accuracy check).
+    ``cores`` is the number of BLAS threads the oracle's LAPACK calls ran on (read
+    from the loaded BLAS library), beside the host's CPU model and logical CPUs."""
     import oracle
     from oracle import semi_implicit as S
     import workloads
@@ -329,9 +401,14 @@ def cpu_baseline(cfg):
     t = time.perf_counter()
     F1 = S.step(ops, F, 0.0)
     step_s = time.perf_counter() - t
-    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max(int(p["num_threads"]) for p in threadpool_info() if p.get("user_api") == "blas")
+    except Exception:
+        threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     res = {"value": 1.0 / step_s, "unit": "steps/s", "cores": threads, "kind": "oracle",
-           "sample": f"one full step (t=0, from the initial state) at Nx={ops.nx}: {step_s:.1f} s"}
+           "sample": f"one full step (t=0, from the initial state) at Nx={ops.nx}: {step_s:.1f} s",
+           "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count()}
     return res, S.moments(ops, F1)
 
 
@@ -346,12 +423,16 @@ def main():
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--lu-streams", type=int, default=None, help="concurrent factorization groups (library default 1)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
-    ap.add_argument("--ensemble", action="store_true", help="also time the 64-discharge batching form")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-discharge batching form")
     ap.add_argument("--no-krylov", action="store_true", help="skip the GMRES V-solver leg")
     ap.add_argument("--no-banded", action="store_true", help="skip the banded harmonic-basis V-solver leg")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid-model (ions + electrons) leg")
+    ap.add_argument("--no-hessenberg", action="store_true", help="skip the Hessenberg-form V-solver leg")
+    ap.add_argument("--no-paper-grid", action="store_true", help="skip the legs at the paper's timed grid")
     ap.add_argument("--no-implicit", action="store_true", help="skip the fully implicit step leg")
-    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 (split-operand) variant of the mixed step")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 variants (split and plain operands)")
+    ap.add_argument("--no-golden", action="store_true",
+                    help="skip the comparison of the first 100 steps with the stored oracle run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
@@ -412,6 +493,12 @@ def main():
                      "panel_pairs": pairs,
                      "launches_per_step": n_upd_launches,
                      "avg_launch_ms": main_run["ms_update"] / n_upd_launches},
+        "v_solve_roofline": {"bound": "mfma", "what": "whole velocity-space solve: formation, factorization, "
+                                                      "solves and FP64 refinement, wall time",
+                             "lu_flops": info.lu_flops_per_step, "ms": main_run["ms_vwall"],
+                             "achieved": info.lu_flops_per_step / (main_run["ms_vwall"] * 1e-3) / 1e12,
+                             "peak": peak, "unit": "TFLOP/s",
+                             "frac": info.lu_flops_per_step / (main_run["ms_vwall"] * 1e-3) / 1e12 / peak},
         "breakdown_ms": {"lu_update_launches": main_run["ms_update"], "lu_panel_u12_launches": main_run["ms_panel"],
                          "v_step_wall": main_run["ms_vwall"], "x_and_field_wall": main_run["ms_x"],
                          "lu_streams": main_run["lu_streams"]},
@@ -421,7 +508,9 @@ def main():
     if fp64 is not None:
         line["fp64"] = {"steps_per_s": 1000.0 / fp64["ms_per_step"], "ms_per_step": fp64["ms_per_step"],
                         "speedup_mixed_over_fp64": fp64["ms_per_step"] / main_run["ms_per_step"],
-                        "ms_update": fp64["ms_update"], "ms_panel": fp64["ms_panel"],
+                        "ms_update": fp64["ms_update"], "ms_panel": fp64["ms_panel"], "ms_vwall": fp64["ms_vwall"],
+                        "v_solve_frac_fp64_peak": info.lu_flops_per_step / (fp64["ms_vwall"] * 1e-3) / 1e12
+                        / MI355X_PEAK_TFLOPS["fp64"],
                         "update_tflops": _update_flops(npad, 128, nx_total, bool(fp64["panel_pairs"]))
                         / (fp64["ms_update"] * 1e-3) / 1e12,
                         "update_frac_fp64_peak": _update_flops(npad, 128, nx_total, bool(fp64["panel_pairs"]))
@@ -447,7 +536,7 @@ def main():
         bf = run_gpu(cfg, "mixed_bf16x3", args.steps, warm, torch, args.lu_streams, one_step=True)
         nup = bf["update_launches"]
         line["bf16x3"] = {"steps_per_s": 1000.0 / bf["ms_per_step"], "ms_per_step": bf["ms_per_step"],
-                          "ms_update": bf["ms_update"], "ms_panel": bf["ms_panel"],
+                          "ms_update": bf["ms_update"], "ms_panel": bf["ms_panel"], "ms_vwall": bf["ms_vwall"],
                           "update_hbm_frac": (_update_bytes(npad, 128, nx_total, 4, bool(bf["panel_pairs"]))
                                               / (bf["ms_update"] / nup * 1e-3))
                           / (MI355X_PEAK_HBM_GBS * 1e9),
@@ -455,6 +544,28 @@ def main():
         if fp64 is not None:
             line["bf16x3"]["speedup_over_fp64"] = fp64["ms_per_step"] / bf["ms_per_step"]
             line["bf16x3"]["vs_fp64_gpu"] = dict(moment_errors(bf["moments"], fp64["moments"]), steps=bf["n_end"])
+    bfp = None
+    if not args.no_bf16 and args.precision != "mixed_bf16":
+        # plain bf16 operands in the trailing updates (one product), same FP64 refinement
+        bfp = run_gpu(cfg, "mixed_bf16", args.steps, warm, torch, args.lu_streams, one_step=True)
+        nup = bfp["update_launches"]
+        line["bf16"] = {"steps_per_s": 1000.0 / bfp["ms_per_step"], "ms_per_step": bfp["ms_per_step"],
+                        "ms_update": bfp["ms_update"], "ms_panel": bfp["ms_panel"], "ms_vwall": bfp["ms_vwall"],
+                        "update_hbm_frac": (_update_bytes(npad, 128, nx_total, 4, bool(bfp["panel_pairs"]))
+                                            / (bfp["ms_update"] / nup * 1e-3)) / (MI355X_PEAK_HBM_GBS * 1e9),
+                        "refine": {"sweeps": bfp["refine_sweeps"], "resid": bfp["refine_resid"]}}
+        if fp64 is not None:
+            line["bf16"]["speedup_over_fp64"] = fp64["ms_per_step"] / bfp["ms_per_step"]
+            line["bf16"]["vs_fp64_gpu"] = dict(moment_errors(bfp["moments"], fp64["moments"]), steps=bfp["n_end"])
+    if not args.no_golden and args.nx == 256:
+        vs = {}
+        for prec in dict.fromkeys([args.precision, "fp64", "mixed_bf16x3", "mixed_bf16"]):
+            r = golden_check(cfg, prec, torch)
+            if r is None:
+                break
+            vs[prec] = r
+        if vs:
+            line.setdefault("accuracy", {})["vs_oracle_stored_run"] = vs
     if not args.no_banded:
         bd = run_gpu(cfg, "fp64", args.steps, warm, torch, args.lu_streams, banded=True)
         line["banded"] = {"solver": "FP64 batched LU of the harmonic-basis systems restricted to their band "
@@ -464,6 +575,17 @@ def main():
         if fp64 is not None:
             line["banded"]["speedup_over_fp64_lu"] = fp64["ms_per_step"] / bd["ms_per_step"]
             line["banded"]["vs_fp64_lu"] = dict(moment_errors(bd["moments"], fp64["moments"]), steps=bd["n_end"])
+    if not args.no_hessenberg:
+        hs = run_gpu(cfg, "fp64", args.steps, warm, torch, args.lu_streams, vsolver="hessenberg")
+        line["hessenberg"] = {"solver": "harmonic-basis systems in Hessenberg form (one Householder reduction per "
+                                        "discharge at setup, one O(n^2) Givens solve per point and step), FP64",
+                              "steps_per_s": 1000.0 / hs["ms_per_step"], "ms_per_step": hs["ms_per_step"],
+                              "ms_vwall": hs["ms_vwall"], "setup_s": hs["setup_s"]}
+        if fp64 is not None:
+            line["hessenberg"]["speedup_over_fp64_lu"] = fp64["ms_per_step"] / hs["ms_per_step"]
+            line["hessenberg"]["vs_fp64_lu"] = dict(moment_errors(hs["moments"], fp64["moments"]), steps=hs["n_end"])
+    if not args.no_paper_grid:
+        line["paper_grid"] = paper_grid(torch, min(args.steps, 20))
     if not args.no_hybrid:
         line["hybrid"] = run_hybrid(cfg, min(args.steps, 20), 2, torch)
     if not args.no_implicit:
@@ -471,7 +593,7 @@ def main():
         line["implicit"]["semi_implicit_simulated_s_per_wall_s"] = cfg["dt_s"] / (main_run["ms_per_step"] * 1e-3)
     if not args.no_adjoint:
         line["adjoint"] = run_adjoint(torch)
-    if args.ensemble:
+    if not args.no_ensemble:
         line["ensemble"] = run_ensemble(torch)
         line["ensemble"]["point_steps_per_s_single_discharge"] = nx_total * value
     if not args.no_cpu:
@@ -483,6 +605,8 @@ def main():
             acc["vs_oracle_one_step"]["fp64"] = moment_errors(fp64["first_step_moments"], mom1)
         if bf is not None:
             acc["vs_oracle_one_step"]["mixed_bf16x3"] = moment_errors(bf["first_step_moments"], mom1)
+        if bfp is not None:
+            acc["vs_oracle_one_step"]["mixed_bf16"] = moment_errors(bfp["first_step_moments"], mom1)
     print(json.dumps(line), flush=True)
 
 

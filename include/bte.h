@@ -97,7 +97,7 @@ typedef struct {
 } bte_process;
 
 typedef struct {
-  int32_t nx, nr, ntheta, nl;   /* nl must equal ntheta; nx per discharge if n_discharges == 1 */
+  int32_t nx, nr, ntheta, nl;   /* 1 <= nl <= ntheta harmonics; nx per discharge if n_discharges == 1 */
   int32_t v_bc;                 /* bte_vbc                                                      */
   double L_m;                   /* electrode gap                                                */
   double eps_max_eV;            /* speed domain [0, sqrt(2 e eps_max / m_e)]                    */
@@ -254,12 +254,26 @@ bte_status bte_hybrid_step(bte_handle* h, double* F, double* ni, double t_s, voi
  *     and the acceleration operator couples l to l +- 1, so
  *     I - dt (n0 C_h + E A_h) is banded with half-bandwidth 2 Nr - 1; the
  *     batched LU with partial pivoting runs restricted to that band (fill
- *     included) in FP64, between F_h = P_S F and F* = P_O F_h*.  The other
- *     arguments are ignored.  Returns BTE_EUNSUPPORTED when ntheta > 64.
+ *     included) in FP64, between F_h = P_S F and F* = P_O F_h*.  With
+ *     nl < ntheta the operator part of the ordinate system has rank Nr nl and the
+ *     reduction is exact: (I - P_O K P_S)^-1 = I - P_O P_S + P_O (I - K)^-1 P_S
+ *     (T_S T_O = I_nl), so F* = F + P_O (F_h* - F_h) with the Nr nl harmonic
+ *     systems factored.  The other arguments are ignored.  Returns
+ *     BTE_EUNSUPPORTED when ntheta > 64.
+ *   BTE_VSOLVER_HESSENBERG: the same harmonic-basis systems (B - s A_h) u = F_h,
+ *     B = I - dt n0 C_h (block diagonal in l), s = dt E, by their Hessenberg
+ *     form: K = B^-1 A_h is reduced here, once per discharge, by Householder
+ *     similarity to K = Q H Q^T (H upper Hessenberg), and each V step computes
+ *     u = Q (I - s H)^-1 W F_h, W = Q^T B^-1, with one O(n^2) Givens solve per
+ *     point instead of a factorization (the frequency-response form of Laub,
+ *     1981), in FP64.  Setup is on the host, O(n^3) per discharge; the handle
+ *     then holds W, Q and H (3 (Nr nl)^2 doubles per discharge).  A zero
+ *     rotation latches BTE_ESINGULAR.  Other arguments ignored; BTE_EUNSUPPORTED
+ *     when ntheta > 64.
  * The adjoint step always factors the dense ordinate-space systems (it needs
  * the transposed solves).
  * Synchronous (factors the bins).  Errors: BTE_EINVAL, BTE_ESINGULAR, BTE_ENOMEM, BTE_EHIP. */
-typedef enum { BTE_VSOLVER_LU = 0, BTE_VSOLVER_GMRES = 1, BTE_VSOLVER_BANDED = 2 } bte_vsolver;
+typedef enum { BTE_VSOLVER_LU = 0, BTE_VSOLVER_GMRES = 1, BTE_VSOLVER_BANDED = 2, BTE_VSOLVER_HESSENBERG = 3 } bte_vsolver;
 bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E_bound, double bin_scale,
                            int32_t restart, int32_t cycles, double rtol, int32_t factor_precision);
 
@@ -314,15 +328,18 @@ bte_status bte_field_eval(bte_handle* h, const double* F_half, double t_s, bte_f
  *        2 M_v [Nr][Nr], 3 G_v [Nr][Nr], 4 eigenvalues Lambda [Nr], 5 U [Nr][Nr],
  *        6 xhat [sum Nx], 7 moment weights [3][n] (number, energy in eV, k_i),
  *        8 C^(s,b) [n_params][n][n], 9 Q of discharge 0 [Nr][Ntheta][Nx][Nx] (row-major Q_ia),
- *        10 C_h [n][n], 11 A_h [n][n]: the operators of C_ord and A_ord in the harmonic
- *        basis, unknowns ordered l-major (l * Nr + k), so that C_ord = P_O C_h P_S,
+ *        10 C_h [Nr nl][Nr nl], 11 A_h [Nr nl][Nr nl]: the operators of C_ord and A_ord in
+ *        the harmonic basis, unknowns ordered l-major (l * Nr + k), so that C_ord = P_O C_h P_S,
  *        12 T_O [Ntheta][nl] (F[k][a] = sum_l T_O[a][l] F_h[l][k]),
  *        13 T_S [nl][Ntheta] (F_h[l][k] = sum_a T_S[l][a] F[k][a]).
  * host_out must hold the documented number of doubles. */
 bte_status bte_get_operator(bte_handle* h, int32_t which, double* host_out);
 
 /* The same operators (which = 0..13) assembled on the host from a configuration,
- * without a device or handle (synchronous).  Used to verify the assembly. */
+ * without a device or handle (synchronous).  Used to verify the assembly.  Also
+ * the Hessenberg form of discharge 0 (BTE_VSOLVER_HESSENBERG, n = Nr nl, n0 and
+ * dt of the configuration): 14 W = Q^T B^-1 [n][n], 15 Q [n][n] (orthogonal),
+ * 16 H [n][n] (upper Hessenberg, row-major), with B^-1 A_h = Q H Q^T. */
 bte_status bte_host_operator(const bte_config* cfg, int32_t which, double* host_out);
 
 /* Verification: forms and factors (I - dt (n0 C + E A)) at every point with the

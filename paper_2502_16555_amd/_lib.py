@@ -54,6 +54,7 @@ class bte_info(C.Structure):
 VSOLVER_LU = 0
 VSOLVER_GMRES = 1
 VSOLVER_BANDED = 2
+VSOLVER_HESSENBERG = 3
 TUNE_LU_STREAMS = 0
 TUNE_UPDATE_KC = 1
 TUNE_FORM_XPB = 2

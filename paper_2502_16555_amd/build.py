@@ -16,8 +16,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libbte.so")
-SOURCES = ["assemble.cpp", "bte_api.cpp", "kernels_x.hip", "kernels_lu.hip", "kernels_update.hip",
-           "kernels_refine.hip", "kernels_gmres.hip", "kernels_ion.hip", "kernels_implicit.hip"]
+SOURCES = ["assemble.cpp", "hessenberg.cpp", "bte_api.cpp", "kernels_x.hip", "kernels_lu.hip", "kernels_update.hip",
+           "kernels_refine.hip", "kernels_gmres.hip", "kernels_ion.hip", "kernels_implicit.hip", "kernels_hess.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -373,14 +373,15 @@ void gauss_legendre(int n, std::vector<double>* x, std::vector<double>* w) {
 void assemble(const AssemblyInput& in, HostOps* out) {
   HostOps& H = *out;
   const int nr = in.nr, nth = in.ntheta, nl = in.nl;
-  if (nr < 4 || nth < 2 || nl != nth || nth % 2 != 0)
-    throw std::runtime_error("need nr >= 4, even ntheta >= 2 and nl == ntheta");
+  if (nr < 4 || nth < 2 || nl < 1 || nl > nth || nth % 2 != 0)
+    throw std::runtime_error("need nr >= 4, even ntheta >= 2 and 1 <= nl <= ntheta");
   if (in.proc.empty()) throw std::runtime_error("no collision process");
   const int n = nr * nth;
+  const int nhm = nr * nl;   // harmonic unknowns
   const int nproc = static_cast<int>(in.proc.size());
   const int nbins = static_cast<int>(in.bin_edges_eV.size()) - 1;
   if (nbins < 1) throw std::runtime_error("need at least one energy bin");
-  H.nr = nr; H.nth = nth; H.n = n; H.n_bins = nbins; H.n_params = nproc * nbins;
+  H.nr = nr; H.nth = nth; H.nl = nl; H.n = n; H.nh = nhm; H.n_bins = nbins; H.n_params = nproc * nbins;
   H.vmax = speed_of(in.eps_max_eV);
   Spline sp = make_spline(nr, H.vmax, in.v_bc);
   H.knots = sp.t;
@@ -504,7 +505,7 @@ void assemble(const AssemblyInput& in, HostOps* out) {
         const double x = s * X[q * nl + l];
         if (x == 0.0) continue;
         for (int k = 0; k < nr; ++k)
-          for (int j = 0; j < nr; ++j) Out[(size_t)(q * nr + k) * n + l * nr + j] += R[k * nr + j] * x;
+          for (int j = 0; j < nr; ++j) Out[(size_t)(q * nr + k) * nhm + l * nr + j] += R[k * nr + j] * x;
       }
   };
   H.TO = TO;
@@ -512,7 +513,7 @@ void assemble(const AssemblyInput& in, HostOps* out) {
 
   // --- acceleration operator -------------------------------------------------------
   H.Aord.assign((size_t)n * n, 0.0);
-  H.Ah.assign((size_t)n * n, 0.0);
+  H.Ah.assign((size_t)nhm * nhm, 0.0);
   {
     std::vector<double> R1 = matmul(Minv, D1, nr, nr, nr), R0 = matmul(Minv, D0, nr, nr, nr);
     kron_add(H.Aord, R1, th_a, kECharge / kMElectron);
@@ -533,7 +534,7 @@ void assemble(const AssemblyInput& in, HostOps* out) {
   for (int b = 0; b <= nbins; ++b) edges_v[b] = speed_of(in.bin_edges_eV[b]);
   H.Csb.assign((size_t)H.n_params * n * n, 0.0);
   H.Cord.assign((size_t)n * n, 0.0);
-  H.Ch.assign((size_t)n * n, 0.0);
+  H.Ch.assign((size_t)nhm * nhm, 0.0);
   std::vector<double> ki(nr, 0.0);
   for (int s = 0; s < nproc; ++s) {
     const Process& P = in.proc[s];

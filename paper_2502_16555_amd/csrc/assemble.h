@@ -40,7 +40,7 @@ struct XOps {
 };
 
 struct HostOps {
-  int nr = 0, nth = 0, n = 0, n_params = 0, n_bins = 1;
+  int nr = 0, nth = 0, nl = 0, n = 0, nh = 0, n_params = 0, n_bins = 1;   // n = nr nth, nh = nr nl
   double vmax = 0.0;
   std::vector<double> knots;
   std::vector<double> mu, w;          // GL ordinates
@@ -53,8 +53,9 @@ struct HostOps {
   // harmonic-space operators, unknowns ordered l-major (index l * nr + k): the
   // collision operator is block diagonal in l and the acceleration operator
   // couples l to l +- 1, so both are banded with half-bandwidth 2 nr - 1
-  std::vector<double> Ch, Ah;         // [n][n]
-  std::vector<double> TO, TS;         // [nth][nl] and [nl][nth] (T_S T_O = I for nl = nth)
+  std::vector<double> Ch, Ah;         // [nh][nh]
+  std::vector<double> TO, TS;         // [nth][nl] and [nl][nth] (T_S T_O = I_nl: Gauss-Legendre
+                                      // quadrature is exact for Y_q Y_l, q + l <= 2 nl - 2 < 2 nth)
   std::vector<double> mom;            // [3][n] number, energy (eV), ionization weights
   std::vector<XOps> xops;             // per discharge
 };

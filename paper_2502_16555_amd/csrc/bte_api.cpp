@@ -10,9 +10,11 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "assemble.h"
+#include "hessenberg.h"
 #include "internal.h"
 
 static_assert(bte::kIonScratchDoubles == BTE_ION_SCRATCH_DOUBLES, "ion scratch size");
@@ -75,6 +77,11 @@ struct bte_handle {
   // preconditioner (a DevOps over nd * nbins matrices) and the GMRES workspace
   bool krylov = false;
   bool banded = false;         // V solves in the harmonic basis, banded LU
+  bool hess = false;           // V solves in the harmonic basis, Hessenberg form
+  int hess_n = 0, hess_ld = 0;
+  double *d_hW = nullptr, *d_hQ = nullptr, *d_hH = nullptr;   // [nd][n][n] each
+  size_t* d_hoff = nullptr;                                   // [nd] offsets d n^2
+  std::vector<size_t> hoff_host;
   ImplicitWs iw;               // fully implicit step
   DevOps bd;                   // its factors (FP64) and harmonic operators
   double* d_TO = nullptr;
@@ -89,6 +96,7 @@ struct bte_handle {
     kallocs.clear();
     krylov = false;
     banded = false;
+    hess = false;
   }
   template <typename T>
   T* kalloc(size_t count) {
@@ -442,10 +450,25 @@ void v_solve_banded(bte_handle* h, double* F, hipStream_t s) {
   DevOps& d = h->d;
   DevOps& b = h->bd;
   b.E = d.E;   // the field of this step
-  bte::launch_to_harm(d, F, h->d_TS, d.B, s);
+  const int nl = h->cfg.nl;
+  bte::launch_to_harm(d, nl, b.npad, F, h->d_TS, d.B, s);
   bte::launch_lu_factor(b, 0, s, h->timing ? &h->lu_timer[0] : nullptr);
   bte::launch_lu_solve_mapped(b, 0, false, nullptr, nullptr, d.nx_total, d.B, d.X, false, false, s);
-  bte::launch_from_harm(d, d.X, h->d_TO, F, s);
+  bte::launch_from_harm(d, nl, b.npad, d.X, d.B, h->d_TO, F, s);
+}
+
+// V(dt) in the harmonic basis by the Hessenberg form of every discharge:
+// Fh = P_S F, u = Q_d (I - dt E H_d)^-1 W_d Fh, back to ordinates.
+void v_solve_hess(bte_handle* h, double* F, hipStream_t s) {
+  DevOps& d = h->d;
+  const int nl = h->cfg.nl, n = h->hess_n, ld = h->hess_ld;
+  bte::launch_to_harm(d, nl, ld, F, h->d_TS, d.B, s);
+  for (int q = 0; q < d.nd; ++q)
+    bte::launch_mat_apply(h->d_hW + h->hoff_host[q], d.B, d.X, n, ld, h->x_off[q], h->nx_per[q], s);
+  bte::launch_hess_solve(d, h->d_hH, h->d_hoff, n, ld, d.X, d.R, s);
+  for (int q = 0; q < d.nd; ++q)
+    bte::launch_mat_apply(h->d_hQ + h->hoff_host[q], d.R, d.X, n, ld, h->x_off[q], h->nx_per[q], s);
+  bte::launch_from_harm(d, nl, ld, d.X, d.B, h->d_TO, F, s);
 }
 
 // V(dt) in place on F (field already in d.E).  transpose: solve with A^T.
@@ -460,6 +483,10 @@ void v_solve(bte_handle* h, double* F, bool transpose, hipStream_t s, bool allow
   }
   if (allow_krylov && h->banded && !transpose) {
     v_solve_banded(h, F, s);
+    return;
+  }
+  if (allow_krylov && h->hess && !transpose) {
+    v_solve_hess(h, F, s);
     return;
   }
   bte::launch_pad_rows(d, F, d.B, s);
@@ -1192,17 +1219,59 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
     h->drop_krylov();
     return BTE_OK;
   }
-  if (kind == BTE_VSOLVER_BANDED) {
-    // the transforms stage one point and the nl x nl transform in LDS
-    if (h->cfg.nl != h->cfg.ntheta || h->cfg.ntheta > 64) return BTE_EUNSUPPORTED;
+  if (kind == BTE_VSOLVER_HESSENBERG) {
+    // the transforms stage one point and the nl x ntheta transform in LDS
+    if (h->cfg.ntheta > 64) return BTE_EUNSUPPORTED;
     try {
       HIP_OK(hipSetDevice(h->device));
       HIP_OK(hipDeviceSynchronize());
       h->drop_krylov();
       const DevOps& d = h->d;
       const bte::HostOps& H = h->host;
-      const int n = d.n, nxt = d.nx_total, np = d.npad;
+      const int n = H.nh, nd = d.nd;
+      const size_t nn = (size_t)n * n;
+      const int nthreads = static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+      h->d_hW = h->kalloc<double>(nn * nd);
+      h->d_hQ = h->kalloc<double>(nn * nd);
+      h->d_hH = h->kalloc<double>(nn * nd);
+      h->hoff_host.assign(nd, 0);
+      for (int q = 0; q < nd; ++q) {
+        bte::HessForm f;
+        bte::hessenberg_setup(H, h->n0_host[q], h->cfg.dt_s, nthreads, &f);
+        h->hoff_host[q] = nn * q;
+        HIP_OK(hipMemcpy(h->d_hW + nn * q, f.W.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h->d_hQ + nn * q, f.Q.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h->d_hH + nn * q, f.Hc.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+      }
+      h->d_hoff = h->kalloc<size_t>(nd);
+      HIP_OK(hipMemcpy(h->d_hoff, h->hoff_host.data(), nd * sizeof(size_t), hipMemcpyHostToDevice));
+      h->d_TO = h->kalloc<double>(H.TO.size());
+      h->d_TS = h->kalloc<double>(H.TS.size());
+      HIP_OK(hipMemcpy(h->d_TO, H.TO.data(), H.TO.size() * sizeof(double), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(h->d_TS, H.TS.data(), H.TS.size() * sizeof(double), hipMemcpyHostToDevice));
+      h->hess_n = n;
+      h->hess_ld = ((n + bte::kNB - 1) / bte::kNB) * bte::kNB;
+      h->hess = true;
+      return BTE_OK;
+    } catch (const std::exception& e) {
+      h->drop_krylov();
+      return map_exc(e);
+    }
+  }
+  if (kind == BTE_VSOLVER_BANDED) {
+    // the transforms stage one point and the nl x ntheta transform in LDS
+    if (h->cfg.ntheta > 64) return BTE_EUNSUPPORTED;
+    try {
+      HIP_OK(hipSetDevice(h->device));
+      HIP_OK(hipDeviceSynchronize());
+      h->drop_krylov();
+      const DevOps& d = h->d;
+      const bte::HostOps& H = h->host;
+      const int n = H.nh, nxt = d.nx_total;   // harmonic unknowns nr * nl
+      const int np = ((n + bte::kNB - 1) / bte::kNB) * bte::kNB;
       DevOps b = d;
+      b.n = n;
+      b.npad = np;
       // operators by columns (the formation kernel reads columns contiguously)
       std::vector<double> T1((size_t)n * n), T2((size_t)n * n);
       for (int i = 0; i < n; ++i)
@@ -1464,6 +1533,18 @@ bte_status bte_host_operator(const bte_config* cfg, int32_t which, double* host_
     bte::AssemblyInput in = make_input(cfg);
     bte_handle tmp;
     bte::assemble(in, &tmp.host);
+    if (which >= 14 && which <= 16) {
+      bte::HessForm f;
+      const int nthreads = static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+      bte::hessenberg_setup(tmp.host, cfg->n0_per[0], cfg->dt_s, nthreads, &f);
+      const int n = f.n;
+      if (which == 14) std::memcpy(host_out, f.W.data(), f.W.size() * sizeof(double));
+      if (which == 15) std::memcpy(host_out, f.Q.data(), f.Q.size() * sizeof(double));
+      if (which == 16)
+        for (int r = 0; r < n; ++r)
+          for (int c = 0; c < n; ++c) host_out[(size_t)r * n + c] = f.Hc[(size_t)c * n + r];
+      return BTE_OK;
+    }
     return bte_get_operator(&tmp, which, host_out);
   } catch (const std::exception& e) {
     return map_exc(e);

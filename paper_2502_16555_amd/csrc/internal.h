@@ -125,6 +125,14 @@ void launch_gmres_arnoldi(const DevOps& d, const GmresOps& q, int j, hipStream_t
 void launch_gmres_combine(const DevOps& d, const GmresOps& q, hipStream_t s);
 void launch_gmres_status(const DevOps& d, const GmresOps& q, hipStream_t s);
 
+// ---- Hessenberg form of the V systems (kernels_hess.hip) ------------------------
+// Out[x] = M In[x] for points x0 .. x0+nx-1 (M row-major n x n, rows of length ld).
+void launch_mat_apply(const double* M, const double* In, double* Out, int n, int ld, int x0, int nx, hipStream_t s);
+// (I - dt E_x H_d) Z[x] = Y[x] for every point (H_d column-major at Hc + h_off[d]);
+// a zero rotation latches kStSingular, a non-finite solution kStNonFinite.
+void launch_hess_solve(const DevOps& d, const double* Hc, const size_t* h_off, int n, int ld, const double* Y,
+                       double* Z, hipStream_t s);
+
 // ---- heavies' update (kernels_ion.hip) ----------------------------------------
 // n_i^{n+1} of eq. fluid_step for every discharge, with E^n already in d.ion_E.
 void launch_ion_update(const DevOps& d, const double* F, const double* ni_in, double* ni_out, hipStream_t s);
@@ -209,9 +217,12 @@ void launch_lu_solve_mapped(const DevOps& f, int precision, bool transpose, cons
                             hipStream_t s);
 // FP32 -> FP16 copy of n elements (factor storage for preconditioning solves).
 void launch_to_half(const float* src, void* dst, size_t n, hipStream_t s);
-// Ordinate -> harmonic coefficients (P_S, l-major, padded rows) and back (P_O).
-void launch_to_harm(const DevOps& d, const double* F, const double* TS, double* Bh, hipStream_t s);
-void launch_from_harm(const DevOps& d, const double* Xh, const double* TO, double* F, hipStream_t s);
+// Ordinate -> harmonic coefficients (P_S, l-major, rows of npad_h, l < nl) and
+// back: F = P_O Xh for nl = nth, F += P_O (Xh - Bh) for nl < nth.
+void launch_to_harm(const DevOps& d, int nl, int npad_h, const double* F, const double* TS, double* Bh,
+                    hipStream_t s);
+void launch_from_harm(const DevOps& d, int nl, int npad_h, const double* Xh, const double* Bh, const double* TO,
+                      double* F, hipStream_t s);
 // Copy F (rows of n) into padded rows of npad and back.
 void launch_pad_rows(const DevOps& d, const double* F, double* Bp, hipStream_t s);
 void launch_unpad_rows(const DevOps& d, const double* Bp, double* F, hipStream_t s);

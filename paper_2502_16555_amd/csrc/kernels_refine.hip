@@ -34,21 +34,25 @@ __global__ void k_unpad(const double* __restrict__ Bp, double* __restrict__ F, i
   }
 }
 
-// Ordinates <-> harmonics of every point (nl = nth): harmonic coefficients
+// Ordinates <-> harmonics of every point: harmonic coefficients
 // Bh[l * nr + k] = sum_a TS[l][a] F[k][a] (P_S of eq. (proj_ops), l-major, padded
-// rows of npad) and back F[k][a] = sum_l TO[a][l] Xh[l * nr + k] (P_O).
+// rows of npad, l < nl) and back.  With nl = nth, P_O P_S = I and the way back is
+// F[k][a] = sum_l TO[a][l] Xh[l * nr + k] (P_O).  With nl < nth the operator part
+// of the V system has rank nr nl, (I - P_O K P_S)^-1 = I - P_O P_S + P_O (I - K)^-1 P_S
+// (T_S T_O = I_nl), so the way back adds the solution's harmonic change to the
+// state: F[k][a] += sum_l TO[a][l] (Xh - Bh)[l * nr + k].
 __global__ __launch_bounds__(256) void k_to_harm(const double* __restrict__ F, const double* __restrict__ TS,
-                                                 double* __restrict__ Bh, int nr, int nth, int npad) {
+                                                 double* __restrict__ Bh, int nr, int nth, int nl, int npad) {
   extern __shared__ double sh[];
   const int n = nr * nth, x = blockIdx.x;
   double* sF = sh;
   double* sT = sh + n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) sF[i] = F[(size_t)x * n + i];
-  for (int i = threadIdx.x; i < nth * nth; i += blockDim.x) sT[i] = TS[i];
+  for (int i = threadIdx.x; i < nl * nth; i += blockDim.x) sT[i] = TS[i];
   __syncthreads();
   for (int o = threadIdx.x; o < npad; o += blockDim.x) {
     double v = 0.0;
-    if (o < n) {
+    if (o < nr * nl) {
       const int l = o / nr, k = o % nr;
       for (int a = 0; a < nth; ++a) v += sT[l * nth + a] * sF[k * nth + a];
     }
@@ -56,20 +60,23 @@ __global__ __launch_bounds__(256) void k_to_harm(const double* __restrict__ F, c
   }
 }
 
-__global__ __launch_bounds__(256) void k_from_harm(const double* __restrict__ Xh, const double* __restrict__ TO,
-                                                   double* __restrict__ F, int nr, int nth, int npad) {
+__global__ __launch_bounds__(256) void k_from_harm(const double* __restrict__ Xh, const double* __restrict__ Bh,
+                                                   const double* __restrict__ TO, double* __restrict__ F, int nr,
+                                                   int nth, int nl, int npad) {
   extern __shared__ double sh[];
-  const int n = nr * nth, x = blockIdx.x;
+  const int n = nr * nth, nhm = nr * nl, x = blockIdx.x;
+  const bool reduced = nl < nth;
   double* sX = sh;
-  double* sT = sh + n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) sX[i] = Xh[(size_t)x * npad + i];
-  for (int i = threadIdx.x; i < nth * nth; i += blockDim.x) sT[i] = TO[i];
+  double* sT = sh + nhm;
+  for (int i = threadIdx.x; i < nhm; i += blockDim.x)
+    sX[i] = reduced ? Xh[(size_t)x * npad + i] - Bh[(size_t)x * npad + i] : Xh[(size_t)x * npad + i];
+  for (int i = threadIdx.x; i < nth * nl; i += blockDim.x) sT[i] = TO[i];
   __syncthreads();
   for (int o = threadIdx.x; o < n; o += blockDim.x) {
     const int k = o / nth, a = o % nth;
     double v = 0.0;
-    for (int l = 0; l < nth; ++l) v += sT[a * nth + l] * sX[l * nr + k];
-    F[(size_t)x * n + o] = v;
+    for (int l = 0; l < nl; ++l) v += sT[a * nl + l] * sX[l * nr + k];
+    F[(size_t)x * n + o] = reduced ? F[(size_t)x * n + o] + v : v;
   }
 }
 
@@ -376,14 +383,16 @@ __global__ void k_adjoint_reduce(const double* __restrict__ pscal, const double*
 
 }  // namespace
 
-void launch_to_harm(const DevOps& d, const double* F, const double* TS, double* Bh, hipStream_t s) {
-  const size_t sh = (size_t)(d.n + d.nth * d.nth) * sizeof(double);
-  k_to_harm<<<d.nx_total, 256, sh, s>>>(F, TS, Bh, d.nr, d.nth, d.npad);
+void launch_to_harm(const DevOps& d, int nl, int npad_h, const double* F, const double* TS, double* Bh,
+                    hipStream_t s) {
+  const size_t sh = (size_t)(d.n + nl * d.nth) * sizeof(double);
+  k_to_harm<<<d.nx_total, 256, sh, s>>>(F, TS, Bh, d.nr, d.nth, nl, npad_h);
 }
 
-void launch_from_harm(const DevOps& d, const double* Xh, const double* TO, double* F, hipStream_t s) {
-  const size_t sh = (size_t)(d.n + d.nth * d.nth) * sizeof(double);
-  k_from_harm<<<d.nx_total, 256, sh, s>>>(Xh, TO, F, d.nr, d.nth, d.npad);
+void launch_from_harm(const DevOps& d, int nl, int npad_h, const double* Xh, const double* Bh, const double* TO,
+                      double* F, hipStream_t s) {
+  const size_t sh = (size_t)(d.nr * nl + nl * d.nth) * sizeof(double);
+  k_from_harm<<<d.nx_total, 256, sh, s>>>(Xh, Bh, TO, F, d.nr, d.nth, nl, npad_h);
 }
 
 void launch_pad_rows(const DevOps& d, const double* F, double* Bp, hipStream_t s) {

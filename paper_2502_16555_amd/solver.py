@@ -132,9 +132,11 @@ class Solver:
     def set_vsolver(self, kind: str = "lu", n_bins: int = 32, E_bound: float = 0.0, bin_scale: float = 0.0,
                     restart: int = 20, cycles: int = 2, rtol: float = 1e-12, factor_precision: str = "mixed_fp32"):
         """Select the velocity-space solver: "lu" (batched factorization), "gmres"
-        (restarted GMRES with the field-binned preconditioner, factored here) or
-        "banded" (banded LU of the harmonic-basis systems)."""
-        k = {"lu": _lib.VSOLVER_LU, "gmres": _lib.VSOLVER_GMRES, "banded": _lib.VSOLVER_BANDED}[kind]
+        (restarted GMRES with the field-binned preconditioner, factored here),
+        "banded" (banded LU of the harmonic-basis systems) or "hessenberg" (the
+        harmonic-basis systems in Hessenberg form, reduced here)."""
+        k = {"lu": _lib.VSOLVER_LU, "gmres": _lib.VSOLVER_GMRES, "banded": _lib.VSOLVER_BANDED,
+             "hessenberg": _lib.VSOLVER_HESSENBERG}[kind]
         check(self.lib.bte_set_vsolver(self.h, k, int(n_bins), float(E_bound), float(bin_scale), int(restart),
                                        int(cycles), float(rtol), _lib.PRECISION[factor_precision]),
               "bte_set_vsolver")

@@ -60,9 +60,9 @@ def test_bad_configs_are_rejected():
     bad = dict(cfg, ntheta=7, nl=7)          # odd number of ordinates
     with pytest.raises(BteError):
         host_operator(bad, 2, 16 * 16)
-    bad = dict(cfg, nl=4)                    # nl != ntheta
-    with pytest.raises(BteError):
-        host_operator(bad, 2, 16 * 16)
+    for nl in (0, 9):                        # nl outside 1..ntheta
+        with pytest.raises(BteError):
+            host_operator(dict(cfg, nl=nl), 2, 16 * 16)
 
 
 CASES = {
@@ -71,6 +71,9 @@ CASES = {
                                                              kinds=("elastic", "excitation", "ionization"), n_bins=3),
     "natural_bc": lambda: dict(workloads.small_config(nx=5, nr=7, nth=4, kinds=("elastic", "ionization")),
                                v_bc="natural"),
+    # fewer harmonics than ordinates (the paper's timed runs use Nl = 3 with Ntheta = 16)
+    "reduced_nl": lambda: dict(workloads.small_config(nx=6, nr=8, nth=8, kinds=("elastic", "excitation",
+                                                                                "ionization"), n_bins=2), nl=3),
 }
 
 
@@ -123,19 +126,19 @@ def test_harmonic_operators_are_banded_and_match_ordinates(case):
     from paper_2502_16555_amd import host_operator
     cfg = CASES[case]()
     ops = oracle.build_operators(cfg)
-    nr, nth = ops.nr, ops.nth
-    n = nr * nth
-    Ch = host_operator(cfg, 10, n * n).reshape(n, n)
-    Ah = host_operator(cfg, 11, n * n).reshape(n, n)
-    TO = host_operator(cfg, 12, nth * nth).reshape(nth, nth)
-    TS = host_operator(cfg, 13, nth * nth).reshape(nth, nth)
-    assert np.abs(TS @ TO - np.eye(nth)).max() < 1e-12
+    nr, nth, nl = ops.nr, ops.nth, ops.nl
+    n, nh = nr * nth, nr * nl
+    Ch = host_operator(cfg, 10, nh * nh).reshape(nh, nh)
+    Ah = host_operator(cfg, 11, nh * nh).reshape(nh, nh)
+    TO = host_operator(cfg, 12, nth * nl).reshape(nth, nl)
+    TS = host_operator(cfg, 13, nl * nth).reshape(nl, nth)
+    assert np.abs(TS @ TO - np.eye(nl)).max() < 1e-12
     # P_S: ordinate index k * nth + a -> harmonic index l * nr + k
-    PS = np.zeros((n, n))
-    PO = np.zeros((n, n))
+    PS = np.zeros((nh, n))
+    PO = np.zeros((n, nh))
     for k in range(nr):
         for a in range(nth):
-            for l in range(nth):
+            for l in range(nl):
                 PS[l * nr + k, k * nth + a] = TS[l, a]
                 PO[k * nth + a, l * nr + k] = TO[a, l]
 
@@ -144,8 +147,38 @@ def test_harmonic_operators_are_banded_and_match_ordinates(case):
 
     assert rel(PO @ Ch @ PS, ops.Cord) < 5e-12
     assert rel(PO @ Ah @ PS, ops.Aord) < 1e-12
-    i, j = np.indices((n, n))
+    i, j = np.indices((nh, nh))
     outside = np.abs(i - j) > 2 * nr - 1
     assert not Ch[outside].any() and not Ah[outside].any()
     # C_h does not couple different l at all
     assert not Ch[(i // nr) != (j // nr)].any()
+
+
+@pytest.mark.parametrize("case", ["three_processes_binned", "reduced_nl"])
+def test_hessenberg_form_of_the_harmonic_systems(case):
+    """The host setup of the Hessenberg V solver: with B = I - dt n0 C_h and
+    K = B^-1 A_h (harmonic basis), Q is orthogonal, H is upper Hessenberg with
+    exact zeros below the subdiagonal, Q H Q^T = K and W = Q^T B^-1, so that
+    Q (I - s H)^-1 W b solves (B - s A_h) u = b for any s = dt E."""
+    from paper_2502_16555_amd import host_operator
+    cfg = CASES[case]()
+    nr, nl = cfg["nr"], cfg["nl"]
+    n = nr * nl
+    Ch = host_operator(cfg, 10, n * n).reshape(n, n)
+    Ah = host_operator(cfg, 11, n * n).reshape(n, n)
+    W = host_operator(cfg, 14, n * n).reshape(n, n)
+    Q = host_operator(cfg, 15, n * n).reshape(n, n)
+    Hm = host_operator(cfg, 16, n * n).reshape(n, n)
+    B = np.eye(n) - cfg["dt_s"] * cfg["n0_m3"] * Ch
+    K = np.linalg.solve(B, Ah)
+    assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-13
+    assert not np.tril(Hm, -2).any()
+    assert np.abs(Q @ Hm @ Q.T - K).max() < 1e-12 * np.abs(K).max()
+    assert np.abs(W - Q.T @ np.linalg.inv(B)).max() < 1e-12 * np.abs(W).max()
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(n)
+    for E in (0.0, 7e3, -1.5e4):
+        s = cfg["dt_s"] * E
+        u = Q @ np.linalg.solve(np.eye(n) - s * Hm, W @ b)
+        ref = np.linalg.solve(B - s * Ah, b)
+        assert np.abs(u - ref).max() < 1e-11 * np.abs(ref).max(), E

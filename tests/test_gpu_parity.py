@@ -76,6 +76,10 @@ CASES = {
 BANDED_CASES = {
     "wide_band": lambda: workloads.small_config(nx=5, nr=8, nth=48, kinds=("elastic", "excitation", "ionization"),
                                                 E=1e4, field_kind="rf"),
+    # fewer harmonics than ordinates: Nr Nl = 36 harmonic unknowns, n = 192 ordinate unknowns
+    "reduced_nl": lambda: dict(workloads.small_config(nx=5, nr=12, nth=16, kinds=("elastic", "excitation",
+                                                                                  "ionization"),
+                                                      E=1.2e4, field_kind="rf"), nl=3),
 }
 
 
@@ -144,6 +148,7 @@ FULL_SIZE = {
     "krylov": ("fp64", dict(n_bins=128, bin_scale=100.0, restart=12, cycles=3, rtol=1e-12,
                             factor_precision="mixed_fp32"), 1e-9),
     "banded": ("fp64", "banded", 1e-10),
+    "hessenberg": ("fp64", "hessenberg", 1e-10),
 }
 
 
@@ -161,8 +166,8 @@ def test_full_size_substeps_at_sampled_points(torch, variant):
     cfg = workloads.config("C2")
     ops = oracle.build_operators(cfg)
     s = solver(cfg, precision=prec)
-    if vsolver == "banded":
-        s.set_vsolver("banded")
+    if vsolver in ("banded", "hessenberg"):
+        s.set_vsolver(vsolver)
     elif vsolver is not None:
         s.set_vsolver("gmres", **vsolver)
     ne = workloads.density_profile(ops.xhat, cfg["ic"]["ne_peak"])
@@ -541,9 +546,9 @@ def _golden_run(torch, name, n_file_steps, mode, tol):
     sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
     import make_golden
     assert str(g["config_hash"]) == make_golden.config_hash(cfg), f"{name} workload changed since the golden run"
-    s = solver(cfg, precision="fp64" if mode == "banded" else mode)
-    if mode == "banded":
-        s.set_vsolver("banded")
+    s = solver(cfg, precision="fp64" if mode in ("banded", "hessenberg") else mode)
+    if mode in ("banded", "hessenberg"):
+        s.set_vsolver(mode)
     ne = workloads.density_profile(s.xhat(), cfg["ic"]["ne_peak"])
     Fg = s.initial_state(cuda(torch, ne), cfg["ic"]["Te_eV"])
     every = int(g["every"])
@@ -567,7 +572,7 @@ def _golden_run(torch, name, n_file_steps, mode, tol):
     s.close()
 
 
-GOLDEN_MODES = ["fp64", "mixed_fp32", "mixed_bf16x3", "mixed_bf16", "banded"]
+GOLDEN_MODES = ["fp64", "mixed_fp32", "mixed_bf16x3", "mixed_bf16", "banded", "hessenberg"]
 
 
 @pytest.mark.parametrize("mode", GOLDEN_MODES)
@@ -589,7 +594,7 @@ def test_c1_golden_cycle(torch, mode):
     _golden_run(torch, "C1", 1000, mode, 2e-10)
 
 
-@pytest.mark.parametrize("mode", [m for m in GOLDEN_MODES if m != "banded"])
+@pytest.mark.parametrize("mode", [m for m in GOLDEN_MODES if m not in ("banded", "hessenberg")])
 def test_c2_golden_run(torch, mode):
     """The benchmark workload itself (Nx=256, Nr=64, Ntheta=32: 256 systems of
     order 2048 per step) for the first 100 steps of the RF cycle against the
@@ -904,7 +909,7 @@ def test_krylov_vstep_matches_oracle(torch, case, fprec):
     s.close()
 
 
-@pytest.mark.parametrize("case", ["ragged", "panels", "panels4", "wide_band"])
+@pytest.mark.parametrize("case", ["ragged", "panels", "panels4", "wide_band", "reduced_nl"])
 def test_banded_vstep_matches_oracle(torch, case):
     """The V step solved in the harmonic basis by the banded LU (half-bandwidth
     2 Nr - 1 of the l-major ordering, fill of the interchanges included) against
@@ -927,6 +932,94 @@ def test_banded_vstep_matches_oracle(torch, case):
     Fd2 = cuda(torch, F)
     s.vstep(Fd2, cuda(torch, E))
     assert np.array_equal(Fd2.cpu().numpy(), Fd.cpu().numpy())
+    s.close()
+
+
+def paper_grid_config(nx=100):
+    """The grid of the paper's timed semi-implicit runs (table of the hybrid
+    solver's performance): Nr = 64, Ntheta = 16, Nl = 3, Nx = 100, with the
+    realistic RF physics of the other workloads."""
+    cfg = workloads.config("C1")
+    return dict(cfg, nx=nx, nx_per=[nx], ntheta=16, nl=3)
+
+
+@pytest.mark.parametrize("prec,vsolver", [("fp64", "lu"), ("mixed_fp32", "lu"), ("fp64", "banded"),
+                                          ("fp64", "hessenberg")])
+def test_reduced_harmonics_at_paper_grid(torch, prec, vsolver):
+    """Nl = 3 < Ntheta = 16 at the paper's timed grid (n = 1024 ordinate unknowns,
+    Nr Nl = 192 harmonic ones): the dense LU of the ordinate systems and the
+    exact reduction to the harmonic systems (I - P_O P_S + P_O (I - K)^-1 P_S)
+    against the oracle's direct solves at sampled points, with the field at its
+    RF peak, then five full steps against the oracle at every point."""
+    cfg = paper_grid_config()
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg, precision=prec)
+    if vsolver != "lu":
+        s.set_vsolver(vsolver)
+    rng = np.random.default_rng(41)
+    ne = workloads.density_profile(ops.xhat, cfg["ic"]["ne_peak"])
+    F = S.initial_state(ops, ne, cfg["ic"]["Te_eV"]) * (1.0 + 0.1 * rng.standard_normal((ops.nx, ops.nr, ops.nth)))
+    E = cfg["field"]["E0"] * (1.0 + 0.5 * ops.xhat)
+    Fv = cuda(torch, F)
+    s.vstep(Fv, cuda(torch, E))
+    code, sweeps, resid = s.status()
+    assert code == 0, (code, sweeps, resid)
+    xs = [0, 1, 50, 98, 99]
+    ref = S.v_step(ops, F, E, xs=xs)
+    got = Fv.cpu().numpy()
+    for x in xs:
+        close(got[x], ref[x], 1e-10, f"V(dt) at x = {x}")
+    F0 = S.initial_state(ops, ne, cfg["ic"]["Te_eV"])
+    Fg, Fo = cuda(torch, F0), F0
+    t0 = 0.2 * cfg["T_rf_s"]
+    for k in range(5):
+        s.step(Fg, t0 + k * ops.dt)
+        Fo = S.step(ops, Fo, t0 + k * ops.dt)
+    assert s.status()[0] == 0
+    close(Fg.cpu().numpy(), Fo, 1e-10, "five steps")
+    s.close()
+
+
+@pytest.mark.parametrize("case", ["ragged", "panels", "panels4", "wide_band", "reduced_nl"])
+def test_hessenberg_vstep_matches_oracle(torch, case):
+    """The V step by the Hessenberg form of the harmonic-basis systems (one
+    Householder reduction per discharge at setup, one Givens solve per point)
+    against the oracle's dense ordinate-space solves, fields up to 2e4 V/m of
+    either sign, ragged sizes, a wide band and Nl < Ntheta."""
+    cfg = BANDED_CASES[case]() if case in BANDED_CASES else CASES[case]()
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg, precision="fp64")
+    s.set_vsolver("hessenberg")
+    F = _state(ops, 3)
+    rng = np.random.default_rng(5)
+    E = rng.uniform(-2e4, 2e4, size=ops.nx)
+    Fh = cuda(torch, F)
+    s.vstep(Fh, cuda(torch, E))
+    assert s.status()[0] == 0
+    close(Fh.cpu().numpy(), S.v_step(ops, F, E), 1e-10, f"{case} hessenberg")
+    s.close()
+
+
+def test_hessenberg_steps_ensemble(torch):
+    """Full RF steps of an uneven ensemble (three pressures: three Hessenberg
+    forms) against the oracle per discharge."""
+    cfg, members = _ensemble_case()
+    ops = [oracle.build_operators(m) for m in members]
+    F0 = [S.initial_state(o, workloads.density_profile(o.xhat, 1e16), 1.0) for o in ops]
+    s = solver(cfg, precision="fp64")
+    s.set_vsolver("hessenberg")
+    t0 = 0.2 * cfg["T_rf_s"]
+    F = cuda(torch, np.concatenate(F0))
+    ref = list(F0)
+    for k in range(3):
+        s.step(F, t0 + k * cfg["dt_s"])
+        ref = [S.step(o, r, t0 + k * cfg["dt_s"]) for o, r in zip(ops, ref)]
+    assert s.status()[0] == 0
+    got = F.cpu().numpy()
+    o = 0
+    for d, r in enumerate(ref):
+        close(got[o:o + r.shape[0]], r, 1e-10, f"discharge {d} hessenberg")
+        o += r.shape[0]
     s.close()
 
 
@@ -1057,3 +1150,62 @@ def test_c3_ensemble_at_size(torch):
         for x in xs:
             close(gv[offs[d] + x], rv[x], 1e-10, f"V(dt) of discharge {d} at x = {x}")
     s.close()
+
+
+@pytest.mark.slow
+def test_c4_cycle_gradient_against_central_differences(torch):
+    """The differentiation workload at its size: Nx = 128, Nr = 64, Ntheta = 32,
+    one RF cycle of 1000 steps, checkpoints every 50, nine parameters (eight
+    energy-bin scalings tied across the three processes, and the RF amplitude).
+    The loss is the weighted misfit of the cycle-mean density to the profile of
+    the same solver at seeded +-10% perturbed parameters.  The adjoint gradient
+    (autograd through bte_adjoint_step) against central differences of the
+    forward run with h = 1e-6 relative, on the amplitude and two bins (the bulk
+    and the ionization tail): agreement to 1e-5.  The steps are the mixed form
+    (FP32 factors refined to the FP64 backward error), which keeps the eight
+    cycles of the test within two minutes."""
+    import time
+    from paper_2502_16555_amd import Solver
+    from paper_2502_16555_amd.autograd import cycle_mean_density
+    cfg = workloads.config("C4")
+    nb = cfg["n_bins"]
+    s = Solver(cfg, precision="mixed_fp32")
+    ne = workloads.density_profile(s.xhat(), cfg["ic"]["ne_peak"])
+    F0 = s.initial_state(cuda(torch, ne), cfg["ic"]["Te_eV"])
+    s.close()
+    n_steps, every = cfg["n_steps"], cfg["checkpoint_every"]
+    w = torch.as_tensor(np.random.default_rng(4).uniform(0.5, 1.5, cfg["nx"]), device="cuda:0")
+
+    def nbar_of(theta):
+        scal = theta[:nb].reshape(1, nb).expand(len(cfg["processes"]), nb)
+        return cycle_mean_density(scal, theta[nb], F0, cfg, n_steps, every=every, precision="mixed_fp32")
+
+    theta_t = torch.as_tensor(workloads.perturbed_scalings(nb + 1, seed=2), dtype=torch.float64)
+    with torch.no_grad():
+        target = nbar_of(theta_t)
+
+    def loss(theta):
+        return (w * (nbar_of(theta) - target) ** 2).sum() / 1e30
+
+    theta = torch.ones(nb + 1, dtype=torch.float64, requires_grad=True)
+    t = time.perf_counter()
+    L = loss(theta)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t
+    t = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t_rev = time.perf_counter() - t
+    grad = theta.grad.numpy()
+    h = 1e-6
+    fd = {}
+    with torch.no_grad():
+        for j in (nb, 0, 5):
+            tp, tm = theta.detach().clone(), theta.detach().clone()
+            tp[j] *= 1 + h
+            tm[j] *= 1 - h
+            fd[j] = float(loss(tp) - loss(tm)) / (2 * h)
+    print(f"C4 cycle: forward {t_fwd:.1f} s, reverse {t_rev:.1f} s, ratio {(t_fwd + t_rev) / t_fwd:.2f}; "
+          + ", ".join(f"theta[{j}]: adjoint {grad[j]:.6e} fd {fd[j]:.6e}" for j in fd))
+    for j, f in fd.items():
+        assert abs(grad[j] - f) <= 1e-5 * abs(f), (j, grad[j], f)

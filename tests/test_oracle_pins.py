@@ -482,3 +482,40 @@ def test_ionization_rate_is_sensitive_to_speed_mode_rounding():
     assert d_ne < 1e-14
     assert 1e-10 < d_ki < 1e-7, d_ki
 
+
+def test_reduced_harmonic_basis_vstep():
+    """Fewer harmonics than ordinates (Nl < Ntheta; the paper's timed runs use
+    Nl = 3 with Ntheta = 16).  With T_S T_O = I_Nl (Gauss-Legendre quadrature is
+    exact for Y_q Y_l) P = P_O P_S is a projector of rank Nr Nl, the ordinate
+    operators P_O X P_S vanish on its complement, so the V step leaves
+    (I - P) F unchanged and conserves nothing it should not touch; and the
+    oracle's direct solve of the full Nr Ntheta system equals the exact
+    reduction to Nr Nl unknowns,
+        (I - P_O K P_S)^-1 b = (I - P_O P_S) b + P_O (I - P_S K' P_O)^-1 P_S b,
+    K' = dt (n0 C + E A) in ordinate form, solved here as a separate small system."""
+    cfg = dict(workloads.small_config(nx=4, nr=8, nth=8, kinds=("elastic", "excitation", "ionization"),
+                                      E=8e3, field_kind="rf"), nl=3)
+    ops = oracle.build_operators(cfg)
+    nr, nth, nl = ops.nr, ops.nth, ops.nl
+    assert np.abs(ops.T_S @ ops.T_O - np.eye(nl)).max() < 1e-13
+    PS = np.kron(np.eye(nr), ops.T_S)          # [k][a] -> [k][l]
+    PO = np.kron(np.eye(nr), ops.T_O)          # [k][l] -> [k][a]
+    P = PO @ PS
+    Q = np.eye(nr * nth) - P
+    assert np.abs(P @ P - P).max() < 1e-13
+    for X in (ops.Cord, ops.Aord):
+        sc = np.abs(X).max()
+        assert np.abs(X @ Q).max() < 1e-12 * sc and np.abs(Q @ X).max() < 1e-12 * sc
+    rng = np.random.default_rng(31)
+    F = rng.standard_normal((ops.nx, nr, nth))
+    E = np.array([0.0, 5e3, -1.2e4, 2e4])
+    Fs = S.v_step(ops, F, E)
+    for x in range(ops.nx):
+        b = F[x].ravel()
+        got = Fs[x].ravel()
+        assert np.abs(Q @ (got - b)).max() < 1e-12 * np.abs(b).max()
+        Kp = ops.dt * (ops.n0 * PS @ ops.Cord @ PO + E[x] * PS @ ops.Aord @ PO)
+        red = Q @ b + PO @ np.linalg.solve(np.eye(nr * nl) - Kp, PS @ b)
+        assert np.abs(red - got).max() < 1e-12 * np.abs(got).max()
+    # the number functional ignores the complement (only l = 0 carries density)
+    assert np.abs(ops.u_ord @ Q).max() < 1e-13 * np.abs(ops.u_ord).max()
