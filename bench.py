@@ -282,10 +282,11 @@ def run_implicit(cfg, torch, mults=(1.0,)):
     return out
 
 
-def run_adjoint(torch, n_steps=100, every=50):
+def run_adjoint(torch, n_steps=1000, every=50):
     """Adjoint cost on the differentiation workload (Nx=128, Nr=64, Ntheta=32,
-    8 bins x 3 processes + E0, FP64): time of the checkpointed forward pass vs
-    forward + reverse pass, operators set up beforehand."""
+    8 bins x 3 processes + E0, FP64, one RF cycle of 1000 steps, checkpoints
+    every 50): time of the checkpointed forward pass vs forward + reverse pass,
+    operators set up beforehand."""
     import workloads
     from paper_2502_16555_amd import Solver
     from paper_2502_16555_amd.autograd import forward_cycle, reverse_cycle
