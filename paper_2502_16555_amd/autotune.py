@@ -22,7 +22,7 @@ def candidates(precision: str) -> dict:
     kc = [16, 8] if precision == "fp64" else [16, 32]
     if precision in ("mixed_bf16", "mixed_bf16x3"):
         kc = [32]   # the bf16 updates have a fixed chunk
-    return {_lib.TUNE_LU_STREAMS: [1, 2], _lib.TUNE_UPDATE_KC: kc, _lib.TUNE_FORM_XPB: [16, 4, 8, 32]}
+    return {_lib.TUNE_LU_STREAMS: [1, 2], _lib.TUNE_UPDATE_KC: kc, _lib.TUNE_FORM_XPB: [8, 4, 16, 32]}
 
 
 def size_class(n: int, nx_total: int, precision: str) -> str:

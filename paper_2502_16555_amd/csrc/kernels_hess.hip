@@ -64,7 +64,7 @@ constexpr int kHessThreads = 256;
 
 // (I - s H) z = y for one point per block; H column-major (n x n, upper
 // Hessenberg), y and z rows of length ld.  Thread t holds rows t + q NT of the
-// current column of G Z, of y and of the next column of G (loaded one step ahead).
+// current column of G Z, of y and of the next D columns of G (loaded D steps ahead).
 template <int RPT>
 __global__ __launch_bounds__(kHessThreads) void k_hess_solve(const double* __restrict__ Hc,
                                                              const size_t* __restrict__ h_off,
@@ -78,62 +78,78 @@ __global__ __launch_bounds__(kHessThreads) void k_hess_solve(const double* __res
   const double s = dt * E[x];
   __shared__ double s_c[kMaxRows], s_s[kMaxRows], s_w[kMaxRows];
   __shared__ double s_bc[2][3];
-  double cur[RPT], y[RPT], g[RPT], gn[RPT];
-  // column c of G = I - s H, rows 0..c+1 (zero below)
-  auto load_col = [&](double (&dst)[RPT], int c) {
+  // columns of H in flight, raw (the transform to G = I - s H is applied where a
+  // column is used, so that no instruction waits on a load before then): slot u
+  // holds column k - 1 for the steps k = n - 1 - u (mod D), D steps ahead of use
+  constexpr int D = 8;
+  double cur[RPT], y[RPT], hq[D][RPT];
+  auto load_h = [&](double (&dst)[RPT], int c) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int r = tid + q * NT;
-      dst[q] = (r <= c + 1 && r < n) ? ((r == c ? 1.0 : 0.0) - s * H[(size_t)c * n + r]) : 0.0;
+      dst[q] = (r <= c + 1 && r < n) ? H[(size_t)c * n + r] : 0.0;
     }
   };
+  // entry (r, c) of G from the raw H entry h
+  auto gval = [&](int r, int c, double h) { return (r == c ? 1.0 : 0.0) - s * h; };
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = tid + q * NT;
     y[q] = (r < n) ? Y[(size_t)x * ld + r] : 0.0;
   }
-  load_col(cur, n - 1);
-  if (n >= 2) load_col(g, n - 2);
+  load_h(cur, n - 1);
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) cur[q] = gval(tid + q * NT, n - 1, cur[q]);
+#pragma unroll
+  for (int u = 0; u < D; ++u)
+    if (n - 2 - u >= 0) load_h(hq[u], n - 2 - u);
   bool bad = false;
-  for (int k = n - 1; k >= 1; --k) {
-    if (k >= 2) load_col(gn, k - 2);   // in flight during this step
-    const int par = k & 1;
-    if (tid == k % NT) {
-      // rows k of column k-1 (a) and of the current column k (b): the rotation
-      // that zeroes row k of the new column k-1; R[k][k] = hypot(a, b)
-      const int qk = k / NT;
-      double a = 0.0, b = 0.0, yk = 0.0;
+  for (int kb = n - 1; kb >= 1; kb -= D) {
 #pragma unroll
-      for (int q = 0; q < RPT; ++q)
-        if (q == qk) {
-          a = g[q];
-          b = cur[q];
-          yk = y[q];
-        }
-      const double rr = hypot(a, b);
-      const double c = rr > 0.0 ? b / rr : 1.0, sg = rr > 0.0 ? a / rr : 0.0;
-      const double wk = yk / rr;
-      if (rr == 0.0) bad = true;
-      s_bc[par][0] = c;
-      s_bc[par][1] = sg;
-      s_bc[par][2] = wk;
-      s_c[k] = c;
-      s_s[k] = sg;
-      s_w[k] = wk;
-    }
-    __syncthreads();
-    const double c = s_bc[par][0], sg = s_bc[par][1], wk = s_bc[par][2];
+    for (int u = 0; u < D; ++u) {
+      const int k = kb - u;
+      if (k < 1) break;
+      const int par = k & 1;
+      double g[RPT];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = tid + q * NT;
-      if (r < k) {
-        const double rk = c * cur[q] + sg * g[q];   // column k of R
-        y[q] -= rk * wk;
-        cur[q] = -sg * cur[q] + c * g[q];           // the new column k-1
+      for (int q = 0; q < RPT; ++q) g[q] = gval(tid + q * NT, k - 1, hq[u][q]);
+      if (tid == k % NT) {
+        // rows k of column k-1 (a) and of the current column k (b): the rotation
+        // that zeroes row k of the new column k-1; R[k][k] = hypot(a, b)
+        const int qk = k / NT;
+        double a = 0.0, b = 0.0, yk = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+          if (q == qk) {
+            a = g[q];
+            b = cur[q];
+            yk = y[q];
+          }
+        const double rr = hypot(a, b);
+        const double ri = 1.0 / rr;
+        const double c = rr > 0.0 ? b * ri : 1.0, sg = rr > 0.0 ? a * ri : 0.0;
+        const double wk = yk * ri;
+        if (rr == 0.0) bad = true;
+        s_bc[par][0] = c;
+        s_bc[par][1] = sg;
+        s_bc[par][2] = wk;
+        s_c[k] = c;
+        s_s[k] = sg;
+        s_w[k] = wk;
       }
-    }
+      __syncthreads();
+      const double c = s_bc[par][0], sg = s_bc[par][1], wk = s_bc[par][2];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) g[q] = gn[q];
+      for (int q = 0; q < RPT; ++q) {
+        const int r = tid + q * NT;
+        if (r < k) {
+          const double rk = c * cur[q] + sg * g[q];   // column k of R
+          y[q] -= rk * wk;
+          cur[q] = -sg * cur[q] + c * g[q];           // the new column k-1
+        }
+      }
+      if (k - 1 - D >= 0) load_h(hq[u], k - 1 - D);    // for the step k - D
+    }
   }
   if (tid == 0) {
     const double r0 = cur[0];

@@ -52,7 +52,7 @@ constexpr int NB = kNB;
 // Matrix formation, column c of points x0..x0+xpb-1: I - dt (n0_x C + E_x A) with
 // identity padding.  CT/AT hold C^T and A^T row-major, i.e. the columns of C
 // and A contiguously; a block reads its column of each once and writes it into
-// xpb matrices with 16-byte stores, so the launch is bound by the writes.
+// xpb matrices with 16-byte streaming stores, so the launch is bound by the writes.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* __restrict__ CT,
@@ -91,11 +91,13 @@ __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* 
         T v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) v[u] = static_cast<T>(-dt * (nn * cv[ch][u] + e * av[ch][u]) + (r0 + u == c ? 1.0 : 0.0));
+        // streaming (non-temporal) stores: most columns are read back only by a
+        // later panel or update, so they need not stay in the caches
         if constexpr (sizeof(T) == 4) {
-          *reinterpret_cast<float4*>(col + r0) = make_float4(v[0], v[1], v[2], v[3]);
+          __builtin_nontemporal_store(f32x4{v[0], v[1], v[2], v[3]}, reinterpret_cast<f32x4*>(col + r0));
         } else {
-          *reinterpret_cast<double2*>(col + r0) = make_double2(v[0], v[1]);
-          *reinterpret_cast<double2*>(col + r0 + 2) = make_double2(v[2], v[3]);
+          __builtin_nontemporal_store(f64x2{v[0], v[1]}, reinterpret_cast<f64x2*>(col + r0));
+          __builtin_nontemporal_store(f64x2{v[2], v[3]}, reinterpret_cast<f64x2*>(col + r0 + 2));
         }
       }
     }
@@ -1267,7 +1269,7 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   T* li = static_cast<T*>(d.linv) + (size_t)m0 * kLinvElems;  // inverses of L11 and its diagonal blocks
   int* piv = d.piv + (size_t)m0 * d.npad;
   int* perm = d.perm + (size_t)m0 * kMaxPanels * kPermStride;
-  const int xpb = d.form_xpb > 0 ? d.form_xpb : 16;  // matrices per formation block
+  const int xpb = d.form_xpb > 0 ? d.form_xpb : 8;   // matrices per formation block
   dim3 gform(d.npad, (nmat + xpb - 1) / xpb);
   k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, xpb,
                                   d.band_kl, d.band_ku);

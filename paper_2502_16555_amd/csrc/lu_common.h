@@ -12,6 +12,7 @@ namespace {
 
 using f64x4 = double __attribute__((ext_vector_type(4)));
 using f32x4 = float __attribute__((ext_vector_type(4)));
+using f64x2 = double __attribute__((ext_vector_type(2)));
 
 constexpr int kXcd = 8;  // XCDs of an MI355X; workgroups are dealt to them round-robin
 

