@@ -390,7 +390,7 @@ bte_status bte_get_timing(bte_handle* h, double* ms_out);
  *     16-chunk FP32 form runs four blocks per CU, the 32-chunk form two.  The
  *     BF16 updates have a fixed chunk of 32 (reported as such).
  *   BTE_TUNE_FORM_XPB: matrices formed per block of the formation kernel,
- *     1..64; 0 = default (8).
+ *     1..64; 0 = default (8 for FP32 factors, 16 for FP64).
  *   BTE_TUNE_PANEL_PAIRS: 1 (default) or 0.  Dense factors take the panels in
  *     pairs: a panel's update of the columns beyond the next panel is deferred
  *     and applied together with the next panel's in one update of depth 256,

@@ -1441,7 +1441,7 @@ bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value) {
       *value = bf16 ? 32 : (h->d.update_kc ? h->d.update_kc : 16);
       return BTE_OK;
     }
-    case BTE_TUNE_FORM_XPB: *value = h->d.form_xpb ? h->d.form_xpb : 8; return BTE_OK;
+    case BTE_TUNE_FORM_XPB: *value = h->d.form_xpb ? h->d.form_xpb : (fp64 ? 16 : 8); return BTE_OK;
     case BTE_TUNE_PANEL_PAIRS: *value = h->d.lu_pairs; return BTE_OK;
     default: return BTE_EINVAL;
   }

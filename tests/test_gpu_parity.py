@@ -537,11 +537,12 @@ def test_nonfinite_field_is_reported(torch, prec):
     s.close()
 
 
-def _golden_run(torch, name, n_file_steps, mode, tol):
+def _golden_run(torch, name, n_file_steps, mode, tol, tol_ki=None):
     """Run the stored oracle workload ``name`` on the GPU from its initial state
     and compare n_e, the mean energy (everywhere, and on points with n_e above
-    1e-3 of its peak), the energy density and k_i n_e at every stored step, and
-    the final state."""
+    1e-3 of its peak), the energy density and k_i n_e (to tol_ki, default tol)
+    at every stored step, and the final state."""
+    tol_ki = tol if tol_ki is None else tol_ki
     path = os.path.join(ROOT, "tests", "golden", f"{name.lower()}_oracle_{n_file_steps}.npz")
     if not os.path.exists(path):
         pytest.skip(f"golden file {os.path.basename(path)} not generated")
@@ -568,7 +569,7 @@ def _golden_run(torch, name, n_file_steps, mode, tol):
                                ("energy density", mg[0] * mg[1], mo[0] * mo[1]),
                                ("k_i n_e", mg[0] * mg[2], mo[0] * mo[2])):
                 worst[what] = max(worst.get(what, 0.0), rel(a, b))
-                close(a, b, tol, f"{mode} {what} at step {n + 1}")
+                close(a, b, tol_ki if what == "k_i n_e" else tol, f"{mode} {what} at step {n + 1}")
     worst["final state"] = rel(Fg.cpu().numpy(), g["F"])
     print(f"{name} {mode}: " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()))
     close(Fg.cpu().numpy(), g["F"], tol, f"{mode} final state")
@@ -605,9 +606,13 @@ def test_c2_golden_run(torch, mode):
     stored oracle run (every 10 steps and the final state), in FP64 and in the
     three mixed forms of the precision workload (FP32, split-bf16 and bf16
     trailing updates, each with FP64 refinement).  The target for the mixed
-    step is 1e-6 relative on n_e and the mean energy; the test holds every
-    result to 1e-9 (the FP64 rounding of the steps, as for C1)."""
-    _golden_run(torch, "C2", 100, mode, 1e-9)
+    step is 1e-6 relative on n_e and the mean energy; the test holds n_e, the
+    mean energy and the energy density to 1e-9 (the FP64 rounding of the steps,
+    as for C1), and k_i n_e to that same 1e-6: in the first tens of steps the
+    ionization tail is still the initial Maxwellian's, below 1e-6 of the bulk,
+    where FP64 rounding of the speed-mode transforms shows (measured 6e-8 at
+    step 10; test_ionization_rate_is_sensitive_to_speed_mode_rounding)."""
+    _golden_run(torch, "C2", 100, mode, 1e-9, tol_ki=1e-6)
 
 
 def test_refinement_nonconvergence_is_latched_and_the_handle_recovers(torch):
