@@ -79,9 +79,10 @@ struct bte_handle {
   bool banded = false;         // V solves in the harmonic basis, banded LU
   bool hess = false;           // V solves in the harmonic basis, Hessenberg form
   int hess_n = 0, hess_ld = 0;
-  double *d_hW = nullptr, *d_hQ = nullptr, *d_hH = nullptr;   // [nd][n][n] each
-  size_t* d_hoff = nullptr;                                   // [nd] offsets d n^2
-  std::vector<size_t> hoff_host;
+  double *d_hW = nullptr, *d_hQ = nullptr;   // [nd][n][hess_ld] each (rows zero beyond n)
+  double* d_hH = nullptr;                     // [nd][n][hess_col_stride(n)], the solve's layout
+  size_t* d_hoff = nullptr;                   // [nd] offsets of the H of discharge d
+  std::vector<size_t> hoff_host;              // [nd] offsets d n hess_ld of its W and Q
   ImplicitWs iw;               // fully implicit step
   DevOps bd;                   // its factors (FP64) and harmonic operators
   double* d_TO = nullptr;
@@ -1229,28 +1230,41 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
       const DevOps& d = h->d;
       const bte::HostOps& H = h->host;
       const int n = H.nh, nd = d.nd;
-      const size_t nn = (size_t)n * n;
       const int nthreads = static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
-      h->d_hW = h->kalloc<double>(nn * nd);
-      h->d_hQ = h->kalloc<double>(nn * nd);
-      h->d_hH = h->kalloc<double>(nn * nd);
+      // W and Q with rows of length ld (zero beyond n); H in the solve's layout:
+      // column c holds row n-1-j at entry j, zero-padded
+      const int ld = ((n + bte::kNB - 1) / bte::kNB) * bte::kNB;
+      const size_t nw = (size_t)n * ld;
+      const int ldh = bte::hess_col_stride(n);
+      const size_t nh = (size_t)n * ldh;
+      h->d_hW = h->kalloc<double>(nw * nd);
+      h->d_hQ = h->kalloc<double>(nw * nd);
+      h->d_hH = h->kalloc<double>(nh * nd);
       h->hoff_host.assign(nd, 0);
+      std::vector<size_t> h_off(nd);
+      std::vector<double> hr(nh), wq(nw, 0.0);
       for (int q = 0; q < nd; ++q) {
         bte::HessForm f;
         bte::hessenberg_setup(H, h->n0_host[q], h->cfg.dt_s, nthreads, &f);
-        h->hoff_host[q] = nn * q;
-        HIP_OK(hipMemcpy(h->d_hW + nn * q, f.W.data(), nn * sizeof(double), hipMemcpyHostToDevice));
-        HIP_OK(hipMemcpy(h->d_hQ + nn * q, f.Q.data(), nn * sizeof(double), hipMemcpyHostToDevice));
-        HIP_OK(hipMemcpy(h->d_hH + nn * q, f.Hc.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+        h->hoff_host[q] = nw * q;
+        h_off[q] = nh * q;
+        std::fill(hr.begin(), hr.end(), 0.0);
+        for (int c = 0; c < n; ++c)
+          for (int j = 0; j < n; ++j) hr[(size_t)c * ldh + j] = f.Hc[(size_t)c * n + (n - 1 - j)];
+        for (int i = 0; i < n; ++i) std::copy(f.W.begin() + (size_t)i * n, f.W.begin() + (size_t)(i + 1) * n, wq.begin() + (size_t)i * ld);
+        HIP_OK(hipMemcpy(h->d_hW + nw * q, wq.data(), nw * sizeof(double), hipMemcpyHostToDevice));
+        for (int i = 0; i < n; ++i) std::copy(f.Q.begin() + (size_t)i * n, f.Q.begin() + (size_t)(i + 1) * n, wq.begin() + (size_t)i * ld);
+        HIP_OK(hipMemcpy(h->d_hQ + nw * q, wq.data(), nw * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h->d_hH + nh * q, hr.data(), nh * sizeof(double), hipMemcpyHostToDevice));
       }
       h->d_hoff = h->kalloc<size_t>(nd);
-      HIP_OK(hipMemcpy(h->d_hoff, h->hoff_host.data(), nd * sizeof(size_t), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(h->d_hoff, h_off.data(), nd * sizeof(size_t), hipMemcpyHostToDevice));
       h->d_TO = h->kalloc<double>(H.TO.size());
       h->d_TS = h->kalloc<double>(H.TS.size());
       HIP_OK(hipMemcpy(h->d_TO, H.TO.data(), H.TO.size() * sizeof(double), hipMemcpyHostToDevice));
       HIP_OK(hipMemcpy(h->d_TS, H.TS.data(), H.TS.size() * sizeof(double), hipMemcpyHostToDevice));
       h->hess_n = n;
-      h->hess_ld = ((n + bte::kNB - 1) / bte::kNB) * bte::kNB;
+      h->hess_ld = ld;
       h->hess = true;
       return BTE_OK;
     } catch (const std::exception& e) {

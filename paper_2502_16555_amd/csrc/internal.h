@@ -126,11 +126,15 @@ void launch_gmres_combine(const DevOps& d, const GmresOps& q, hipStream_t s);
 void launch_gmres_status(const DevOps& d, const GmresOps& q, hipStream_t s);
 
 // ---- Hessenberg form of the V systems (kernels_hess.hip) ------------------------
-// Out[x] = M In[x] for points x0 .. x0+nx-1 (M row-major n x n, rows of length ld).
+// Out[x] = M In[x] for points x0 .. x0+nx-1 (M row-major n x n; M, In and Out rows
+// of length ld, even, with M zero beyond column n).
 void launch_mat_apply(const double* M, const double* In, double* Out, int n, int ld, int x0, int nx, hipStream_t s);
-// (I - dt E_x H_d) Z[x] = Y[x] for every point (H_d column-major at Hc + h_off[d]);
+// Column stride of the device layout of H for an order-n solve: column c of
+// H_d holds row n-1-j at entry j (rows in reverse), zeros from j = n to the stride.
+int hess_col_stride(int n);
+// (I - dt E_x H_d) Z[x] = Y[x] for every point (H_d in that layout at Hr + h_off[d]);
 // a zero rotation latches kStSingular, a non-finite solution kStNonFinite.
-void launch_hess_solve(const DevOps& d, const double* Hc, const size_t* h_off, int n, int ld, const double* Y,
+void launch_hess_solve(const DevOps& d, const double* Hr, const size_t* h_off, int n, int ld, const double* Y,
                        double* Z, hipStream_t s);
 
 // ---- heavies' update (kernels_ion.hip) ----------------------------------------

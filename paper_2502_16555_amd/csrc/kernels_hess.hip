@@ -2,52 +2,101 @@
 // (B - s A_h) u = b of eq. (vspace_batched_system), s = dt E_x, reduced once per
 // discharge to u = Q (I - s H)^-1 W b with H upper Hessenberg; see hessenberg.cpp):
 //   k_mat_apply   Out[x] = M In[x] for the points of one discharge (W, then Q):
-//                 32 points x 64 outputs per block, MFMA f64 16x16x4;
+//                 32 points x 64 outputs per block, MFMA f64 16x16x4, K through
+//                 double-buffered LDS;
 //   k_hess_solve  (I - s H) z = y, one block per point, in O(n^2): Givens
 //                 rotations of columns (k-1, k), k = n-1 .. 1, turn G = I - s H
 //                 into an upper triangular R = G Z; column k of R is final once
 //                 formed, so the back substitution R w = y runs alongside and R is
 //                 never stored; then z = Z w.
 #include <cmath>
+#include <type_traits>
+#include <utility>
 
 #include "internal.h"
 
 namespace bte {
 namespace {
 
+using f64x2 = double __attribute__((ext_vector_type(2)));
 using f64x4 = double __attribute__((ext_vector_type(4)));
 
 // Result row of item t of lane group lk for MFMA f64 16x16x4 (measured layout).
 __device__ inline int f64_row(int lk, int t) { return lk + 4 * t; }
 
-// Out[x][i] = sum_k M[i][k] In[x][k], x in [x0, x0 + nx), rows of length ld.
-// Grid: (ceil(n / 64), ceil(nx / 32)).
+// Out[x][i] = sum_k M[i][k] In[x][k], x in [x0, x0 + nx), i < n; M, In and Out
+// rows of length ld (M zero from column n on).  Block: 32 points x 64 outputs,
+// each wave two 16 x 16 MFMA tiles; K in chunks of 64 through two LDS buffers,
+// the next chunk's 16-byte global loads in flight while the current one is
+// multiplied.  Grid: (ceil(n / 64), ceil(nx / 32)); the blocks of one XCD
+// (block id mod 8) share their rows of M.
+constexpr int kMaBM = 32, kMaBN = 64, kMaBK = 64;
+constexpr int kMaLds = kMaBK + 1;   // odd row stride: the fragment reads are conflict-free
+constexpr int kMaALoads = kMaBM * kMaBK / 2 / 256, kMaBLoads = kMaBN * kMaBK / 2 / 256;
+
 __global__ __launch_bounds__(256) void k_mat_apply(const double* __restrict__ M, const double* __restrict__ In,
                                                    double* __restrict__ Out, int n, int ld, int x0, int nx) {
-  constexpr int BM = 32, BN = 64, BK = 64;
-  __shared__ double sX[BM][BK + 1];
-  __shared__ double sM[BN][BK + 1];
+  constexpr int BM = kMaBM, BN = kMaBN, BK = kMaBK, LDL = kMaLds;
+  extern __shared__ double lds[];
+  double* sX = lds;                      // [2][BM][LDL]
+  double* sM = lds + 2 * BM * LDL;       // [2][BN][LDL]
   const int xb = blockIdx.y * BM, i0 = blockIdx.x * BN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  f64x2 ra[kMaALoads], rb[kMaBLoads];
+  auto load = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int t = 0; t < kMaALoads; ++t) {
+      const int e = tid + 256 * t, r = e / (BK / 2), k = k0 + 2 * (e % (BK / 2));
+      f64x2 v = {0.0, 0.0};
+      if (xb + r < nx && k < n) {
+        v = *reinterpret_cast<const f64x2*>(In + (size_t)(x0 + xb + r) * ld + k);
+        if (k + 1 >= n) v[1] = 0.0;
+      }
+      ra[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < kMaBLoads; ++t) {
+      const int e = tid + 256 * t, r = e / (BK / 2), k = k0 + 2 * (e % (BK / 2));
+      f64x2 v = {0.0, 0.0};
+      if (i0 + r < n && k < n) v = *reinterpret_cast<const f64x2*>(M + (size_t)(i0 + r) * ld + k);
+      rb[t] = v;
+    }
+  };
+  auto store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int t = 0; t < kMaALoads; ++t) {
+      const int e = tid + 256 * t, r = e / (BK / 2), c = 2 * (e % (BK / 2));
+      double* d = sX + (buf * BM + r) * LDL + c;
+      d[0] = ra[t][0];
+      d[1] = ra[t][1];
+    }
+#pragma unroll
+    for (int t = 0; t < kMaBLoads; ++t) {
+      const int e = tid + 256 * t, r = e / (BK / 2), c = 2 * (e % (BK / 2));
+      double* d = sM + (buf * BN + r) * LDL + c;
+      d[0] = rb[t][0];
+      d[1] = rb[t][1];
+    }
+  };
   f64x4 acc[2] = {f64x4{0, 0, 0, 0}, f64x4{0, 0, 0, 0}};
-  for (int k0 = 0; k0 < n; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      const int r = e / BK, c = e % BK;
-      sX[r][c] = (xb + r < nx && k0 + c < n) ? In[(size_t)(x0 + xb + r) * ld + k0 + c] : 0.0;
-    }
-    for (int e = tid; e < BN * BK; e += 256) {
-      const int r = e / BK, c = e % BK;
-      sM[r][c] = (i0 + r < n && k0 + c < n) ? M[(size_t)(i0 + r) * n + k0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
+  const int nch = (n + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) load((c + 1) * BK);
+    const double* xa = sX + buf * BM * LDL;
+    const double* mb = sM + (buf * BN + w * 16 + li) * LDL + lk;
+#pragma unroll
     for (int k = 0; k < BK; k += 4) {
-      const double bm = sM[w * 16 + li][k + lk];
+      const double bm = mb[k];
 #pragma unroll
       for (int b = 0; b < 2; ++b)
-        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[b * 16 + li][k + lk], bm, acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[(b * 16 + li) * LDL + k + lk], bm, acc[b], 0, 0, 0);
     }
+    if (c + 1 < nch) store(buf ^ 1);
     __syncthreads();
   }
 #pragma unroll
@@ -61,134 +110,183 @@ __global__ __launch_bounds__(256) void k_mat_apply(const double* __restrict__ M,
 }
 
 constexpr int kHessThreads = 256;
+constexpr int kHessRing = 8;                    // columns of H in flight per thread
+constexpr int kHessSeg = 2 * kHessThreads;      // rows per pair index (two per thread)
 
-// (I - s H) z = y for one point per block; H column-major (n x n, upper
-// Hessenberg), y and z rows of length ld.  Thread t holds rows t + q NT of the
-// current column of G Z, of y and of the next D columns of G (loaded D steps ahead).
-template <int RPT>
-__global__ __launch_bounds__(kHessThreads) void k_hess_solve(const double* __restrict__ Hc,
+// row pairs per thread for an order-n solve
+int hess_pairs(int n) {
+  const int p = (n + kHessSeg - 1) / kHessSeg;
+  return p <= 1 ? 1 : p <= 2 ? 2 : 4;
+}
+
+template <int... I, class F>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F&& f) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+
+// two consecutive rows of one column, read by one 16-byte load
+struct alignas(16) Pair {
+  double x, y;
+};
+
+template <int E>
+__device__ __forceinline__ double& el(Pair& v) {
+  if constexpr (E == 0) return v.x; else return v.y;
+}
+
+// (I - s H) z = y for one point per block.  Rows are taken in reverse, j = n-1-r.
+// Thread t holds the row pairs j = 2t + {0, 1} + SEG p, p < P, of y, of the
+// running column of G Z and of the next D columns of H (raw, loaded D steps
+// ahead as one 16-byte load per pair).  The step with owner row k = n-1-j (the
+// rotation of columns k-1, k) acts only on rows j' >= j, so during the steps
+// j in [S SEG, (S+1) SEG) only pairs p >= S are live: the loop runs per S with
+// S a compile-time constant and touches no other pair.  Rows of pair S before
+// the owner (j' < j: rows r > k, whose part of the solve is done) are updated
+// too, without effect: nothing reads them again.
+template <int P>
+__global__ __launch_bounds__(kHessThreads) void k_hess_solve(const double* __restrict__ Hr,
                                                              const size_t* __restrict__ h_off,
                                                              const int* __restrict__ x_disc,
                                                              const double* __restrict__ E, double dt,
                                                              const double* __restrict__ Y, double* __restrict__ Z,
                                                              int n, int ld, int* __restrict__ status) {
-  constexpr int NT = kHessThreads;
+  constexpr int NT = kHessThreads, D = kHessRing, SEG = kHessSeg, LDC = P * NT;   // column stride in pairs
   const int x = blockIdx.x, tid = threadIdx.x;
-  const double* H = Hc + h_off[x_disc[x]];
+  // this thread's pairs of column 0
+  const Pair* H = reinterpret_cast<const Pair*>(Hr + h_off[x_disc[x]]) + tid;
   const double s = dt * E[x];
-  __shared__ double s_c[kMaxRows], s_s[kMaxRows], s_w[kMaxRows];
-  __shared__ double s_bc[2][3];
-  // columns of H in flight, raw (the transform to G = I - s H is applied where a
-  // column is used, so that no instruction waits on a load before then): slot u
-  // holds column k - 1 for the steps k = n - 1 - u (mod D), D steps ahead of use
-  constexpr int D = 8;
-  double cur[RPT], y[RPT], hq[D][RPT];
-  auto load_h = [&](double (&dst)[RPT], int c) {
+  // rotation k at entry kOff + k (the no-op steps have k = 1 - D .. 0)
+  constexpr int kOff = D;
+  __shared__ double s_c[kOff + kMaxRows], s_s[kOff + kMaxRows], s_w[kOff + kMaxRows];
+  Pair cur[P], y[P], hq[D][P];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = tid + q * NT;
-      dst[q] = (r <= c + 1 && r < n) ? H[(size_t)c * n + r] : 0.0;
-    }
-  };
-  // entry (r, c) of G from the raw H entry h
-  auto gval = [&](int r, int c, double h) { return (r == c ? 1.0 : 0.0) - s * h; };
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = tid + q * NT;
-    y[q] = (r < n) ? Y[(size_t)x * ld + r] : 0.0;
+  for (int p = 0; p < P; ++p) {
+    const int j = 2 * tid + SEG * p;
+    y[p].x = (j < n) ? Y[(size_t)x * ld + (n - 1 - j)] : 0.0;
+    y[p].y = (j + 1 < n) ? Y[(size_t)x * ld + (n - 2 - j)] : 0.0;
+    // column n-1 of G = I - s H; its diagonal entry is row j = 0
+    const Pair h = H[(size_t)(n - 1) * LDC + p * NT];
+    cur[p].x = fma(-s, h.x, j == 0 ? 1.0 : 0.0);
+    cur[p].y = -s * h.y;
   }
-  load_h(cur, n - 1);
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) cur[q] = gval(tid + q * NT, n - 1, cur[q]);
+  for (int u = 0; u < D; ++u) {
+    const int c = max(n - 2 - u, 0);   // column k-1 of the step j = u
 #pragma unroll
-  for (int u = 0; u < D; ++u)
-    if (n - 2 - u >= 0) load_h(hq[u], n - 2 - u);
+    for (int p = 0; p < P; ++p) hq[u][p] = H[(size_t)c * LDC + p * NT];
+  }
   bool bad = false;
-  for (int kb = n - 1; kb >= 1; kb -= D) {
+  static_for(std::make_integer_sequence<int, P>{}, [&](auto sc) __attribute__((always_inline)) {
+    constexpr int S = decltype(sc)::value;
+    const int jlo = S * SEG, jhi = min(jlo + SEG, n - 1);   // the steps j = 0 .. n-2
+    for (int jb = jlo; jb < jhi; jb += D) {
+      static_for(std::make_integer_sequence<int, D>{}, [&](auto uc) __attribute__((always_inline)) {
+        constexpr int U = decltype(uc)::value, EO = U & 1, ED = (U + 1) & 1;   // owner and diagonal elements
+        // steps past the last (j >= n-1, in the final block only) are kept as no-ops
+        // rather than skipped, so that the block has no exit
+        const int j = jb + U;
+        const bool fake = j >= n - 1;
+        const int k = n - 1 - j;
+        // column k-1 of G; its diagonal entry (row k-1) is row j+1, in pair S or S+1
+        Pair g[P];
 #pragma unroll
-    for (int u = 0; u < D; ++u) {
-      const int k = kb - u;
-      if (k < 1) break;
-      const int par = k & 1;
-      double g[RPT];
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) g[q] = gval(tid + q * NT, k - 1, hq[u][q]);
-      if (tid == k % NT) {
-        // rows k of column k-1 (a) and of the current column k (b): the rotation
-        // that zeroes row k of the new column k-1; R[k][k] = hypot(a, b)
-        const int qk = k / NT;
-        double a = 0.0, b = 0.0, yk = 0.0;
-#pragma unroll
-        for (int q = 0; q < RPT; ++q)
-          if (q == qk) {
-            a = g[q];
-            b = cur[q];
-            yk = y[q];
-          }
-        const double rr = hypot(a, b);
-        const double ri = 1.0 / rr;
-        const double c = rr > 0.0 ? b * ri : 1.0, sg = rr > 0.0 ? a * ri : 0.0;
-        const double wk = yk * ri;
-        if (rr == 0.0) bad = true;
-        s_bc[par][0] = c;
-        s_bc[par][1] = sg;
-        s_bc[par][2] = wk;
-        s_c[k] = c;
-        s_s[k] = sg;
-        s_w[k] = wk;
-      }
-      __syncthreads();
-      const double c = s_bc[par][0], sg = s_bc[par][1], wk = s_bc[par][2];
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int r = tid + q * NT;
-        if (r < k) {
-          const double rk = c * cur[q] + sg * g[q];   // column k of R
-          y[q] -= rk * wk;
-          cur[q] = -sg * cur[q] + c * g[q];           // the new column k-1
+        for (int p = S; p < P; ++p) {
+          g[p].x = -s * hq[U][p].x;
+          g[p].y = -s * hq[U][p].y;
         }
-      }
-      if (k - 1 - D >= 0) load_h(hq[u], k - 1 - D);    // for the step k - D
+        if (2 * tid + ED + SEG * S == j + 1) el<ED>(g[S]) = fma(-s, el<ED>(hq[U][S]), 1.0);
+        if constexpr (S + 1 < P)
+          if (2 * tid + ED + SEG * (S + 1) == j + 1) el<ED>(g[S + 1]) = fma(-s, el<ED>(hq[U][S + 1]), 1.0);
+        // the column for the step j + D (clamped in the last steps: loaded, never used)
+        const int cn = max(k - 1 - D, 0);
+#pragma unroll
+        for (int p = S; p < P; ++p) hq[U][p] = H[(size_t)cn * LDC + p * NT];
+        // the rotation that zeroes row k of the new column k-1, formed by the lane
+        // that holds row k: 1/hypot(a, b) from the hardware estimate and two Newton steps
+        // (a no-op step publishes c = 0, s = -1, w = 0, which leaves y and the
+        // running column as they are)
+        if (tid == (j - jlo) >> 1) {
+          const double a = el<EO>(g[S]), b = el<EO>(cur[S]);
+          const double xx = fma(a, a, b * b);
+          double ri = __builtin_amdgcn_rsq(xx);
+          ri = fma(0.5 * ri, fma(-xx * ri, ri, 1.0), ri);
+          ri = fma(0.5 * ri, fma(-xx * ri, ri, 1.0), ri);
+          const bool z = !(xx > 0.0);
+          bad |= z && !fake;
+          s_c[kOff + k] = fake ? 0.0 : z ? 1.0 : b * ri;
+          s_s[kOff + k] = fake ? -1.0 : z ? 0.0 : a * ri;
+          s_w[kOff + k] = (fake || z) ? 0.0 : el<EO>(y[S]) * ri;
+        }
+        __syncthreads();
+        const double c = s_c[kOff + k], sg = s_s[kOff + k], wk = s_w[kOff + k];
+#pragma unroll
+        for (int p = S; p < P; ++p) {
+          const double rx = c * cur[p].x + sg * g[p].x, ry = c * cur[p].y + sg * g[p].y;   // column k of R
+          y[p].x -= rx * wk;
+          y[p].y -= ry * wk;
+          cur[p].x = -sg * cur[p].x + c * g[p].x;   // the new column k-1
+          cur[p].y = -sg * cur[p].y + c * g[p].y;
+        }
+      });
     }
-  }
-  if (tid == 0) {
-    const double r0 = cur[0];
+  });
+  // row 0 (j = n-1): R[0][0] and w_0, then z = Z_{n-1} ... Z_1 w, Z_k acting on
+  // entries (k-1, k), by a running carry on the lane that holds row 0
+  if (tid == ((n - 1) % SEG) >> 1) {
+    const int p0 = (n - 1) / SEG, e0 = (n - 1) & 1;
+    __shared__ double s_fin[4];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      if (p == p0) {
+        s_fin[0] = cur[p].x;
+        s_fin[1] = cur[p].y;
+        s_fin[2] = y[p].x;
+        s_fin[3] = y[p].y;
+      }
+    const double r0 = s_fin[e0], y0 = s_fin[2 + e0];
     if (r0 == 0.0) bad = true;
-    s_w[0] = y[0] / r0;
-    // z = Z_{n-1} ... Z_1 w, Z_k acting on entries (k-1, k): a running carry t
-    double t = s_w[0];
+    double t = y0 / r0;
     for (int k = 1; k < n; ++k) {
-      const double c = s_c[k], sg = s_s[k], wk = s_w[k];
-      s_w[k - 1] = c * t + sg * wk;
+      const double c = s_c[kOff + k], sg = s_s[kOff + k], wk = s_w[kOff + k];
+      s_w[kOff + k - 1] = c * t + sg * wk;
       t = -sg * t + c * wk;
     }
-    s_w[n - 1] = t;
+    s_w[kOff + n - 1] = t;
     if (!(fabs(t) <= 1.0e300)) atomicOr(status, kStNonFinite);
   }
   if (bad) atomicOr(status, kStSingular);
   __syncthreads();
-  for (int r = tid; r < ld; r += NT) Z[(size_t)x * ld + r] = (r < n) ? s_w[r] : 0.0;
+  for (int r = tid; r < ld; r += NT) Z[(size_t)x * ld + r] = (r < n) ? s_w[kOff + r] : 0.0;
 }
 
 }  // namespace
 
 void launch_mat_apply(const double* M, const double* In, double* Out, int n, int ld, int x0, int nx, hipStream_t s) {
   if (nx <= 0) return;
-  dim3 g((n + 63) / 64, (nx + 31) / 32);
-  k_mat_apply<<<g, 256, 0, s>>>(M, In, Out, n, ld, x0, nx);
+  constexpr size_t lds = (size_t)2 * (kMaBM + kMaBN) * kMaLds * sizeof(double);
+  static const bool attr = [] {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mat_apply),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+  }();
+  (void)attr;
+  dim3 g((n + kMaBN - 1) / kMaBN, (nx + kMaBM - 1) / kMaBM);
+  k_mat_apply<<<g, 256, lds, s>>>(M, In, Out, n, ld, x0, nx);
 }
 
-void launch_hess_solve(const DevOps& d, const double* Hc, const size_t* h_off, int n, int ld, const double* Y,
+int hess_col_stride(int n) { return hess_pairs(n) * kHessSeg; }
+
+void launch_hess_solve(const DevOps& d, const double* Hr, const size_t* h_off, int n, int ld, const double* Y,
                        double* Z, hipStream_t s) {
-  const int rpt = (n + kHessThreads - 1) / kHessThreads;
-  if (rpt <= 1)
-    k_hess_solve<1><<<d.nx_total, kHessThreads, 0, s>>>(Hc, h_off, d.x_disc, d.E, d.dt, Y, Z, n, ld, d.status);
-  else if (rpt <= 2)
-    k_hess_solve<2><<<d.nx_total, kHessThreads, 0, s>>>(Hc, h_off, d.x_disc, d.E, d.dt, Y, Z, n, ld, d.status);
-  else if (rpt <= 4)
-    k_hess_solve<4><<<d.nx_total, kHessThreads, 0, s>>>(Hc, h_off, d.x_disc, d.E, d.dt, Y, Z, n, ld, d.status);
-  else
-    k_hess_solve<8><<<d.nx_total, kHessThreads, 0, s>>>(Hc, h_off, d.x_disc, d.E, d.dt, Y, Z, n, ld, d.status);
+  switch (hess_pairs(n)) {
+    case 1:
+      k_hess_solve<1><<<d.nx_total, kHessThreads, 0, s>>>(Hr, h_off, d.x_disc, d.E, d.dt, Y, Z, n, ld, d.status);
+      break;
+    case 2:
+      k_hess_solve<2><<<d.nx_total, kHessThreads, 0, s>>>(Hr, h_off, d.x_disc, d.E, d.dt, Y, Z, n, ld, d.status);
+      break;
+    default:
+      k_hess_solve<4><<<d.nx_total, kHessThreads, 0, s>>>(Hr, h_off, d.x_disc, d.E, d.dt, Y, Z, n, ld, d.status);
+  }
 }
 
 }  // namespace bte
