@@ -399,12 +399,23 @@ bte_status bte_get_timing(bte_handle* h, double* ms_out);
  *     as well (the solves follow).  Unlike the other keys this one changes the
  *     rounding of the trailing updates (not the pivots of a well-separated
  *     column); it only takes effect at the next factorization.
+ *   BTE_TUNE_STATIC_PIVOTING: 0 or 1 (default 1 for the mixed precisions, 0 for
+ *     FP64, where 1 is BTE_EINVAL).  1 factors the FP32 matrices without row
+ *     interchanges (static pivoting: a pivot below 2^-20 of the largest entry
+ *     of its 128 x 128 diagonal block is replaced by that bound, with its sign);
+ *     each panel is then its diagonal block's factorization plus L21 = A21
+ *     U11^-1, row-parallel, instead of 128 sequential pivot searches.  The FP64
+ *     refinement works with the exact matrix, so the solution meets the same
+ *     refine_rtol; a system that the perturbed factors cannot resolve latches
+ *     BTE_ENOCONV (never BTE_ESINGULAR).  Changes the factors, not the result
+ *     beyond rounding; takes effect at the next factorization.
  * Returns BTE_EINVAL for an unknown key or a value out of range. */
 typedef enum {
   BTE_TUNE_LU_STREAMS = 0,
   BTE_TUNE_UPDATE_KC = 1,
   BTE_TUNE_FORM_XPB = 2,
-  BTE_TUNE_PANEL_PAIRS = 3
+  BTE_TUNE_PANEL_PAIRS = 3,
+  BTE_TUNE_STATIC_PIVOTING = 4
 } bte_tune_key;
 bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value);
 bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value);

@@ -59,6 +59,7 @@ TUNE_LU_STREAMS = 0
 TUNE_UPDATE_KC = 1
 TUNE_FORM_XPB = 2
 TUNE_PANEL_PAIRS = 3
+TUNE_STATIC_PIVOTING = 4
 ION_SCRATCH_DOUBLES = 2097152   # BTE_ION_SCRATCH_DOUBLES
 
 EXPORTS = {

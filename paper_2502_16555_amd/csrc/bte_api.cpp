@@ -231,6 +231,8 @@ void fill_devops(bte_handle* h) {
   d.n_params = H.n_params;
   d.n_bins = H.n_bins;
   d.precision = c.precision;
+  // FP32 factors are refined to the FP64 backward error: static pivoting by default
+  d.static_piv = c.precision != BTE_FP64 ? 1 : 0;
   d.dt = c.dt_s;
   h->x_off.assign(nd + 1, 0);
   h->nx_per.resize(nd);
@@ -343,6 +345,7 @@ void fill_devops(bte_handle* h) {
   d.linv = h->alloc<char>(nxt * bte::kLinvElems * elt);
   d.piv = h->alloc<int>(nxt * d.npad);
   d.perm = h->alloc<int>(nxt * bte::kMaxPanels * bte::kPermStride);
+  d.mirror = h->alloc<int>(nxt);
   d.E = h->alloc<double>(nxt);
   d.field_rhs = h->alloc<double>(nxt);
   d.B = h->alloc<double>(nxt * d.npad);
@@ -1309,6 +1312,8 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
       b.precision = 0;
       b.update_kc = 0;
       b.form_xpb = 0;
+      b.static_piv = 0;
+      b.mirror = nullptr;
       b.band_kl = 2 * d.nr - 1;
       b.band_ku = 2 * d.nr - 1;
       h->bd = b;
@@ -1365,6 +1370,8 @@ bte_status bte_set_vsolver(bte_handle* h, int32_t kind, int32_t n_bins, double E
     f.precision = lu_prec;
     f.update_kc = 0;
     f.form_xpb = 0;
+    f.static_piv = 0;   // the bins keep partially pivoted factors
+    f.mirror = nullptr;
     bte::launch_lu_factor(f, lu_prec, nullptr);
     HIP_OK(hipDeviceSynchronize());
     if (fp16) {  // keep the factors in FP16 only: half the bytes per preconditioner solve
@@ -1440,6 +1447,11 @@ bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value) {
       if (value != 0 && value != 1) return BTE_EINVAL;
       h->d.lu_pairs = value;
       return BTE_OK;
+    case BTE_TUNE_STATIC_PIVOTING:
+      if (value != 0 && value != 1) return BTE_EINVAL;
+      if (fp64 && value == 1) return BTE_EINVAL;
+      h->d.static_piv = value;
+      return BTE_OK;
     default:
       return BTE_EINVAL;
   }
@@ -1457,6 +1469,7 @@ bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value) {
     }
     case BTE_TUNE_FORM_XPB: *value = h->d.form_xpb ? h->d.form_xpb : (fp64 ? 16 : 8); return BTE_OK;
     case BTE_TUNE_PANEL_PAIRS: *value = h->d.lu_pairs; return BTE_OK;
+    case BTE_TUNE_STATIC_PIVOTING: *value = h->d.static_piv; return BTE_OK;
     default: return BTE_EINVAL;
   }
 }

@@ -33,6 +33,9 @@ struct DevOps {
   int update_kc = 0;           // K chunk of the trailing update (0: default)
   int band_kl = 0, band_ku = 0;  // banded systems: lower / upper bandwidth (0: dense)
   int form_xpb = 0;            // matrices per formation block (0: default)
+  int static_piv = 0;          // FP32 factors: static pivoting (no interchanges) instead of partial
+  int* mirror = nullptr;       // [matrices] static pivoting: 1 where the factors are of the angularly
+                               // mirrored matrix (E < 0, formed with |E|; the solves mirror in and out)
   double dt = 0.0;
   // per discharge (device)
   int* x_off = nullptr;        // [nd+1]

@@ -14,12 +14,11 @@
 #include <utility>
 
 #include "internal.h"
+#include "lu_common.h"
 
 namespace bte {
 namespace {
 
-using f64x2 = double __attribute__((ext_vector_type(2)));
-using f64x4 = double __attribute__((ext_vector_type(4)));
 
 // Result row of item t of lane group lk for MFMA f64 16x16x4 (measured layout).
 __device__ inline int f64_row(int lk, int t) { return lk + 4 * t; }
@@ -110,18 +109,15 @@ __global__ __launch_bounds__(256) void k_mat_apply(const double* __restrict__ M,
 }
 
 constexpr int kHessThreads = 256;
-constexpr int kHessRing = 8;                    // columns of H in flight per thread
+// columns of H in flight per thread: fewer at four pairs, where eight would not fit in registers
+template <int P>
+constexpr int hess_ring() { return P >= 4 ? 4 : 8; }
 constexpr int kHessSeg = 2 * kHessThreads;      // rows per pair index (two per thread)
 
 // row pairs per thread for an order-n solve
 int hess_pairs(int n) {
   const int p = (n + kHessSeg - 1) / kHessSeg;
   return p <= 1 ? 1 : p <= 2 ? 2 : 4;
-}
-
-template <int... I, class F>
-__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F&& f) {
-  (f(std::integral_constant<int, I>{}), ...);
 }
 
 // two consecutive rows of one column, read by one 16-byte load
@@ -140,9 +136,17 @@ __device__ __forceinline__ double& el(Pair& v) {
 // ahead as one 16-byte load per pair).  The step with owner row k = n-1-j (the
 // rotation of columns k-1, k) acts only on rows j' >= j, so during the steps
 // j in [S SEG, (S+1) SEG) only pairs p >= S are live: the loop runs per S with
-// S a compile-time constant and touches no other pair.  Rows of pair S before
-// the owner (j' < j: rows r > k, whose part of the solve is done) are updated
-// too, without effect: nothing reads them again.
+// S a compile-time constant and touches no other pair.  Rows before the owner
+// (j' < j: rows r > k, whose part of the solve is done) are updated too, without
+// effect: nothing reads them again.
+//
+// The steps go two at a time: rows j, j+1 (j even) are one pair of one lane,
+// which forms both rotations from its own entries and publishes them together;
+// after one barrier every lane applies the two in turn.  With G = I - s H the
+// update of a row by the rotation (c, sg, w) of a step whose fresh column has
+// the raw entry h in that row is
+//     y <- y - w c x + (w sg s) h,   x <- -sg x - (c s) h,
+// plus c (to x) and -w sg (to y) on the column's diagonal row.
 template <int P>
 __global__ __launch_bounds__(kHessThreads) void k_hess_solve(const double* __restrict__ Hr,
                                                              const size_t* __restrict__ h_off,
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(kHessThreads) void k_hess_solve(const double* __res
                                                              const double* __restrict__ E, double dt,
                                                              const double* __restrict__ Y, double* __restrict__ Z,
                                                              int n, int ld, int* __restrict__ status) {
-  constexpr int NT = kHessThreads, D = kHessRing, SEG = kHessSeg, LDC = P * NT;   // column stride in pairs
+  constexpr int NT = kHessThreads, D = hess_ring<P>(), SEG = kHessSeg, LDC = P * NT;   // column stride in pairs
   const int x = blockIdx.x, tid = threadIdx.x;
   // this thread's pairs of column 0
   const Pair* H = reinterpret_cast<const Pair*>(Hr + h_off[x_disc[x]]) + tid;
@@ -176,58 +180,108 @@ __global__ __launch_bounds__(kHessThreads) void k_hess_solve(const double* __res
     for (int p = 0; p < P; ++p) hq[u][p] = H[(size_t)c * LDC + p * NT];
   }
   bool bad = false;
+  // Rotation jn (owner row kn = n-1-jn), which zeroes row kn of the new column
+  // kn-1: a = G[kn][kn-1] (sub-diagonal), b of the running column, yv of y.
+  // 1/hypot(a, b) from the hardware estimate and two Newton steps.  Steps past
+  // the last (jn >= n-1) are no-ops: c = 0, s = -1, w = 0 leave y and the
+  // running column as they are.
+  auto form = [&](int jn, double a, double b, double yv, double& rc, double& rs, double& rw)
+      __attribute__((always_inline)) {
+    const bool fake = jn >= n - 1;
+    const double xx = fma(a, a, b * b);
+    double ri = __builtin_amdgcn_rsq(xx);
+    ri = fma(0.5 * ri, fma(-xx * ri, ri, 1.0), ri);
+    ri = fma(0.5 * ri, fma(-xx * ri, ri, 1.0), ri);
+    const bool z = !(xx > 0.0);
+    bad |= z && !fake;
+    rc = fake ? 0.0 : z ? 1.0 : b * ri;
+    rs = fake ? -1.0 : z ? 0.0 : a * ri;
+    rw = (fake || z) ? 0.0 : yv * ri;
+  };
+  // Rotations jn, jn+1 (jn even) by the lane holding that pair (cv, yv), with
+  // the raw entries h0 of step jn's fresh column and h1 of step jn+1's: row jn+1
+  // is the diagonal of the first, the sub-diagonal of the second.
+  auto form2 = [&](int jn, const Pair& cv, const Pair& yv, const Pair& h0, const Pair& h1)
+      __attribute__((always_inline)) {
+    double c0, s0, w0, c1, s1, w1;
+    form(jn, -s * h0.x, cv.x, yv.x, c0, s0, w0);
+    const double g = fma(-s, h0.y, 1.0);
+    const double r1 = c0 * cv.y + s0 * g;
+    const double b1 = -s0 * cv.y + c0 * g;
+    const double y1 = yv.y - r1 * w0;
+    form(jn + 1, -s * h1.y, b1, y1, c1, s1, w1);
+    const int kn = n - 1 - jn;
+    s_c[kOff + kn] = c0;
+    s_s[kOff + kn] = s0;
+    s_w[kOff + kn] = w0;
+    s_c[kOff + kn - 1] = c1;
+    s_s[kOff + kn - 1] = s1;
+    s_w[kOff + kn - 1] = w1;
+  };
+  // steps 0 and 1: rows 0, 1 are pair 0 of thread 0
+  if (tid == 0) form2(0, cur[0], y[0], hq[0][0], hq[1][0]);
   static_for(std::make_integer_sequence<int, P>{}, [&](auto sc) __attribute__((always_inline)) {
     constexpr int S = decltype(sc)::value;
     const int jlo = S * SEG, jhi = min(jlo + SEG, n - 1);   // the steps j = 0 .. n-2
     for (int jb = jlo; jb < jhi; jb += D) {
-      static_for(std::make_integer_sequence<int, D>{}, [&](auto uc) __attribute__((always_inline)) {
-        constexpr int U = decltype(uc)::value, EO = U & 1, ED = (U + 1) & 1;   // owner and diagonal elements
-        // steps past the last (j >= n-1, in the final block only) are kept as no-ops
-        // rather than skipped, so that the block has no exit
+      static_for(std::make_integer_sequence<int, D / 2>{}, [&](auto uc) __attribute__((always_inline)) {
+        // steps j, j+1 with slots U, U+1 of the ring; the no-op steps past the
+        // last keep the final block free of exits
+        constexpr int U = 2 * decltype(uc)::value, U2 = (U + 2) % D, U3 = (U + 3) % D;
         const int j = jb + U;
-        const bool fake = j >= n - 1;
         const int k = n - 1 - j;
-        // column k-1 of G; its diagonal entry (row k-1) is row j+1, in pair S or S+1
-        Pair g[P];
-#pragma unroll
-        for (int p = S; p < P; ++p) {
-          g[p].x = -s * hq[U][p].x;
-          g[p].y = -s * hq[U][p].y;
-        }
-        if (2 * tid + ED + SEG * S == j + 1) el<ED>(g[S]) = fma(-s, el<ED>(hq[U][S]), 1.0);
-        if constexpr (S + 1 < P)
-          if (2 * tid + ED + SEG * (S + 1) == j + 1) el<ED>(g[S + 1]) = fma(-s, el<ED>(hq[U][S + 1]), 1.0);
-        // the column for the step j + D (clamped in the last steps: loaded, never used)
-        const int cn = max(k - 1 - D, 0);
-#pragma unroll
-        for (int p = S; p < P; ++p) hq[U][p] = H[(size_t)cn * LDC + p * NT];
-        // the rotation that zeroes row k of the new column k-1, formed by the lane
-        // that holds row k: 1/hypot(a, b) from the hardware estimate and two Newton steps
-        // (a no-op step publishes c = 0, s = -1, w = 0, which leaves y and the
-        // running column as they are)
-        if (tid == (j - jlo) >> 1) {
-          const double a = el<EO>(g[S]), b = el<EO>(cur[S]);
-          const double xx = fma(a, a, b * b);
-          double ri = __builtin_amdgcn_rsq(xx);
-          ri = fma(0.5 * ri, fma(-xx * ri, ri, 1.0), ri);
-          ri = fma(0.5 * ri, fma(-xx * ri, ri, 1.0), ri);
-          const bool z = !(xx > 0.0);
-          bad |= z && !fake;
-          s_c[kOff + k] = fake ? 0.0 : z ? 1.0 : b * ri;
-          s_s[kOff + k] = fake ? -1.0 : z ? 0.0 : a * ri;
-          s_w[kOff + k] = (fake || z) ? 0.0 : el<EO>(y[S]) * ri;
-        }
         __syncthreads();
-        const double c = s_c[kOff + k], sg = s_s[kOff + k], wk = s_w[kOff + k];
+        const double c0 = s_c[kOff + k], sg0 = s_s[kOff + k], w0 = s_w[kOff + k];
+        const double c1 = s_c[kOff + k - 1], sg1 = s_s[kOff + k - 1], w1 = s_w[kOff + k - 1];
+        const double wc0 = w0 * c0, ws0 = w0 * sg0, cs0 = c0 * s, wss0 = ws0 * s;
+        const double wc1 = w1 * c1, ws1 = w1 * sg1, cs1 = c1 * s, wss1 = ws1 * s;
+        // the diagonal of step j's column, row j+1, is the second row of the
+        // owner's pair; it matters only when that row is the last (j+1 = n-1)
+        const bool dJ = 2 * tid + 1 + SEG * S == j + 1;
+        auto rot = [&](Pair& cv, Pair& yv, const Pair& h0, const Pair& h1, bool own)
+            __attribute__((always_inline)) {
+          yv.x = fma(wss0, h0.x, fma(-wc0, cv.x, yv.x));
+          yv.y = fma(wss0, h0.y, fma(-wc0, cv.y, yv.y));
+          cv.x = fma(-sg0, cv.x, -cs0 * h0.x);
+          cv.y = fma(-sg0, cv.y, -cs0 * h0.y);
+          if (own) {
+            cv.y += dJ ? c0 : 0.0;
+            yv.y -= dJ ? ws0 : 0.0;
+          }
+          yv.x = fma(wss1, h1.x, fma(-wc1, cv.x, yv.x));
+          yv.y = fma(wss1, h1.y, fma(-wc1, cv.y, yv.y));
+          cv.x = fma(-sg1, cv.x, -cs1 * h1.x);
+          cv.y = fma(-sg1, cv.y, -cs1 * h1.y);
+        };
+        // The diagonal of step j+1's column is row j+2, the first of the next
+        // owner's pair (pair S, or pair S+1 when j+2 starts it).
+        rot(cur[S], y[S], hq[U][S], hq[U + 1][S], true);
+        const bool dS = 2 * tid + SEG * S == j + 2;
+        cur[S].x += dS ? c1 : 0.0;
+        y[S].x -= dS ? ws1 : 0.0;
+        // the next two rotations, by the lane holding rows j+2, j+3 in pair S
+        if (tid == ((j + 2 - jlo) >> 1)) form2(j + 2, cur[S], y[S], hq[U2][S], hq[U3][S]);
+#pragma unroll
+        for (int p = S + 1; p < P; ++p) rot(cur[p], y[p], hq[U][p], hq[U + 1][p], false);
+        if constexpr (S + 1 < P) {
+          const bool dN = 2 * tid + SEG * (S + 1) == j + 2;
+          cur[S + 1].x += dN ? c1 : 0.0;
+          y[S + 1].x -= dN ? ws1 : 0.0;
+        }
+        // the columns for the steps j + D, j + 1 + D (clamped in the last steps:
+        // loaded, never used)
+        const int cn0 = max(k - 1 - D, 0), cn1 = max(k - 2 - D, 0);
 #pragma unroll
         for (int p = S; p < P; ++p) {
-          const double rx = c * cur[p].x + sg * g[p].x, ry = c * cur[p].y + sg * g[p].y;   // column k of R
-          y[p].x -= rx * wk;
-          y[p].y -= ry * wk;
-          cur[p].x = -sg * cur[p].x + c * g[p].x;   // the new column k-1
-          cur[p].y = -sg * cur[p].y + c * g[p].y;
+          hq[U][p] = H[(size_t)cn0 * LDC + p * NT];
+          hq[U + 1][p] = H[(size_t)cn1 * LDC + p * NT];
         }
       });
+    }
+    // the first two rotations of pair S+1 (rows (S+1) SEG + {0, 1}: thread 0)
+    if constexpr (S + 1 < P) {
+      constexpr int jn = (S + 1) * SEG;
+      if (jn < n - 1 && tid == 0) form2(jn, cur[S + 1], y[S + 1], hq[jn % D][S + 1], hq[(jn + 1) % D][S + 1]);
     }
   });
   // row 0 (j = n-1): R[0][0] and w_0, then z = Z_{n-1} ... Z_1 w, Z_k acting on

@@ -58,7 +58,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* __restrict__ CT,
                                               const double* __restrict__ AT, const double* __restrict__ E,
                                               const double* __restrict__ n0x, double dt, int n, int npad, int nmat,
-                                              int xpb, int kl, int ku) {
+                                              int xpb, int kl, int ku, int* __restrict__ mirror, int do_mirror) {
   constexpr int CH = kMaxRows / 1024;  // 4-row groups per thread
   const int c = blockIdx.x, tid = threadIdx.x;
   const int x0 = blockIdx.y * xpb, x1 = min(nmat, x0 + xpb);
@@ -82,7 +82,15 @@ __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* 
       av[ch][u] = in ? AT[(size_t)c * n + r] : 0.0;
     }
   for (int x = x0; x < x1; ++x) {
-    const double e = E[x], nn = n0x[x];
+    // static pivoting (do_mirror): a point with E < 0 is formed with |E|, the
+    // matrix of its angularly mirrored system (ordinates theta -> pi - theta in
+    // every speed block: M(-E) = J M(E) J), whose unpivoted factors stay as well
+    // conditioned as those of a positive field; the solves mirror their vectors
+    double e = E[x];
+    const double nn = n0x[x];
+    const bool mx = do_mirror && e < 0.0;
+    if (mirror && c == 0 && tid == 0) mirror[x] = mx ? 1 : 0;   // the flags follow the factors
+    if (mx) e = -e;
     T* col = LU + ((size_t)x * npad + c) * npad;
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
@@ -490,6 +498,224 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
     pm[1 + kMaxSwapRows + t] = x;
   }
   if (tid == 0) pm[0] = nRf;
+}
+
+// ---------------------------------------------------------------------------
+// Static pivoting (FP32 factors): the panel without row interchanges.  A pivot
+// smaller than tau = 2^-20 max|A11| is replaced by tau with its sign (static
+// pivoting, as in Li and Demmel's SuperLU_DIST); the FP64 refinement that
+// follows every FP32 solve works with the unperturbed matrix.  Pivots and
+// permutations are written as the identity, so that the U12, update and solve
+// kernels apply them as no-ops.
+//   k_diag_static  one 256-thread block per matrix, thread t holding the 8 x 8
+//                  tile (rows 8 (t / 16), columns 8 (t mod 16)) of the 128 x 128
+//                  diagonal block: A11 = L11 U11 by rank-1 steps, then
+//                  X = U11^-1 by rank-1 steps from the last row up, one barrier
+//                  per step (the step's row and column through LDS); X goes
+//                  row-major into the matrix's linv slot;
+//   k_l21_mfma     L21 = A21 X for 128 rows per block: one MFMA product (K =
+//                  128, the zero blocks of X skipped), A21 straight from HBM.
+// ---------------------------------------------------------------------------
+constexpr float kStaticPivotRel = 9.5367431640625e-07f;   // 2^-20
+
+__global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, float* __restrict__ linv,
+                                                     int* __restrict__ piv, int* __restrict__ perm,
+                                                     int* __restrict__ status, int npad, int k0) {
+  const int mat = blockIdx.x;
+  float* A = LU + (size_t)mat * npad * npad;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15, lane = tid & 63, wid = tid >> 6;
+  __shared__ __align__(16) float s_row[2][NB];   // the step's row (zeros outside its range)
+  __shared__ __align__(16) float s_col[2][NB];   // the step's column (zeros outside its range)
+  __shared__ float s_piv[2];
+  __shared__ float s_red[4];
+  float a[8][8];   // a[rr][cc]: row 8 tr + rr, column 8 tc + cc
+#pragma unroll
+  for (int cc = 0; cc < 8; ++cc) {
+    const float4* cp = reinterpret_cast<const float4*>(A + (size_t)(k0 + 8 * tc + cc) * npad + k0 + 8 * tr);
+    const float4 v0 = cp[0], v1 = cp[1];
+    a[0][cc] = v0.x; a[1][cc] = v0.y; a[2][cc] = v0.z; a[3][cc] = v0.w;
+    a[4][cc] = v1.x; a[5][cc] = v1.y; a[6][cc] = v1.z; a[7][cc] = v1.w;
+  }
+  float m = 0.0f;
+  bool nonfinite = false;
+#pragma unroll
+  for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const float v = fabsf(a[rr][cc]);
+      nonfinite |= !(v <= FLT_MAX);
+      m = fmaxf(m, v);
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (lane == 0) s_red[wid] = m;
+  __syncthreads();
+  const float tau = fmaxf(fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3])) * kStaticPivotRel, FLT_MIN);
+  auto put8 = [&](float* dst, const float (&v)[8]) __attribute__((always_inline)) {
+    reinterpret_cast<float4*>(dst)[0] = make_float4(v[0], v[1], v[2], v[3]);
+    reinterpret_cast<float4*>(dst)[1] = make_float4(v[4], v[5], v[6], v[7]);
+  };
+  auto get8 = [&](const float* src, float (&v)[8]) __attribute__((always_inline)) {
+    const float4 v0 = reinterpret_cast<const float4*>(src)[0], v1 = reinterpret_cast<const float4*>(src)[1];
+    v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+    v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+  };
+  // ---- A11 = L11 U11: step k publishes column k below the pivot and row k
+  // right of it (zeros elsewhere) and the pivot; the buffers alternate with k
+  // (one is rewritten two steps later, past the barrier in between).  Column
+  // j's multipliers are scaled by its pivot's reciprocal after the loop.
+  float rp_own[8];
+#pragma unroll
+  for (int cc = 0; cc < 8; ++cc) rp_own[cc] = 1.0f;
+  for (int kb = 0; kb < 16; ++kb) {
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 8 * kb + kk, par = kk & 1;
+      if (tc == kb) {
+        float v[8];
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) v[rr] = (tr > kb || (tr == kb && rr > kk)) ? a[rr][kk] : 0.0f;
+        put8(&s_col[par][8 * tr], v);
+      }
+      if (tr == kb) {
+        float v[8];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) v[cc] = (tc > kb || (tc == kb && cc > kk)) ? a[kk][cc] : 0.0f;
+        put8(&s_row[par][8 * tc], v);
+        if (tc == kb) s_piv[par] = a[kk][kk];
+      }
+      __syncthreads();
+      float cv[8], rv[8];
+      get8(&s_col[par][8 * tr], cv);
+      get8(&s_row[par][8 * tc], rv);
+      float pv = s_piv[par];
+      if (!(fabsf(pv) >= tau)) pv = pv < 0.0f ? -tau : tau;   // also a NaN pivot (reported above)
+      const float rp = __builtin_amdgcn_rcpf(pv);
+      if (tc == kb) {
+        rp_own[kk] = rp;
+        if (tr == kb) a[kk][kk] = pv;
+      }
+      if (4 * wid + 3 >= kb) {   // a wavefront whose rows all lie above row k skips
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) rv[cc] *= rp;
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc) a[rr][cc] = fmaf(-cv[rr], rv[cc], a[rr][cc]);
+      }
+    }
+  }
+#pragma unroll
+  for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc)
+      if (8 * tr + rr > 8 * tc + cc) a[rr][cc] *= rp_own[cc];
+#pragma unroll
+  for (int cc = 0; cc < 8; ++cc) {
+    float4* cp = reinterpret_cast<float4*>(A + (size_t)(k0 + 8 * tc + cc) * npad + k0 + 8 * tr);
+    cp[0] = make_float4(a[0][cc], a[1][cc], a[2][cc], a[3][cc]);
+    cp[1] = make_float4(a[4][cc], a[5][cc], a[6][cc], a[7][cc]);
+  }
+  if (tid < NB) {
+    piv[(size_t)mat * npad + k0 + tid] = k0 + tid;
+    int* pm = perm + ((size_t)mat * kMaxPanels + k0 / NB) * kPermStride;
+    pm[1 + tid] = k0 + tid;
+    pm[1 + kMaxSwapRows + tid] = k0 + tid;
+    if (tid == 0) pm[0] = NB;
+  }
+  // ---- X = U11^-1 from X = I, k = 127 .. 0: row k of X times 1/u_kk, then
+  // X[i][:] -= u_ik X[k][:] for the rows i < k.  Step k publishes row k of X
+  // (scaled) and column k of U above the diagonal (zeros elsewhere).
+  __shared__ float s_rd[NB];
+  if (tr == tc) {
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr) s_rd[8 * tr + rr] = 1.0f / a[rr][rr];
+  }
+  float x[8][8];
+#pragma unroll
+  for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) x[rr][cc] = (tr == tc && rr == cc) ? 1.0f : 0.0f;
+  __syncthreads();
+  for (int kb = 15; kb >= 0; --kb) {
+#pragma unroll
+    for (int kk = 7; kk >= 0; --kk) {
+      const int k = 8 * kb + kk, par = kk & 1;
+      if (tr == kb) {
+        const float rd = s_rd[k];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) x[kk][cc] *= rd;
+        put8(&s_row[par][8 * tc], x[kk]);
+      }
+      if (tc == kb) {
+        float v[8];
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) v[rr] = (tr < kb || (tr == kb && rr < kk)) ? a[rr][kk] : 0.0f;
+        put8(&s_col[par][8 * tr], v);
+      }
+      __syncthreads();
+      if (32 * wid < k) {   // a wavefront whose rows all lie at or below row k skips
+        float cv[8], rv[8];
+        get8(&s_col[par][8 * tr], cv);
+        get8(&s_row[par][8 * tc], rv);
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc) x[rr][cc] = fmaf(-cv[rr], rv[cc], x[rr][cc]);
+      }
+    }
+  }
+  float* xo = linv + (size_t)mat * kLinvElems;   // X row-major
+#pragma unroll
+  for (int rr = 0; rr < 8; ++rr) put8(xo + (8 * tr + rr) * NB + 8 * tc, x[rr]);
+  if (__syncthreads_or(nonfinite) && tid == 0) atomicOr(status, kStNonFinite);
+}
+
+__global__ __launch_bounds__(256, 2) void k_l21_mfma(float* __restrict__ LU, const float* __restrict__ linv,
+                                                     int npad, int k0, int ntiles, int nmat) {
+  int mat, tile;
+  xcd_map(blockIdx.x, ntiles, nmat, &mat, &tile);
+  if (mat >= nmat) return;
+  float* A = LU + (size_t)mat * npad * npad;
+  constexpr int LD = NB + 4;   // B fragment reads: lanes (li, lk) on banks li + 4 lk
+  __shared__ __align__(16) float sX[NB][LD];
+  const int r0 = k0 + NB + tile * NB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  // this wave's rows of A21 (32 w + 16 rb + li), all of K, into registers
+  float av[32][2];
+#pragma unroll
+  for (int q = 0; q < 32; ++q)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) av[q][rb] = A[(size_t)(k0 + 4 * q + lk) * npad + r0 + 32 * w + 16 * rb + li];
+  const float4* xs = reinterpret_cast<const float4*>(linv + (size_t)mat * kLinvElems);
+  for (int e = tid; e < NB * NB / 4; e += 256) {
+    const int rw = e / (NB / 4), q = e % (NB / 4);
+    *reinterpret_cast<float4*>(&sX[rw][4 * q]) = xs[e];
+  }
+  __syncthreads();
+  using Acc = Mma<float>::acc;
+  Acc acc[2][8];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb) acc[rb][cb] = Acc{0, 0, 0, 0};
+  // X is upper triangular: column block cb takes the K rows 0 .. 16 cb + 15
+#pragma unroll
+  for (int q = 0; q < 32; ++q)
+#pragma unroll
+    for (int cb = q / 4; cb < 8; ++cb) {
+      const float bv = sX[4 * q + lk][16 * cb + li];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) acc[rb][cb] = Mma<float>::step(av[q][rb], bv, acc[rb][cb]);
+    }
+  // every A21 entry of these rows is in registers: L21 goes out in place
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb)
+      *reinterpret_cast<float4*>(A + (size_t)(k0 + 16 * cb + li) * npad + r0 + 32 * w + 16 * rb + 4 * lk) =
+          make_float4(acc[rb][cb][0], acc[rb][cb][1], acc[rb][cb][2], acc[rb][cb][3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1071,7 +1297,8 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
                                                 double* __restrict__ Xout,
                                                 const int* __restrict__ status, int accumulate, int check_done,
                                                 int npad, const int* __restrict__ mat_of,
-                                                const int* __restrict__ skip, int band_lo, int band_up, int paired) {
+                                                const int* __restrict__ skip, int band_lo, int band_up, int paired,
+                                                const int* __restrict__ mirror, int n, int nth) {
   if (check_done && status[1]) return;
   // right-hand side / solution row: the block; factors: that row's own matrix,
   // or the one mat_of names (a shared factorization, e.g. a preconditioner bin)
@@ -1085,7 +1312,11 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NWV = 1024 / 64;
   const double* b = Bin + (size_t)row * npad;
-  for (int i = tid; i < npad; i += 1024) sb[i] = b[i];
+  // factors of the mirrored matrix: the right-hand side comes in mirrored and
+  // the solution goes out mirrored (ordinate theta -> nth-1-theta of each speed)
+  const bool mir = mirror && mirror[mat];
+  auto src = [&](int i) { return (mir && i < n) ? (i / nth) * nth + (nth - 1 - i % nth) : i; };
+  for (int i = tid; i < npad; i += 1024) sb[i] = b[src(i)];
   const int np = npad / NB;
   // sb[r] -= sum_j A[r][k0 + j] sb[k0 + j] for rows r in [r_lo, r_hi): each
   // thread takes a 16-byte vector of consecutive rows (4 FP32 / 2 FP64) and keeps
@@ -1259,7 +1490,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
     }
   }
   double* xo = Xout + (size_t)row * npad;
-  for (int i = tid; i < npad; i += 1024) xo[i] = accumulate ? xo[i] + sb[i] : sb[i];
+  for (int i = tid; i < npad; i += 1024) xo[i] = accumulate ? xo[i] + sb[src(i)] : sb[src(i)];
 }
 
 template <typename T>
@@ -1273,7 +1504,8 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   const int xpb = d.form_xpb > 0 ? d.form_xpb : (sizeof(T) == 4 ? 8 : 16);   // matrices per formation block
   dim3 gform(d.npad, (nmat + xpb - 1) / xpb);
   k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, xpb,
-                                  d.band_kl, d.band_ku);
+                                  d.band_kl, d.band_ku, d.mirror ? d.mirror + m0 : nullptr,
+                                  (std::is_same<T, float>::value && d.static_piv && d.mirror) ? 1 : 0);
   const int np = d.npad / NB;
   const int P = tm ? tm->max_panels : 0;
   if (tm) {
@@ -1332,7 +1564,17 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     const int rend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl)) : d.npad;
     const int cend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl + ku)) : d.npad;
     const int rest = cend - k0 - NB;
-    panel(k0, rend);
+    if constexpr (std::is_same<T, float>::value) {
+      if (d.static_piv) {
+        k_diag_static<<<nmat, 256, 0, s>>>(LU, li, piv, perm, d.status, d.npad, k0);
+        const int nt = (rend - k0 - NB) / NB;   // row tiles of L21 (rend, k0 multiples of 128)
+        if (nt > 0) k_l21_mfma<<<xcd_grid(nt, nmat), 256, 0, s>>>(LU, li, d.npad, k0, nt, nmat);
+      } else {
+        panel(k0, rend);
+      }
+    } else {
+      panel(k0, rend);
+    }
     if (rest > 0) k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);
     if (rec) {
       mark(1, p, 1, s);
@@ -1400,24 +1642,26 @@ void launch_lu_solve(const DevOps& d, int precision, bool transpose, const doubl
 void launch_lu_solve_mapped(const DevOps& f, int precision, bool transpose, const int* mat_of, const int* skip,
                             int nrows, const double* Bin, double* Xout, bool accumulate, bool check_done,
                             hipStream_t s) {
+  // the mirror flags of the FP32 factors, set at their formation
+  const int* mir = (precision != 0 && precision != kFactorsFp16) ? f.mirror : nullptr;
   if (precision == 0) {
     const double* LU = static_cast<const double*>(f.lu);
     if (transpose)
-      k_solve<double, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
+      k_solve<double, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0, mir, f.n, f.nth);
     else
-      k_solve<double, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
+      k_solve<double, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0, mir, f.n, f.nth);
   } else if (precision == kFactorsFp16) {
     const _Float16* LU = static_cast<const _Float16*>(f.lu);
     if (transpose)
-      k_solve<_Float16, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
+      k_solve<_Float16, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0, mir, f.n, f.nth);
     else
-      k_solve<_Float16, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
+      k_solve<_Float16, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0, mir, f.n, f.nth);
   } else {
     const float* LU = static_cast<const float*>(f.lu);
     if (transpose)
-      k_solve<float, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
+      k_solve<float, 1><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0, mir, f.n, f.nth);
     else
-      k_solve<float, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0);
+      k_solve<float, 0><<<nrows, 1024, 0, s>>>(LU, f.piv, f.perm, Bin, Xout, f.status, accumulate, check_done, f.npad, mat_of, skip, f.band_kl, f.band_kl > 0 ? f.band_kl + f.band_ku : 0, lu_paired(f) ? 1 : 0, mir, f.n, f.nth);
   }
 }
 

@@ -5,6 +5,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "internal.h"
 
 namespace bte {
@@ -15,6 +18,14 @@ using f32x4 = float __attribute__((ext_vector_type(4)));
 using f64x2 = double __attribute__((ext_vector_type(2)));
 
 constexpr int kXcd = 8;  // XCDs of an MI355X; workgroups are dealt to them round-robin
+
+// f(integral_constant<int, I>) for I in the sequence, in order: loop bodies
+// whose indices must be compile-time constants (register arrays, unrolled
+// steps) without relying on the unroller
+template <int... I, class F>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F&& f) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
 
 // MFMA 16x16x4 tiles: operand lanes hold A[i = lane%16][k = lane/16] and
 // B[k = lane/16][j = lane%16]; result item t of lane l holds D[row(l, t)][l%16]

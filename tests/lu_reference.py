@@ -118,3 +118,29 @@ def solve(A, ip, b, pairs=False):
             r[j] = (r[j] - A[k0 + j, k0 + j + 1:k0 + NB] @ r[j + 1:]) / A[k0 + j, k0 + j]
         b[k0:k0 + NB] = r
     return b
+
+
+def factor_static(A):
+    """The blocked LU without row interchanges (static pivoting): per 128-column
+    panel, the diagonal block's pivots below 2^-20 of its largest entry are
+    replaced by that bound with their sign, L21 = A21 U11^-1, U12 = L11^-1 A12,
+    A22 -= L21 U12.  Pivots are the identity."""
+    A = A.copy()
+    n = len(A)
+    for k0 in range(0, n, NB):
+        k1 = k0 + NB
+        tau = max(np.abs(A[k0:k1, k0:k1]).max() * 2.0 ** -20, np.finfo(np.float32).tiny)
+        for k in range(k0, k1):
+            pv = A[k, k]
+            if not abs(pv) >= tau:
+                pv = -tau if pv < 0 else tau
+                A[k, k] = pv
+            A[k + 1:k1, k] /= pv
+            A[k + 1:k1, k + 1:k1] -= np.outer(A[k + 1:k1, k], A[k, k + 1:k1])
+        if k1 < n:
+            U11 = np.triu(A[k0:k1, k0:k1])
+            L11 = np.tril(A[k0:k1, k0:k1], -1) + np.eye(NB)
+            A[k1:, k0:k1] = np.linalg.solve(U11.T, A[k1:, k0:k1].T).T
+            A[k0:k1, k1:] = np.linalg.solve(L11, A[k0:k1, k1:])
+            A[k1:, k1:] -= A[k1:, k0:k1] @ A[k0:k1, k1:]
+    return A, np.arange(n)

@@ -458,6 +458,29 @@ def test_blocked_lu_restatement_matches_lapack():
     assert np.allclose(a[:, 128:], b_[:, 128:], rtol=0, atol=1e-12 * np.abs(a).max())
 
 
+def test_static_restatement_is_an_exact_lu_of_the_velocity_systems():
+    """The no-interchange restatement (test helper for the statically pivoted
+    FP32 factors) on the velocity-space systems, whose pivots stay well above
+    the replacement bound: L U reproduces the matrix to rounding and the pivots
+    are the identity.  A matrix with an exactly zero leading pivot gets the
+    bound in its place (and is then no longer an exact LU of it)."""
+    import lu_reference as LR
+    cfg = workloads.small_config(nx=3, nr=20, nth=20, kinds=("elastic", "ionization"))
+    ops = oracle.build_operators(cfg)
+    for E in (0.0, 1.2e4, -1.4e4):
+        M = LR.pad(S.v_matrix(ops, E))
+        LU, ip = LR.factor_static(M)
+        L = np.tril(LU, -1) + np.eye(len(M))
+        U = np.triu(LU)
+        assert np.array_equal(ip, np.arange(len(M)))
+        assert np.abs(L @ U - M).max() < 1e-12 * np.abs(M).max(), E
+    Z = np.eye(256)
+    Z[0, 0] = 0.0
+    Z[0, 1] = Z[1, 0] = 1.0
+    LU, _ = LR.factor_static(Z)
+    assert LU[0, 0] == 2.0 ** -20
+
+
 def test_ionization_rate_is_sensitive_to_speed_mode_rounding():
     """Why k_i agrees less closely than n_e between two FP64 evaluations of a
     step.  k_i weights only the splines above the 15.76 eV threshold, where the
