@@ -84,7 +84,7 @@ KRYLOV = dict(n_bins=128, bin_scale=100.0, restart=12, cycles=3, rtol=1e-12, fac
 
 
 def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=False, krylov=False, banded=False,
-            pairs=None, vsolver=None):
+            pairs=None, vsolver=None, static_piv=None):
     from paper_2502_16555_amd import Solver, _lib
     t0 = time.time()
     s = Solver(cfg, precision=precision)
@@ -99,6 +99,8 @@ def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=Fals
         s.set_tuning(_lib.TUNE_LU_STREAMS, lu_streams)
     if pairs is not None:
         s.set_tuning(_lib.TUNE_PANEL_PAIRS, pairs)
+    if static_piv is not None:
+        s.set_tuning(_lib.TUNE_STATIC_PIVOTING, static_piv)
     import workloads
     ne = workloads.density_profile(s.xhat(), cfg["ic"]["ne_peak"])
     F = s.initial_state(torch.as_tensor(ne, device="cuda:0"), cfg["ic"]["Te_eV"])
@@ -145,6 +147,7 @@ def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=Fals
            "ms_update": tm[0] / nt, "ms_panel": tm[1] / nt, "ms_vwall": tm[2] / nt, "ms_x": tm[4] / nt,
            "update_launches": tm[3] / nt, "lu_streams": s.get_tuning(_lib.TUNE_LU_STREAMS),
            "panel_pairs": s.get_tuning(_lib.TUNE_PANEL_PAIRS),
+           "static_pivoting": s.get_tuning(_lib.TUNE_STATIC_PIVOTING),
            "info": s.info}
     s.close()
     return out
@@ -426,6 +429,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-discharge batching form")
     ap.add_argument("--no-krylov", action="store_true", help="skip the GMRES V-solver leg")
+    ap.add_argument("--no-partial", action="store_true",
+                    help="skip the mixed step with partially pivoted FP32 factors")
     ap.add_argument("--no-banded", action="store_true", help="skip the banded harmonic-basis V-solver leg")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid-model (ions + electrons) leg")
     ap.add_argument("--no-hessenberg", action="store_true", help="skip the Hessenberg-form V-solver leg")
@@ -505,6 +510,8 @@ def main():
                          "lu_streams": main_run["lu_streams"]},
         "lu_tflops_step": info.lu_flops_per_step / (main_run["ms_per_step"] * 1e-3) / 1e12,
         "refine": {"sweeps": main_run["refine_sweeps"], "resid": main_run["refine_resid"]},
+        "pivoting": ("static (no interchanges; E < 0 points factored as their angular mirror image)"
+                     if main_run["static_pivoting"] else "partial"),
     }
     if fp64 is not None:
         line["fp64"] = {"steps_per_s": 1000.0 / fp64["ms_per_step"], "ms_per_step": fp64["ms_per_step"],
@@ -520,6 +527,18 @@ def main():
         line["accuracy"] = {
             "mixed_vs_fp64_gpu": dict(moment_errors(main_run["moments"], fp64["moments"]),
                                       steps=main_run["n_end"])}
+    if not args.no_partial and args.precision != "fp64":
+        # the same mixed step with partially pivoted FP32 factors (128 pivot
+        # searches per panel), for comparison with the statically pivoted default
+        pp = run_gpu(cfg, args.precision, args.steps, warm, torch, args.lu_streams, static_piv=0)
+        line["partial_pivoting"] = {"steps_per_s": 1000.0 / pp["ms_per_step"], "ms_per_step": pp["ms_per_step"],
+                                    "ms_update": pp["ms_update"], "ms_panel": pp["ms_panel"],
+                                    "ms_vwall": pp["ms_vwall"],
+                                    "refine": {"sweeps": pp["refine_sweeps"], "resid": pp["refine_resid"]},
+                                    "static_over_partial_speedup": pp["ms_per_step"] / main_run["ms_per_step"]}
+        if fp64 is not None:
+            line["partial_pivoting"]["vs_fp64_gpu"] = dict(moment_errors(pp["moments"], fp64["moments"]),
+                                                           steps=pp["n_end"])
     if not args.no_krylov:
         kr = run_gpu(cfg, "fp64", args.steps, warm, torch, args.lu_streams, krylov=True)
         line["krylov"] = {"solver": "restarted GMRES per point, FP64, field-binned preconditioner "

@@ -109,9 +109,7 @@ __global__ __launch_bounds__(256) void k_mat_apply(const double* __restrict__ M,
 }
 
 constexpr int kHessThreads = 256;
-// columns of H in flight per thread: fewer at four pairs, where eight would not fit in registers
-template <int P>
-constexpr int hess_ring() { return P >= 4 ? 4 : 8; }
+constexpr int kHessRing = 8;   // columns of H in flight per thread (fewer measured slower)
 constexpr int kHessSeg = 2 * kHessThreads;      // rows per pair index (two per thread)
 
 // row pairs per thread for an order-n solve
@@ -154,7 +152,7 @@ __global__ __launch_bounds__(kHessThreads) void k_hess_solve(const double* __res
                                                              const double* __restrict__ E, double dt,
                                                              const double* __restrict__ Y, double* __restrict__ Z,
                                                              int n, int ld, int* __restrict__ status) {
-  constexpr int NT = kHessThreads, D = hess_ring<P>(), SEG = kHessSeg, LDC = P * NT;   // column stride in pairs
+  constexpr int NT = kHessThreads, D = kHessRing, SEG = kHessSeg, LDC = P * NT;   // column stride in pairs
   const int x = blockIdx.x, tid = threadIdx.x;
   // this thread's pairs of column 0
   const Pair* H = reinterpret_cast<const Pair*>(Hr + h_off[x_disc[x]]) + tid;
