@@ -2,7 +2,8 @@
 
 The library exposes launch shapes that do not change results (bte_set_tuning):
 the number of concurrent factorization groups, the K chunk of the trailing
-update tiles and the number of matrices per formation block.  The best shape
+update tiles, the number of matrices per formation block and the look-ahead
+of the statically pivoted panels.  The best shape
 depends on the size class of the problem (unknowns per point, number of points,
 precision), e.g. a 64-discharge ensemble of 7000+ points against a single
 discharge of 9.  ``autotune`` times a few steps per candidate by coordinate
@@ -22,7 +23,10 @@ def candidates(precision: str) -> dict:
     kc = [16, 8] if precision == "fp64" else [16, 32]
     if precision in ("mixed_bf16", "mixed_bf16x3"):
         kc = [32]   # the bf16 updates have a fixed chunk
-    return {_lib.TUNE_LU_STREAMS: [1, 2], _lib.TUNE_UPDATE_KC: kc, _lib.TUNE_FORM_XPB: [8, 4, 16, 32]}
+    c = {_lib.TUNE_LU_STREAMS: [1, 2], _lib.TUNE_UPDATE_KC: kc, _lib.TUNE_FORM_XPB: [8, 4, 16, 32]}
+    if precision != "fp64":
+        c[_lib.TUNE_LOOK_AHEAD] = [0, 1]   # the statically pivoted panels on a side stream
+    return c
 
 
 def size_class(n: int, nx_total: int, precision: str) -> str:

@@ -71,6 +71,8 @@ struct bte_handle {
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kMaxLuStreams] = {};
   std::vector<hipEvent_t> lu_ev;   // kMaxLuStreams * 8 * max_panels
+  std::vector<hipEvent_t> la_ev;   // 2 kMaxPanels: the factorization's look-ahead (side stream gs[0])
+  int look_ahead = 0;              // BTE_TUNE_LOOK_AHEAD
   bte::LuTimer lu_timer[kMaxLuStreams];
   double ms_acc[6] = {0, 0, 0, 0, 0, 0};
   // Krylov V solver (bte_set_vsolver): factors of the field-binned
@@ -146,6 +148,8 @@ struct bte_handle {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     for (auto& e : lu_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : la_ev)
       if (e) (void)hipEventDestroy(e);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     for (auto& e : join_ev)
@@ -408,7 +412,11 @@ void factor_all(bte_handle* h, hipStream_t s) {
   const int prec = h->cfg.precision;
   const int G = std::max(1, std::min(h->lu_streams, d.nx_total));
   if (G == 1) {
-    bte::launch_lu_factor(d, prec, s, h->timing ? &h->lu_timer[0] : nullptr);
+    // the side stream of the first group is free: the look-ahead takes it
+    bte::LuLookAhead la;
+    la.side = h->gs[0];
+    la.ev = h->la_ev.data();
+    bte::launch_lu_factor(d, prec, s, h->timing ? &h->lu_timer[0] : nullptr, 0, -1, h->look_ahead ? &la : nullptr);
     return;
   }
   HIP_OK(hipEventRecord(h->fork_ev, s));
@@ -784,6 +792,8 @@ bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle
       HIP_OK(hipEventCreateWithFlags(&h->join_ev[g], hipEventDisableTiming));
     }
     HIP_OK(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+    h->la_ev.assign(2 * bte::kMaxPanels, nullptr);
+    for (auto& e : h->la_ev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     // pointers inside cfg are not retained
     h->cfg.proc = nullptr;
@@ -1452,6 +1462,10 @@ bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value) {
       if (fp64 && value == 1) return BTE_EINVAL;
       h->d.static_piv = value;
       return BTE_OK;
+    case BTE_TUNE_LOOK_AHEAD:
+      if (value != 0 && value != 1) return BTE_EINVAL;
+      h->look_ahead = value;
+      return BTE_OK;
     default:
       return BTE_EINVAL;
   }
@@ -1470,6 +1484,7 @@ bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value) {
     case BTE_TUNE_FORM_XPB: *value = h->d.form_xpb ? h->d.form_xpb : (fp64 ? 16 : 8); return BTE_OK;
     case BTE_TUNE_PANEL_PAIRS: *value = h->d.lu_pairs; return BTE_OK;
     case BTE_TUNE_STATIC_PIVOTING: *value = h->d.static_piv; return BTE_OK;
+    case BTE_TUNE_LOOK_AHEAD: *value = h->look_ahead; return BTE_OK;
     default: return BTE_EINVAL;
   }
 }

@@ -204,8 +204,17 @@ inline bool lu_paired(const DevOps& d) { return d.lu_pairs != 0 && d.band_kl == 
 // ---- V step (kernels_lu.hip) ------------------------------------------------
 // Forms I - dt (n0 C + E A) (padded to npad with identity) and factors it in
 // place, for the points m0 .. m0+count-1 (count < 0: to the last point).
+// Look-ahead of the statically pivoted FP32 factorization: a side stream and
+// 2 kMaxPanels events (no timing).  Where a trailing update precedes the next
+// panel, its first tile column (that panel's columns) goes first, and the next
+// panel's diagonal-block factorization and L21 run on the side stream while the
+// rest of the update runs on the main stream.
+struct LuLookAhead {
+  hipStream_t side = nullptr;
+  hipEvent_t* ev = nullptr;
+};
 void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer = nullptr, int m0 = 0,
-                      int count = -1);
+                      int count = -1, const LuLookAhead* la = nullptr);
 // A22 -= L21 U12 of the kd = 128 (one panel) or 256 (two panels) columns from
 // k0 for nmat matrices (mtr x mtc tiles of 128, column tiles tj0 .. tj0 + mtc - 1
 // of the trailing matrix from k0 + kd): kind 0 FP64, 1 FP32, 2 FP32 with bf16

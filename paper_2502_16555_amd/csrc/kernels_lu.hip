@@ -1494,7 +1494,8 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
 }
 
 template <typename T>
-void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, int bf16_terms) {
+void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, int bf16_terms,
+                 const LuLookAhead* la) {
   const size_t np2 = (size_t)d.npad * d.npad;
   T* LU = static_cast<T*>(d.lu) + (size_t)m0 * np2;
   T* xs = static_cast<T*>(d.xscr) + (size_t)m0 * d.npad * NB;
@@ -1555,6 +1556,17 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     launch_update(kind, LU, d.npad, k0, mtr, mtc, 0, nmat, alt_kc, s, kd);
     if (tm) ++tm->launches;
   };
+  // statically pivoted FP32 panels: the diagonal block and L21 (on stream st)
+  auto static_panel = [&](int k0, int rend, hipStream_t st) {
+    if constexpr (std::is_same<T, float>::value) {
+      k_diag_static<<<nmat, 256, 0, st>>>(LU, li, piv, perm, d.status, d.npad, k0);
+      const int nt = (rend - k0 - NB) / NB;   // row tiles of L21 (rend, k0 multiples of 128)
+      if (nt > 0) k_l21_mfma<<<xcd_grid(nt, nmat), 256, 0, st>>>(LU, li, d.npad, k0, nt, nmat);
+    }
+  };
+  const bool stat = std::is_same<T, float>::value && d.static_piv;
+  const bool ahead = stat && la && la->side && la->ev && np <= kMaxPanels;
+  bool done_ahead[kMaxPanels] = {};   // panel already factored on the side stream
   for (int p = 0; p < np; ++p) {
     const int k0 = p * NB;
     const bool rec = tm && p < P;
@@ -1564,14 +1576,9 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     const int rend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl)) : d.npad;
     const int cend = kl > 0 ? std::min(d.npad, round_up(k0 + NB + kl + ku)) : d.npad;
     const int rest = cend - k0 - NB;
-    if constexpr (std::is_same<T, float>::value) {
-      if (d.static_piv) {
-        k_diag_static<<<nmat, 256, 0, s>>>(LU, li, piv, perm, d.status, d.npad, k0);
-        const int nt = (rend - k0 - NB) / NB;   // row tiles of L21 (rend, k0 multiples of 128)
-        if (nt > 0) k_l21_mfma<<<xcd_grid(nt, nmat), 256, 0, s>>>(LU, li, d.npad, k0, nt, nmat);
-      } else {
-        panel(k0, rend);
-      }
+    if (stat) {
+      if (done_ahead[p]) (void)hipStreamWaitEvent(s, la->ev[2 * p + 1], 0);
+      else static_panel(k0, rend, s);
     } else {
       panel(k0, rend);
     }
@@ -1599,12 +1606,28 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
       mark(0, p, 0, s);
     }
     const int mtr = rest > 0 ? (rend - k0 - NB) / 128 : 0;
+    // with the look-ahead, an update that reaches the next panel takes that
+    // panel's tile column first; the panel then factors on the side stream
+    // while the other tile columns update on this one
+    auto update_ahead = [&](int ku0, int kd) {
+      const int kn = k0 + NB, rn = kl > 0 ? std::min(d.npad, round_up(kn + NB + kl)) : d.npad;
+      launch_update(kind, LU, d.npad, ku0, mtr, 1, 0, nmat, alt_kc, s, kd);
+      (void)hipEventRecord(la->ev[2 * (p + 1)], s);
+      (void)hipStreamWaitEvent(la->side, la->ev[2 * (p + 1)], 0);
+      static_panel(kn, rn, la->side);
+      (void)hipEventRecord(la->ev[2 * (p + 1) + 1], la->side);
+      done_ahead[p + 1] = true;
+      if (nct > 1) launch_update(kind, LU, d.npad, ku0, mtr, nct - 1, 1, nmat, alt_kc, s, kd);
+      if (tm) tm->launches += nct > 1 ? 2 : 1;
+    };
     if (first) {
       update(k0, mtr, 1, NB);                    // the next panel's columns only
     } else if (second) {
-      update(k0 - NB, mtr, nct, 2 * NB);         // both panels, the columns beyond
+      if (ahead && mtr > 0 && nct >= 1) update_ahead(k0 - NB, 2 * NB);
+      else update(k0 - NB, mtr, nct, 2 * NB);    // both panels, the columns beyond
     } else if (mtr > 0) {
-      update(k0, mtr, nct, NB);
+      if (ahead && nct >= 1 && p + 1 < np) update_ahead(k0, NB);
+      else update(k0, mtr, nct, NB);
     }
     if (rec) {
       mark(0, p, 1, s);
@@ -1615,12 +1638,13 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
 
 }  // namespace
 
-void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer, int m0, int count) {
+void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer, int m0, int count,
+                      const LuLookAhead* la) {
   if (count < 0) count = d.nx_total - m0;
   if (count <= 0) return;
   // precision: 0 FP64, 1 FP32, 2 FP32 with a bf16 update, 3 FP32 with a split (3-term) bf16 update
-  if (precision == 0) factor_impl<double>(d, s, timer, m0, count, 0);
-  else factor_impl<float>(d, s, timer, m0, count, precision == 2 ? 1 : (precision == 3 ? 3 : 0));
+  if (precision == 0) factor_impl<double>(d, s, timer, m0, count, 0, nullptr);
+  else factor_impl<float>(d, s, timer, m0, count, precision == 2 ? 1 : (precision == 3 ? 3 : 0), la);
 }
 
 namespace {

@@ -19,15 +19,16 @@ class FakeSolver:
 def test_coordinate_descent_finds_separable_minimum():
     s = FakeSolver()
     cost = {_lib.TUNE_LU_STREAMS: {1: 3.0, 2: 1.0}, _lib.TUNE_UPDATE_KC: {32: 0.5, 16: 2.0},
-            _lib.TUNE_FORM_XPB: {16: 1.0, 4: 4.0, 8: 0.25, 32: 2.0}}
+            _lib.TUNE_FORM_XPB: {16: 1.0, 4: 4.0, 8: 0.25, 32: 2.0}, _lib.TUNE_LOOK_AHEAD: {0: 0.5, 1: 0.25}}
 
     def measure():
         return sum(cost[k][s.settings[k]] for k in cost)
 
     best, c, trials = AT.coordinate_descent(s.set_tuning, measure, AT.candidates("mixed_fp32"))
-    assert best == {_lib.TUNE_LU_STREAMS: 2, _lib.TUNE_UPDATE_KC: 32, _lib.TUNE_FORM_XPB: 8}
-    assert c == measure() == 1.75
-    assert len(trials) == 1 + 1 + 1 + 3
+    assert best == {_lib.TUNE_LU_STREAMS: 2, _lib.TUNE_UPDATE_KC: 32, _lib.TUNE_FORM_XPB: 8,
+                    _lib.TUNE_LOOK_AHEAD: 1}
+    assert c == measure() == 2.0
+    assert len(trials) == 1 + 1 + 1 + 3 + 1
     assert s.settings == best          # the handle is left at the best settings
 
 
