@@ -509,10 +509,11 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
 // kernels apply them as no-ops.
 //   k_diag_static  one 256-thread block per matrix, thread t holding the 8 x 8
 //                  tile (rows 8 (t / 16), columns 8 (t mod 16)) of the 128 x 128
-//                  diagonal block: A11 = L11 U11 by rank-1 steps, then
-//                  X = U11^-1 by rank-1 steps from the last row up, one barrier
-//                  per step (the step's row and column through LDS); X goes
-//                  row-major into the matrix's linv slot;
+//                  diagonal block: A11 = L11 U11 by rank-1 steps, one barrier
+//                  per step (the step's row and column through LDS); then
+//                  X = U11^-1 by 16 x 16 blocks in LDS (the diagonal blocks,
+//                  then seven levels of off-diagonal blocks); X goes row-major
+//                  into the matrix's linv slot;
 //   k_l21_mfma     L21 = A21 X for 128 rows per block: one MFMA product (K =
 //                  128, the zero blocks of X skipped), A21 straight from HBM.
 // ---------------------------------------------------------------------------
@@ -623,51 +624,75 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
     pm[1 + kMaxSwapRows + tid] = k0 + tid;
     if (tid == 0) pm[0] = NB;
   }
-  // ---- X = U11^-1 from X = I, k = 127 .. 0: row k of X times 1/u_kk, then
-  // X[i][:] -= u_ik X[k][:] for the rows i < k.  Step k publishes row k of X
-  // (scaled) and column k of U above the diagonal (zeros elsewhere).
-  __shared__ float s_rd[NB];
-  if (tr == tc) {
+  // ---- X = U11^-1 by 16 x 16 blocks (X upper triangular, kept transposed in
+  // LDS, XT[col][row]): the diagonal blocks X_bb = U_bb^-1 by back substitution,
+  // then by levels d = 1..7 the blocks X_{a,a+d} = -X_aa sum_{m=a+1}^{a+d}
+  // U_am X_{m,a+d}; the blocks of one level are independent.
+  __shared__ __align__(16) float sU[NB][NB + 4];    // U11 row-major, zeros below the diagonal
+  __shared__ __align__(16) float sXT[NB][NB + 4];   // X transposed
+  __shared__ float sT[8][16][17];                   // a level's sums, per block
 #pragma unroll
-    for (int rr = 0; rr < 8; ++rr) s_rd[8 * tr + rr] = 1.0f / a[rr][rr];
+  for (int rr = 0; rr < 8; ++rr) {
+    const int i = 8 * tr + rr;
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int jj = 8 * tc + cc;
+      sU[i][jj] = (i <= jj) ? a[rr][cc] : 0.0f;
+      sXT[i][jj] = 0.0f;
+    }
   }
-  float x[8][8];
-#pragma unroll
-  for (int rr = 0; rr < 8; ++rr)
-#pragma unroll
-    for (int cc = 0; cc < 8; ++cc) x[rr][cc] = (tr == tc && rr == cc) ? 1.0f : 0.0f;
   __syncthreads();
-  for (int kb = 15; kb >= 0; --kb) {
+  if (tid < NB) {   // thread (b, c): column c of X_bb
+    const int b = tid >> 4, c = tid & 15, o = 16 * b;
+    float xv[16];
 #pragma unroll
-    for (int kk = 7; kk >= 0; --kk) {
-      const int k = 8 * kb + kk, par = kk & 1;
-      if (tr == kb) {
-        const float rd = s_rd[k];
+    for (int i = 15; i >= 0; --i) {
+      float v = (i == c) ? 1.0f : 0.0f;
 #pragma unroll
-        for (int cc = 0; cc < 8; ++cc) x[kk][cc] *= rd;
-        put8(&s_row[par][8 * tc], x[kk]);
-      }
-      if (tc == kb) {
-        float v[8];
+      for (int m2 = i + 1; m2 < 16; ++m2) v = fmaf(-sU[o + i][o + m2], xv[m2], v);
+      xv[i] = v / sU[o + i][o + i];
+    }
 #pragma unroll
-        for (int rr = 0; rr < 8; ++rr) v[rr] = (tr < kb || (tr == kb && rr < kk)) ? a[rr][kk] : 0.0f;
-        put8(&s_col[par][8 * tr], v);
+    for (int i = 0; i < 16; ++i) sXT[o + c][o + i] = xv[i];
+  }
+  __syncthreads();
+  {
+    const int i = tid >> 4, c = tid & 15;   // this thread's element of every block of a level
+    for (int d = 1; d < 8; ++d) {
+      for (int ab = 0; ab + d < 8; ++ab) {
+        const int b = ab + d;
+        // T[i][c] = sum_{m=ab+1}^{b} sum_q U[16 ab + i][16 m + q] X[16 m + q][16 b + c]
+        float t = 0.0f;
+        for (int m2 = ab + 1; m2 <= b; ++m2) {
+#pragma unroll
+          for (int q = 0; q < 16; q += 4) {
+            const float4 u = *reinterpret_cast<const float4*>(&sU[16 * ab + i][16 * m2 + q]);
+            const float4 x = *reinterpret_cast<const float4*>(&sXT[16 * b + c][16 * m2 + q]);
+            t = fmaf(u.x, x.x, t);
+            t = fmaf(u.y, x.y, t);
+            t = fmaf(u.z, x.z, t);
+            t = fmaf(u.w, x.w, t);
+          }
+        }
+        sT[ab][i][c] = t;
       }
       __syncthreads();
-      if (32 * wid < k) {   // a wavefront whose rows all lie at or below row k skips
-        float cv[8], rv[8];
-        get8(&s_col[par][8 * tr], cv);
-        get8(&s_row[par][8 * tc], rv);
+      for (int ab = 0; ab + d < 8; ++ab) {
+        const int b = ab + d;
+        // X_{ab,b}[i][c] = -sum_q X_{ab,ab}[i][q] T[q][c]
+        float v = 0.0f;
 #pragma unroll
-        for (int rr = 0; rr < 8; ++rr)
-#pragma unroll
-          for (int cc = 0; cc < 8; ++cc) x[rr][cc] = fmaf(-cv[rr], rv[cc], x[rr][cc]);
+        for (int q = 0; q < 16; ++q) v = fmaf(sXT[16 * ab + q][16 * ab + i], sT[ab][q][c], v);
+        sXT[16 * b + c][16 * ab + i] = -v;
       }
+      __syncthreads();
     }
   }
   float* xo = linv + (size_t)mat * kLinvElems;   // X row-major
-#pragma unroll
-  for (int rr = 0; rr < 8; ++rr) put8(xo + (8 * tr + rr) * NB + 8 * tc, x[rr]);
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int k = e / NB, c = e % NB;
+    xo[e] = sXT[c][k];
+  }
   if (__syncthreads_or(nonfinite) && tid == 0) atomicOr(status, kStNonFinite);
 }
 
