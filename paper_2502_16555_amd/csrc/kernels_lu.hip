@@ -713,10 +713,15 @@ __global__ __launch_bounds__(256, 2) void k_l21_mfma(float* __restrict__ LU, con
   for (int q = 0; q < 32; ++q)
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) av[q][rb] = A[(size_t)(k0 + 4 * q + lk) * npad + r0 + 32 * w + 16 * rb + li];
+  // X into LDS: every load issued before the first store (one wait, not sixteen)
   const float4* xs = reinterpret_cast<const float4*>(linv + (size_t)mat * kLinvElems);
-  for (int e = tid; e < NB * NB / 4; e += 256) {
-    const int rw = e / (NB / 4), q = e % (NB / 4);
-    *reinterpret_cast<float4*>(&sX[rw][4 * q]) = xs[e];
+  float4 xr[NB * NB / 4 / 256];
+#pragma unroll
+  for (int u = 0; u < NB * NB / 4 / 256; ++u) xr[u] = xs[tid + 256 * u];
+#pragma unroll
+  for (int u = 0; u < NB * NB / 4 / 256; ++u) {
+    const int e = tid + 256 * u, rw = e / (NB / 4), q = e % (NB / 4);
+    *reinterpret_cast<float4*>(&sX[rw][4 * q]) = xr[u];
   }
   __syncthreads();
   using Acc = Mma<float>::acc;
