@@ -20,7 +20,8 @@ constexpr int kMaxPanels = kMaxRows / kNB;
 constexpr int kPermStride = 1 + 2 * kMaxSwapRows;  // one panel's row permutation: nR, rows, sources
 // per matrix: the eight 16 x 16 diagonal-block inverses of a panel's unit lower
 // block L11 (row-major), then the inverse of L11 itself (column-major)
-constexpr int kLinvElems = 8 * 256 + kNB * kNB;
+constexpr int kLinvXOff = 8 * 256 + kNB * kNB;   // after L11's inverses: U11^-1 of a statically pivoted panel
+constexpr int kLinvElems = kLinvXOff + kNB * kNB;
 constexpr int kFactorsFp16 = 4;   // solve precision code: FP32 factors stored in FP16
 
 // Device status word bits.
@@ -65,7 +66,7 @@ struct DevOps {
   void* lu = nullptr;          // [nx_total][npad][npad] of T (double or float), column-major
   void* xscr = nullptr;        // [nx_total][npad][kNB] of T: interchange staging of extra rows
   int lu_pairs = 1;             // dense factors: panels in pairs (K = 256 trailing updates)
-  void* linv = nullptr;        // [nx_total][kLinvElems] of T: inverses of L11's diagonal blocks, then of L11
+  void* linv = nullptr;        // [nx_total][kLinvElems] of T: inverses of L11's diagonal blocks, of L11, of U11
   int* piv = nullptr;          // [nx_total][npad]
   int* perm = nullptr;         // [nx_total][kMaxPanels][kPermStride] row permutation of every panel
   double* E = nullptr;         // [nx_total]

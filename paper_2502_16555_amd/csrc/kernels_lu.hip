@@ -52,7 +52,9 @@ constexpr int NB = kNB;
 // Matrix formation, column c of points x0..x0+xpb-1: I - dt (n0_x C + E_x A) with
 // identity padding.  CT/AT hold C^T and A^T row-major, i.e. the columns of C
 // and A contiguously; a block reads its column of each once and writes it into
-// xpb matrices with 16-byte streaming stores, so the launch is bound by the writes.
+// xpb matrices with 16-byte streaming stores.  The blocks of one column run
+// together on one XCD, so that the column comes from HBM once and from that
+// XCD's L2 for the others, and the launch is bound by the writes.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* __restrict__ CT,
@@ -60,8 +62,11 @@ __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* 
                                               const double* __restrict__ n0x, double dt, int n, int npad, int nmat,
                                               int xpb, int kl, int ku, int* __restrict__ mirror, int do_mirror) {
   constexpr int CH = kMaxRows / 1024;  // 4-row groups per thread
-  const int c = blockIdx.x, tid = threadIdx.x;
-  const int x0 = blockIdx.y * xpb, x1 = min(nmat, x0 + xpb);
+  const int tid = threadIdx.x;
+  int c, xb;
+  xcd_map(blockIdx.x, (nmat + xpb - 1) / xpb, npad, &c, &xb);
+  if (c >= npad) return;
+  const int x0 = xb * xpb, x1 = min(nmat, x0 + xpb);
   // banded factors (lower / upper bandwidth kl / ku, kl > 0): only rows
   // [r_lo, r_hi) of column c are ever read, from the U rows of the first panel
   // whose trailing columns reach c to the last L row of c's own panel
@@ -513,7 +518,9 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
 //                  per step (the step's row and column through LDS); then
 //                  X = U11^-1 by 16 x 16 blocks in LDS (the diagonal blocks,
 //                  then seven levels of off-diagonal blocks); X goes row-major
-//                  into the matrix's linv slot;
+//                  into the matrix's linv slot after L11's inverses, and the
+//                  inverses of L11's eight diagonal blocks (k_dinv's output)
+//                  are formed beside those of U11's, by the other 128 threads;
 //   k_l21_mfma     L21 = A21 X for 128 rows per block: one MFMA product (K =
 //                  128, the zero blocks of X skipped), A21 straight from HBM.
 // ---------------------------------------------------------------------------
@@ -631,6 +638,9 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
   __shared__ __align__(16) float sU[NB][NB + 4];    // U11 row-major, zeros below the diagonal
   __shared__ __align__(16) float sXT[NB][NB + 4];   // X transposed
   __shared__ float sT[8][16][17];                   // a level's sums, per block
+  // (the strict lower parts of L11's diagonal blocks wait in sT, which the
+  // levels use only later)
+  const bool dblk = (tr >> 1) == (tc >> 1);
 #pragma unroll
   for (int rr = 0; rr < 8; ++rr) {
     const int i = 8 * tr + rr;
@@ -639,6 +649,7 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
       const int jj = 8 * tc + cc;
       sU[i][jj] = (i <= jj) ? a[rr][cc] : 0.0f;
       sXT[i][jj] = 0.0f;
+      if (dblk && i > jj) sT[tr >> 1][i & 15][jj & 15] = a[rr][cc];
     }
   }
   __syncthreads();
@@ -654,6 +665,18 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) sXT[o + c][o + i] = xv[i];
+  } else {          // thread (b, c): column c of L_bb^-1 (unit lower) by forward substitution
+    const int b = (tid - NB) >> 4, c = tid & 15;
+    float x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = (r == c) ? 1.0f : 0.0f;
+#pragma unroll
+    for (int r = 1; r < 16; ++r)
+#pragma unroll
+      for (int k = 0; k < r; ++k) x[r] -= sT[b][r][k] * x[k];
+    float* out = linv + (size_t)mat * kLinvElems + b * 256;   // [b][r][c] row-major
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[r * 16 + c] = x[r];
   }
   __syncthreads();
   {
@@ -688,7 +711,7 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
       __syncthreads();
     }
   }
-  float* xo = linv + (size_t)mat * kLinvElems;   // X row-major
+  float* xo = linv + (size_t)mat * kLinvElems + kLinvXOff;   // X row-major
   for (int e = tid; e < NB * NB; e += 256) {
     const int k = e / NB, c = e % NB;
     xo[e] = sXT[c][k];
@@ -714,7 +737,7 @@ __global__ __launch_bounds__(256, 2) void k_l21_mfma(float* __restrict__ LU, con
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) av[q][rb] = A[(size_t)(k0 + 4 * q + lk) * npad + r0 + 32 * w + 16 * rb + li];
   // X into LDS: every load issued before the first store (one wait, not sixteen)
-  const float4* xs = reinterpret_cast<const float4*>(linv + (size_t)mat * kLinvElems);
+  const float4* xs = reinterpret_cast<const float4*>(linv + (size_t)mat * kLinvElems + kLinvXOff);
   float4 xr[NB * NB / 4 / 256];
 #pragma unroll
   for (int u = 0; u < NB * NB / 4 / 256; ++u) xr[u] = xs[tid + 256 * u];
@@ -1234,61 +1257,62 @@ __global__ __launch_bounds__(256) void k_perm_lp(T* __restrict__ LU, const int* 
 // One wavefront's triangular solve with a 128 x 128 diagonal block staged in
 // LDS; v0 / v1 hold rows lane / 64 + lane and each solved value is passed on by
 // a lane read.  FWD: ascending (lower triangular), else descending (upper);
-// SCALE: a value is multiplied by the reciprocal of its diagonal entry before
-// it is passed on (non-unit diagonal); TR: the block is used transposed.  For
-// FP32 and FP16 factors the entries the chain needs are read from LDS in chunks
-// of 4 pivots with the next chunk in flight, so that the sequential chain does
-// not wait on an LDS read at every step (4x shorter chains at n = 2048); the
-// two halves of the block are separate loops, so that the register holding
-// the current pivot is known at compile time.
+// SCALE: a value is multiplied by the reciprocal of its diagonal entry (s_rc)
+// before it is passed on (non-unit diagonal); TR: the block is used
+// transposed.  The staged block holds only the strict triangle that the chain
+// reads, with zeros elsewhere, so every step updates all rows without a mask
+// (a finished row gets exactly zero).  A scaled row keeps its unscaled value
+// to the end and is multiplied once after the chain, giving the same product
+// as scaling it at its own step.  For FP32 and FP16 factors the entries the
+// chain needs are read from LDS in chunks of 4 pivots with the next chunk in
+// flight, so that the sequential chain does not wait on an LDS read at every
+// step; the two halves of the block are separate loops, so that the register
+// holding the current pivot is known at compile time and the half of the rows
+// that a half of the pivots cannot reach is skipped.
 // ---------------------------------------------------------------------------
 template <typename T, bool FWD, bool SCALE, bool TR, int H>
-__device__ __attribute__((always_inline)) inline void diag_half(const T (*sD)[NB + 1], int lane, double& v0,
-                                                                double& v1, double r0, double r1) {
+__device__ __attribute__((always_inline)) inline void diag_half(const T (*sD)[NB + 1], const double* s_rc,
+                                                                int lane, double& v0, double& v1) {
   // pivots 64 H .. 64 H + 63, whose values live in v0 (H = 0) or v1 (H = 1);
   // the entries of 4 pivots are in registers while those of the next 4 load
   constexpr int CH = 4;
   constexpr int base = 64 * H;
+  constexpr bool R0 = FWD ? H == 0 : true;   // rows 0 .. 63 below / above these pivots
+  constexpr bool R1 = FWD ? true : H == 1;   // rows 64 .. 127
   T c0[CH], c1[CH], n0[CH], n1[CH];
-  auto ld = [&](T (&a)[CH], T (&b)[CH], int i0) {
+  double q[CH], nq[CH];
+  auto ld = [&](T (&a)[CH], T (&b)[CH], double (&r)[CH], int i0) {
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-      a[u] = TR ? sD[i0 + u][lane] : sD[lane][i0 + u];
-      b[u] = TR ? sD[i0 + u][64 + lane] : sD[64 + lane][i0 + u];
+      if (R0) a[u] = TR ? sD[i0 + u][lane] : sD[lane][i0 + u];
+      if (R1) b[u] = TR ? sD[i0 + u][64 + lane] : sD[64 + lane][i0 + u];
+      if (SCALE) r[u] = s_rc[i0 + u];
     }
   };
-  ld(c0, c1, base + (FWD ? 0 : 64 - CH));
+  ld(c0, c1, q, base + (FWD ? 0 : 64 - CH));
   for (int k = 0; k < 64 / CH; ++k) {
     const int i0 = base + (FWD ? k * CH : 64 - CH - k * CH);
-    if (k + 1 < 64 / CH) ld(n0, n1, FWD ? i0 + CH : i0 - CH);
+    if (k + 1 < 64 / CH) ld(n0, n1, nq, FWD ? i0 + CH : i0 - CH);
 #pragma unroll
     for (int uu = 0; uu < CH; ++uu) {
       const int u = FWD ? uu : CH - 1 - uu;
-      const int i = i0 + u;
-      double& vp = H ? v1 : v0;
-      if constexpr (SCALE) {
-        if (lane == i - base) vp = vp * (H ? r1 : r0);
-      }
-      const double xi = readlane_f64(vp, i - base);
-      if (FWD ? lane > i : lane < i) v0 -= static_cast<double>(c0[u]) * xi;
-      if (FWD ? 64 + lane > i : 64 + lane < i) v1 -= static_cast<double>(c1[u]) * xi;
+      double xi = readlane_f64(H ? v1 : v0, i0 + u - base);
+      if constexpr (SCALE) xi *= q[u];
+      if constexpr (R0) v0 -= static_cast<double>(c0[u]) * xi;
+      if constexpr (R1) v1 -= static_cast<double>(c1[u]) * xi;
     }
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
       c0[u] = n0[u];
       c1[u] = n1[u];
+      q[u] = nq[u];
     }
   }
 }
 
 template <typename T, bool FWD, bool SCALE, bool TR>
-__device__ __attribute__((always_inline)) inline void diag_chain(const T (*sD)[NB + 1], int lane, double& v0,
-                                                                 double& v1) {
-  double r0 = 1.0, r1 = 1.0;
-  if constexpr (SCALE) {
-    r0 = 1.0 / static_cast<double>(sD[lane][lane]);
-    r1 = 1.0 / static_cast<double>(sD[64 + lane][64 + lane]);
-  }
+__device__ __attribute__((always_inline)) inline void diag_chain(const T (*sD)[NB + 1], const double* s_rc,
+                                                                 int lane, double& v0, double& v1) {
   if constexpr (sizeof(T) == 8) {
     // FP64: one loop, unrolled by 4 (prefetched chunks spill next to the strip)
 #pragma unroll 4
@@ -1296,20 +1320,21 @@ __device__ __attribute__((always_inline)) inline void diag_chain(const T (*sD)[N
       const int i = FWD ? k : NB - 1 - k;
       const double l0 = TR ? sD[i][lane] : sD[lane][i];
       const double l1 = TR ? sD[i][64 + lane] : sD[64 + lane][i];
-      if constexpr (SCALE) {
-        if (i < 64 && lane == i) v0 = v0 * r0;
-        if (i >= 64 && lane == i - 64) v1 = v1 * r1;
-      }
-      const double xi = (i < 64) ? readlane_f64(v0, i) : readlane_f64(v1, i - 64);
-      if (FWD ? lane > i : lane < i) v0 -= l0 * xi;
-      if (FWD ? 64 + lane > i : 64 + lane < i) v1 -= l1 * xi;
+      double xi = (i < 64) ? readlane_f64(v0, i) : readlane_f64(v1, i - 64);
+      if constexpr (SCALE) xi *= s_rc[i];
+      v0 -= l0 * xi;
+      v1 -= l1 * xi;
     }
   } else if constexpr (FWD) {
-    diag_half<T, FWD, SCALE, TR, 0>(sD, lane, v0, v1, r0, r1);
-    diag_half<T, FWD, SCALE, TR, 1>(sD, lane, v0, v1, r0, r1);
+    diag_half<T, FWD, SCALE, TR, 0>(sD, s_rc, lane, v0, v1);
+    diag_half<T, FWD, SCALE, TR, 1>(sD, s_rc, lane, v0, v1);
   } else {
-    diag_half<T, FWD, SCALE, TR, 1>(sD, lane, v0, v1, r0, r1);
-    diag_half<T, FWD, SCALE, TR, 0>(sD, lane, v0, v1, r0, r1);
+    diag_half<T, FWD, SCALE, TR, 1>(sD, s_rc, lane, v0, v1);
+    diag_half<T, FWD, SCALE, TR, 0>(sD, s_rc, lane, v0, v1);
+  }
+  if constexpr (SCALE) {
+    v0 *= s_rc[lane];
+    v1 *= s_rc[64 + lane];
   }
 }
 
@@ -1320,6 +1345,10 @@ __device__ __attribute__((always_inline)) inline void diag_chain(const T (*sD)[N
 // Diagonal blocks are staged in LDS and solved by one wavefront (two rows per
 // lane); the off-diagonal strips are applied column-oriented (thread per row)
 // or, for the transposed factors, as per-column dot products (wave per column).
+// The next diagonal block is loaded into registers before the strip that
+// precedes its use, so that its loads travel with the strip's; a panel's
+// gather / scatter is skipped when the panel interchanges no rows (always,
+// for statically pivoted factors).
 // ---------------------------------------------------------------------------
 template <typename T, int TRANSPOSE>
 __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const int* __restrict__ piv,
@@ -1336,6 +1365,8 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
   if (skip && skip[row]) return;
   __shared__ double sb[kMaxRows];
   __shared__ T sD[NB][NB + 1];
+  __shared__ double s_rc[NB];
+  __shared__ int s_nr[kMaxPanels];
   __shared__ double s_part[sizeof(T) < 8 ? 512 * Vec4<T>::per : 1];
   const int mat = mat_of ? mat_of[row] : row;
   const T* A = LU + (size_t)mat * npad * npad;
@@ -1348,6 +1379,8 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
   auto src = [&](int i) { return (mir && i < n) ? (i / nth) * nth + (nth - 1 - i % nth) : i; };
   for (int i = tid; i < npad; i += 1024) sb[i] = b[src(i)];
   const int np = npad / NB;
+  const int* pmat = perm + (size_t)mat * kMaxPanels * kPermStride;
+  if (tid < np) s_nr[tid] = pmat[(size_t)tid * kPermStride];   // rows each panel's interchanges move
   // sb[r] -= sum_j A[r][k0 + j] sb[k0 + j] for rows r in [r_lo, r_hi): each
   // thread takes a 16-byte vector of consecutive rows (4 FP32 / 2 FP64) and keeps
   // JB column loads in flight (16 FP32, 8 FP64 and FP16: 16 FP64 loads spilled); FP32 and FP16 split the 128 columns between the
@@ -1396,63 +1429,76 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
       }
     }
   };
-  auto stage_diag = [&](int k0) {  // all loads issued before the LDS stores
-    constexpr int NS = NB * NB / 1024;
-    T v[NS];
+  // diagonal block of the panel at k0: loads into registers, then LDS stores
+  // of the strict triangle the chain reads (lower: L; upper: U, whose
+  // diagonal goes to s_rc as reciprocals), zeros elsewhere
+  constexpr int NS = NB * NB / 1024;
+  T dv[NS];
+  auto load_diag = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
       const int e = tid + 1024 * u;
-      v[u] = A[(size_t)(k0 + e / NB) * npad + k0 + e % NB];
-    }
-#pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int e = tid + 1024 * u;
-      sD[e % NB][e / NB] = v[u];
+      dv[u] = A[(size_t)(k0 + e / NB) * npad + k0 + e % NB];
     }
   };
+  auto store_diag = [&](bool upper) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + 1024 * u;
+      const int r = e % NB, c = e / NB;
+      if (upper && r == c) s_rc[r] = 1.0 / static_cast<double>(dv[u]);
+      sD[r][c] = (upper ? r < c : r > c) ? dv[u] : T(0);
+    }
+  };
+  // the panel's interchanges as one gather / scatter over its rows (INV: the
+  // inverse), skipped when the panel moves no rows
+  auto permute = [&](int q, bool inv) {
+    const int nR = s_nr[q];
+    if (nR == 0) return;
+    const int* pm = pmat + (size_t)q * kPermStride;
+    double pv = 0.0;
+    if (tid < nR) pv = sb[pm[1 + (inv ? 0 : kMaxSwapRows) + tid]];
+    __syncthreads();
+    if (tid < nR) sb[pm[1 + (inv ? kMaxSwapRows : 0) + tid]] = pv;
+    __syncthreads();
+  };
+  // wave 0 solves the panel's rows of sb with the staged block
+  auto chain = [&](int k0, auto fwd, auto scale, auto tr) {
+    if (w == 0) {
+      double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
+      diag_chain<T, decltype(fwd)::value, decltype(scale)::value, decltype(tr)::value>(sD, s_rc, lane, v0, v1);
+      sb[k0 + lane] = v0;
+      sb[k0 + 64 + lane] = v1;
+    }
+  };
+  using Yes = std::true_type;
+  using No = std::false_type;
+  load_diag(0);
   __syncthreads();
   if (!TRANSPOSE) {
     for (int p = 0; p < np; ++p) {
       const int k0 = p * NB;
-      // P_p: the panel's interchanges as one gather / scatter over its rows;
-      // the first panel of a pair applies P_{p+1} too, the second none
+      // P_p (a pair's first panel applies P_{p+1} too, its second none)
       const bool first = paired && p % 2 == 0 && p + 2 < np;
       const bool second = paired && p % 2 == 1 && p + 1 < np;
-      auto gather = [&](int q) {
-        const int* pm = perm + ((size_t)mat * kMaxPanels + q) * kPermStride;
-        const int nR = pm[0];
-        double pv = 0.0;
-        if (tid < nR) pv = sb[pm[1 + kMaxSwapRows + tid]];
-        __syncthreads();
-        if (tid < nR) sb[pm[1 + tid]] = pv;
-        __syncthreads();
-      };
-      stage_diag(k0);
-      if (!second) gather(p);
-      if (first) gather(p + 1);
+      store_diag(false);
+      if (!second) permute(p, false);
+      if (first) permute(p + 1, false);
       __syncthreads();
-      if (w == 0) {  // unit lower triangular diagonal block
-        double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
-        diag_chain<T, true, false, false>(sD, lane, v0, v1);
-        sb[k0 + lane] = v0;
-        sb[k0 + 64 + lane] = v1;
-      }
+      chain(k0, Yes(), No(), No());   // unit lower triangular diagonal block
       __syncthreads();
+      if (p + 1 < np) load_diag(k0 + NB);   // the last panel's block serves U too
       // banded factors: L below a panel reaches band_lo rows
       strip(k0, k0 + NB, band_lo > 0 ? min(npad, (k0 + NB + band_lo + NB - 1) / NB * NB) : npad);
       __syncthreads();
     }
     for (int p = np - 1; p >= 0; --p) {
       const int k0 = p * NB;
-      stage_diag(k0);
+      store_diag(true);
       __syncthreads();
-      if (w == 0) {  // upper triangular diagonal block (reciprocals of the diagonal off the chain)
-        double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
-        diag_chain<T, false, true, false>(sD, lane, v0, v1);
-        sb[k0 + lane] = v0;
-        sb[k0 + 64 + lane] = v1;
-      }
+      chain(k0, No(), Yes(), No());   // upper triangular diagonal block
       __syncthreads();
+      if (p > 0) load_diag(k0 - NB);
       // banded factors: U has upper bandwidth band_up (kl + ku with the fill of
       // the interchanges)
       strip(k0, band_up > 0 ? max(0, (k0 - band_up) / NB * NB) : 0, k0);
@@ -1462,15 +1508,11 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
     // z = U^-T c, forward over panels (U^T is lower triangular)
     for (int p = 0; p < np; ++p) {
       const int k0 = p * NB;
-      stage_diag(k0);
+      store_diag(true);
       __syncthreads();
-      if (w == 0) {  // U^T: lower triangular
-        double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
-        diag_chain<T, true, true, true>(sD, lane, v0, v1);
-        sb[k0 + lane] = v0;
-        sb[k0 + 64 + lane] = v1;
-      }
+      chain(k0, Yes(), Yes(), Yes());
       __syncthreads();
+      if (p + 1 < np) load_diag(k0 + NB);   // the last panel's block serves L^T too
       // c[col] -= sum_j U[k0+j][col] z_j for col >= k0 + NB (wave per column)
       for (int col = k0 + NB + w; col < npad; col += NWV) {
         const T* cp = A + (size_t)col * npad + k0;
@@ -1484,6 +1526,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
     // for p = m..1: z <- L_p^-T z, then z <- P_p^T z
     for (int p = np - 1; p >= 0; --p) {
       const int k0 = p * NB;
+      if (p < np - 1) load_diag(k0);
       // z_j -= sum_{r >= k0+NB} L[r][k0+j] z_r (wave per column j)
       for (int j = w; j < NB; j += NWV) {
         const T* cp = A + (size_t)(k0 + j) * npad;
@@ -1492,29 +1535,17 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
         if (lane == 0) sb[k0 + j] -= s;
       }
-      stage_diag(k0);
+      store_diag(false);
       __syncthreads();
-      if (w == 0) {  // L11^T is unit upper triangular
-        double v0 = sb[k0 + lane], v1 = sb[k0 + 64 + lane];
-        diag_chain<T, false, false, true>(sD, lane, v0, v1);
-        sb[k0 + lane] = v0;
-        sb[k0 + 64 + lane] = v1;
-      }
+      chain(k0, No(), No(), Yes());   // L11^T is unit upper triangular
       __syncthreads();
       // P_p^T: inverse of the panel's gather / scatter (a pair's first panel
       // applies P_{p+1}^T then P_p^T, its second none)
       const bool first = paired && p % 2 == 0 && p + 2 < np;
       const bool second = paired && p % 2 == 1 && p + 1 < np;
       if (!second) {
-        for (int q = first ? p + 1 : p; q >= p; --q) {
-          const int* pm = perm + ((size_t)mat * kMaxPanels + q) * kPermStride;
-          const int nR = pm[0];
-          double pv = 0.0;
-          if (tid < nR) pv = sb[pm[1 + tid]];
-          __syncthreads();
-          if (tid < nR) sb[pm[1 + kMaxSwapRows + tid]] = pv;
-          __syncthreads();
-        }
+        if (first) permute(p + 1, true);
+        permute(p, true);
       }
       __syncthreads();
     }
@@ -1533,7 +1564,7 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   int* piv = d.piv + (size_t)m0 * d.npad;
   int* perm = d.perm + (size_t)m0 * kMaxPanels * kPermStride;
   const int xpb = d.form_xpb > 0 ? d.form_xpb : (sizeof(T) == 4 ? 8 : 16);   // matrices per formation block
-  dim3 gform(d.npad, (nmat + xpb - 1) / xpb);
+  const dim3 gform(xcd_grid((nmat + xpb - 1) / xpb, d.npad));
   k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, xpb,
                                   d.band_kl, d.band_ku, d.mirror ? d.mirror + m0 : nullptr,
                                   (std::is_same<T, float>::value && d.static_piv && d.mirror) ? 1 : 0);
@@ -1612,7 +1643,7 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     } else {
       panel(k0, rend);
     }
-    if (rest > 0) k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);
+    if (rest > 0 && !stat) k_dinv<T><<<nmat, 128, 0, s>>>(LU, li, d.npad, k0);   // (k_diag_static makes them)
     if (rec) {
       mark(1, p, 1, s);
       mark(2, p, 0, s);
@@ -1624,10 +1655,11 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     if (second) {
       // this panel's U12 from its top rows with panel p-1's deferred update,
       // the interchanges' other rows moved down, panel p-1's L rows permuted
+      // (statically pivoted panels interchange no rows: nothing to move)
       k_u12pre<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, xs, d.npad, k0, nct, nmat);
-      k_move_down<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, d.npad, k0, nct, nmat);
+      if (!stat) k_move_down<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, d.npad, k0, nct, nmat);
       k_u12<T, true><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
-      k_perm_lp<T><<<xcd_grid(NB / 16, nmat), 256, 0, s>>>(LU, perm, d.npad, k0, nmat);
+      if (!stat) k_perm_lp<T><<<xcd_grid(NB / 16, nmat), 256, 0, s>>>(LU, perm, d.npad, k0, nmat);
     } else if (rest > 0) {
       k_u12<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
     }
