@@ -82,14 +82,18 @@ __global__ __launch_bounds__(256) void k_from_harm(const double* __restrict__ Xh
 
 // ---------------------------------------------------------------------------
 // FP64 residual R = B - X + dt n0_x (X C^T) + dt E_x (X A^T)  (TRANSPOSE: C, A)
-// rows = collocation points, 32 x 64 output tiles, MFMA f64 16x16x4.
+// rows = collocation points, 32 x 64 output tiles, MFMA f64 16x16x4; eight
+// wavefronts per tile, each 16 points x 16 outputs, two per SIMD so that one
+// wave's LDS reads overlap the other's products.
 // ---------------------------------------------------------------------------
 // MODE 0: the refinement residual above, with the per-point maxima (skipped once
 // the refinement is done); MODE 1: R = B - M X only; MODE 2: R = M X (operator
 // action of Alg. vspace_action, for the Krylov solver); MODE 3: R = B - dt E (X A^T)
 // (the field-coupling term of the fully implicit Jacobian, eq. 1dbte_jac_action).
+constexpr int kResThreads = 512;
+
 template <int TRANSPOSE, int MODE = 0>
-__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv, const double* __restrict__ Xv,
+__global__ __launch_bounds__(kResThreads) void k_residual(const double* __restrict__ Bv, const double* __restrict__ Xv,
                                                   double* __restrict__ Rv, const double* __restrict__ C,
                                                   const double* __restrict__ Aop, const double* __restrict__ E,
                                                   const double* __restrict__ n0x, unsigned long long* __restrict__ rmax,
@@ -106,13 +110,15 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
     }
     if (all) return;
   }
-  constexpr int LX = BM * BK / 256, LO = BN * BK / 256;  // loads per thread and tile
+  constexpr int NT = kResThreads;
+  constexpr int LX = BM * BK / NT, LO = BN * BK / NT;  // loads per thread and tile
   __shared__ double sX[BM][BK + 1];
   __shared__ double sC[BN][BK + 1];
   __shared__ double sA[BN][BK + 1];
   __shared__ unsigned long long s_rm[4][BM], s_bm[4][BM], s_xm[4][BM];
   const int x0 = blockIdx.y * BM, i0 = blockIdx.x * BN;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = (tid >> 6) & 3, b = tid >> 8;   // outputs 16 w.., points 16 b..
   const int li = lane & 15, lk = lane >> 4;
   // operator element e of a tile: row r (output index i), column c (k); the
   // transposed form walks i fastest so that its loads stay coalesced
@@ -129,13 +135,13 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < LX; ++u) {
-      const int e = tid + 256 * u, r = e / BK, c = e % BK;
+      const int e = tid + NT * u, r = e / BK, c = e % BK;
       px[u] = (x0 + r < nx && k0 + c < n) ? Xv[(size_t)(x0 + r) * npad + k0 + c] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < LO; ++u) {
       int r, c;
-      op_rc(tid + 256 * u, &r, &c);
+      op_rc(tid + NT * u, &r, &c);
       const int i = i0 + r, k = k0 + c;
       double cv = 0.0, av = 0.0;
       if (i < n && k < n) {
@@ -147,19 +153,18 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
       pa[u] = av;
     }
   };
-  f64x4 accC[2], accA[2];
-  for (int b = 0; b < 2; ++b) accC[b] = accA[b] = f64x4{0, 0, 0, 0};
+  f64x4 accC = f64x4{0, 0, 0, 0}, accA = f64x4{0, 0, 0, 0};
   fetch(0);
   for (int k0 = 0; k0 < n; k0 += BK) {
 #pragma unroll
     for (int u = 0; u < LX; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       sX[e / BK][e % BK] = px[u];
     }
 #pragma unroll
     for (int u = 0; u < LO; ++u) {
       int r, c;
-      op_rc(tid + 256 * u, &r, &c);
+      op_rc(tid + NT * u, &r, &c);
       sC[r][c] = pc[u];
       sA[r][c] = pa[u];
     }
@@ -169,20 +174,16 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
     for (int k = 0; k < BK; k += 4) {
       const double bc = sC[w * 16 + li][k + lk];
       const double ba = sA[w * 16 + li][k + lk];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const double ax = sX[b * 16 + li][k + lk];
-        accC[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bc, accC[b], 0, 0, 0);
-        accA[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, ba, accA[b], 0, 0, 0);
-      }
+      const double ax = sX[b * 16 + li][k + lk];
+      accC = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bc, accC, 0, 0, 0);
+      accA = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, ba, accA, 0, 0, 0);
     }
     __syncthreads();
   }
   // epilogue: residual, then max |r| and max |b| per point, reduced over the
   // block before one atomic per point (bit patterns of non-negative doubles
   // order like the values, and a NaN orders above +inf)
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
+  {
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const int xl = b * 16 + f64_row(lk, it);
@@ -193,9 +194,9 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
         if (x < nx && i < n) {
           const size_t o = (size_t)x * npad + i;
           if (MODE == 3) {
-            Rv[o] = Bv[o] - dt * E[x] * accA[b][it];
+            Rv[o] = Bv[o] - dt * E[x] * accA[it];
           } else {
-            const double mx = Xv[o] - dt * n0x[x] * accC[b][it] - dt * E[x] * accA[b][it];
+            const double mx = Xv[o] - dt * n0x[x] * accC[it] - dt * E[x] * accA[it];
             Rv[o] = (MODE == 1) ? Bv[o] - mx : mx;
           }
         }
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
       if (x < nx && i < n) {
         const size_t o = (size_t)x * npad + i;
         const double bv = Bv[o], xv = Xv[o];
-        const double r = bv - xv + dt * n0x[x] * accC[b][it] + dt * E[x] * accA[b][it];
+        const double r = bv - xv + dt * n0x[x] * accC[it] + dt * E[x] * accA[it];
         Rv[o] = r;
         rb = static_cast<unsigned long long>(__double_as_longlong(fabs(r)));
         bb = static_cast<unsigned long long>(__double_as_longlong(fabs(bv)));
@@ -223,6 +224,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ Bv,
         s_xm[w][xl] = xb;
       }
     }
+  }
   if (MODE != 0) return;
   __syncthreads();
   if (tid < BM && x0 + tid < nx) {
@@ -407,10 +409,10 @@ void launch_apply(const DevOps& d, int mode, const double* B, const double* X, d
                   hipStream_t s) {
   dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32);
   if (mode == 1)
-    k_residual<0, 1><<<g, 256, 0, s>>>(B, X, R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
+    k_residual<0, 1><<<g, kResThreads, 0, s>>>(B, X, R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
                                        d.n, d.npad, d.nx_total, skip);
   else
-    k_residual<0, 2><<<g, 256, 0, s>>>(B, X, R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
+    k_residual<0, 2><<<g, kResThreads, 0, s>>>(B, X, R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
                                        d.n, d.npad, d.nx_total, skip);
 }
 
@@ -418,20 +420,20 @@ void launch_apply_field(const DevOps& d, int mode, const double* B, const double
                         hipStream_t s) {
   dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32);
   if (mode == 3)
-    k_residual<0, 3><<<g, 256, 0, s>>>(B, X, R, d.Cord, d.Aord, E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
+    k_residual<0, 3><<<g, kResThreads, 0, s>>>(B, X, R, d.Cord, d.Aord, E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
                                        d.n, d.npad, d.nx_total, nullptr);
   else
-    k_residual<0, 2><<<g, 256, 0, s>>>(B, X, R, d.Cord, d.Aord, E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
+    k_residual<0, 2><<<g, kResThreads, 0, s>>>(B, X, R, d.Cord, d.Aord, E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt,
                                        d.n, d.npad, d.nx_total, nullptr);
 }
 
 void launch_residual(const DevOps& d, bool transpose, hipStream_t s) {
   dim3 g((d.n + 63) / 64, (d.nx_total + 31) / 32);
   if (transpose)
-    k_residual<1><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt, d.n,
+    k_residual<1><<<g, kResThreads, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt, d.n,
                                     d.npad, d.nx_total, nullptr);
   else
-    k_residual<0><<<g, 256, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt, d.n,
+    k_residual<0><<<g, kResThreads, 0, s>>>(d.B, d.X, d.R, d.Cord, d.Aord, d.E, d.n0x, d.rmax, d.bmax, d.xmax, d.status, d.dt, d.n,
                                     d.npad, d.nx_total, nullptr);
 }
 

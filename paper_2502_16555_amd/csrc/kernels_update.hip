@@ -197,7 +197,15 @@ __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int np
                                                       int nmat) {
   using V = typename Vec4<T>::type;
   constexpr int PER = Vec4<T>::per;
-  constexpr int LD = 128 + 4;
+  // LDS rows of the K chunk (64 banks of 4 bytes).  FP32: a pitch of 144 puts
+  // an operand read (lanes li + 16 lk, rows k + lk, 16 columns) on 64 distinct
+  // banks, and U12's transposed stores (16 columns, rows 4 q + m) write column
+  // j of row r at j ^ SW(r), SW(r) = 16 ((r / 4) mod 4), so that the four q
+  // fall on different banks too; the swizzle is uniform over a wave at each
+  // k step of the product, whose reads take column block bj ^ (k / 4 mod 4).
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int LD = F32 ? 128 + 16 : 128 + 4;
+  auto sw = [](int r) { return F32 ? 16 * ((r >> 2) & 3) : 0; };
   constexpr int RP = 128 / P;
   constexpr int LDC = RP + 4 / (sizeof(T) / 4);
   int mat, tile;
@@ -245,7 +253,7 @@ __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int np
       const int j = e / (KC / PER), k = (e % (KC / PER)) * PER;
       const T* v = reinterpret_cast<const T*>(&rb[u]);
 #pragma unroll
-      for (int m = 0; m < PER; ++m) sB[buf][k + m][j] = v[m];
+      for (int m = 0; m < PER; ++m) sB[buf][k + m][j ^ sw(k + m)] = v[m];
     }
   };
   typename Mma<T>::acc acc[4][4];
@@ -280,7 +288,7 @@ __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int np
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][k + lk][wr + bi * 16 + li];
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][k + lk][wc + bj * 16 + li];
+      for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][k + lk][wc + (bj * 16 ^ sw(k)) + li];
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
