@@ -512,10 +512,10 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
 // follows every FP32 solve works with the unperturbed matrix.  Pivots and
 // permutations are written as the identity, so that the U12, update and solve
 // kernels apply them as no-ops.
-//   k_diag_static  one 256-thread block per matrix, thread t holding the 8 x 8
-//                  tile (rows 8 (t / 16), columns 8 (t mod 16)) of the 128 x 128
-//                  diagonal block: A11 = L11 U11 by rank-1 steps, one barrier
-//                  per step (the step's row and column through LDS); then
+//   k_diag_static  one 256-thread block per matrix, the 128 x 128 diagonal
+//                  block in LDS: A11 = L11 U11 by 16-column steps (a panel
+//                  factored by one wavefront in registers, its U12 rows by
+//                  forward substitution, the trailing update on MFMA); then
 //                  X = U11^-1 by 16 x 16 blocks in LDS (the diagonal blocks,
 //                  then seven levels of off-diagonal blocks); X goes row-major
 //                  into the matrix's linv slot after L11's inverses, and the
@@ -531,98 +531,149 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
                                                      int* __restrict__ status, int npad, int k0) {
   const int mat = blockIdx.x;
   float* A = LU + (size_t)mat * npad * npad;
-  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15, lane = tid & 63, wid = tid >> 6;
-  __shared__ __align__(16) float s_row[2][NB];   // the step's row (zeros outside its range)
-  __shared__ __align__(16) float s_col[2][NB];   // the step's column (zeros outside its range)
-  __shared__ float s_piv[2];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  // LDS: two 128 x 132 regions and the level sums.  During the factorization
+  // the block sits column-major in the second region (sA[c][r]) and the first
+  // holds the current step's MFMA operands; afterwards the first holds U11
+  // row-major (sU) and the second X = U11^-1 transposed (sXT).
+  __shared__ __align__(16) float sU[NB][NB + 4];
+  __shared__ __align__(16) float sXT[NB][NB + 4];
+  __shared__ float sT[8][16][17];   // a level's sums, per block
+  __shared__ float sL11[16][17];
   __shared__ float s_red[4];
-  float a[8][8];   // a[rr][cc]: row 8 tr + rr, column 8 tc + cc
-#pragma unroll
-  for (int cc = 0; cc < 8; ++cc) {
-    const float4* cp = reinterpret_cast<const float4*>(A + (size_t)(k0 + 8 * tc + cc) * npad + k0 + 8 * tr);
-    const float4 v0 = cp[0], v1 = cp[1];
-    a[0][cc] = v0.x; a[1][cc] = v0.y; a[2][cc] = v0.z; a[3][cc] = v0.w;
-    a[4][cc] = v1.x; a[5][cc] = v1.y; a[6][cc] = v1.z; a[7][cc] = v1.w;
-  }
+  float (*sA)[NB + 4] = sXT;
+  constexpr int LQ = NB + 16;   // operand rows: lanes li + 16 lk fall on distinct banks
+  float (*sLt)[LQ] = reinterpret_cast<float (*)[LQ]>(&sU[0][0]);             // sLt[k][r] = -L[r][c0 + k]
+  float (*sUt)[LQ] = reinterpret_cast<float (*)[LQ]>(&sU[0][0] + 16 * LQ);   // sUt[k][c] = U[c0 + k][c]
   float m = 0.0f;
   bool nonfinite = false;
 #pragma unroll
-  for (int rr = 0; rr < 8; ++rr)
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + 256 * u, c = e >> 5, r4 = (e & 31) * 4;
+    const float4 v = *reinterpret_cast<const float4*>(A + (size_t)(k0 + c) * npad + k0 + r4);
+    *reinterpret_cast<float4*>(&sA[c][r4]) = v;
+    const float w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int cc = 0; cc < 8; ++cc) {
-      const float v = fabsf(a[rr][cc]);
-      nonfinite |= !(v <= FLT_MAX);
-      m = fmaxf(m, v);
+    for (int q = 0; q < 4; ++q) {
+      const float av = fabsf(w4[q]);
+      nonfinite |= !(av <= FLT_MAX);
+      m = fmaxf(m, av);
     }
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
   if (lane == 0) s_red[wid] = m;
   __syncthreads();
   const float tau = fmaxf(fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3])) * kStaticPivotRel, FLT_MIN);
-  auto put8 = [&](float* dst, const float (&v)[8]) __attribute__((always_inline)) {
-    reinterpret_cast<float4*>(dst)[0] = make_float4(v[0], v[1], v[2], v[3]);
-    reinterpret_cast<float4*>(dst)[1] = make_float4(v[4], v[5], v[6], v[7]);
-  };
-  auto get8 = [&](const float* src, float (&v)[8]) __attribute__((always_inline)) {
-    const float4 v0 = reinterpret_cast<const float4*>(src)[0], v1 = reinterpret_cast<const float4*>(src)[1];
-    v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
-    v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
-  };
-  // ---- A11 = L11 U11: step k publishes column k below the pivot and row k
-  // right of it (zeros elsewhere) and the pivot; the buffers alternate with k
-  // (one is rewritten two steps later, past the barrier in between).  Column
-  // j's multipliers are scaled by its pivot's reciprocal after the loop.
-  float rp_own[8];
+  // ---- A11 = L11 U11 by 16-column steps c0 = 16 kb: wavefront 0 factors the
+  // step's panel (rows c0.., two per lane) in registers, each pivot row passed
+  // on by lane reads, with no barrier; then U12 = L11^-1 A12 for the step's 16
+  // rows (a thread per column) and A22 -= L21 U12 on MFMA in 16 x 16 tiles.
+  for (int kb = 0; kb < NB / 16; ++kb) {
+    const int c0 = 16 * kb;
+    if (wid == 0) {
+      const int ra = c0 + lane, rb = c0 + 64 + lane;
+      const bool va = ra < NB, vb = rb < NB;
+      float p[16], q[16];
 #pragma unroll
-  for (int cc = 0; cc < 8; ++cc) rp_own[cc] = 1.0f;
-  for (int kb = 0; kb < 16; ++kb) {
+      for (int j = 0; j < 16; ++j) p[j] = q[j] = 0.0f;
+      if (va) {
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      const int k = 8 * kb + kk, par = kk & 1;
-      if (tc == kb) {
-        float v[8];
-#pragma unroll
-        for (int rr = 0; rr < 8; ++rr) v[rr] = (tr > kb || (tr == kb && rr > kk)) ? a[rr][kk] : 0.0f;
-        put8(&s_col[par][8 * tr], v);
+        for (int j = 0; j < 16; ++j) p[j] = sA[c0 + j][ra];
       }
-      if (tr == kb) {
-        float v[8];
+      if (vb) {
 #pragma unroll
-        for (int cc = 0; cc < 8; ++cc) v[cc] = (tc > kb || (tc == kb && cc > kk)) ? a[kk][cc] : 0.0f;
-        put8(&s_row[par][8 * tc], v);
-        if (tc == kb) s_piv[par] = a[kk][kk];
+        for (int j = 0; j < 16; ++j) q[j] = sA[c0 + j][rb];
       }
-      __syncthreads();
-      float cv[8], rv[8];
-      get8(&s_col[par][8 * tr], cv);
-      get8(&s_row[par][8 * tc], rv);
-      float pv = s_piv[par];
-      if (!(fabsf(pv) >= tau)) pv = pv < 0.0f ? -tau : tau;   // also a NaN pivot (reported above)
-      const float rp = __builtin_amdgcn_rcpf(pv);
-      if (tc == kb) {
-        rp_own[kk] = rp;
-        if (tr == kb) a[kk][kk] = pv;
+      // the lane tests stay inside the loop (hoisted, they would take 32 SGPRs)
+      int lv = lane;
+      asm volatile("" : "+v"(lv));
+      const bool two = c0 + 64 < NB;   // a second row per lane
+      static_for(std::make_integer_sequence<int, 16>(), [&](auto jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(jc)::value;
+        float pv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p[j]), j));
+        if (!(fabsf(pv) >= tau)) pv = pv < 0.0f ? -tau : tau;   // also a NaN pivot (reported above)
+        const float rp = __builtin_amdgcn_rcpf(pv);
+        float u[16];
+#pragma unroll
+        for (int c = j + 1; c < 16; ++c) u[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p[c]), j));
+        // first half: lane j holds the pivot row; rows above it keep their U
+        // entries (a zero multiplier leaves them exactly)
+        const bool below = lv > j;
+        const float l = p[j] * rp;
+        const float lm = below ? l : 0.0f;
+        p[j] = below ? l : (lv == j ? pv : p[j]);
+#pragma unroll
+        for (int c = j + 1; c < 16; ++c) p[c] = fmaf(-lm, u[c], p[c]);
+        if (two) {
+          const float l2 = q[j] * rp;
+          q[j] = l2;
+#pragma unroll
+          for (int c = j + 1; c < 16; ++c) q[c] = fmaf(-l2, u[c], q[c]);
+        }
+      });
+      // the panel in place; L21 (negated) and L11 staged for the products
+      if (va) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) sA[c0 + j][ra] = p[j];
+        if (lane >= 16) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) sLt[j][ra] = -p[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) sL11[lane][j] = p[j];
+        }
       }
-      if (4 * wid + 3 >= kb) {   // a wavefront whose rows all lie above row k skips
+      if (vb) {
 #pragma unroll
-        for (int cc = 0; cc < 8; ++cc) rv[cc] *= rp;
-#pragma unroll
-        for (int rr = 0; rr < 8; ++rr)
-#pragma unroll
-          for (int cc = 0; cc < 8; ++cc) a[rr][cc] = fmaf(-cv[rr], rv[cc], a[rr][cc]);
+        for (int j = 0; j < 16; ++j) {
+          sA[c0 + j][rb] = q[j];
+          sLt[j][rb] = -q[j];
+        }
       }
     }
+    __syncthreads();
+    const int ncol = NB - c0 - 16;
+    if (tid < ncol) {   // U12 column c by forward substitution with the unit lower L11
+      const int c = c0 + 16 + tid;
+      float x[16];
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const float4 v = *reinterpret_cast<const float4*>(&sA[c][c0 + 4 * q4]);
+        x[4 * q4] = v.x;
+        x[4 * q4 + 1] = v.y;
+        x[4 * q4 + 2] = v.z;
+        x[4 * q4 + 3] = v.w;
+      }
+#pragma unroll
+      for (int i = 1; i < 16; ++i)
+#pragma unroll
+        for (int j = 0; j < i; ++j) x[i] = fmaf(-sL11[i][j], x[j], x[i]);
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4)
+        *reinterpret_cast<float4*>(&sA[c][c0 + 4 * q4]) = make_float4(x[4 * q4], x[4 * q4 + 1], x[4 * q4 + 2], x[4 * q4 + 3]);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sUt[i][c] = x[i];
+    }
+    __syncthreads();
+    const int nt = ncol / 16;
+    for (int t = wid; t < nt * nt; t += 4) {
+      const int r0 = c0 + 16 + 16 * (t % nt), cc = c0 + 16 + 16 * (t / nt);
+      const float4 cv = *reinterpret_cast<const float4*>(&sA[cc + li][r0 + 4 * lk]);
+      f32x4 acc = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4)
+        acc = Mma<float>::step(sLt[4 * q4 + lk][r0 + li], sUt[4 * q4 + lk][cc + li], acc);
+      *reinterpret_cast<float4*>(&sA[cc + li][r0 + 4 * lk]) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    }
+    __syncthreads();
   }
+  // the factors to the matrix; pivots and permutation as the identity
 #pragma unroll
-  for (int rr = 0; rr < 8; ++rr)
-#pragma unroll
-    for (int cc = 0; cc < 8; ++cc)
-      if (8 * tr + rr > 8 * tc + cc) a[rr][cc] *= rp_own[cc];
-#pragma unroll
-  for (int cc = 0; cc < 8; ++cc) {
-    float4* cp = reinterpret_cast<float4*>(A + (size_t)(k0 + 8 * tc + cc) * npad + k0 + 8 * tr);
-    cp[0] = make_float4(a[0][cc], a[1][cc], a[2][cc], a[3][cc]);
-    cp[1] = make_float4(a[4][cc], a[5][cc], a[6][cc], a[7][cc]);
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + 256 * u, c = e >> 5, r4 = (e & 31) * 4;
+    *reinterpret_cast<float4*>(A + (size_t)(k0 + c) * npad + k0 + r4) = *reinterpret_cast<const float4*>(&sA[c][r4]);
   }
   if (tid < NB) {
     piv[(size_t)mat * npad + k0 + tid] = k0 + tid;
@@ -634,24 +685,37 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
   // ---- X = U11^-1 by 16 x 16 blocks (X upper triangular, kept transposed in
   // LDS, XT[col][row]): the diagonal blocks X_bb = U_bb^-1 by back substitution,
   // then by levels d = 1..7 the blocks X_{a,a+d} = -X_aa sum_{m=a+1}^{a+d}
-  // U_am X_{m,a+d}; the blocks of one level are independent.
-  __shared__ __align__(16) float sU[NB][NB + 4];    // U11 row-major, zeros below the diagonal
-  __shared__ __align__(16) float sXT[NB][NB + 4];   // X transposed
-  __shared__ float sT[8][16][17];                   // a level's sums, per block
-  // (the strict lower parts of L11's diagonal blocks wait in sT, which the
-  // levels use only later)
-  const bool dblk = (tr >> 1) == (tc >> 1);
+  // U_am X_{m,a+d}; the blocks of one level are independent.  U11 goes
+  // row-major into sU, the strict lower parts of L11's diagonal blocks into sT
+  // (which the levels use only later), then sXT is cleared.
 #pragma unroll
-  for (int rr = 0; rr < 8; ++rr) {
-    const int i = 8 * tr + rr;
+  for (int u = 0; u < 4; ++u) {   // 4 x 4 blocks, transposed in registers
+    const int i4 = 4 * (tid & 31), j4 = 4 * (tid >> 5) + 32 * u;
+    float w[4][4];   // w[jj][ii] = A[i4 + ii][j4 + jj]
 #pragma unroll
-    for (int cc = 0; cc < 8; ++cc) {
-      const int jj = 8 * tc + cc;
-      sU[i][jj] = (i <= jj) ? a[rr][cc] : 0.0f;
-      sXT[i][jj] = 0.0f;
-      if (dblk && i > jj) sT[tr >> 1][i & 15][jj & 15] = a[rr][cc];
+    for (int jj = 0; jj < 4; ++jj) {
+      const float4 v = *reinterpret_cast<const float4*>(&sA[j4 + jj][i4]);
+      w[jj][0] = v.x;
+      w[jj][1] = v.y;
+      w[jj][2] = v.z;
+      w[jj][3] = v.w;
+    }
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int i = i4 + ii;
+      float o[4];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) o[jj] = (i <= j4 + jj) ? w[jj][ii] : 0.0f;
+      *reinterpret_cast<float4*>(&sU[i][j4]) = make_float4(o[0], o[1], o[2], o[3]);
+      if ((i >> 4) == (j4 >> 4)) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          if (i > j4 + jj) sT[i >> 4][i & 15][(j4 + jj) & 15] = w[jj][ii];
+      }
     }
   }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += 256) sXT[e >> 7][e & (NB - 1)] = 0.0f;
   __syncthreads();
   if (tid < NB) {   // thread (b, c): column c of X_bb
     const int b = tid >> 4, c = tid & 15, o = 16 * b;
@@ -679,42 +743,43 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
     for (int r = 0; r < 16; ++r) out[r * 16 + c] = x[r];
   }
   __syncthreads();
-  {
-    const int i = tid >> 4, c = tid & 15;   // this thread's element of every block of a level
-    for (int d = 1; d < 8; ++d) {
-      for (int ab = 0; ab + d < 8; ++ab) {
-        const int b = ab + d;
-        // T[i][c] = sum_{m=ab+1}^{b} sum_q U[16 ab + i][16 m + q] X[16 m + q][16 b + c]
-        float t = 0.0f;
-        for (int m2 = ab + 1; m2 <= b; ++m2) {
+  // levels on MFMA, the blocks of a level spread over the wavefronts: T_ab into
+  // sT (lane (li, lk) holds rows 4 lk.. of column li), then X_{ab,b} = -X_aa T_ab
+  // from sT, written transposed
+  for (int d = 1; d < 8; ++d) {
+    for (int ab = wid; ab + d < 8; ab += 4) {
+      const int b = ab + d;
+      f32x4 t = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int m2 = ab + 1; m2 <= b; ++m2)
 #pragma unroll
-          for (int q = 0; q < 16; q += 4) {
-            const float4 u = *reinterpret_cast<const float4*>(&sU[16 * ab + i][16 * m2 + q]);
-            const float4 x = *reinterpret_cast<const float4*>(&sXT[16 * b + c][16 * m2 + q]);
-            t = fmaf(u.x, x.x, t);
-            t = fmaf(u.y, x.y, t);
-            t = fmaf(u.z, x.z, t);
-            t = fmaf(u.w, x.w, t);
-          }
-        }
-        sT[ab][i][c] = t;
-      }
-      __syncthreads();
-      for (int ab = 0; ab + d < 8; ++ab) {
-        const int b = ab + d;
-        // X_{ab,b}[i][c] = -sum_q X_{ab,ab}[i][q] T[q][c]
-        float v = 0.0f;
+        for (int q4 = 0; q4 < 4; ++q4)
+          t = Mma<float>::step(sU[16 * ab + li][16 * m2 + 4 * q4 + lk], sXT[16 * b + li][16 * m2 + 4 * q4 + lk], t);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v = fmaf(sXT[16 * ab + q][16 * ab + i], sT[ab][q][c], v);
-        sXT[16 * b + c][16 * ab + i] = -v;
-      }
-      __syncthreads();
+      for (int it = 0; it < 4; ++it) sT[ab][4 * lk + it][li] = t[it];
     }
+    __syncthreads();
+    for (int ab = wid; ab + d < 8; ab += 4) {
+      const int b = ab + d;
+      f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4)
+        x = Mma<float>::step(sXT[16 * ab + 4 * q4 + lk][16 * ab + li], sT[ab][4 * q4 + lk][li], x);
+      *reinterpret_cast<float4*>(&sXT[16 * b + li][16 * ab + 4 * lk]) = make_float4(-x[0], -x[1], -x[2], -x[3]);
+    }
+    __syncthreads();
   }
-  float* xo = linv + (size_t)mat * kLinvElems + kLinvXOff;   // X row-major
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int k = e / NB, c = e % NB;
-    xo[e] = sXT[c][k];
+  // X row-major: 4 x 4 blocks transposed in registers
+  float* xo = linv + (size_t)mat * kLinvElems + kLinvXOff;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int k4 = 4 * (tid & 31), c4 = 4 * (tid >> 5) + 32 * u;
+    float4 v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = *reinterpret_cast<const float4*>(&sXT[c4 + j][k4]);
+    *reinterpret_cast<float4*>(xo + (size_t)(k4 + 0) * NB + c4) = make_float4(v[0].x, v[1].x, v[2].x, v[3].x);
+    *reinterpret_cast<float4*>(xo + (size_t)(k4 + 1) * NB + c4) = make_float4(v[0].y, v[1].y, v[2].y, v[3].y);
+    *reinterpret_cast<float4*>(xo + (size_t)(k4 + 2) * NB + c4) = make_float4(v[0].z, v[1].z, v[2].z, v[3].z);
+    *reinterpret_cast<float4*>(xo + (size_t)(k4 + 3) * NB + c4) = make_float4(v[0].w, v[1].w, v[2].w, v[3].w);
   }
   if (__syncthreads_or(nonfinite) && tid == 0) atomicOr(status, kStNonFinite);
 }
