@@ -540,7 +540,7 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
   __shared__ __align__(16) float sU[NB][NB + 4];
   __shared__ __align__(16) float sXT[NB][NB + 4];
   __shared__ float sT[8][16][17];   // a level's sums, per block
-  __shared__ float sL11[16][17];
+  __shared__ __align__(16) float sL11[16][20];   // rows as 16-byte vectors
   __shared__ float s_red[4];
   float (*sA)[NB + 4] = sXT;
   constexpr int LQ = NB + 16;   // operand rows: lanes li + 16 lk fall on distinct banks
@@ -647,9 +647,19 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
         x[4 * q4 + 3] = v.w;
       }
 #pragma unroll
-      for (int i = 1; i < 16; ++i)
+      for (int i = 1; i < 16; ++i) {
+        float lr[16];
 #pragma unroll
-        for (int j = 0; j < i; ++j) x[i] = fmaf(-sL11[i][j], x[j], x[i]);
+        for (int j4 = 0; j4 < i; j4 += 4) {
+          const float4 v = *reinterpret_cast<const float4*>(&sL11[i][j4]);
+          lr[j4] = v.x;
+          lr[j4 + 1] = v.y;
+          lr[j4 + 2] = v.z;
+          lr[j4 + 3] = v.w;
+        }
+#pragma unroll
+        for (int j = 0; j < i; ++j) x[i] = fmaf(-lr[j], x[j], x[i]);
+      }
 #pragma unroll
       for (int q4 = 0; q4 < 4; ++q4)
         *reinterpret_cast<float4*>(&sA[c][c0 + 4 * q4]) = make_float4(x[4 * q4], x[4 * q4 + 1], x[4 * q4 + 2], x[4 * q4 + 3]);
@@ -790,7 +800,7 @@ __global__ __launch_bounds__(256, 2) void k_l21_mfma(float* __restrict__ LU, con
   xcd_map(blockIdx.x, ntiles, nmat, &mat, &tile);
   if (mat >= nmat) return;
   float* A = LU + (size_t)mat * npad * npad;
-  constexpr int LD = NB + 4;   // B fragment reads: lanes (li, lk) on banks li + 4 lk
+  constexpr int LD = NB + 16;   // B fragment reads: lanes (li, lk) on banks li + 16 lk (64 banks)
   __shared__ __align__(16) float sX[NB][LD];
   const int r0 = k0 + NB + tile * NB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -965,7 +975,15 @@ __global__ __launch_bounds__(256, 2) void k_u12(T* __restrict__ LU, const T* __r
                                                int nct, int nmat) {
   using V = typename Vec4<T>::type;
   constexpr int PER = Vec4<T>::per;
-  constexpr int KC = 16, LD = 128 + 4;
+  // LDS rows of the K chunk (64 banks of 4 bytes).  FP32: a pitch of 144 puts
+  // an operand read (lanes li + 16 lk, rows k + lk) on 64 distinct banks; the
+  // transposed stores of the K operand write column j of row r at j ^ SW(r),
+  // SW(r) = 16 ((r / 4) mod 4) for the vectors of W (16 columns, rows 4 q + m)
+  // and 4 ((r / 4) mod 4) for the gather (4 columns, rows k), which keeps them
+  // conflict-free as well; SW is uniform over a wave at each k step.
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int KC = 16, LD = F32 ? 128 + 16 : 128 + 4;
+  auto sw = [](int r) { return F32 ? (FROM_W ? 16 : 4) * ((r >> 2) & 3) : 0; };
   int mat, ct;
   xcd_map(blockIdx.x, nct, nmat, &mat, &ct);
   if (mat >= nmat) return;
@@ -1053,13 +1071,13 @@ __global__ __launch_bounds__(256, 2) void k_u12(T* __restrict__ LU, const T* __r
         const int e = tid + u * 256;
         const int q = e % (KC / 4), j = e / (KC / 4);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sB[buf][4 * q + i][j] = rb[4 * u + i];
+        for (int i = 0; i < 4; ++i) sB[buf][4 * q + i][j ^ sw(4 * q + i)] = rb[4 * u + i];
       }
     } else {
 #pragma unroll
       for (int u = 0; u < NBS; ++u) {
         const int e = tid + u * 256;
-        sB[buf][e % KC][e / KC] = rb[u];
+        sB[buf][e % KC][(e / KC) ^ sw(e % KC)] = rb[u];
       }
     }
   };
@@ -1081,7 +1099,7 @@ __global__ __launch_bounds__(256, 2) void k_u12(T* __restrict__ LU, const T* __r
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][k + lk][rowb[bi] * 16 + li];
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][k + lk][wc + bj * 16 + li];
+      for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][k + lk][(wc + bj * 16 + li) ^ sw(k)];
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi) {
         if (ch <= rowb[bi]) {  // KC = 16: chunk ch is row block ch of the K range
@@ -1154,7 +1172,10 @@ __global__ __launch_bounds__(256, 2) void k_u12pre(T* __restrict__ LU, const int
                                                 T* __restrict__ xscr, int npad, int k1, int nct, int nmat) {
   using V = typename Vec4<T>::type;
   constexpr int PER = Vec4<T>::per;
-  constexpr int KC = 16, LD = 128 + 4;
+  // FP32 operand layout as in k_u12 (the U_p stores are W's pattern)
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int KC = 16, LD = F32 ? 128 + 16 : 128 + 4;
+  auto sw = [](int r) { return F32 ? 16 * ((r >> 2) & 3) : 0; };
   int mat, ct;
   xcd_map(blockIdx.x, nct, nmat, &mat, &ct);
   if (mat >= nmat) return;
@@ -1200,7 +1221,7 @@ __global__ __launch_bounds__(256, 2) void k_u12pre(T* __restrict__ LU, const int
       const int j = e / (KC / PER), k = (e % (KC / PER)) * PER;
       const T* v = reinterpret_cast<const T*>(&rb[u]);
 #pragma unroll
-      for (int m = 0; m < PER; ++m) sB[buf][k + m][j] = v[m];
+      for (int m = 0; m < PER; ++m) sB[buf][k + m][j ^ sw(k + m)] = v[m];
     }
   };
   typename Mma<T>::acc acc[4][4];
@@ -1221,7 +1242,7 @@ __global__ __launch_bounds__(256, 2) void k_u12pre(T* __restrict__ LU, const int
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi) av[bi] = sA[buf][k + lk][wr + bi * 16 + li];
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][k + lk][wc + bj * 16 + li];
+      for (int bj = 0; bj < 4; ++bj) bv[bj] = sB[buf][k + lk][(wc + bj * 16 + li) ^ sw(k)];
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
