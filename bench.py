@@ -32,7 +32,7 @@ MI355X_PEAK_HBM_GBS = 8000.0
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters
 # read for a 1 GiB copy (x2.0 and x1.0).  Valid for the kernel source it was taken
 # on (hash of kernels_update.hip); reported as null once that file has changed.
-KUPDATE_TRAFFIC = {"source_sha256_16": "d5cfcc103aa95365", "fetch_bytes": 1.155e9, "write_bytes": 6.979e8,
+KUPDATE_TRAFFIC = {"source_sha256_16": "b7aca7d9552e8d89", "fetch_bytes": 1.159e9, "write_bytes": 6.979e8,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -134,17 +134,25 @@ def run_gpu(cfg, precision, steps, warmup, torch, lu_streams=None, one_step=Fals
         raise RuntimeError(f"{precision}: device status {code} in the timed steps")
     mom = s.moments(F).cpu().numpy()
     n_end = n
-    # kernel-level breakdown (separate, instrumented steps)
+    # kernel-level breakdown (separate, instrumented steps), then the phase
+    # walls alone (no events inside the factorization to lengthen them)
     s.set_timing(True)
     nt = 3
     for _ in range(nt):
         s.step(F, n * dt)
         n += 1
     tm = s.timing()
+    s.set_timing(True, walls_only=True)
+    ntw = 10
+    for _ in range(ntw):
+        s.step(F, n * dt)
+        n += 1
+    tw = s.timing()
     s.set_timing(False)
     out = {"ms_per_step": ms, "wall_s": wall, "setup_s": setup_s, "refine_sweeps": sweeps, "refine_resid": resid,
            "moments": mom, "n_end": n_end, "first_step_moments": first,
-           "ms_update": tm[0] / nt, "ms_panel": tm[1] / nt, "ms_vwall": tm[2] / nt, "ms_x": tm[4] / nt,
+           "ms_update": tm[0] / nt, "ms_panel": tm[1] / nt, "ms_vwall": tw[2] / ntw, "ms_x": tw[4] / ntw,
+           "ms_vwall_kernel_timing": tm[2] / nt,
            "update_launches": tm[3] / nt, "lu_streams": s.get_tuning(_lib.TUNE_LU_STREAMS),
            "panel_pairs": s.get_tuning(_lib.TUNE_PANEL_PAIRS),
            "static_pivoting": s.get_tuning(_lib.TUNE_STATIC_PIVOTING),
@@ -507,6 +515,7 @@ def main():
                              "frac": info.lu_flops_per_step / (main_run["ms_vwall"] * 1e-3) / 1e12 / peak},
         "breakdown_ms": {"lu_update_launches": main_run["ms_update"], "lu_panel_u12_launches": main_run["ms_panel"],
                          "v_step_wall": main_run["ms_vwall"], "x_and_field_wall": main_run["ms_x"],
+                         "v_step_wall_with_launch_events": main_run["ms_vwall_kernel_timing"],
                          "lu_streams": main_run["lu_streams"]},
         "lu_tflops_step": info.lu_flops_per_step / (main_run["ms_per_step"] * 1e-3) / 1e12,
         "refine": {"sweeps": main_run["refine_sweeps"], "resid": main_run["refine_resid"]},

@@ -366,8 +366,12 @@ bte_status bte_set_refine(bte_handle* h, int32_t max_iter, double rtol);
 bte_status bte_get_status(bte_handle* h, int32_t* refine_iters, double* final_resid);
 
 /* Kernel-level timing of bte_step (HIP events on the streams the kernels run
- * on; each timed step synchronizes the caller's stream).  enable (1) /
- * disable (0, default); enabling clears the sums.  bte_get_timing fills
+ * on).  enable: 1 = events around the phases of the step and around every LU
+ * launch group, each timed step synchronizing the caller's stream; 2 = around
+ * the phases only, with no wait between steps (the events of up to 64 steps
+ * are read when their ring is full or by bte_get_timing), so that the walls
+ * are those of steps running back to back ([0], [1] and [3] stay zero); 0 =
+ * off (default).  Any call clears the sums; other values are EINVAL.  bte_get_timing fills
  * ms_out[0..5] with sums over the timed steps of: [0] the durations of the LU
  * trailing-update launches, [1] the durations of the LU panel + U12 launches
  * (both summed over the concurrent factorization streams, so they can exceed

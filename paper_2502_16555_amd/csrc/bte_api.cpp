@@ -60,8 +60,28 @@ struct bte_handle {
   int refine_max_iter = 10;
   double refine_rtol = 1e-14;
   double bytes = 0.0;
-  bool timing = false;
+  int timing = 0;   // 1: phases and LU launch groups, 2: phases only
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // timing 2: the phase events of up to kWallRing steps, read (one wait) when
+  // the ring is full or the sums are asked for, so that the timed steps run
+  // back to back as untimed ones do
+  static constexpr int kWallRing = 64;
+  std::vector<hipEvent_t> wall_ev;   // 4 per step
+  int wall_n = 0;                    // steps recorded and not yet read
+  void wall_flush() {
+    if (wall_n == 0) return;
+    HIP_OK(hipEventSynchronize(wall_ev[4 * (wall_n - 1) + 3]));
+    for (int i = 0; i < wall_n; ++i) {
+      float a = 0, b = 0, c = 0;
+      HIP_OK(hipEventElapsedTime(&a, wall_ev[4 * i], wall_ev[4 * i + 1]));
+      HIP_OK(hipEventElapsedTime(&b, wall_ev[4 * i + 1], wall_ev[4 * i + 2]));
+      HIP_OK(hipEventElapsedTime(&c, wall_ev[4 * i + 2], wall_ev[4 * i + 3]));
+      ms_acc[2] += b;
+      ms_acc[4] += a + c;
+      ms_acc[5] += 1.0;
+    }
+    wall_n = 0;
+  }
   // the factorization runs as lu_streams groups of points on side streams
   // (fork/join by events) so that one group's latency-bound panels overlap
   // another group's MFMA updates
@@ -146,6 +166,8 @@ struct bte_handle {
   }
   ~bte_handle() {
     for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : wall_ev)
       if (e) (void)hipEventDestroy(e);
     for (auto& e : lu_ev)
       if (e) (void)hipEventDestroy(e);
@@ -416,7 +438,7 @@ void factor_all(bte_handle* h, hipStream_t s) {
     bte::LuLookAhead la;
     la.side = h->gs[0];
     la.ev = h->la_ev.data();
-    bte::launch_lu_factor(d, prec, s, h->timing ? &h->lu_timer[0] : nullptr, 0, -1, h->look_ahead ? &la : nullptr);
+    bte::launch_lu_factor(d, prec, s, h->timing == 1 ? &h->lu_timer[0] : nullptr, 0, -1, h->look_ahead ? &la : nullptr);
     return;
   }
   HIP_OK(hipEventRecord(h->fork_ev, s));
@@ -424,7 +446,7 @@ void factor_all(bte_handle* h, hipStream_t s) {
     const int m0 = static_cast<int>((static_cast<long long>(g) * d.nx_total) / G);
     const int m1 = static_cast<int>((static_cast<long long>(g + 1) * d.nx_total) / G);
     HIP_OK(hipStreamWaitEvent(h->gs[g], h->fork_ev, 0));
-    bte::launch_lu_factor(d, prec, h->gs[g], h->timing ? &h->lu_timer[g] : nullptr, m0, m1 - m0);
+    bte::launch_lu_factor(d, prec, h->gs[g], h->timing == 1 ? &h->lu_timer[g] : nullptr, m0, m1 - m0);
     HIP_OK(hipEventRecord(h->join_ev[g], h->gs[g]));
     HIP_OK(hipStreamWaitEvent(s, h->join_ev[g], 0));
   }
@@ -464,7 +486,7 @@ void v_solve_banded(bte_handle* h, double* F, hipStream_t s) {
   b.E = d.E;   // the field of this step
   const int nl = h->cfg.nl;
   bte::launch_to_harm(d, nl, b.npad, F, h->d_TS, d.B, s);
-  bte::launch_lu_factor(b, 0, s, h->timing ? &h->lu_timer[0] : nullptr);
+  bte::launch_lu_factor(b, 0, s, h->timing == 1 ? &h->lu_timer[0] : nullptr);
   bte::launch_lu_solve_mapped(b, 0, false, nullptr, nullptr, d.nx_total, d.B, d.X, false, false, s);
   bte::launch_from_harm(d, nl, b.npad, d.X, d.B, h->d_TO, F, s);
 }
@@ -839,6 +861,20 @@ bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void*
     HIP_OK(hipSetDevice(h->device));
     hipStream_t s = S(stream);
     h->last_stream = s;
+    if (h->timing == 2) {
+      hipEvent_t* we = h->wall_ev.data() + 4 * h->wall_n;
+      HIP_OK(hipEventRecord(we[0], s));
+      x_half(h, F, false, s);
+      eval_field(h, F, t_s, field, s);
+      HIP_OK(hipEventRecord(we[1], s));
+      v_solve(h, F, false, s, true);
+      HIP_OK(hipEventRecord(we[2], s));
+      x_half(h, F, false, s);
+      HIP_OK(hipEventRecord(we[3], s));
+      if (++h->wall_n == bte_handle::kWallRing) h->wall_flush();
+      HIP_OK(hipGetLastError());
+      return BTE_OK;
+    }
     if (h->timing) HIP_OK(hipEventRecord(h->ev[0], s));
     x_half(h, F, false, s);
     eval_field(h, F, t_s, field, s);
@@ -1221,7 +1257,18 @@ bte_status bte_set_refine(bte_handle* h, int32_t max_iter, double rtol) {
 
 bte_status bte_set_timing(bte_handle* h, int32_t enable) {
   if (!h) return BTE_EINVAL;
-  h->timing = enable != 0;
+  if (enable < 0 || enable > 2) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    h->wall_flush();   // pending records of an earlier walls-only run are dropped with the sums
+    if (enable == 2 && h->wall_ev.empty()) {
+      h->wall_ev.assign(4 * bte_handle::kWallRing, nullptr);
+      for (auto& e : h->wall_ev) HIP_OK(hipEventCreate(&e));
+    }
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
+  h->timing = enable;
   std::fill(std::begin(h->ms_acc), std::end(h->ms_acc), 0.0);
   return BTE_OK;
 }
@@ -1491,6 +1538,12 @@ bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value) {
 
 bte_status bte_get_timing(bte_handle* h, double* ms_out) {
   if (!h || !ms_out) return BTE_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    h->wall_flush();
+  } catch (const std::exception& e) {
+    return map_exc(e);
+  }
   for (int i = 0; i < 6; ++i) ms_out[i] = h->ms_acc[i];
   return BTE_OK;
 }

@@ -230,8 +230,10 @@ class Solver:
         """Refinement sweeps and stop of the mixed-precision V step (bte_set_refine)."""
         check(self.lib.bte_set_refine(self.h, int(max_iter), float(rtol)), "bte_set_refine")
 
-    def set_timing(self, on: bool):
-        check(self.lib.bte_set_timing(self.h, 1 if on else 0), "bte_set_timing")
+    def set_timing(self, on, walls_only: bool = False):
+        """Kernel-level timing of step() (on: events around every LU launch
+        group too; walls_only: around the step's phases only)."""
+        check(self.lib.bte_set_timing(self.h, (2 if walls_only else 1) if on else 0), "bte_set_timing")
 
     def timing(self):
         out = (C.c_double * 6)()

@@ -953,6 +953,45 @@ def test_graph_replays_match_eager_steps(torch, prec, groups):
     s.close()
 
 
+def test_step_timing_levels(torch):
+    """Timing level 1 times the LU launch groups and the phases; level 2 only
+    the phases, with the steps' events read when the sums are asked for (more
+    steps than the 64-step event ring included).  Neither changes the steps,
+    and an unknown level is rejected."""
+    cfg = CASES["panels"]()
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg, precision="mixed_fp32")
+    F0 = _state(ops, 31)
+    Fa = cuda(torch, F0)
+    Fb = cuda(torch, F0)
+    t0 = 0.1 * cfg["T_rf_s"]
+    for k in range(70):
+        s.step(Fa, t0 + k * cfg["dt_s"])
+    s.set_timing(True)
+    for k in range(3):
+        s.step(Fb, t0 + k * cfg["dt_s"])
+    t1 = s.timing()
+    assert t1[5] == 3 and t1[0] > 0 and t1[1] > 0 and t1[2] > 0 and t1[3] > 0
+    s.set_timing(True, walls_only=True)
+    for k in range(3, 70):
+        s.step(Fb, t0 + k * cfg["dt_s"])
+    t2 = s.timing()
+    assert t2[5] == 67 and t2[0] == 0 and t2[1] == 0 and t2[3] == 0
+    assert t2[2] > 0 and t2[4] > 0
+    s.set_timing(False)
+    torch.cuda.synchronize()
+    assert s.status()[0] == 0
+    assert np.array_equal(Fa.cpu().numpy(), Fb.cpu().numpy())
+    with pytest.raises(Exception):
+        _raw_set_timing(s, 3)
+    s.close()
+
+
+def _raw_set_timing(s, level):
+    from paper_2502_16555_amd._lib import check
+    check(s.lib.bte_set_timing(s.h, level), "bte_set_timing")
+
+
 def test_autotuned_shapes_leave_results_unchanged(torch, tmp_path):
     """The autotuner picks launch shapes by timing; the steps after tuning equal
     the default-shape steps bit for bit, for FP64 and mixed precision."""
