@@ -61,6 +61,7 @@ TUNE_FORM_XPB = 2
 TUNE_PANEL_PAIRS = 3
 TUNE_STATIC_PIVOTING = 4
 TUNE_LOOK_AHEAD = 5
+TUNE_FORM_OVERLAP = 6
 ION_SCRATCH_DOUBLES = 2097152   # BTE_ION_SCRATCH_DOUBLES
 
 EXPORTS = {

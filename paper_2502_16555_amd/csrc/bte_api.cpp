@@ -93,6 +93,8 @@ struct bte_handle {
   std::vector<hipEvent_t> lu_ev;   // kMaxLuStreams * 8 * max_panels
   std::vector<hipEvent_t> la_ev;   // 2 kMaxPanels: the factorization's look-ahead (side stream gs[0])
   int look_ahead = 0;              // BTE_TUNE_LOOK_AHEAD
+  int form_overlap = 0;            // BTE_TUNE_FORM_OVERLAP
+  hipEvent_t form_ev[2] = {nullptr, nullptr};
   bte::LuTimer lu_timer[kMaxLuStreams];
   double ms_acc[6] = {0, 0, 0, 0, 0, 0};
   // Krylov V solver (bte_set_vsolver): factors of the field-binned
@@ -172,6 +174,8 @@ struct bte_handle {
     for (auto& e : lu_ev)
       if (e) (void)hipEventDestroy(e);
     for (auto& e : la_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : form_ev)
       if (e) (void)hipEventDestroy(e);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     for (auto& e : join_ev)
@@ -438,7 +442,11 @@ void factor_all(bte_handle* h, hipStream_t s) {
     bte::LuLookAhead la;
     la.side = h->gs[0];
     la.ev = h->la_ev.data();
-    bte::launch_lu_factor(d, prec, s, h->timing == 1 ? &h->lu_timer[0] : nullptr, 0, -1, h->look_ahead ? &la : nullptr);
+    la.look_ahead = h->look_ahead;
+    la.form_overlap = h->form_overlap;
+    la.form_ev[0] = h->form_ev[0];
+    la.form_ev[1] = h->form_ev[1];
+    bte::launch_lu_factor(d, prec, s, h->timing == 1 ? &h->lu_timer[0] : nullptr, 0, -1, &la);
     return;
   }
   HIP_OK(hipEventRecord(h->fork_ev, s));
@@ -816,6 +824,7 @@ bte_status bte_setup_operators(const bte_config* cfg, int hip_device, bte_handle
     HIP_OK(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
     h->la_ev.assign(2 * bte::kMaxPanels, nullptr);
     for (auto& e : h->la_ev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& e : h->form_ev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     // pointers inside cfg are not retained
     h->cfg.proc = nullptr;
@@ -1513,6 +1522,10 @@ bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value) {
       if (value != 0 && value != 1) return BTE_EINVAL;
       h->look_ahead = value;
       return BTE_OK;
+    case BTE_TUNE_FORM_OVERLAP:
+      if (value != 0 && value != 1) return BTE_EINVAL;
+      h->form_overlap = value;
+      return BTE_OK;
     default:
       return BTE_EINVAL;
   }
@@ -1532,6 +1545,7 @@ bte_status bte_get_tuning(bte_handle* h, int32_t key, int32_t* value) {
     case BTE_TUNE_PANEL_PAIRS: *value = h->d.lu_pairs; return BTE_OK;
     case BTE_TUNE_STATIC_PIVOTING: *value = h->d.static_piv; return BTE_OK;
     case BTE_TUNE_LOOK_AHEAD: *value = h->look_ahead; return BTE_OK;
+    case BTE_TUNE_FORM_OVERLAP: *value = h->form_overlap; return BTE_OK;
     default: return BTE_EINVAL;
   }
 }

@@ -210,9 +210,16 @@ inline bool lu_paired(const DevOps& d) { return d.lu_pairs != 0 && d.band_kl == 
 // panel, its first tile column (that panel's columns) goes first, and the next
 // panel's diagonal-block factorization and L21 run on the side stream while the
 // rest of the update runs on the main stream.
+// Formation overlap (form_overlap; statically pivoted dense factors with the
+// panels in pairs): the columns and rows below 256 are formed on the main
+// stream, the rest on the side stream between form_ev[0] and form_ev[1], and
+// the first K = 256 update waits for it.
 struct LuLookAhead {
   hipStream_t side = nullptr;
   hipEvent_t* ev = nullptr;
+  int look_ahead = 0;
+  int form_overlap = 0;
+  hipEvent_t form_ev[2] = {nullptr, nullptr};
 };
 void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* timer = nullptr, int m0 = 0,
                       int count = -1, const LuLookAhead* la = nullptr);

@@ -54,17 +54,21 @@ constexpr int NB = kNB;
 // and A contiguously; a block reads its column of each once and writes it into
 // xpb matrices with 16-byte streaming stores.  The blocks of one column run
 // together on one XCD, so that the column comes from HBM once and from that
-// XCD's L2 for the others, and the launch is bound by the writes.
+// XCD's L2 for the others, and the launch is bound by the writes.  part 0
+// forms columns c_lo.. whole; part 1 columns below split whole and the first
+// split rows of the others; part 2 (c_lo = split) the rest, rows from split.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* __restrict__ CT,
                                               const double* __restrict__ AT, const double* __restrict__ E,
                                               const double* __restrict__ n0x, double dt, int n, int npad, int nmat,
-                                              int xpb, int kl, int ku, int* __restrict__ mirror, int do_mirror) {
+                                              int xpb, int kl, int ku, int* __restrict__ mirror, int do_mirror,
+                                              int c_lo, int part, int split) {
   constexpr int CH = kMaxRows / 1024;  // 4-row groups per thread
   const int tid = threadIdx.x;
   int c, xb;
-  xcd_map(blockIdx.x, (nmat + xpb - 1) / xpb, npad, &c, &xb);
+  xcd_map(blockIdx.x, (nmat + xpb - 1) / xpb, npad - c_lo, &c, &xb);
+  c += c_lo;
   if (c >= npad) return;
   const int x0 = xb * xpb, x1 = min(nmat, x0 + xpb);
   // banded factors (lower / upper bandwidth kl / ku, kl > 0): only rows
@@ -76,6 +80,8 @@ __global__ __launch_bounds__(256) void k_form(T* __restrict__ LU, const double* 
     r_lo = max(0, (kp - kl - ku) / NB * NB - NB);
     r_hi = min(npad, (kp + NB + kl + NB - 1) / NB * NB);
   }
+  if (part == 1 && c >= split) r_hi = min(r_hi, split);
+  if (part == 2) r_lo = max(r_lo, split);
   double cv[CH][4], av[CH][4];
 #pragma unroll
   for (int ch = 0; ch < CH; ++ch)
@@ -520,7 +526,8 @@ __global__ __launch_bounds__(NT) void k_panel(T* __restrict__ LU, int* __restric
 //                  then seven levels of off-diagonal blocks); X goes row-major
 //                  into the matrix's linv slot after L11's inverses, and the
 //                  inverses of L11's eight diagonal blocks (k_dinv's output)
-//                  are formed beside those of U11's, by the other 128 threads;
+//                  are formed beside those of U11's, by the other 128 threads,
+//                  and L11^-1 (k_l11inv's output) by the same levels after X;
 //   k_l21_mfma     L21 = A21 X for 128 rows per block: one MFMA product (K =
 //                  128, the zero blocks of X skipped), A21 straight from HBM.
 // ---------------------------------------------------------------------------
@@ -541,6 +548,7 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
   __shared__ __align__(16) float sXT[NB][NB + 4];
   __shared__ float sT[8][16][17];   // a level's sums, per block
   __shared__ __align__(16) float sL11[16][20];   // rows as 16-byte vectors
+  __shared__ float sYd[8][16][16];                // inverses of L11's diagonal blocks
   __shared__ float s_red[4];
   float (*sA)[NB + 4] = sXT;
   constexpr int LQ = NB + 16;   // operand rows: lanes li + 16 lk fall on distinct banks
@@ -715,7 +723,7 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
       const int i = i4 + ii;
       float o[4];
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) o[jj] = (i <= j4 + jj) ? w[jj][ii] : 0.0f;
+      for (int jj = 0; jj < 4; ++jj) o[jj] = w[jj][ii];   // L's strict lower part rides below U
       *reinterpret_cast<float4*>(&sU[i][j4]) = make_float4(o[0], o[1], o[2], o[3]);
       if ((i >> 4) == (j4 >> 4)) {
 #pragma unroll
@@ -725,7 +733,8 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
     }
   }
   __syncthreads();
-  for (int e = tid; e < NB * NB; e += 256) sXT[e >> 7][e & (NB - 1)] = 0.0f;
+  for (int e = tid; e < NB * NB / 4; e += 256)
+    *reinterpret_cast<float4*>(&sXT[e >> 5][(e & 31) * 4]) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   __syncthreads();
   if (tid < NB) {   // thread (b, c): column c of X_bb
     const int b = tid >> 4, c = tid & 15, o = 16 * b;
@@ -750,7 +759,10 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
       for (int k = 0; k < r; ++k) x[r] -= sT[b][r][k] * x[k];
     float* out = linv + (size_t)mat * kLinvElems + b * 256;   // [b][r][c] row-major
 #pragma unroll
-    for (int r = 0; r < 16; ++r) out[r * 16 + c] = x[r];
+    for (int r = 0; r < 16; ++r) {
+      out[r * 16 + c] = x[r];
+      sYd[b][r][c] = x[r];
+    }
   }
   __syncthreads();
   // levels on MFMA, the blocks of a level spread over the wavefronts: T_ab into
@@ -790,6 +802,49 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
     *reinterpret_cast<float4*>(xo + (size_t)(k4 + 1) * NB + c4) = make_float4(v[0].y, v[1].y, v[2].y, v[3].y);
     *reinterpret_cast<float4*>(xo + (size_t)(k4 + 2) * NB + c4) = make_float4(v[0].z, v[1].z, v[2].z, v[3].z);
     *reinterpret_cast<float4*>(xo + (size_t)(k4 + 3) * NB + c4) = make_float4(v[0].w, v[1].w, v[2].w, v[3].w);
+  }
+  // ---- Y = L11^-1 (in place of k_l11inv) by the same levels: Y_bb from sYd,
+  // then Y_{a+d,a} = -Y_{a+d,a+d} sum_{m=a}^{a+d-1} L_{a+d,m} Y_{m,a}, with L's
+  // strict lower part in sU and Y kept transposed in the X region (zeros above
+  // its diagonal); Y leaves column-major after the diagonal-block inverses
+  __syncthreads();
+  for (int e = tid; e < NB * NB / 4; e += 256) {   // YT row k: Y_bb's column k mod 16 in block b, zeros elsewhere
+    const int k = e >> 5, i4 = (e & 31) * 4, b = k >> 4;
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if ((i4 >> 4) == b) {
+      const int r = i4 & 15, c = k & 15;
+      v = make_float4(sYd[b][r][c], sYd[b][r + 1][c], sYd[b][r + 2][c], sYd[b][r + 3][c]);
+    }
+    *reinterpret_cast<float4*>(&sXT[k][i4]) = v;
+  }
+  __syncthreads();
+  for (int d = 1; d < 8; ++d) {
+    for (int a = wid; a + d < 8; a += 4) {
+      const int r = a + d;
+      f32x4 t = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int m2 = a; m2 < r; ++m2)
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4)
+          t = Mma<float>::step(sU[16 * r + li][16 * m2 + 4 * q4 + lk], sXT[16 * a + li][16 * m2 + 4 * q4 + lk], t);
+#pragma unroll
+      for (int it = 0; it < 4; ++it) sT[a][4 * lk + it][li] = t[it];
+    }
+    __syncthreads();
+    for (int a = wid; a + d < 8; a += 4) {
+      const int r = a + d;
+      f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4)
+        x = Mma<float>::step(sXT[16 * r + 4 * q4 + lk][16 * r + li], sT[a][4 * q4 + lk][li], x);
+      *reinterpret_cast<float4*>(&sXT[16 * a + li][16 * r + 4 * lk]) = make_float4(-x[0], -x[1], -x[2], -x[3]);
+    }
+    __syncthreads();
+  }
+  float* yo = linv + (size_t)mat * kLinvElems + 8 * 256;   // column-major: (i, k) at k NB + i
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + 256 * u, k = e >> 5, i4 = (e & 31) * 4;
+    *reinterpret_cast<float4*>(yo + (size_t)k * NB + i4) = *reinterpret_cast<const float4*>(&sXT[k][i4]);
   }
   if (__syncthreads_or(nonfinite) && tid == 0) atomicOr(status, kStNonFinite);
 }
@@ -1650,11 +1705,30 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   int* piv = d.piv + (size_t)m0 * d.npad;
   int* perm = d.perm + (size_t)m0 * kMaxPanels * kPermStride;
   const int xpb = d.form_xpb > 0 ? d.form_xpb : (sizeof(T) == 4 ? 8 : 16);   // matrices per formation block
-  const dim3 gform(xcd_grid((nmat + xpb - 1) / xpb, d.npad));
-  k_form<T><<<gform, 256, 0, s>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, xpb,
-                                  d.band_kl, d.band_ku, d.mirror ? d.mirror + m0 : nullptr,
-                                  (std::is_same<T, float>::value && d.static_piv && d.mirror) ? 1 : 0);
   const int np = d.npad / NB;
+  const bool stat = std::is_same<T, float>::value && d.static_piv;
+  const bool pairs = lu_paired(d);
+  auto form = [&](hipStream_t st, int c_lo, int part) {
+    const dim3 gform(xcd_grid((nmat + xpb - 1) / xpb, d.npad - c_lo));
+    k_form<T><<<gform, 256, 0, st>>>(LU, d.CordT, d.AordT, d.E + m0, d.n0x + m0, d.dt, d.n, d.npad, nmat, xpb,
+                                     d.band_kl, d.band_ku, d.mirror ? d.mirror + m0 : nullptr,
+                                     (std::is_same<T, float>::value && d.static_piv && d.mirror) ? 1 : 0, c_lo,
+                                     part, 2 * NB);
+  };
+  // formation overlap (optional; statically pivoted dense pairs): the first
+  // pair reads only columns and rows below 2 NB until its K = 256 update, so
+  // the rest of the matrix is formed on the side stream meanwhile, and that
+  // update waits (measured slower at n = 2048: the two share HBM and the CUs)
+  const bool fsplit = stat && pairs && la && la->form_overlap && la->side && np >= 4 && d.band_kl == 0;
+  if (fsplit) {
+    (void)hipEventRecord(la->form_ev[0], s);
+    (void)hipStreamWaitEvent(la->side, la->form_ev[0], 0);
+    form(la->side, 2 * NB, 2);
+    (void)hipEventRecord(la->form_ev[1], la->side);
+    form(s, 0, 1);
+  } else {
+    form(s, 0, 0);
+  }
   const int P = tm ? tm->max_panels : 0;
   if (tm) {
     tm->used = 0;
@@ -1673,10 +1747,10 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   // kl below it; partial pivoting widens the upper band to kl + ku
   const int kl = d.band_kl, ku = d.band_ku;
   auto round_up = [](int v) { return (v + NB - 1) / NB * NB; };
-  // panels in pairs (dense systems): panel p's update of the columns beyond
-  // panel p+1 is deferred and applied with panel p+1's in one K = 256 update,
-  // which reads and writes A22 half as often; the last two panels go singly
-  const bool pairs = lu_paired(d);
+  // panels in pairs (dense systems, `pairs` above): panel p's update of the
+  // columns beyond panel p+1 is deferred and applied with panel p+1's in one
+  // K = 256 update, which reads and writes A22 half as often; the last two
+  // panels go singly
   auto panel = [&](int k0, int rend) {
     const int rows = rend - k0;
     constexpr int NT = kPanelThreads;  // 512 threads holding up to 4 rows each
@@ -1711,8 +1785,7 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
       if (nt > 0) k_l21_mfma<<<xcd_grid(nt, nmat), 256, 0, st>>>(LU, li, d.npad, k0, nt, nmat);
     }
   };
-  const bool stat = std::is_same<T, float>::value && d.static_piv;
-  const bool ahead = stat && la && la->side && la->ev && np <= kMaxPanels;
+  const bool ahead = stat && la && la->look_ahead && la->side && la->ev && np <= kMaxPanels;
   bool done_ahead[kMaxPanels] = {};   // panel already factored on the side stream
   for (int p = 0; p < np; ++p) {
     const int k0 = p * NB;
@@ -1737,7 +1810,7 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
       mark(3, p, 0, s);
     }
     const int nct = rest / 128;  // U12 tiles of 128 columns
-    if (rest > 0) k_l11inv<T><<<xcd_grid(NB / 32, nmat), 128, 0, s>>>(LU, li, d.npad, k0, nmat);
+    if (rest > 0 && !stat) k_l11inv<T><<<xcd_grid(NB / 32, nmat), 128, 0, s>>>(LU, li, d.npad, k0, nmat);   // (k_diag_static forms L11^-1)
     if (second) {
       // this panel's U12 from its top rows with panel p-1's deferred update,
       // the interchanges' other rows moved down, panel p-1's L rows permuted
@@ -1768,6 +1841,7 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
       if (nct > 1) launch_update(kind, LU, d.npad, ku0, mtr, nct - 1, 1, nmat, alt_kc, s, kd);
       if (tm) tm->launches += nct > 1 ? 2 : 1;
     };
+    if (fsplit && p == 1) (void)hipStreamWaitEvent(s, la->form_ev[1], 0);   // the rest of the matrix is formed
     if (first) {
       update(k0, mtr, 1, NB);                    // the next panel's columns only
     } else if (second) {

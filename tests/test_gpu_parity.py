@@ -752,8 +752,9 @@ def test_static_pivoting_is_rejected_for_fp64(torch):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
 def test_factorization_schedule_does_not_change_results(torch, prec):
-    """Factoring the points in 1..4 concurrent groups, and with or without the
-    look-ahead of the statically pivoted panels (off by default), gives bit-identical steps,
+    """Factoring the points in 1..4 concurrent groups, with or without the
+    look-ahead of the statically pivoted panels and the overlap of the formation
+    with the first pair (both off by default), gives bit-identical steps,
     with the panels in pairs (K = 256 trailing updates) and singly; the two
     forms round the trailing updates differently and agree to rounding (four
     panels: one pair, then two single panels)."""
@@ -779,17 +780,22 @@ def test_factorization_schedule_does_not_change_results(torch, prec):
         for g, o in enumerate(outs[1:], start=2):
             assert np.array_equal(o, outs[0]), f"pairs={pairs}: {g} groups differ from 1"
         if prec != "fp64":
-            # one group without the look-ahead of the statically pivoted panels
-            s = solver(cfg, precision=prec)
-            s.set_tuning(_lib.TUNE_PANEL_PAIRS, pairs)
-            assert s.get_tuning(_lib.TUNE_LOOK_AHEAD) == 0
-            s.set_tuning(_lib.TUNE_LOOK_AHEAD, 1)
-            F = cuda(torch, F0)
-            for n in range(3):
-                s.step(F, n * cfg["dt_s"])
-            assert s.status()[0] == 0
-            assert np.array_equal(F.cpu().numpy(), outs[0]), f"pairs={pairs}: look-ahead changes the result"
-            s.close()
+            # one group with the look-ahead of the statically pivoted panels and
+            # the formation overlap (both off by default)
+            for ahead, fover in ((1, 1), (0, 1), (1, 0)):
+                s = solver(cfg, precision=prec)
+                s.set_tuning(_lib.TUNE_PANEL_PAIRS, pairs)
+                assert s.get_tuning(_lib.TUNE_LOOK_AHEAD) == 0
+                assert s.get_tuning(_lib.TUNE_FORM_OVERLAP) == 0
+                s.set_tuning(_lib.TUNE_LOOK_AHEAD, ahead)
+                s.set_tuning(_lib.TUNE_FORM_OVERLAP, fover)
+                F = cuda(torch, F0)
+                for n in range(3):
+                    s.step(F, n * cfg["dt_s"])
+                assert s.status()[0] == 0
+                assert np.array_equal(F.cpu().numpy(), outs[0]), \
+                    f"pairs={pairs}: look-ahead {ahead} / formation overlap {fover} change the result"
+                s.close()
         res[pairs] = outs[0]
     tol = 1e-12 if prec == "fp64" else 1e-13   # mixed: refined to the FP64 backward error
     close(res[1], res[0], tol, "pairs vs single panels")
