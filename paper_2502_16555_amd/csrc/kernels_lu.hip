@@ -547,13 +547,14 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
   __shared__ __align__(16) float sU[NB][NB + 4];
   __shared__ __align__(16) float sXT[NB][NB + 4];
   __shared__ float sT[8][16][17];   // a level's sums, per block
-  __shared__ __align__(16) float sL11[16][20];   // rows as 16-byte vectors
+  __shared__ __align__(16) float sL11[2][16][20];   // rows as 16-byte vectors, per step parity
   __shared__ float sYd[8][16][16];                // inverses of L11's diagonal blocks
   __shared__ float s_red[4];
   float (*sA)[NB + 4] = sXT;
   constexpr int LQ = NB + 16;   // operand rows: lanes li + 16 lk fall on distinct banks
-  float (*sLt)[LQ] = reinterpret_cast<float (*)[LQ]>(&sU[0][0]);             // sLt[k][r] = -L[r][c0 + k]
-  float (*sUt)[LQ] = reinterpret_cast<float (*)[LQ]>(&sU[0][0] + 16 * LQ);   // sUt[k][c] = U[c0 + k][c]
+  // per step parity p: rows 32 p .. 32 p + 15 hold -L[r][c0 + k] (k = row),
+  // rows 32 p + 16 .. 32 p + 31 U[c0 + k][c]
+  float (*sLt)[LQ] = reinterpret_cast<float (*)[LQ]>(&sU[0][0]);
   float m = 0.0f;
   bool nonfinite = false;
 #pragma unroll
@@ -577,71 +578,91 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
   // ---- A11 = L11 U11 by 16-column steps c0 = 16 kb: wavefront 0 factors the
   // step's panel (rows c0.., two per lane) in registers, each pivot row passed
   // on by lane reads, with no barrier; then U12 = L11^-1 A12 for the step's 16
-  // rows (a thread per column) and A22 -= L21 U12 on MFMA in 16 x 16 tiles.
-  for (int kb = 0; kb < NB / 16; ++kb) {
+  // rows (a thread per column) and A22 -= L21 U12 on MFMA in 16 x 16 tiles:
+  // first the tiles of the next step's panel columns, then the others on
+  // wavefronts 1-3 while wavefront 0 factors that panel (the staging buffers
+  // alternate with the step).
+  auto panel = [&](int kb) __attribute__((always_inline)) {
     const int c0 = 16 * kb;
-    if (wid == 0) {
-      const int ra = c0 + lane, rb = c0 + 64 + lane;
-      const bool va = ra < NB, vb = rb < NB;
-      float p[16], q[16];
+    float (*sLtb)[LQ] = sLt + 32 * (kb & 1);
+    float (*sL11b)[20] = sL11[kb & 1];
+    const int ra = c0 + lane, rb = c0 + 64 + lane;
+    const bool va = ra < NB, vb = rb < NB;
+    float p[16], q[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) p[j] = q[j] = 0.0f;
-      if (va) {
+    for (int j = 0; j < 16; ++j) p[j] = q[j] = 0.0f;
+    if (va) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) p[j] = sA[c0 + j][ra];
+      for (int j = 0; j < 16; ++j) p[j] = sA[c0 + j][ra];
+    }
+    if (vb) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) q[j] = sA[c0 + j][rb];
+    }
+    // the lane tests stay inside the loop (hoisted, they would take 32 SGPRs)
+    int lv = lane;
+    asm volatile("" : "+v"(lv));
+    const bool two = c0 + 64 < NB;   // a second row per lane
+    static_for(std::make_integer_sequence<int, 16>(), [&](auto jc) __attribute__((always_inline)) {
+      constexpr int j = decltype(jc)::value;
+      float pv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p[j]), j));
+      if (!(fabsf(pv) >= tau)) pv = pv < 0.0f ? -tau : tau;   // also a NaN pivot (reported above)
+      const float rp = __builtin_amdgcn_rcpf(pv);
+      float u[16];
+#pragma unroll
+      for (int c = j + 1; c < 16; ++c) u[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p[c]), j));
+      // first half: lane j holds the pivot row; rows above it keep their U
+      // entries (a zero multiplier leaves them exactly)
+      const bool below = lv > j;
+      const float l = p[j] * rp;
+      const float lm = below ? l : 0.0f;
+      p[j] = below ? l : (lv == j ? pv : p[j]);
+#pragma unroll
+      for (int c = j + 1; c < 16; ++c) p[c] = fmaf(-lm, u[c], p[c]);
+      if (two) {
+        const float l2 = q[j] * rp;
+        q[j] = l2;
+#pragma unroll
+        for (int c = j + 1; c < 16; ++c) q[c] = fmaf(-l2, u[c], q[c]);
       }
-      if (vb) {
+    });
+    // the panel in place; L21 (negated) and L11 staged for the products
+    if (va) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) q[j] = sA[c0 + j][rb];
-      }
-      // the lane tests stay inside the loop (hoisted, they would take 32 SGPRs)
-      int lv = lane;
-      asm volatile("" : "+v"(lv));
-      const bool two = c0 + 64 < NB;   // a second row per lane
-      static_for(std::make_integer_sequence<int, 16>(), [&](auto jc) __attribute__((always_inline)) {
-        constexpr int j = decltype(jc)::value;
-        float pv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p[j]), j));
-        if (!(fabsf(pv) >= tau)) pv = pv < 0.0f ? -tau : tau;   // also a NaN pivot (reported above)
-        const float rp = __builtin_amdgcn_rcpf(pv);
-        float u[16];
+      for (int j = 0; j < 16; ++j) sA[c0 + j][ra] = p[j];
+      if (lane >= 16) {
 #pragma unroll
-        for (int c = j + 1; c < 16; ++c) u[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p[c]), j));
-        // first half: lane j holds the pivot row; rows above it keep their U
-        // entries (a zero multiplier leaves them exactly)
-        const bool below = lv > j;
-        const float l = p[j] * rp;
-        const float lm = below ? l : 0.0f;
-        p[j] = below ? l : (lv == j ? pv : p[j]);
+        for (int j = 0; j < 16; ++j) sLtb[j][ra] = -p[j];
+      } else {
 #pragma unroll
-        for (int c = j + 1; c < 16; ++c) p[c] = fmaf(-lm, u[c], p[c]);
-        if (two) {
-          const float l2 = q[j] * rp;
-          q[j] = l2;
-#pragma unroll
-          for (int c = j + 1; c < 16; ++c) q[c] = fmaf(-l2, u[c], q[c]);
-        }
-      });
-      // the panel in place; L21 (negated) and L11 staged for the products
-      if (va) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) sA[c0 + j][ra] = p[j];
-        if (lane >= 16) {
-#pragma unroll
-          for (int j = 0; j < 16; ++j) sLt[j][ra] = -p[j];
-        } else {
-#pragma unroll
-          for (int j = 0; j < 16; ++j) sL11[lane][j] = p[j];
-        }
-      }
-      if (vb) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          sA[c0 + j][rb] = q[j];
-          sLt[j][rb] = -q[j];
-        }
+        for (int j = 0; j < 16; ++j) sL11b[lane][j] = p[j];
       }
     }
-    __syncthreads();
+    if (vb) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        sA[c0 + j][rb] = q[j];
+        sLtb[j][rb] = -q[j];
+      }
+    }
+  };
+  // A22 tile (rows r0.., columns cc..) -= L21 U12 of step kb
+  auto tile = [&](int kb, int r0, int cc) __attribute__((always_inline)) {
+    float (*sLtb)[LQ] = sLt + 32 * (kb & 1);
+    float (*sUtb)[LQ] = sLt + 32 * (kb & 1) + 16;
+    const float4 cv = *reinterpret_cast<const float4*>(&sA[cc + li][r0 + 4 * lk]);
+    f32x4 acc = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4)
+      acc = Mma<float>::step(sLtb[4 * q4 + lk][r0 + li], sUtb[4 * q4 + lk][cc + li], acc);
+    *reinterpret_cast<float4*>(&sA[cc + li][r0 + 4 * lk]) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+  };
+  if (wid == 0) panel(0);
+  __syncthreads();
+  for (int kb = 0; kb < NB / 16; ++kb) {
+    const int c0 = 16 * kb;
+    float (*sL11b)[20] = sL11[kb & 1];
+    float (*sUtb)[LQ] = sLt + 32 * (kb & 1) + 16;
     const int ncol = NB - c0 - 16;
     if (tid < ncol) {   // U12 column c by forward substitution with the unit lower L11
       const int c = c0 + 16 + tid;
@@ -659,7 +680,7 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
         float lr[16];
 #pragma unroll
         for (int j4 = 0; j4 < i; j4 += 4) {
-          const float4 v = *reinterpret_cast<const float4*>(&sL11[i][j4]);
+          const float4 v = *reinterpret_cast<const float4*>(&sL11b[i][j4]);
           lr[j4] = v.x;
           lr[j4 + 1] = v.y;
           lr[j4 + 2] = v.z;
@@ -672,20 +693,20 @@ __global__ __launch_bounds__(256) void k_diag_static(float* __restrict__ LU, flo
       for (int q4 = 0; q4 < 4; ++q4)
         *reinterpret_cast<float4*>(&sA[c][c0 + 4 * q4]) = make_float4(x[4 * q4], x[4 * q4 + 1], x[4 * q4 + 2], x[4 * q4 + 3]);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) sUt[i][c] = x[i];
+      for (int i = 0; i < 16; ++i) sUtb[i][c] = x[i];
     }
     __syncthreads();
     const int nt = ncol / 16;
-    for (int t = wid; t < nt * nt; t += 4) {
-      const int r0 = c0 + 16 + 16 * (t % nt), cc = c0 + 16 + 16 * (t / nt);
-      const float4 cv = *reinterpret_cast<const float4*>(&sA[cc + li][r0 + 4 * lk]);
-      f32x4 acc = {cv.x, cv.y, cv.z, cv.w};
-#pragma unroll
-      for (int q4 = 0; q4 < 4; ++q4)
-        acc = Mma<float>::step(sLt[4 * q4 + lk][r0 + li], sUt[4 * q4 + lk][cc + li], acc);
-      *reinterpret_cast<float4*>(&sA[cc + li][r0 + 4 * lk]) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    if (nt > 0) {
+      for (int t = wid; t < nt; t += 4) tile(kb, c0 + 16 + 16 * t, c0 + 16);
+      __syncthreads();
+      if (wid == 0) {
+        panel(kb + 1);
+      } else {
+        for (int t = wid - 1; t < nt * (nt - 1); t += 3) tile(kb, c0 + 16 + 16 * (t % nt), c0 + 32 + 16 * (t / nt));
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   // the factors to the matrix; pivots and permutation as the identity
 #pragma unroll
