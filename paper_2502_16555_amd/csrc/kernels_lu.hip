@@ -1564,7 +1564,7 @@ __global__ __launch_bounds__(1024) void k_solve(const T* __restrict__ LU, const 
 #pragma unroll
         for (int u = 0; u < JB; ++u) {
           const int c = k0 + grp * CW + jb + u;
-          if (v) x[u] = *reinterpret_cast<const V*>(A + (size_t)c * npad + r);
+          if (v) x[u] = ntload(reinterpret_cast<const V*>(A + (size_t)c * npad + r));
         }
 #pragma unroll
         for (int u = 0; u < JB; ++u) {

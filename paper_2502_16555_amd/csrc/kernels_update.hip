@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int np
     for (int u = 0; u < NV; ++u) {
       const int e = tid + u * 256;
       const int col = e / (RP / PER), rr = (e % (RP / PER)) * PER;
-      dst[u] = *reinterpret_cast<const V*>(A + (size_t)(c0 + col) * npad + r0 + pass * RP + rr);
+      dst[u] = ntload(reinterpret_cast<const V*>(A + (size_t)(c0 + col) * npad + r0 + pass * RP + rr));
     }
   };
   for (int ch = 0; ch < NCH; ++ch) {

@@ -19,6 +19,14 @@ using f64x2 = double __attribute__((ext_vector_type(2)));
 
 constexpr int kXcd = 8;  // XCDs of an MI355X; workgroups are dealt to them round-robin
 
+// Non-temporal 16-byte load of data read once (the solves' factors, a
+// trailing update's old tile), so that it does not displace what is reused.
+template <typename V>
+__device__ inline V ntload(const V* p) {
+  using I = int __attribute__((ext_vector_type(sizeof(V) / 4)));
+  return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const I*>(p)));
+}
+
 // f(integral_constant<int, I>) for I in the sequence, in order: loop bodies
 // whose indices must be compile-time constants (register arrays, unrolled
 // steps) without relying on the unroller
