@@ -32,7 +32,7 @@ MI355X_PEAK_HBM_GBS = 8000.0
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters
 # read for a 1 GiB copy (x2.0 and x1.0).  Valid for the kernel source it was taken
 # on (hash of kernels_update.hip); reported as null once that file has changed.
-KUPDATE_TRAFFIC = {"source_sha256_16": "b7aca7d9552e8d89", "fetch_bytes": 1.159e9, "write_bytes": 6.979e8,
+KUPDATE_TRAFFIC = {"source_sha256_16": "380b72ee07cf3be8", "fetch_bytes": 1.145e9, "write_bytes": 6.979e8,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 
