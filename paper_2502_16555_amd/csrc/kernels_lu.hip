@@ -33,6 +33,11 @@
 // k_u12's gather.  Panel p+1's interchanges then also reach panel p's L
 // columns, so the solve applies P_p P_{p+1} before L_p and L_{p+1}
 // (A = ... P_p^T P_{p+1}^T L' ...).
+// Statically pivoted FP32 factors (the mixed precisions' default) take no
+// interchanges: each panel is k_diag_static (the 128 x 128 diagonal block's
+// factors, U11^-1, L11^-1 and the inverses of L11's diagonal blocks, in
+// place of k_panel, k_dinv and k_l11inv) and k_l21_mfma (L21 = A21 U11^-1),
+// and k_move_down and k_perm_lp have nothing to move (see below).
 #include <algorithm>
 #include <cfloat>
 #include <climits>
