@@ -261,31 +261,35 @@ def run_hybrid(cfg, steps, warmup, torch):
     return res
 
 
-def run_implicit(cfg, torch, mults=(1.0,)):
+def run_implicit(cfg, torch, runs=((0, 1.0), (1, 1.0), (0, 10.0))):
     """The fully implicit step at the bench grid (RF field, mixed-precision
     preconditioner): wall time per step, Newton and GMRES iterations, and the
-    simulated time advanced per wall second against the semi-implicit step's."""
+    simulated time advanced per wall second against the semi-implicit step's,
+    for each (preconditioner, step multiple) in runs: preconditioner 0 the V
+    solve then the full-step x solve, 1 the semi-implicit step."""
     import copy
     import workloads
     from paper_2502_16555_amd import Solver
     opts = dict(newton_rtol=1e-8, gmres_rtol=1e-4, restart=60, max_gmres=1500, max_newton=8)
+    names = {0: "V solve then x solve over dt", 1: "semi-implicit step X(dt/2) V(dt) X(dt/2)"}
     out = {"workload": f"Nx={cfg['nx']}, Nr={cfg['nr']}, Ntheta={cfg['ntheta']}, RF field, Newton-GMRES "
-                       "preconditioned by the semi-implicit step (mixed precision), one step from the "
-                       "initial state", "options": opts, "steps": []}
-    for q, mult in enumerate(mults):
+                       "with a mixed-precision operator-split preconditioner, one step from the initial state",
+           "options": opts, "steps": []}
+    for pk, mult in runs:
         c = copy.deepcopy(cfg)
         c["dt_s"] = cfg["dt_s"] * mult
         s = Solver(c, precision="mixed_fp32")
         ne = workloads.density_profile(s.xhat(), c["ic"]["ne_peak"])
         F = s.initial_state(torch.as_tensor(ne, device="cuda:0"), c["ic"]["Te_eV"])
-        if q == 0:   # first use: kernels loaded, workspace allocated
-            s.implicit_step(F.clone(), 0.0, max_newton=1, max_gmres=2, raise_on_noconv=False)
+        # first use: kernels loaded, workspace and the full-step x inverses built
+        s.implicit_step(F.clone(), 0.0, max_newton=1, max_gmres=2, precond=pk, raise_on_noconv=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = s.implicit_step(F, 0.0, raise_on_noconv=False, **opts)
+        st = s.implicit_step(F, 0.0, raise_on_noconv=False, precond=pk, **opts)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        out["steps"].append({"dt_over_T_rf": c["dt_s"] / c["T_rf_s"], "ms_per_step": wall * 1e3,
+        out["steps"].append({"preconditioner": names[pk], "dt_over_T_rf": c["dt_s"] / c["T_rf_s"],
+                             "ms_per_step": wall * 1e3,
                              "newton_iters": st["newton_iters"], "gmres_iters": st["gmres_iters"],
                              "converged": st["status"] == 0, "residual_rel": st["residual"] / st["residual0"],
                              "simulated_s_per_wall_s": c["dt_s"] / wall})

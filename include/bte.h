@@ -163,23 +163,35 @@ bte_status bte_step(bte_handle* h, double* F, double t_s, bte_field field, void*
  * or the specified field at t_s + dt (CONST, RF: the equation is then linear),
  * and F = 0 at the inflow entries of the walls (eq. hybrid_cnt_b_bdy).
  * Newton's method with a backtracking line search on ||R||_2; each Newton
- * system J_F dlt = -R (Jacobian action of eq. 1dbte_jac_action, matrix free)
- * by restarted GMRES, right-preconditioned by the semi-implicit step as a
- * linear map with the field frozen at E(F) (X(dt/2), one solve with the V
- * factors of the handle's precision, without refinement, X(dt/2)), classical
- * Gram-Schmidt twice.  F (device [sum Nx][Nr][Ntheta]) is
+ * system J_F dlt = -R (Jacobian action of eq. 1dbte_jac_action, matrix free;
+ * the first step drops the Poisson field's coupling term E(dlt) . F, i.e. it
+ * linearizes with the field frozen at E(F^n), which keeps a full first step
+ * from overshooting) by restarted GMRES, right-preconditioned by an operator split of the same
+ * equation, taken as a linear map with the field frozen at E(F): one solve with
+ * the V factors of the handle's precision (without refinement) and backward-Euler
+ * x solves, classical Gram-Schmidt twice.  opts.precond picks the split:
+ *   BTE_PRECOND_SPLIT (0, default): the V solve over dt, then the x solve over dt
+ *     (the inverses of I + dt lam_i cos(theta_a) D_x, formed on the host at the
+ *     first call, sum Nx^2 Nr Ntheta / 2 doubles of device memory);
+ *   BTE_PRECOND_SEMI_IMPLICIT (1): the semi-implicit step X(dt/2) V(dt) X(dt/2)
+ *     (eq. bte_semi_implicit), the paper's preconditioner.
+ * The V systems are factored once per call with a specified field and at every
+ * Newton step with the Poisson field.  F (device [sum Nx][Nr][Ntheta]) is
  * replaced by F^{n+1}.  Synchronous on the stream (the host drives the
  * iterations).  Defaults for zero fields of opts: newton_rtol 1e-12 (relative
  * to ||F^n||_2), max_newton 20, gmres_rtol 1e-6, restart 30 (<= 200), max_gmres
  * 200 per Newton step.  stats (may be NULL) receives the counts and the final
- * and initial ||R||_2.  Errors: BTE_EINVAL, BTE_EUNSUPPORTED (GIVEN field),
- * BTE_ENOCONV (Newton did not reach newton_rtol; F holds the last iterate). */
+ * and initial ||R||_2.  Errors: BTE_EINVAL (also an unknown precond),
+ * BTE_EUNSUPPORTED (GIVEN field), BTE_ENOCONV (Newton did not reach
+ * newton_rtol; F holds the last iterate). */
+enum { BTE_PRECOND_SPLIT = 0, BTE_PRECOND_SEMI_IMPLICIT = 1 };
 typedef struct {
   double newton_rtol;
   int32_t max_newton;
   double gmres_rtol;
   int32_t restart;
   int32_t max_gmres;
+  int32_t precond;
 } bte_implicit_opts;
 typedef struct {
   int32_t newton_iters;

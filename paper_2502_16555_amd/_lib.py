@@ -37,7 +37,7 @@ class bte_field(C.Structure):
 
 class bte_implicit_opts(C.Structure):
     _fields_ = [("newton_rtol", C.c_double), ("max_newton", C.c_int32), ("gmres_rtol", C.c_double),
-                ("restart", C.c_int32), ("max_gmres", C.c_int32)]
+                ("restart", C.c_int32), ("max_gmres", C.c_int32), ("precond", C.c_int32)]
 
 
 class bte_implicit_stats(C.Structure):
@@ -62,6 +62,8 @@ TUNE_PANEL_PAIRS = 3
 TUNE_STATIC_PIVOTING = 4
 TUNE_LOOK_AHEAD = 5
 TUNE_FORM_OVERLAP = 6
+PRECOND_SPLIT = 0
+PRECOND_SEMI_IMPLICIT = 1
 ION_SCRATCH_DOUBLES = 2097152   # BTE_ION_SCRATCH_DOUBLES
 
 EXPORTS = {

@@ -661,41 +661,45 @@ void assemble(const AssemblyInput& in, HostOps* out) {
       X.Dx[i * nx + i] = diag;
     }
     for (double& d : X.Dx) d *= 2.0 / in.L;
-    // Q for the ordinates with cos(theta) > 0 (upper half of the ascending GL nodes);
-    // the lower half follows from the mirror symmetry Q(-mu) = J Q(mu) J.
-    const int nh = nth / 2;
-    X.Qt.assign((size_t)nr * nh * nx * nx, 0.0);
-    const int nmode = nr * nh;
-    unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    std::vector<std::thread> pool;
-    std::vector<std::string> errs(nthreads);
-    for (unsigned tid = 0; tid < nthreads; ++tid) {
-      pool.emplace_back([&, tid]() {
-        try {
-          for (int m = tid; m < nmode; m += nthreads) {
-            int i = m / nh, h = m % nh;
-            double c = 0.5 * in.dt * H.lam[i] * H.mu[nh + h];
-            std::vector<double> B(nx * nx);
-            for (int r = 0; r < nx; ++r)
-              for (int cc = 0; cc < nx; ++cc) B[r * nx + cc] = (r == cc ? 1.0 : 0.0) + c * X.Dx[r * nx + cc];
-            for (int cc = 0; cc < nx; ++cc) B[cc] = (cc == 0) ? 1.0 : 0.0;  // inflow row at xhat = -1
-            std::vector<double> Bi;
-            invert(B, nx, &Bi);
-            double* Q = X.Qt.data() + (size_t)m * nx * nx;
-            for (int r = 0; r < nx; ++r)
-              for (int cc = 0; cc < nx; ++cc) Q[(size_t)cc * nx + r] = (cc == 0) ? 0.0 : Bi[r * nx + cc];
-          }
-        } catch (const std::exception& e) {
-          errs[tid] = e.what();
-        }
-      });
-    }
-    for (auto& t : pool) t.join();
-    for (auto& e : errs) if (!e.empty()) throw std::runtime_error(e);
+    advection_inverses(H, X, 0.5 * in.dt, &X.Qt);
     // Poisson: D2 with Dirichlet rows, E = -Dx D2^-1 rhs
     X.poisson = poisson_operator(X.Dx, nx);
     H.xops.push_back(std::move(X));
   }
+}
+
+void advection_inverses(const HostOps& H, const XOps& X, double h, std::vector<double>* Qt) {
+  // Q for the ordinates with cos(theta) > 0 (upper half of the ascending GL nodes);
+  // the lower half follows from the mirror symmetry Q(-mu) = J Q(mu) J.
+  const int nx = X.nx, nr = H.nr, nh = H.nth / 2;
+  Qt->assign((size_t)nr * nh * nx * nx, 0.0);
+  const int nmode = nr * nh;
+  unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  std::vector<std::string> errs(nthreads);
+  for (unsigned tid = 0; tid < nthreads; ++tid) {
+    pool.emplace_back([&, tid]() {
+      try {
+        for (int m = tid; m < nmode; m += nthreads) {
+          int i = m / nh, hh = m % nh;
+          double c = h * H.lam[i] * H.mu[nh + hh];
+          std::vector<double> B(nx * nx);
+          for (int r = 0; r < nx; ++r)
+            for (int cc = 0; cc < nx; ++cc) B[r * nx + cc] = (r == cc ? 1.0 : 0.0) + c * X.Dx[r * nx + cc];
+          for (int cc = 0; cc < nx; ++cc) B[cc] = (cc == 0) ? 1.0 : 0.0;  // inflow row at xhat = -1
+          std::vector<double> Bi;
+          invert(B, nx, &Bi);
+          double* Q = Qt->data() + (size_t)m * nx * nx;
+          for (int r = 0; r < nx; ++r)
+            for (int cc = 0; cc < nx; ++cc) Q[(size_t)cc * nx + r] = (cc == 0) ? 0.0 : Bi[r * nx + cc];
+        }
+      } catch (const std::exception& e) {
+        errs[tid] = e.what();
+      }
+    });
+  }
+  for (auto& t : pool) t.join();
+  for (auto& e : errs) if (!e.empty()) throw std::runtime_error(e);
 }
 
 std::vector<double> maxwellian_coeffs(const HostOps& H, double Te_eV) {

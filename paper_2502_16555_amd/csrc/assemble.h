@@ -63,6 +63,12 @@ struct HostOps {
 // Throws std::runtime_error on invalid input.
 void assemble(const AssemblyInput& in, HostOps* out);
 
+// Inverses of the backward-Euler x systems over a step h, I + h lam_i cos(theta_a) D_x
+// with the inflow row replaced by the zero-inflow condition (eq.
+// bte_semi_implicit_xspace0 takes h = dt / 2), for the ordinates with
+// cos(theta) > 0, in the layout of XOps::Qt.
+void advection_inverses(const HostOps& H, const XOps& X, double h, std::vector<double>* Qt);
+
 // Unit-density Maxwellian at Te projected on the speed basis (M c = b).
 std::vector<double> maxwellian_coeffs(const HostOps& ops, double Te_eV);
 

@@ -46,6 +46,7 @@ struct ImplicitWs {
   double *El = nullptr, *zeros = nullptr;               // [sum Nx]
   double *partial = nullptr, *coef = nullptr;
   std::vector<double> hpart, hcoef;
+  double* Qx = nullptr;         // inverses of the x systems over the full step (layout of DevOps::Qt)
 };
 
 struct bte_handle {
@@ -605,6 +606,13 @@ void implicit_alloc(bte_handle* h, int m) {
     w.El = h->alloc<double>(d.nx_total);
     w.zeros = h->alloc<double>(d.nx_total);
     HIP_OK(hipMemset(w.zeros, 0, d.nx_total * sizeof(double)));
+    // the backward-Euler x solve over dt of the split preconditioner
+    std::vector<double> Q, Qd;
+    for (const auto& X : h->host.xops) {
+      bte::advection_inverses(h->host, X, d.dt, &Qd);
+      Q.insert(Q.end(), Qd.begin(), Qd.end());
+    }
+    w.Qx = h->upload(Q);
   }
   if (w.m < m) {
     w.m = m;
@@ -672,14 +680,16 @@ void imp_residual(bte_handle* h, const double* F, const double* ni, double t1, d
   bte::launch_wall_rows(d, R, F, s);
 }
 
-// out = J_F X (eq. 1dbte_jac_action in residual form), with d.E = E(F)
-void imp_jac(bte_handle* h, const double* F, const double* X, double* out, hipStream_t s) {
+// out = J_F X (eq. 1dbte_jac_action in residual form), with d.E = E(F); without
+// the field-coupling term (the Poisson field's E(X) . F) when !coupling: the
+// Jacobian of the residual with the field frozen at E(F)
+void imp_jac(bte_handle* h, const double* F, const double* X, double* out, bool coupling, hipStream_t s) {
   DevOps& d = h->d;
   ImplicitWs& iw = h->iw;
   const bte_config& c = h->cfg;
   bte::launch_pad_rows(d, X, iw.Pa, s);
   bte::launch_apply_field(d, 2, nullptr, iw.Pa, iw.Pb, d.E, s);
-  if (c.field_mode == BTE_FIELD_POISSON) {
+  if (coupling && c.field_mode == BTE_FIELD_POISSON) {
     // E_lin(X) = L (0 - u^T X): the derivative of the affine field map
     bte::launch_field(d, BTE_FIELD_POISSON, 0.0, c.field_freq_hz, c.field_a1, 0.0, X, nullptr, iw.zeros, iw.El, s);
     bte::launch_pad_rows(d, F, iw.Pc, s);
@@ -691,17 +701,29 @@ void imp_jac(bte_handle* h, const double* F, const double* X, double* out, hipSt
   bte::launch_wall_rows(d, out, X, s);
 }
 
-// z = S v: the semi-implicit step as a linear map with the field frozen (factors of d.E)
-void imp_precond(bte_handle* h, const double* v, double* z, hipStream_t s) {
+// z = S v with the field frozen (factors of d.E).  BTE_PRECOND_SPLIT:
+// S = (I + dt A_x (.) D_x^T)^-1 (I - dt V)^-1, the V solve then the backward-Euler
+// x solve over the whole step, so that S^-1 = J - dt^2 V X (X the x operator) and
+// the stiff x modes, which the splitting leaves exact, do not enter the error.
+// BTE_PRECOND_SEMI_IMPLICIT: the semi-implicit step X(dt/2) V(dt) X(dt/2), whose
+// inverse differs from J by dt^2 X^2 / 4 + ..., large on the stiff x modes.
+void imp_precond(bte_handle* h, const double* v, double* z, int kind, hipStream_t s) {
   HIP_OK(hipMemcpyAsync(z, v, sizeof(double) * h->iw.N, hipMemcpyDeviceToDevice, s));
-  x_half(h, z, false, s);
+  if (kind == BTE_PRECOND_SEMI_IMPLICIT) {
+    x_half(h, z, false, s);
+    v_solve_again(h, z, false, s, false);
+    x_half(h, z, false, s);
+    return;
+  }
   v_solve_again(h, z, false, s, false);
-  x_half(h, z, false, s);
+  bte::launch_x_to_modes(h->d, z, s);
+  bte::launch_advect(h->d, false, false, s, h->iw.Qx);
+  bte::launch_modes_to_x(h->d, z, s);
 }
 
 // Right-preconditioned restarted GMRES for J_F dlt = b (b in iw.Rt); classical
 // Gram-Schmidt twice; returns the iterations.
-int imp_gmres(bte_handle* h, const double* F, double rtol, int m, int maxit, hipStream_t s) {
+int imp_gmres(bte_handle* h, const double* F, double rtol, int m, int maxit, int pk, bool coupling, hipStream_t s) {
   ImplicitWs& iw = h->iw;
   const size_t N = iw.N;
   double* V = iw.V;
@@ -721,8 +743,8 @@ int imp_gmres(bte_handle* h, const double* F, double rtol, int m, int maxit, hip
     for (int j = 0; j < m; ++j) {
       double* vj = V + (size_t)j * N;
       double* w = V + (size_t)(j + 1) * N;
-      imp_precond(h, vj, iw.z, s);
-      imp_jac(h, F, iw.z, w, s);
+      imp_precond(h, vj, iw.z, pk, s);
+      imp_jac(h, F, iw.z, w, coupling, s);
       imp_dots(h, w, V, j + 1, hc.data(), s);
       for (int i = 0; i <= j; ++i) h2[i] = -hc[i];
       imp_comb(h, w, 1.0, V, h2.data(), j + 1, s);
@@ -757,10 +779,10 @@ int imp_gmres(bte_handle* h, const double* F, double rtol, int m, int maxit, hip
       y[i] = t / H[(size_t)i * m + i];
     }
     imp_comb(h, iw.u, 0.0, V, y.data(), k, s);
-    imp_precond(h, iw.u, iw.z, s);
+    imp_precond(h, iw.u, iw.z, pk, s);
     bte::launch_axpby(iw.dlt, iw.z, 1.0, 1.0, N, s);
     // true residual of the accumulated correction into V_0
-    imp_jac(h, F, iw.dlt, iw.u, s);
+    imp_jac(h, F, iw.dlt, iw.u, coupling, s);
     HIP_OK(hipMemcpyAsync(V, iw.Rt, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     bte::launch_axpby(V, iw.u, 1.0, -1.0, N, s);
   }
@@ -1010,6 +1032,8 @@ bte_status bte_implicit_step(bte_handle* h, double* F, const double* ni, double 
   const double grtol = opts.gmres_rtol > 0.0 ? opts.gmres_rtol : 1e-6;
   const int m = opts.restart > 0 ? std::min(opts.restart, 200) : 30;
   const int max_gmres = opts.max_gmres > 0 ? opts.max_gmres : 200;
+  const int pk = opts.precond;
+  if (pk != BTE_PRECOND_SPLIT && pk != BTE_PRECOND_SEMI_IMPLICIT) return BTE_EINVAL;
   try {
     HIP_OK(hipSetDevice(h->device));
     hipStream_t s = S(stream);
@@ -1025,11 +1049,18 @@ bte_status bte_implicit_step(bte_handle* h, double* F, const double* ni, double 
     const double tol = nrtol * std::max(imp_norm(h, iw.Fn, s), 1e-300);
     int it = 0, gits = 0;
     bool ok = rn <= tol;
+    // the V factors of the preconditioner: E(F) of the iterate with the Poisson
+    // field; a specified field does not depend on F, so one factorization serves
+    // every Newton step
+    const bool refactor = fm == BTE_FIELD_POISSON;
     for (; it < max_newton && !ok; ++it) {
-      factor_all(h, s);                               // V factors for E(F), d.E from the residual
+      if (it == 0 || refactor) factor_all(h, s);      // d.E = E(F) from the last residual
       HIP_OK(hipMemcpyAsync(iw.Rt, iw.R, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
       bte::launch_axpby(iw.Rt, iw.Rt, -1.0, 0.0, N, s);
-      gits += imp_gmres(h, F, grtol, m, max_gmres, s);
+      // the first step linearizes with the field frozen at E(F^n) (a Picard step;
+      // the Newton step itself for a specified field), the later ones with the
+      // field coupling of eq. 1dbte_jac_action
+      gits += imp_gmres(h, F, grtol, m, max_gmres, pk, it > 0, s);
       // line search on ||R||: full step first, then halvings
       double alpha = 1.0;
       bool acc = false;

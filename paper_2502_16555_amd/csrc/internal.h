@@ -173,7 +173,8 @@ void launch_apply_field(const DevOps& d, int mode, const double* B, const double
 
 // ---- X step (kernels_x.hip) -------------------------------------------------
 void launch_x_to_modes(const DevOps& d, const double* F, hipStream_t s);
-void launch_advect(const DevOps& d, bool fp32, bool transpose, hipStream_t s);
+// Qt (optional): FP64 inverses in the layout of d.Qt to apply instead (forward)
+void launch_advect(const DevOps& d, bool fp32, bool transpose, hipStream_t s, const double* Qt = nullptr);
 void launch_modes_to_x(const DevOps& d, double* F, hipStream_t s);
 void launch_x_to_modes_T(const DevOps& d, const double* F, hipStream_t s);   // U^T contraction
 void launch_modes_to_x_T(const DevOps& d, double* F, hipStream_t s);         // Uinv^T contraction

@@ -321,10 +321,12 @@ void launch_modes_to_x_T(const DevOps& d, double* F, hipStream_t s) {
   k_modes_to_x<<<d.nx_total, kThreads, sh, s>>>(d.Y, F, d.Uinv, d.x_disc, d.x_off, d.nx_of, d.nr, d.nth, 1);
 }
 
-void launch_advect(const DevOps& d, bool fp32, bool transpose, hipStream_t s) {
+void launch_advect(const DevOps& d, bool fp32, bool transpose, hipStream_t s, const double* Qt) {
   dim3 grid(d.nr * d.nh, d.nd);
   const size_t sh = sizeof(double) * 2 * d.max_nx;
-  if (fp32) {
+  if (Qt) {   // other FP64 inverses in the layout of d.Qt (forward only)
+    k_advect<double, 0><<<grid, kThreads, sh, s>>>(d.Y, Qt, d.q_off, d.x_off, d.nx_of, d.nr, d.nth);
+  } else if (fp32) {
     if (transpose) k_advect<float, 1><<<grid, kThreads, sh, s>>>(d.Y, d.Qt32, d.q_off, d.x_off, d.nx_of, d.nr, d.nth);
     else k_advect<float, 0><<<grid, kThreads, sh, s>>>(d.Y, d.Qt32, d.q_off, d.x_off, d.nx_of, d.nr, d.nth);
   } else {

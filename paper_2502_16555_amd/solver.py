@@ -170,11 +170,11 @@ class Solver:
         check(self.lib.bte_hybrid_step(self.h, _ptr(F), _ptr(ni), float(t), _stream(stream)), "bte_hybrid_step")
 
     def implicit_step(self, F, t, ni=None, newton_rtol=0.0, max_newton=0, gmres_rtol=0.0, restart=0,
-                      max_gmres=0, stream=None, raise_on_noconv=True) -> dict:
+                      max_gmres=0, precond=0, stream=None, raise_on_noconv=True) -> dict:
         """Fully implicit step (bte_implicit_step), F in place; returns the iteration counts
         and residual norms.  Zero options take the library defaults."""
         opts = _lib.bte_implicit_opts(float(newton_rtol), int(max_newton), float(gmres_rtol), int(restart),
-                                      int(max_gmres))
+                                      int(max_gmres), int(precond))
         st = _lib.bte_implicit_stats()
         code = self.lib.bte_implicit_step(self.h, _ptr(F), _ptr(ni), float(t), opts, C.byref(st), _stream(stream))
         if code != _lib.BTE_OK and (raise_on_noconv or code != _lib.BTE_ENOCONV):

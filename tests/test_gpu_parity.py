@@ -430,18 +430,18 @@ def test_hybrid_ensemble_per_discharge(torch, nx_per):
     s.close()
 
 
-@pytest.mark.parametrize("kind,prec,dt_mult", [
-    ("const", "fp64", 1.0), ("rf", "mixed_fp32", 1.0), ("poisson", "fp64", 1.0), ("poisson", "mixed_fp32", 1.0),
-    ("rf", "mixed_fp32", 10.0),
-    pytest.param("poisson", "mixed_fp32", 10.0, marks=pytest.mark.skip(
-        reason="does not converge: with the Poisson field and ten times the step, the semi-implicit preconditioner "
-               "(field frozen, no electrostatic coupling) leaves GMRES stalled; measured BTE_ENOCONV after 5 Newton "
-               "steps and 1214 GMRES iterations, residual 0.057 of 0.148, in FP64 and mixed alike"))])
-def test_implicit_step_matches_oracle(torch, kind, prec, dt_mult):
-    """Fully implicit step (Newton-Krylov preconditioned by the semi-implicit step)
-    against the oracle's Newton iteration with a dense Jacobian: specified and
-    Poisson fields, FP64 and mixed preconditioners, and (specified field) a step
-    ten times the semi-implicit one."""
+@pytest.mark.parametrize("kind,prec,dt_mult,precond", [
+    ("const", "fp64", 1.0, 0), ("rf", "mixed_fp32", 1.0, 0), ("poisson", "fp64", 1.0, 0),
+    ("poisson", "mixed_fp32", 1.0, 0), ("rf", "mixed_fp32", 10.0, 0), ("poisson", "mixed_fp32", 10.0, 0),
+    ("rf", "mixed_fp32", 1.0, 1), ("poisson", "fp64", 1.0, 1), ("rf", "mixed_fp32", 10.0, 1)])
+def test_implicit_step_matches_oracle(torch, kind, prec, dt_mult, precond):
+    """Fully implicit step (Newton-Krylov, preconditioned by the V-then-x split
+    (precond 0) or by the semi-implicit step (precond 1)) against the oracle's
+    Newton iteration with a dense Jacobian: specified and Poisson fields, FP64
+    and mixed preconditioners, and steps ten times the semi-implicit one (with
+    the Poisson field, Newton from F^n with a monotone line search stalls there:
+    the full first step overshoots ||R|| a hundredfold; the frozen-field first
+    step does not)."""
     from oracle import implicit as I
     cfg = workloads.small_config(nx=9, nr=10, nth=6, kinds=("elastic", "excitation", "ionization"), E=5e3,
                                  field_kind="rf" if kind == "rf" else "const", n_bins=2)
@@ -455,11 +455,52 @@ def test_implicit_step_matches_oracle(torch, kind, prec, dt_mult):
     s = solver(cfg, precision=prec)
     F = cuda(torch, F0)
     st = s.implicit_step(F, t, ni=cuda(torch, ni) if ni is not None else None, newton_rtol=1e-13,
-                         gmres_rtol=1e-11, restart=40, max_gmres=400)
-    ref, its = I.implicit_step(ops, F0, t, ni)
+                         gmres_rtol=1e-11, restart=40, max_gmres=400, precond=precond)
     assert st["status"] == 0 and st["residual"] <= 1e-13 * np.linalg.norm(F0) * 1.0001, st
     assert s.status()[0] == 0
-    close(F.cpu().numpy(), ref, 1e-10, f"implicit {kind} {prec} x{dt_mult}")
+    got = F.cpu().numpy()
+    if kind == "poisson" and dt_mult > 1.0:
+        # the quadratic equations have more than one root at this step: the
+        # oracle's full-step Newton from F^n lands on another one, so the check
+        # is that this result solves the oracle's equations
+        r = I.residual(ops, got, F0, t + ops.dt, ni)
+        assert np.linalg.norm(r) <= 1e-11 * np.linalg.norm(F0), np.linalg.norm(r)
+    else:
+        ref, its = I.implicit_step(ops, F0, t, ni)
+        close(got, ref, 1e-10, f"implicit {kind} {prec} x{dt_mult} precond {precond}")
+    s.close()
+
+
+def test_implicit_split_preconditioner_beats_semi_implicit(torch):
+    """On a grid whose x modes are stiff over the step (Nx = 96), the V-then-x
+    split leaves GMRES far fewer iterations than the semi-implicit step as
+    preconditioner (whose inverse misses J by dt^2 X^2 / 4 on those modes), and
+    both reach the same Newton solution."""
+    cfg = workloads.small_config(nx=96, nr=12, nth=8, kinds=("elastic", "excitation", "ionization"), E=5e3,
+                                 field_kind="rf", n_bins=1)
+    ops = oracle.build_operators(cfg)
+    F0 = S.initial_state(ops, workloads.density_profile(ops.xhat, 1e16), 2.0)
+    t = 0.2 * cfg["T_rf_s"]
+    out, its = [], []
+    for pk in (0, 1):
+        s = solver(cfg, precision="fp64")
+        F = cuda(torch, F0)
+        st = s.implicit_step(F, t, newton_rtol=1e-12, gmres_rtol=1e-8, restart=60, max_gmres=600, precond=pk)
+        assert st["status"] == 0, (pk, st)
+        out.append(F.cpu().numpy())
+        its.append(st["gmres_iters"])
+        s.close()
+    assert its[0] * 3 <= its[1], its
+    close(out[0], out[1], 1e-10, "split vs semi-implicit preconditioner")
+
+
+def test_implicit_rejects_unknown_preconditioner(torch):
+    cfg = workloads.small_config(nx=9, nr=10, nth=6, field_kind="rf")
+    ops = oracle.build_operators(cfg)
+    s = solver(cfg, precision="fp64")
+    F = cuda(torch, S.initial_state(ops, workloads.density_profile(ops.xhat, 1e16), 2.0))
+    with pytest.raises(Exception, match="invalid argument"):
+        s.implicit_step(F, 0.0, precond=2, raise_on_noconv=False)
     s.close()
 
 
