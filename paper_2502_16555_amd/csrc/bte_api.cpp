@@ -45,6 +45,7 @@ struct ImplicitWs {
   double *Pa = nullptr, *Pb = nullptr, *Pc = nullptr;   // padded rows
   double *El = nullptr, *zeros = nullptr;               // [sum Nx]
   double *partial = nullptr, *coef = nullptr;
+  double* hcol = nullptr;       // [m + 1] the Hessenberg column of the current Arnoldi step
   std::vector<double> hpart, hcoef;
   double* Qx = nullptr;         // inverses of the x systems over the full step (layout of DevOps::Qt)
 };
@@ -619,6 +620,7 @@ void implicit_alloc(bte_handle* h, int m) {
     w.V = h->alloc<double>((size_t)(m + 1) * N);
     w.partial = h->alloc<double>((size_t)bte::dot_blocks() * (m + 1));
     w.coef = h->alloc<double>((size_t)m + 1);
+    w.hcol = h->alloc<double>((size_t)m + 1);
     w.hpart.assign((size_t)bte::dot_blocks() * (m + 1), 0.0);
     w.hcoef.assign((size_t)m + 1, 0.0);
   }
@@ -722,7 +724,10 @@ void imp_precond(bte_handle* h, const double* v, double* z, int kind, hipStream_
 }
 
 // Right-preconditioned restarted GMRES for J_F dlt = b (b in iw.Rt); classical
-// Gram-Schmidt twice; returns the iterations.
+// Gram-Schmidt twice; returns the iterations.  An Arnoldi step runs on the device
+// (both Gram-Schmidt passes, the norm and the normalization, with sums in a fixed
+// order) and reads back only its Hessenberg column; the Givens rotations and the
+// small triangular solve run on the host.
 int imp_gmres(bte_handle* h, const double* F, double rtol, int m, int maxit, int pk, bool coupling, hipStream_t s) {
   ImplicitWs& iw = h->iw;
   const size_t N = iw.N;
@@ -732,7 +737,7 @@ int imp_gmres(bte_handle* h, const double* F, double rtol, int m, int maxit, int
   const double beta0 = imp_norm(h, iw.Rt, s);
   if (!(beta0 > 0.0)) return 0;
   int total = 0;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hc(m + 1), h2(m + 1), y(m);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hc(m + 1), y(m);
   while (total < maxit) {
     const double beta = imp_norm(h, V, s);
     if (!(beta > rtol * beta0)) break;
@@ -745,17 +750,17 @@ int imp_gmres(bte_handle* h, const double* F, double rtol, int m, int maxit, int
       double* w = V + (size_t)(j + 1) * N;
       imp_precond(h, vj, iw.z, pk, s);
       imp_jac(h, F, iw.z, w, coupling, s);
-      imp_dots(h, w, V, j + 1, hc.data(), s);
-      for (int i = 0; i <= j; ++i) h2[i] = -hc[i];
-      imp_comb(h, w, 1.0, V, h2.data(), j + 1, s);
-      imp_dots(h, w, V, j + 1, h2.data(), s);
-      for (int i = 0; i <= j; ++i) {
-        hc[i] += h2[i];
-        h2[i] = -h2[i];
+      for (int pass = 0; pass < 2; ++pass) {
+        bte::launch_dots(w, V, j + 1, N, N, iw.partial, s);
+        bte::launch_gs_reduce(iw.partial, j + 1, pass, iw.hcol, iw.coef, s);
+        bte::launch_comb(w, 1.0, V, iw.coef, j + 1, N, N, s);
       }
-      imp_comb(h, w, 1.0, V, h2.data(), j + 1, s);
-      const double hn = imp_norm(h, w, s);
-      if (hn > 0.0) bte::launch_axpby(w, w, 1.0 / hn, 0.0, N, s);
+      bte::launch_dots(w, w, 1, N, N, iw.partial, s);
+      bte::launch_norm_reduce(iw.partial, iw.hcol + j + 1, s);
+      bte::launch_scale_inv(w, iw.hcol + j + 1, N, s);
+      HIP_OK(hipMemcpyAsync(hc.data(), iw.hcol, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      const double hn = hc[j + 1];
       // Givens rotations on column j
       for (int i = 0; i < j; ++i) {
         const double a = cs[i] * hc[i] + sn[i] * hc[i + 1];

@@ -166,6 +166,12 @@ void launch_dots(const double* w, const double* V, int nvec, size_t stride, size
 void launch_comb(double* y, double beta, const double* V, const double* coef, int nvec, size_t stride, size_t N,
                  hipStream_t s);
 void launch_axpby(double* y, const double* x, double a, double b, size_t N, hipStream_t s);
+// One Gram-Schmidt pass from launch_dots' partials (block order): h[v] = t_v, or
+// h[v] += t_v with accumulate, and coef[v] = -t_v, v < nvec.
+void launch_gs_reduce(const double* partial, int nvec, int accumulate, double* h, double* coef, hipStream_t s);
+// *h = ||w|| from launch_dots(w, w, 1, ...) partials; y /= *h where *h > 0.
+void launch_norm_reduce(const double* partial, double* h, hipStream_t s);
+void launch_scale_inv(double* y, const double* h, size_t N, hipStream_t s);
 // Operator action on padded rows with a given field: mode 2: R = (I - dt (n0 C + E A)) X;
 // mode 3: R = B - dt E (X A^T).
 void launch_apply_field(const DevOps& d, int mode, const double* B, const double* X, double* R, const double* E,

@@ -80,6 +80,40 @@ __global__ __launch_bounds__(kThreads) void k_comb(double* __restrict__ y, doubl
   }
 }
 
+// The Gram-Schmidt coefficients of one pass from k_dots' partial sums, summed
+// over the blocks in block order (the same order on every call): h[v] = t_v
+// (first pass) or h[v] + t_v (second pass), coef[v] = -t_v for k_comb.
+__global__ __launch_bounds__(kThreads) void k_gs_reduce(const double* __restrict__ partial, int nvec, int nb,
+                                                        int accumulate, double* __restrict__ h,
+                                                        double* __restrict__ coef) {
+  for (int v = threadIdx.x; v < nvec; v += blockDim.x) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += partial[(size_t)b * nvec + v];
+    h[v] = accumulate ? h[v] + t : t;
+    coef[v] = -t;
+  }
+}
+
+// *h = sqrt of k_dots' single partial sums (w . w), summed in block order
+__global__ __launch_bounds__(64) void k_norm_reduce(const double* __restrict__ partial, int nb,
+                                                    double* __restrict__ h) {
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += partial[b];
+    *h = sqrt(t);
+  }
+}
+
+// y = y / *h where *h > 0 (else y is left as it is)
+__global__ __launch_bounds__(kThreads) void k_scale_inv(double* __restrict__ y, const double* __restrict__ h,
+                                                        size_t N) {
+  const double hv = *h;
+  if (!(hv > 0.0)) return;
+  const double a = 1.0 / hv;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = a * y[i];
+}
+
 // y = a y + b x
 __global__ __launch_bounds__(kThreads) void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a,
                                                     double b, size_t N) {
@@ -109,6 +143,18 @@ void launch_dots(const double* w, const double* V, int nvec, size_t stride, size
 void launch_comb(double* y, double beta, const double* V, const double* coef, int nvec, size_t stride, size_t N,
                  hipStream_t s) {
   k_comb<<<1024, kThreads, 0, s>>>(y, beta, V, coef, nvec, stride, N);
+}
+
+void launch_gs_reduce(const double* partial, int nvec, int accumulate, double* h, double* coef, hipStream_t s) {
+  k_gs_reduce<<<1, kThreads, 0, s>>>(partial, nvec, kDotBlocks, accumulate, h, coef);
+}
+
+void launch_norm_reduce(const double* partial, double* h, hipStream_t s) {
+  k_norm_reduce<<<1, 64, 0, s>>>(partial, kDotBlocks, h);
+}
+
+void launch_scale_inv(double* y, const double* h, size_t N, hipStream_t s) {
+  k_scale_inv<<<1024, kThreads, 0, s>>>(y, h, N);
 }
 
 void launch_axpby(double* y, const double* x, double a, double b, size_t N, hipStream_t s) {
