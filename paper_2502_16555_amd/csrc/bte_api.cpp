@@ -585,7 +585,7 @@ void eval_field(bte_handle* h, const double* Fh, double t_s, const bte_field& f,
 
 
 // ---- fully implicit step (eq. bte_fully_implicit) ------------------------------
-void implicit_alloc(bte_handle* h, int m) {
+void implicit_alloc(bte_handle* h, int m, int precond) {
   ImplicitWs& w = h->iw;
   const DevOps& d = h->d;
   const size_t N = (size_t)d.nx_total * d.n, P = (size_t)d.nx_total * d.npad;
@@ -607,7 +607,10 @@ void implicit_alloc(bte_handle* h, int m) {
     w.El = h->alloc<double>(d.nx_total);
     w.zeros = h->alloc<double>(d.nx_total);
     HIP_OK(hipMemset(w.zeros, 0, d.nx_total * sizeof(double)));
-    // the backward-Euler x solve over dt of the split preconditioner
+  }
+  if (precond == BTE_PRECOND_SPLIT && !w.Qx) {
+    // the backward-Euler x solve over dt of the split preconditioner, per
+    // discharge in the layout (and at the offsets) of the half-step inverses
     std::vector<double> Q, Qd;
     for (const auto& X : h->host.xops) {
       bte::advection_inverses(h->host, X, d.dt, &Qd);
@@ -1043,7 +1046,7 @@ bte_status bte_implicit_step(bte_handle* h, double* F, const double* ni, double 
     HIP_OK(hipSetDevice(h->device));
     hipStream_t s = S(stream);
     h->last_stream = s;
-    implicit_alloc(h, m);
+    implicit_alloc(h, m, pk);
     ImplicitWs& iw = h->iw;
     const size_t N = iw.N;
     const double t1 = t_s + h->cfg.dt_s;

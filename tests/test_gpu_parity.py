@@ -494,6 +494,30 @@ def test_implicit_split_preconditioner_beats_semi_implicit(torch):
     close(out[0], out[1], 1e-10, "split vs semi-implicit preconditioner")
 
 
+@pytest.mark.parametrize("precond", [0, 1])
+def test_implicit_ensemble_matches_oracle_per_discharge(torch, precond):
+    """The fully implicit step over an uneven ensemble (Nx = 5, 9, 7; different
+    pressures and amplitudes) in one Krylov space: each discharge's part
+    against the oracle's Newton iteration for that discharge alone."""
+    from oracle import implicit as I
+    cfg, members = _ensemble_case()
+    ops = [oracle.build_operators(m) for m in members]
+    F0 = [S.initial_state(o, workloads.density_profile(o.xhat, 1e16), 1.0) for o in ops]
+    t = 0.3 * cfg["T_rf_s"]
+    s = solver(cfg, precision="mixed_fp32")
+    F = cuda(torch, np.concatenate(F0))
+    st = s.implicit_step(F, t, newton_rtol=1e-13, gmres_rtol=1e-11, restart=40, max_gmres=400, precond=precond)
+    assert st["status"] == 0, st
+    assert s.status()[0] == 0
+    got = F.cpu().numpy()
+    o = 0
+    for d, (op, f0) in enumerate(zip(ops, F0)):
+        ref, _ = I.implicit_step(op, f0, t)
+        close(got[o:o + f0.shape[0]], ref, 1e-10, f"discharge {d} precond {precond}")
+        o += f0.shape[0]
+    s.close()
+
+
 def test_implicit_rejects_unknown_preconditioner(torch):
     cfg = workloads.small_config(nx=9, nr=10, nth=6, field_kind="rf")
     ops = oracle.build_operators(cfg)
