@@ -400,6 +400,45 @@ def paper_grid(torch, steps):
         r = run_gpu(cfg, prec, steps, 3, torch, vsolver=vs)
         out["solvers"][name] = {"ms_per_step": r["ms_per_step"], "steps_per_s": 1000.0 / r["ms_per_step"],
                                 "setup_s": r["setup_s"]}
+    out["implicit"] = paper_grid_implicit(cfg, torch, out["solvers"]["lu_mixed_fp32"]["ms_per_step"])
+    return out
+
+
+def paper_grid_implicit(cfg, torch, semi_ms, mult=4, n_steps=5):
+    """The paper's comparison on its timed grid: the fully implicit step at
+    mult = 4 times the semi-implicit dt (dt f = 2e-4 against 5e-5 in the table of
+    the hybrid solver's performance), mixed-precision preconditioner, n_steps
+    consecutive steps from the initial state, with each preconditioner.  The
+    overall speedup is the semi-implicit time for the same simulated time over
+    the fully implicit one (the table's last column)."""
+    import copy
+    import workloads
+    from paper_2502_16555_amd import Solver
+    opts = dict(newton_rtol=1e-8, gmres_rtol=1e-4, restart=60, max_gmres=1500, max_newton=8)
+    c = copy.deepcopy(cfg)
+    c["dt_s"] = cfg["dt_s"] * mult
+    out = {"dt_over_T_rf": c["dt_s"] / c["T_rf_s"], "steps": n_steps, "options": opts,
+           "semi_implicit_ms_per_step": semi_ms, "runs": []}
+    for pk, name in ((0, "V solve then x solve over dt"), (1, "semi-implicit step X(dt/2) V(dt) X(dt/2)")):
+        s = Solver(c, precision="mixed_fp32")
+        ne = workloads.density_profile(s.xhat(), c["ic"]["ne_peak"])
+        F = s.initial_state(torch.as_tensor(ne, device="cuda:0"), c["ic"]["Te_eV"])
+        s.implicit_step(F.clone(), 0.0, max_newton=1, max_gmres=2, precond=pk, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        newton = gmres = 0
+        ok = True
+        t0 = time.perf_counter()
+        for k in range(n_steps):
+            st = s.implicit_step(F, k * c["dt_s"], raise_on_noconv=False, precond=pk, **opts)
+            newton += st["newton_iters"]
+            gmres += st["gmres_iters"]
+            ok = ok and st["status"] == 0
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / n_steps
+        out["runs"].append({"preconditioner": name, "ms_per_step": ms, "newton_per_step": newton / n_steps,
+                            "gmres_per_step": gmres / n_steps, "converged": ok,
+                            "speedup_over_semi_implicit": mult * semi_ms / ms})
+        s.close()
     return out
 
 

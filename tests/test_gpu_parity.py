@@ -518,6 +518,27 @@ def test_implicit_ensemble_matches_oracle_per_discharge(torch, precond):
     s.close()
 
 
+@pytest.mark.parametrize("precond", [0, 1])
+def test_implicit_step_with_reduced_harmonics(torch, precond):
+    """The fully implicit step with Nl = 3 < Ntheta = 16 (the operator part of the
+    V systems has rank Nr Nl; the rest of the state moves by advection only)
+    against the oracle's Newton iteration, at four times the semi-implicit dt."""
+    from oracle import implicit as I
+    cfg = BANDED_CASES["reduced_nl"]()
+    cfg["dt_s"] *= 4
+    ops = oracle.build_operators(cfg)
+    F0 = S.initial_state(ops, workloads.density_profile(ops.xhat, 1e16), 2.0)
+    t = 0.15 * cfg["T_rf_s"]
+    s = solver(cfg, precision="mixed_fp32")
+    F = cuda(torch, F0)
+    st = s.implicit_step(F, t, newton_rtol=1e-13, gmres_rtol=1e-11, restart=40, max_gmres=400, precond=precond)
+    assert st["status"] == 0, st
+    assert s.status()[0] == 0
+    ref, _ = I.implicit_step(ops, F0, t)
+    close(F.cpu().numpy(), ref, 1e-10, f"reduced harmonics precond {precond}")
+    s.close()
+
+
 def test_implicit_rejects_unknown_preconditioner(torch):
     cfg = workloads.small_config(nx=9, nr=10, nth=6, field_kind="rf")
     ops = oracle.build_operators(cfg)
