@@ -339,19 +339,21 @@ void fill_devops(bte_handle* h) {
   }
   const size_t nxt = d.nx_total;
   {
-    // D_x per discharge (the forward spatial operator of the fully implicit step)
-    std::vector<double> Dx;
-    Dx.reserve(ptot);
-    for (auto& X : H.xops) Dx.insert(Dx.end(), X.Dx.begin(), X.Dx.end());
-    d.dx = h->upload(Dx);
+    // D_x per discharge, column-major (entry (r, c) at c nx + r): the forward
+    // spatial operator of the fully implicit step and the heavies' update
+    std::vector<double> DT;
+    DT.reserve(ptot);
+    for (auto& X : H.xops)
+      for (int cc = 0; cc < X.nx; ++cc)
+        for (int r = 0; r < X.nx; ++r) DT.push_back(X.Dx[(size_t)r * X.nx + cc]);
+    d.dxT = h->upload(DT);
     d.lam = h->upload(H.lam);
     d.mu_th = h->upload(H.mu);
   }
   if (c.field_mode == BTE_FIELD_POISSON) {
-    // the heavies' update of the hybrid step: D_x and D_x^2 per discharge,
-    // column-major (entry (r, c) at c nx + r)
-    std::vector<double> DT, D2;
-    DT.reserve(ptot);
+    // the heavies' update of the hybrid step: D_x (d.dxT above) and D_x^2 per
+    // discharge, column-major (entry (r, c) at c nx + r)
+    std::vector<double> D2;
     D2.reserve(ptot);
     for (auto& X : H.xops) {
       const int nx = X.nx;
@@ -360,10 +362,8 @@ void fill_devops(bte_handle* h) {
           double acc = 0.0;
           for (int k = 0; k < nx; ++k) acc += X.Dx[(size_t)r * nx + k] * X.Dx[(size_t)k * nx + cc];
           D2.push_back(acc);
-          DT.push_back(X.Dx[(size_t)r * nx + cc]);
         }
     }
-    d.dxT = h->upload(DT);
     d.dx2 = h->upload(D2);
     d.ion_M = h->alloc<double>(ptot);
     d.ion_b = h->alloc<double>(nxt);

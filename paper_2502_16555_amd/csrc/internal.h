@@ -88,8 +88,8 @@ struct DevOps {
   double* resid = nullptr;     // [1] final max_x |r|/|b|
   double* scratch3 = nullptr;  // [3*nx_total] moments scratch
   // heavies' update of the hybrid model (Poisson field mode only)
-  double* dx = nullptr;        // concatenated [nx_d][nx_d] CGL derivative (physical), offsets p_off (all modes)
-  double* dxT = nullptr;       // concatenated D_x, column-major (the ion systems)
+  double* dxT = nullptr;       // concatenated [nx_d][nx_d] CGL derivative (physical), column-major, offsets p_off
+                               // (the implicit step's forward operator, the ion systems)
   double* dx2 = nullptr;       // concatenated D_x D_x, column-major
   double* ion_M = nullptr;     // concatenated [nx_d][nx_d] ion systems (column-major)
   double* ion_b = nullptr;     // [nx_total] right-hand sides

@@ -13,23 +13,40 @@ constexpr int kDotBlocks = 256;
 
 // Y_ia <- lambda_i cos(theta_a) D_x Y_ia for every mode of every discharge
 // (mode-major Y of the X step: the modes of discharge d at Y + x_off[d] n, one
-// row of nx_d per mode); A_x = U Lambda U^-1 (x) diag(cos theta).
-__global__ __launch_bounds__(kThreads) void k_x_fwd(double* __restrict__ Y, const double* __restrict__ Dx,
+// row of nx_d per mode); A_x = U Lambda U^-1 (x) diag(cos theta).  D_x is read
+// column-major (entry (x, k) at k nx + x), so that a load over the threads' x is
+// one coalesced row of D_x^T, and each loaded entry serves the MB modes of the
+// block; every output takes its products in ascending k.
+template <int MB>
+__global__ __launch_bounds__(kThreads) void k_x_fwd(double* __restrict__ Y, const double* __restrict__ DT,
                                                     const size_t* __restrict__ dx_off, const double* __restrict__ lam,
                                                     const double* __restrict__ mu, const int* __restrict__ x_off,
                                                     const int* __restrict__ nx_of, int nth, int n) {
-  extern __shared__ double sy[];
-  const int o = blockIdx.x, d = blockIdx.y;
-  const int i = o / nth, a = o % nth, nx = nx_of[d];
-  double* y = Y + (size_t)x_off[d] * n + (size_t)o * nx;
-  for (int j = threadIdx.x; j < nx; j += blockDim.x) sy[j] = y[j];
+  extern __shared__ double sy[];   // [MB][nx]
+  const int o0 = blockIdx.x * MB, d = blockIdx.y;
+  const int nx = nx_of[d], nm = min(MB, n - o0);
+  double* y0 = Y + (size_t)x_off[d] * n;
+  for (int m = 0; m < MB; ++m)
+    for (int j = threadIdx.x; j < nx; j += blockDim.x) sy[m * nx + j] = m < nm ? y0[(size_t)(o0 + m) * nx + j] : 0.0;
   __syncthreads();
-  const double c = lam[i] * mu[a];
-  const double* D = Dx + dx_off[d];
+  const double* D = DT + dx_off[d];
   for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < nx; ++k) s += D[(size_t)x * nx + k] * sy[k];
-    y[x] = c * s;
+    double acc[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) acc[m] = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < nx; ++k) {
+      const double dk = D[(size_t)k * nx + x];
+#pragma unroll
+      for (int m = 0; m < MB; ++m) acc[m] += dk * sy[m * nx + k];
+    }
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      if (m < nm) {
+        const int o = o0 + m;
+        y0[(size_t)o * nx + x] = lam[o / nth] * mu[o % nth] * acc[m];
+      }
+    }
   }
 }
 
@@ -124,9 +141,17 @@ __global__ __launch_bounds__(kThreads) void k_axpby(double* __restrict__ y, cons
 }  // namespace
 
 void launch_x_forward(const DevOps& d, hipStream_t s) {
-  dim3 g(d.n, d.nd);
-  k_x_fwd<<<g, kThreads, sizeof(double) * d.max_nx, s>>>(d.Y, d.dx, d.p_off, d.lam, d.mu_th, d.x_off, d.nx_of,
-                                                         d.nth, d.n);
+  // eight modes per block while their rows fit in 64 KB of LDS, else one
+  constexpr int MB = 8;
+  if ((size_t)MB * d.max_nx * sizeof(double) <= 65536) {
+    dim3 g((d.n + MB - 1) / MB, d.nd);
+    k_x_fwd<MB><<<g, kThreads, sizeof(double) * MB * d.max_nx, s>>>(d.Y, d.dxT, d.p_off, d.lam, d.mu_th, d.x_off,
+                                                                     d.nx_of, d.nth, d.n);
+  } else {
+    dim3 g(d.n, d.nd);
+    k_x_fwd<1><<<g, kThreads, sizeof(double) * d.max_nx, s>>>(d.Y, d.dxT, d.p_off, d.lam, d.mu_th, d.x_off, d.nx_of,
+                                                              d.nth, d.n);
+  }
 }
 
 void launch_wall_rows(const DevOps& d, double* out, const double* X, hipStream_t s) {
