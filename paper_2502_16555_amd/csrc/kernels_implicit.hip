@@ -3,6 +3,8 @@
 // A_x F D_x^T in the speed eigenbasis, the wall rows of the implicit system,
 // and the vector kernels of the Newton-Krylov driver (batched dot products with
 // deterministic two-stage sums, linear combinations).
+#include <stdexcept>
+
 #include "internal.h"
 
 namespace bte {
@@ -141,17 +143,12 @@ __global__ __launch_bounds__(kThreads) void k_axpby(double* __restrict__ y, cons
 }  // namespace
 
 void launch_x_forward(const DevOps& d, hipStream_t s) {
-  // eight modes per block while their rows fit in 64 KB of LDS, else one
+  // eight modes per block: their rows take at most 64 KB of LDS (Nx <= 1024)
   constexpr int MB = 8;
-  if ((size_t)MB * d.max_nx * sizeof(double) <= 65536) {
-    dim3 g((d.n + MB - 1) / MB, d.nd);
-    k_x_fwd<MB><<<g, kThreads, sizeof(double) * MB * d.max_nx, s>>>(d.Y, d.dxT, d.p_off, d.lam, d.mu_th, d.x_off,
-                                                                     d.nx_of, d.nth, d.n);
-  } else {
-    dim3 g(d.n, d.nd);
-    k_x_fwd<1><<<g, kThreads, sizeof(double) * d.max_nx, s>>>(d.Y, d.dxT, d.p_off, d.lam, d.mu_th, d.x_off, d.nx_of,
-                                                              d.nth, d.n);
-  }
+  if ((size_t)MB * d.max_nx * sizeof(double) > 65536) throw std::invalid_argument("Nx above 1024");
+  dim3 g((d.n + MB - 1) / MB, d.nd);
+  k_x_fwd<MB><<<g, kThreads, sizeof(double) * MB * d.max_nx, s>>>(d.Y, d.dxT, d.p_off, d.lam, d.mu_th, d.x_off,
+                                                                   d.nx_of, d.nth, d.n);
 }
 
 void launch_wall_rows(const DevOps& d, double* out, const double* X, hipStream_t s) {

@@ -539,6 +539,24 @@ def test_implicit_step_with_reduced_harmonics(torch, precond):
     s.close()
 
 
+def test_implicit_step_at_largest_nx_solves_oracle_equations(torch):
+    """Nx = 1024, the largest the library takes (the forward x operator's eight
+    mode rows then fill exactly 64 KB of LDS), with a tiny velocity grid: the
+    oracle's residual of eq. bte_fully_implicit at the result is within the
+    Newton tolerance (a dense oracle Newton solve is out of reach at this size)."""
+    from oracle import implicit as I
+    cfg = workloads.small_config(nx=1024, nr=4, nth=2, kinds=("elastic",), E=2e3, field_kind="const", n_bins=1)
+    ops = oracle.build_operators(cfg)
+    F0 = S.initial_state(ops, workloads.density_profile(ops.xhat, 1e16), 2.0)
+    s = solver(cfg, precision="fp64")
+    F = cuda(torch, F0)
+    st = s.implicit_step(F, 0.0, newton_rtol=1e-12, gmres_rtol=1e-10, restart=60, max_gmres=600)
+    assert st["status"] == 0, st
+    r = I.residual(ops, F.cpu().numpy(), F0, ops.dt)
+    assert np.linalg.norm(r) <= 1e-11 * np.linalg.norm(F0), (np.linalg.norm(r), st)
+    s.close()
+
+
 def test_implicit_rejects_unknown_preconditioner(torch):
     cfg = workloads.small_config(nx=9, nr=10, nth=6, field_kind="rf")
     ops = oracle.build_operators(cfg)
