@@ -48,36 +48,57 @@ def _update_traffic():
     return KUPDATE_TRAFFIC["fetch_bytes"] + KUPDATE_TRAFFIC["write_bytes"]
 
 
-def _update_launches(npad: int, nb: int, pairs: bool = True):
+def _update_launches(npad: int, nb: int, group: int = 2):
     """(flops, elements moved) of each trailing-update launch of one
-    factorization.  With the panels in pairs (dense factors), the first panel
-    of a pair updates only the next panel's columns (that column block read and
-    written, L21 and U12 read) and the second applies both panels to the
-    columns beyond (K = 2 nb, A22 read and written once); the last panels go
-    singly (K = nb).  The first panel's update of the second's row block is
-    part of the second's U12 kernel, not of these launches."""
+    factorization, with the panels taken singly (group 1), in pairs (2) or in
+    groups of four (4, statically pivoted dense factors).  In a group, a panel
+    other than the last updates only the next panel's columns with the group's
+    panels so far (K = 128 j: that column block read and written, the L rows and
+    U columns read), and the last applies the whole group to the columns beyond
+    (K = group nb, A22 read and written once); the panels after the last full
+    group go singly (K = nb; pairs: the last two).  The group's earlier panels'
+    updates of a panel's row block are part of its U12 pre-update, not of these
+    launches."""
     npan = npad // nb
     out = []
     for p in range(npan):
         m = npad - p * nb - nb
-        if pairs and p % 2 == 0 and p + 2 < npan:
-            out.append((2.0 * m * nb * nb, 3 * m * nb + nb * nb))
-        elif pairs and p % 2 == 1 and p + 1 < npan:
-            out.append((4.0 * m * m * nb, 2 * m * m + 4 * m * nb))
+        if group == 4:
+            g0 = p // 4 * 4
+            j = p - g0 if g0 + 4 <= npan else -1
+        elif group == 2:
+            j = p % 2 if (p % 2 == 0 and p + 2 < npan) or (p % 2 == 1 and p + 1 < npan) else -1
+        else:
+            j = -1
+        if j >= 0 and j < group - 1:
+            k = (j + 1) * nb
+            if m > 0:
+                out.append((2.0 * m * nb * k, 2 * m * nb + m * k + k * nb))
+        elif j == group - 1:
+            k = group * nb
+            if m > 0:
+                out.append((2.0 * m * m * k, 2 * m * m + 2 * m * k))
         elif m > 0:
             out.append((2.0 * m * m * nb, 2 * m * m + 2 * m * nb))
     return out
 
 
-def _update_bytes(npad: int, nb: int, nmat: int, elt: int, pairs: bool = True) -> float:
+def _update_bytes(npad: int, nb: int, nmat: int, elt: int, group: int = 2) -> float:
     """Algorithmic bytes of one average update launch (see _update_launches)."""
-    ls = _update_launches(npad, nb, pairs)
+    ls = _update_launches(npad, nb, group)
     return sum(b for _, b in ls) * elt * nmat / len(ls)
 
 
-def _update_flops(npad: int, nb: int, nmat: int, pairs: bool = True) -> float:
+def _update_flops(npad: int, nb: int, nmat: int, group: int = 2) -> float:
     """Algorithmic flops of all trailing-update launches of one factorization."""
-    return sum(f for f, _ in _update_launches(npad, nb, pairs)) * nmat
+    return sum(f for f, _ in _update_launches(npad, nb, group)) * nmat
+
+
+def _panel_group(run) -> int:
+    """Panels per deferred-update group of a timed run: groups of four need
+    statically pivoted factors (otherwise the setting 2 takes pairs)."""
+    pp = run["panel_pairs"]
+    return 4 if pp == 2 and run["static_pivoting"] else (2 if pp else 1)
 
 
 KRYLOV = dict(n_bins=128, bin_scale=100.0, restart=12, cycles=3, rtol=1e-12, factor_precision="mixed_fp32")
@@ -527,8 +548,8 @@ def main():
     dtype = {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64", "mixed_bf16x3": "bf16x3+f32+f64"}[args.precision]
     mfma = {"fp64": "fp64", "mixed_fp32": "fp32", "mixed_bf16": "bf16", "mixed_bf16x3": "bf16"}[args.precision]
     # update flops of one step over the summed durations of its update launches
-    pairs = bool(main_run["panel_pairs"])
-    upd_flops = _update_flops(npad, 128, nx_total, pairs)
+    group = _panel_group(main_run)
+    upd_flops = _update_flops(npad, 128, nx_total, group)
     n_upd_launches = main_run["update_launches"]
     achieved = upd_flops / (main_run["ms_update"] * 1e-3) / 1e12
     peak = MI355X_PEAK_TFLOPS[mfma]
@@ -546,8 +567,8 @@ def main():
                      "traffic": _update_traffic() if args.precision == "mixed_fp32" and npad == 2048 and nx_total == 256
                      else None,
                      "algorithmic_bytes_per_launch": _update_bytes(npad, 128, nx_total,
-                                                                   8 if args.precision == "fp64" else 4, pairs),
-                     "panel_pairs": pairs,
+                                                                   8 if args.precision == "fp64" else 4, group),
+                     "panels_per_update_group": group,
                      "launches_per_step": n_upd_launches,
                      "avg_launch_ms": main_run["ms_update"] / n_upd_launches},
         "v_solve_roofline": {"bound": "mfma", "what": "whole velocity-space solve: formation, factorization, "
@@ -571,9 +592,9 @@ def main():
                         "ms_update": fp64["ms_update"], "ms_panel": fp64["ms_panel"], "ms_vwall": fp64["ms_vwall"],
                         "v_solve_frac_fp64_peak": info.lu_flops_per_step / (fp64["ms_vwall"] * 1e-3) / 1e12
                         / MI355X_PEAK_TFLOPS["fp64"],
-                        "update_tflops": _update_flops(npad, 128, nx_total, bool(fp64["panel_pairs"]))
+                        "update_tflops": _update_flops(npad, 128, nx_total, _panel_group(fp64))
                         / (fp64["ms_update"] * 1e-3) / 1e12,
-                        "update_frac_fp64_peak": _update_flops(npad, 128, nx_total, bool(fp64["panel_pairs"]))
+                        "update_frac_fp64_peak": _update_flops(npad, 128, nx_total, _panel_group(fp64))
                         / (fp64["ms_update"] * 1e-3)
                         / 1e12 / MI355X_PEAK_TFLOPS["fp64"]}
         line["accuracy"] = {
@@ -609,7 +630,7 @@ def main():
         nup = bf["update_launches"]
         line["bf16x3"] = {"steps_per_s": 1000.0 / bf["ms_per_step"], "ms_per_step": bf["ms_per_step"],
                           "ms_update": bf["ms_update"], "ms_panel": bf["ms_panel"], "ms_vwall": bf["ms_vwall"],
-                          "update_hbm_frac": (_update_bytes(npad, 128, nx_total, 4, bool(bf["panel_pairs"]))
+                          "update_hbm_frac": (_update_bytes(npad, 128, nx_total, 4, _panel_group(bf))
                                               / (bf["ms_update"] / nup * 1e-3))
                           / (MI355X_PEAK_HBM_GBS * 1e9),
                           "refine": {"sweeps": bf["refine_sweeps"], "resid": bf["refine_resid"]}}
@@ -623,7 +644,7 @@ def main():
         nup = bfp["update_launches"]
         line["bf16"] = {"steps_per_s": 1000.0 / bfp["ms_per_step"], "ms_per_step": bfp["ms_per_step"],
                         "ms_update": bfp["ms_update"], "ms_panel": bfp["ms_panel"], "ms_vwall": bfp["ms_vwall"],
-                        "update_hbm_frac": (_update_bytes(npad, 128, nx_total, 4, bool(bfp["panel_pairs"]))
+                        "update_hbm_frac": (_update_bytes(npad, 128, nx_total, 4, _panel_group(bfp))
                                             / (bfp["ms_update"] / nup * 1e-3)) / (MI355X_PEAK_HBM_GBS * 1e9),
                         "refine": {"sweeps": bfp["refine_sweeps"], "resid": bfp["refine_resid"]}}
         if fp64 is not None:

@@ -407,12 +407,18 @@ bte_status bte_get_timing(bte_handle* h, double* ms_out);
  *     BF16 updates have a fixed chunk of 32 (reported as such).
  *   BTE_TUNE_FORM_XPB: matrices formed per block of the formation kernel,
  *     1..64; 0 = default (8 for FP32 factors, 16 for FP64).
- *   BTE_TUNE_PANEL_PAIRS: 1 (default) or 0.  Dense factors take the panels in
- *     pairs: a panel's update of the columns beyond the next panel is deferred
- *     and applied together with the next panel's in one update of depth 256,
- *     which reads and writes the trailing matrix half as often.  The factors
- *     then store each pair's second interchanges in the first panel's L rows
- *     as well (the solves follow).  Unlike the other keys this one changes the
+ *   BTE_TUNE_PANEL_PAIRS: 2 (default), 1 or 0.  1: dense factors take the
+ *     panels in pairs: a panel's update of the columns beyond the next panel is
+ *     deferred and applied together with the next panel's in one update of
+ *     depth 256, which reads and writes the trailing matrix half as often.  The
+ *     factors then store each pair's second interchanges in the first panel's L
+ *     rows as well (the solves follow).  2: statically pivoted dense factors
+ *     take groups of four panels (the next panel's columns and top rows get the
+ *     group's earlier panels' updates at depth 128 j, the columns beyond the
+ *     group one update of depth 512; a last group that does not fit goes
+ *     singly); other factors take pairs.  Measured at Nx = 256, n = 2048:
+ *     18.2 ms per FP32 step against 18.55 with pairs (BF16x3 14.95 against
+ *     15.1).  0: single panels.  Unlike the other keys this one changes the
  *     rounding of the trailing updates (not the pivots of a well-separated
  *     column); it only takes effect at the next factorization.
  *   BTE_TUNE_STATIC_PIVOTING: 0 or 1 (default 1 for the mixed precisions, 0 for

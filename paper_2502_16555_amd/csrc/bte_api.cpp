@@ -1549,7 +1549,7 @@ bte_status bte_set_tuning(bte_handle* h, int32_t key, int32_t value) {
       h->d.form_xpb = value;
       return BTE_OK;
     case BTE_TUNE_PANEL_PAIRS:
-      if (value != 0 && value != 1) return BTE_EINVAL;
+      if (value < 0 || value > 2) return BTE_EINVAL;
       h->d.lu_pairs = value;
       return BTE_OK;
     case BTE_TUNE_STATIC_PIVOTING:

@@ -65,7 +65,8 @@ struct DevOps {
   double* Y = nullptr;         // [nx_total*n] mode-major scratch of the X step
   void* lu = nullptr;          // [nx_total][npad][npad] of T (double or float), column-major
   void* xscr = nullptr;        // [nx_total][npad][kNB] of T: interchange staging of extra rows
-  int lu_pairs = 1;             // dense factors: panels in pairs (K = 256 trailing updates)
+  int lu_pairs = 2;             // dense factors: 1 panels in pairs (K = 256 trailing updates), 2 statically
+                                // pivoted factors in groups of four (K = 512; pairs otherwise), 0 single panels
   void* linv = nullptr;        // [nx_total][kLinvElems] of T: inverses of L11's diagonal blocks, of L11, of U11
   int* piv = nullptr;          // [nx_total][npad]
   int* perm = nullptr;         // [nx_total][kMaxPanels][kPermStride] row permutation of every panel

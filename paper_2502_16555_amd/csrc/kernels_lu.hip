@@ -1250,7 +1250,8 @@ __global__ __launch_bounds__(256, 2) void k_u12(T* __restrict__ LU, const T* __r
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_u12pre(T* __restrict__ LU, const int* __restrict__ perm,
-                                                T* __restrict__ xscr, int npad, int k1, int nct, int nmat) {
+                                                T* __restrict__ xscr, int npad, int k1, int nct, int nmat,
+                                                int ident, int kj) {
   using V = typename Vec4<T>::type;
   constexpr int PER = Vec4<T>::per;
   // FP32 operand layout as in k_u12 (the U_p stores are W's pattern)
@@ -1261,7 +1262,9 @@ __global__ __launch_bounds__(256, 2) void k_u12pre(T* __restrict__ LU, const int
   xcd_map(blockIdx.x, nct, nmat, &mat, &ct);
   if (mat >= nmat) return;
   T* A = LU + (size_t)mat * npad * npad;
-  const int kp = k1 - NB;
+  // the deferred updates of the kj panels before this one (a pair's first
+  // panel: kj = 1; in groups of four, up to 3): K = 128 kj from column kp
+  const int kp = k1 - kj * NB;
   const int c0 = k1 + NB + ct * 128;
   const int* src = perm + ((size_t)mat * kMaxPanels + k1 / NB) * kPermStride + 1 + kMaxSwapRows;
   __shared__ __align__(16) T smem[4 * KC * LD];   // the operand chunks, then the passes of W
@@ -1271,7 +1274,10 @@ __global__ __launch_bounds__(256, 2) void k_u12pre(T* __restrict__ LU, const int
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
-  if (tid < NB) s_src[tid] = src[tid];
+  // ident: statically pivoted factors, whose top rows are the panel's own (the
+  // identity that the diagonal kernel records too), so that this kernel need
+  // not wait for it
+  if (tid < NB) s_src[tid] = ident ? k1 + tid : src[tid];
   __syncthreads();
   constexpr int NAS = KC * 128 / 256;         // gathered L_p elements per thread and chunk
   constexpr int NBV = KC * 128 / PER / 256;   // U_p vectors per thread and chunk
@@ -1313,7 +1319,7 @@ __global__ __launch_bounds__(256, 2) void k_u12pre(T* __restrict__ LU, const int
   load(0);
   store(0);
   __syncthreads();
-  constexpr int NCH = NB / KC;
+  const int NCH = kj * (NB / KC);
   for (int ch = 0; ch < NCH; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < NCH) load((ch + 1) * KC);
@@ -1745,7 +1751,11 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   // pair reads only columns and rows below 2 NB until its K = 256 update, so
   // the rest of the matrix is formed on the side stream meanwhile, and that
   // update waits (measured slower at n = 2048: the two share HBM and the CUs)
-  const bool fsplit = stat && pairs && la && la->form_overlap && la->side && np >= 4 && d.band_kl == 0;
+  // statically pivoted dense factors in groups of four panels (lu_pairs 2):
+  // the updates of a group's panels on the columns beyond the group are
+  // deferred to one K = 512 update
+  const bool quads = stat && d.lu_pairs == 2 && d.band_kl == 0 && np >= 4;
+  const bool fsplit = !quads && stat && pairs && la && la->form_overlap && la->side && np >= 4 && d.band_kl == 0;
   if (fsplit) {
     (void)hipEventRecord(la->form_ev[0], s);
     (void)hipStreamWaitEvent(la->side, la->form_ev[0], 0);
@@ -1811,6 +1821,54 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
       if (nt > 0) k_l21_mfma<<<xcd_grid(nt, nmat), 256, 0, st>>>(LU, li, d.npad, k0, nt, nmat);
     }
   };
+  if (quads) {
+    // panel p at position j of its group (g0 = p - j): its columns received the
+    // group's earlier panels' updates (one K = 128 j update after panel p-1),
+    // its top rows beyond it get them in the U12 pre-update (K = 128 j); after
+    // it, either the next panel's columns get the updates of panels g0..p, or,
+    // after the group's last panel, the columns beyond the group get all four
+    // (K = 512).  A group that does not fit at the end takes single panels.
+    for (int p = 0; p < np; ++p) {
+      const int k0 = p * NB;
+      const int g0 = p / 4 * 4;
+      const bool full = g0 + 4 <= np;
+      const int j = full ? p - g0 : 0;
+      const bool rec = tm && p < P;
+      if (rec) mark(1, p, 0, s);
+      static_panel(k0, d.npad, s);
+      const int rest = d.npad - k0 - NB;
+      const int nct = rest / 128;
+      if (rec) {
+        mark(1, p, 1, s);
+        mark(2, p, 0, s);
+        mark(2, p, 1, s);
+        mark(3, p, 0, s);
+      }
+      if (rest > 0) {
+        if (j > 0) {
+          k_u12pre<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, xs, d.npad, k0, nct, nmat, 1, j);
+          k_u12<T, true><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
+        } else {
+          k_u12<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
+        }
+      }
+      if (rec) {
+        mark(3, p, 1, s);
+        mark(0, p, 0, s);
+      }
+      const int mtr = rest / 128;
+      if (mtr > 0) {
+        if (full && j < 3) update(g0 * NB, mtr, 1, (j + 1) * NB);   // the next panel's columns
+        else if (full) update(g0 * NB, mtr, nct, 4 * NB);          // the columns beyond the group
+        else update(k0, mtr, nct, NB);
+      }
+      if (rec) {
+        mark(0, p, 1, s);
+        tm->used = p + 1;
+      }
+    }
+    return;
+  }
   const bool ahead = stat && la && la->look_ahead && la->side && la->ev && np <= kMaxPanels;
   bool done_ahead[kMaxPanels] = {};   // panel already factored on the side stream
   for (int p = 0; p < np; ++p) {
@@ -1841,7 +1899,7 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
       // this panel's U12 from its top rows with panel p-1's deferred update,
       // the interchanges' other rows moved down, panel p-1's L rows permuted
       // (statically pivoted panels interchange no rows: nothing to move)
-      k_u12pre<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, xs, d.npad, k0, nct, nmat);
+      k_u12pre<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, xs, d.npad, k0, nct, nmat, 0, 1);
       if (!stat) k_move_down<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, d.npad, k0, nct, nmat);
       k_u12<T, true><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
       if (!stat) k_perm_lp<T><<<xcd_grid(NB / 16, nmat), 256, 0, s>>>(LU, perm, d.npad, k0, nmat);

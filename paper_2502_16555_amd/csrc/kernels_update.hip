@@ -360,8 +360,12 @@ void launch_update_k(int kind, void* LU, int npad, int k0, int mtr, int mtc, int
 
 void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int tj0, int nmat, bool alt_kc,
                    hipStream_t s, int kd) {
-  if (kd == 2 * NB) launch_update_k<2 * NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s);
-  else launch_update_k<NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s);
+  switch (kd) {
+    case 4 * NB: launch_update_k<4 * NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s); break;
+    case 3 * NB: launch_update_k<3 * NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s); break;
+    case 2 * NB: launch_update_k<2 * NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s); break;
+    default: launch_update_k<NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s); break;
+  }
 }
 
 }  // namespace bte

@@ -905,6 +905,44 @@ def test_factorization_schedule_does_not_change_results(torch, prec):
     close(res[1], res[0], tol, "pairs vs single panels")
 
 
+@pytest.mark.parametrize("case", ["panels4", "panels6"])
+@pytest.mark.parametrize("prec", ["mixed_fp32", "mixed_bf16x3", "mixed_bf16"])
+def test_panel_groups_of_four_match_pairs(torch, prec, case):
+    """Statically pivoted factors in groups of four panels (BTE_TUNE_PANEL_PAIRS
+    = 2: the next panel's columns take the group's earlier panels' updates at
+    depth 128 j, its top rows the same in the U12 pre-update, and the columns
+    beyond the group one depth-512 update) against pairs: the same steps to
+    rounding, with one and two factorization groups; partially pivoted factors
+    take pairs for the value 2 (bit-identical).  Four panels (one group) and six
+    (a group, then two single panels)."""
+    from paper_2502_16555_amd import _lib
+    cfg = CASES["panels4"]() if case == "panels4" else \
+        workloads.small_config(nx=5, nr=24, nth=28, kinds=("elastic", "excitation", "ionization"), E=1.2e4,
+                               field_kind="rf")
+    ops = oracle.build_operators(cfg)
+    F0 = _state(ops, 13)
+    out = {}
+    for pairs, g, stat in ((1, 1, 1), (2, 1, 1), (2, 2, 1), (1, 1, 0), (2, 1, 0)):
+        s = solver(cfg, precision=prec)
+        s.set_tuning(_lib.TUNE_PANEL_PAIRS, pairs)
+        s.set_tuning(_lib.TUNE_LU_STREAMS, g)
+        s.set_tuning(_lib.TUNE_STATIC_PIVOTING, stat)
+        assert s.get_tuning(_lib.TUNE_PANEL_PAIRS) == pairs
+        F = cuda(torch, F0)
+        for n in range(3):
+            s.step(F, n * cfg["dt_s"])
+        assert s.status()[0] == 0, (pairs, g, stat, s.status())
+        out[(pairs, g, stat)] = F.cpu().numpy()
+        s.close()
+    assert np.array_equal(out[(2, 2, 1)], out[(2, 1, 1)])
+    assert np.array_equal(out[(2, 1, 0)], out[(1, 1, 0)])
+    close(out[(2, 1, 1)], out[(1, 1, 1)], 1e-13, f"groups of four vs pairs ({prec}, {case})")
+    S_ref = F0
+    for n in range(3):
+        S_ref = S.step(ops, S_ref, n * cfg["dt_s"])
+    close(out[(2, 1, 1)], S_ref, 1e-10, f"groups of four vs the oracle ({prec}, {case})")
+
+
 def _grad_case():
     cfg = workloads.small_config(nx=5, nr=6, nth=4, kinds=("elastic", "excitation", "ionization"), E=6e3,
                                  field_kind="rf", n_bins=2)
