@@ -26,13 +26,14 @@ sys.path.insert(0, ROOT)
 MI355X_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 MI355X_PEAK_HBM_GBS = 8000.0
 
-# HBM bytes of the FP32 trailing update (k_update<float, 16, ...>, K = 128 and 256)
+# HBM bytes of the FP32 trailing update (k_update<float, 16, ...>, K = 128 to 512)
 # per launch, averaged over the 15 launches of one factorization at this workload
-# (panels in pairs), from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters
-# read for a 1 GiB copy (x2.0 and x1.0).  Valid for the kernel source it was taken
-# on (hash of kernels_update.hip); reported as null once that file has changed.
-KUPDATE_TRAFFIC = {"source_sha256_16": "380b72ee07cf3be8", "fetch_bytes": 1.145e9, "write_bytes": 6.979e8,
+# (statically pivoted panels in groups of four: 3 launches of K = 512 and 4 each of
+# K = 384, 256, 128), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled
+# by what the same counters read for a 1 GiB copy (x2.0 and x1.0).  Valid for the
+# kernel source it was taken on (hash of kernels_update.hip); reported as null once
+# that file has changed.
+KUPDATE_TRAFFIC = {"source_sha256_16": "015bec2ee3a8e1ba", "fetch_bytes": 1.0484e9, "write_bytes": 3.579e8,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 
