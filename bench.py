@@ -57,9 +57,10 @@ def _update_launches(npad: int, nb: int, group: int = 2):
     panels so far (K = 128 j: that column block read and written, the L rows and
     U columns read), and the last applies the whole group to the columns beyond
     (K = group nb, A22 read and written once); the panels after the last full
-    group go singly (K = nb; pairs: the last two).  The group's earlier panels'
-    updates of a panel's row block are part of its U12 pre-update, not of these
-    launches."""
+    group go singly (K = nb; pairs: the last two).  Groups of four also update
+    the next panel's top rows beyond it with the update kernel (one tile row,
+    K = 128 j, in place); for pairs that update is part of the second panel's
+    U12 pre-update, not of these launches."""
     npan = npad // nb
     out = []
     for p in range(npan):
@@ -75,6 +76,10 @@ def _update_launches(npad: int, nb: int, group: int = 2):
             k = (j + 1) * nb
             if m > 0:
                 out.append((2.0 * m * nb * k, 2 * m * nb + m * k + k * nb))
+            if group == 4 and m > nb:
+                # groups of four: the next panel's top rows beyond it, in place
+                w = m - nb
+                out.append((2.0 * nb * w * k, 2 * nb * w + nb * k + k * w))
         elif j == group - 1:
             k = group * nb
             if m > 0:

@@ -1822,12 +1822,14 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
     }
   };
   if (quads) {
-    // panel p at position j of its group (g0 = p - j): its columns received the
-    // group's earlier panels' updates (one K = 128 j update after panel p-1),
-    // its top rows beyond it get them in the U12 pre-update (K = 128 j); after
-    // it, either the next panel's columns get the updates of panels g0..p, or,
-    // after the group's last panel, the columns beyond the group get all four
-    // (K = 512).  A group that does not fit at the end takes single panels.
+    // panel p at position j of its group (g0 = p - j): its columns and its top
+    // rows beyond it received the group's earlier panels' updates (two K = 128 j
+    // updates in place after panel p-1: the column block, then the row block;
+    // with no interchanges the top rows are the panel's own), so its U12 comes
+    // straight from its rows; after it, either the next panel gets the updates
+    // of panels g0..p the same way, or, after the group's last panel, the
+    // columns beyond the group get all four (K = 512).  A group that does not
+    // fit at the end takes single panels.
     for (int p = 0; p < np; ++p) {
       const int k0 = p * NB;
       const int g0 = p / 4 * 4;
@@ -1844,23 +1846,24 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
         mark(2, p, 1, s);
         mark(3, p, 0, s);
       }
-      if (rest > 0) {
-        if (j > 0) {
-          k_u12pre<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, perm, xs, d.npad, k0, nct, nmat, 1, j);
-          k_u12<T, true><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
-        } else {
-          k_u12<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
-        }
-      }
+      if (rest > 0) k_u12<T><<<xcd_grid(nct, nmat), 256, 0, s>>>(LU, li, perm, xs, d.npad, k0, nct, nmat);
       if (rec) {
         mark(3, p, 1, s);
         mark(0, p, 0, s);
       }
       const int mtr = rest / 128;
       if (mtr > 0) {
-        if (full && j < 3) update(g0 * NB, mtr, 1, (j + 1) * NB);   // the next panel's columns
-        else if (full) update(g0 * NB, mtr, nct, 4 * NB);          // the columns beyond the group
-        else update(k0, mtr, nct, NB);
+        if (full && j < 3) {
+          update(g0 * NB, mtr, 1, (j + 1) * NB);   // the next panel's columns
+          if (nct > 1) {                           // its top rows beyond it
+            launch_update(kind, LU, d.npad, g0 * NB, 1, nct - 1, 1, nmat, alt_kc, s, (j + 1) * NB);
+            if (tm) ++tm->launches;
+          }
+        } else if (full) {
+          update(g0 * NB, mtr, nct, 4 * NB);       // the columns beyond the group
+        } else {
+          update(k0, mtr, nct, NB);
+        }
       }
       if (rec) {
         mark(0, p, 1, s);
