@@ -59,10 +59,10 @@ def _update_launches(npad: int, nb: int, group: int = 2):
     panels so far (K = 128 j: that column block read and written, the L rows and
     U columns read), and the last applies the whole group to the columns beyond
     (K = group nb, A22 read and written once); the panels after the last full
-    group go singly (K = nb; pairs: the last two).  Groups of four also update
-    the next panel's top rows beyond it with the update kernel (one tile row,
-    K = 128 j, in place); for pairs that update is part of the second panel's
-    U12 pre-update, not of these launches."""
+    group go singly (K = nb; pairs: the last two).  In groups of four the same
+    launch also updates the next panel's top rows beyond it (one tile row, in
+    place; its L rows are the column block's first); for pairs that update is
+    part of the second panel's U12 pre-update, not of these launches."""
     npan = npad // nb
     out = []
     for p in range(npan):
@@ -77,11 +77,13 @@ def _update_launches(npad: int, nb: int, group: int = 2):
         if j >= 0 and j < group - 1:
             k = (j + 1) * nb
             if m > 0:
-                out.append((2.0 * m * nb * k, 2 * m * nb + m * k + k * nb))
-            if group == 4 and m > nb:
-                # groups of four: the next panel's top rows beyond it, in place
-                w = m - nb
-                out.append((2.0 * nb * w * k, 2 * nb * w + nb * k + k * w))
+                fl, el = 2.0 * m * nb * k, 2 * m * nb + m * k + k * nb
+                if group == 4 and m > nb:
+                    # groups of four: the same launch updates the next panel's
+                    # top rows beyond it too (in place)
+                    w = m - nb
+                    fl, el = fl + 2.0 * nb * w * k, el + 2 * nb * w + k * w
+                out.append((fl, el))
         elif j == group - 1:
             k = group * nb
             if m > 0:

@@ -235,9 +235,10 @@ void launch_lu_factor(const DevOps& d, int precision, hipStream_t s, LuTimer* ti
 // k0 for nmat matrices (mtr x mtc tiles of 128, column tiles tj0 .. tj0 + mtc - 1
 // of the trailing matrix from k0 + kd): kind 0 FP64, 1 FP32, 2 FP32 with bf16
 // operands, 3 FP32 with split bf16 operands; alt_kc: K chunk 32 (FP32) / 8
-// (FP64) instead of 16.
+// (FP64) instead of 16.  lrow: that many more tiles in the first tile row, after
+// the rectangle's mtc columns (an L-shaped tile set in one launch).
 void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int tj0, int nmat, bool alt_kc,
-                   hipStream_t s, int kd = kNB);
+                   hipStream_t s, int kd = kNB, int lrow = 0);
 // X = LU^-1 B (or LU^-T B with transpose), rows of length npad, FP64 right-hand sides.
 void launch_lu_solve(const DevOps& d, int precision, bool transpose, const double* Bin, double* Xout,
                      bool accumulate, bool check_done, hipStream_t s);

@@ -1823,8 +1823,8 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
   };
   if (quads) {
     // panel p at position j of its group (g0 = p - j): its columns and its top
-    // rows beyond it received the group's earlier panels' updates (two K = 128 j
-    // updates in place after panel p-1: the column block, then the row block;
+    // rows beyond it received the group's earlier panels' updates (one K = 128 j
+    // update in place after panel p-1 over the column block and the row block;
     // with no interchanges the top rows are the panel's own), so its U12 comes
     // straight from its rows; after it, either the next panel gets the updates
     // of panels g0..p the same way, or, after the group's last panel, the
@@ -1854,11 +1854,9 @@ void factor_impl(const DevOps& d, hipStream_t s, LuTimer* tm, int m0, int nmat, 
       const int mtr = rest / 128;
       if (mtr > 0) {
         if (full && j < 3) {
-          update(g0 * NB, mtr, 1, (j + 1) * NB);   // the next panel's columns
-          if (nct > 1) {                           // its top rows beyond it
-            launch_update(kind, LU, d.npad, g0 * NB, 1, nct - 1, 1, nmat, alt_kc, s, (j + 1) * NB);
-            if (tm) ++tm->launches;
-          }
+          // the next panel's columns, and its top rows beyond it (first tile row)
+          launch_update(kind, LU, d.npad, g0 * NB, mtr, 1, 0, nmat, alt_kc, s, (j + 1) * NB, nct - 1);
+          if (tm) ++tm->launches;
         } else if (full) {
           update(g0 * NB, mtr, nct, 4 * NB);       // the columns beyond the group
         } else {

@@ -87,14 +87,16 @@ using bf16x8 = __bf16 __attribute__((ext_vector_type(8)));
 
 template <int NTERMS, int KD>
 __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int npad, int k0, int mtr, int mtc,
-                                                     int tj0, int nmat) {
+                                                     int tj0, int nmat, int lrow) {
   constexpr int KC = 32;
   constexpr int LDK = KC + 8;               // bf16 per row, padded (80 bytes)
   constexpr int NH = (NTERMS == 1) ? 1 : 2;  // hi (and lo) copies
   int mat, tile;
-  xcd_map(blockIdx.x, mtr * mtc, nmat, &mat, &tile);
+  xcd_map(blockIdx.x, mtr * mtc + lrow, nmat, &mat, &tile);
   if (mat >= nmat) return;
-  const int ti = tile % mtr, tj = tile / mtr;
+  // mtr x mtc tiles, then lrow more in the first tile row (columns mtc ..)
+  const bool band = tile >= mtr * mtc;
+  const int ti = band ? 0 : tile % mtr, tj = band ? mtc + (tile - mtr * mtc) : tile / mtr;
   float* A = LU + (size_t)mat * npad * npad;
   const int r0 = k0 + KD + ti * 128, c0 = k0 + KD + (tj0 + tj) * 128;
   // [L21/U12][buffer][hi/lo][row or column][k], or the epilogue's 128 x 132 floats
@@ -194,7 +196,7 @@ __global__ __launch_bounds__(256) void k_update_bf16(float* __restrict__ LU, int
 // ---------------------------------------------------------------------------
 template <typename T, int KC, int P, int MINB, int NPP, int KD>
 __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int npad, int k0, int mtr, int mtc, int tj0,
-                                                      int nmat) {
+                                                      int nmat, int lrow) {
   using V = typename Vec4<T>::type;
   constexpr int PER = Vec4<T>::per;
   // LDS rows of the K chunk (64 banks of 4 bytes).  FP32: a pitch of 144 puts
@@ -209,9 +211,11 @@ __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int np
   constexpr int RP = 128 / P;
   constexpr int LDC = RP + 4 / (sizeof(T) / 4);
   int mat, tile;
-  xcd_map(blockIdx.x, mtr * mtc, nmat, &mat, &tile);
+  xcd_map(blockIdx.x, mtr * mtc + lrow, nmat, &mat, &tile);
   if (mat >= nmat) return;
-  const int ti = tile % mtr, tj = tile / mtr;
+  // mtr x mtc tiles, then lrow more in the first tile row (columns mtc ..)
+  const bool band = tile >= mtr * mtc;
+  const int ti = band ? 0 : tile % mtr, tj = band ? mtc + (tile - mtr * mtc) : tile / mtr;
   T* A = LU + (size_t)mat * npad * npad;
   const int r0 = k0 + KD + ti * 128, c0 = k0 + KD + (tj0 + tj) * 128;
   constexpr int OPER = 2 * 2 * KC * LD;
@@ -336,22 +340,22 @@ __global__ __launch_bounds__(256, MINB) void k_update(T* __restrict__ LU, int np
 
 template <int KD>
 void launch_update_k(int kind, void* LU, int npad, int k0, int mtr, int mtc, int tj0, int nmat, bool alt_kc,
-                     hipStream_t s) {
-  const dim3 gu = xcd_grid(mtr * mtc, nmat);
+                     hipStream_t s, int lrow) {
+  const dim3 gu = xcd_grid(mtr * mtc + lrow, nmat);
   switch (kind) {
     case 0:
-      if (alt_kc) k_update<double, 8, 4, 2, 1, KD><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, tj0, nmat);
-      else k_update<double, 16, 4, 2, 1, KD><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      if (alt_kc) k_update<double, 8, 4, 2, 1, KD><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, tj0, nmat, lrow);
+      else k_update<double, 16, 4, 2, 1, KD><<<gu, 256, 0, s>>>(static_cast<double*>(LU), npad, k0, mtr, mtc, tj0, nmat, lrow);
       break;
     case 2:
-      k_update_bf16<1, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      k_update_bf16<1, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat, lrow);
       break;
     case 3:
-      k_update_bf16<3, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      k_update_bf16<3, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat, lrow);
       break;
     default:
-      if (alt_kc) k_update<float, 32, 1, 2, 1, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
-      else k_update<float, 16, 4, 4, 1, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat);
+      if (alt_kc) k_update<float, 32, 1, 2, 1, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat, lrow);
+      else k_update<float, 16, 4, 4, 1, KD><<<gu, 256, 0, s>>>(static_cast<float*>(LU), npad, k0, mtr, mtc, tj0, nmat, lrow);
       break;
   }
 }
@@ -359,12 +363,12 @@ void launch_update_k(int kind, void* LU, int npad, int k0, int mtr, int mtc, int
 }  // namespace
 
 void launch_update(int kind, void* LU, int npad, int k0, int mtr, int mtc, int tj0, int nmat, bool alt_kc,
-                   hipStream_t s, int kd) {
+                   hipStream_t s, int kd, int lrow) {
   switch (kd) {
-    case 4 * NB: launch_update_k<4 * NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s); break;
-    case 3 * NB: launch_update_k<3 * NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s); break;
-    case 2 * NB: launch_update_k<2 * NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s); break;
-    default: launch_update_k<NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s); break;
+    case 4 * NB: launch_update_k<4 * NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s, lrow); break;
+    case 3 * NB: launch_update_k<3 * NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s, lrow); break;
+    case 2 * NB: launch_update_k<2 * NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s, lrow); break;
+    default: launch_update_k<NB>(kind, LU, npad, k0, mtr, mtc, tj0, nmat, alt_kc, s, lrow); break;
   }
 }
 
