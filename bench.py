@@ -27,14 +27,14 @@ MI355X_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 MI355X_PEAK_HBM_GBS = 8000.0
 
 # HBM bytes of the FP32 trailing update (k_update<float, 16, ...>, K = 128 to 512)
-# per launch, averaged over the 26 launches of one factorization at this workload
-# (statically pivoted panels in groups of four: 3 launches of K = 512, and 4 each
-# of K = 128, 256, 384 on the next panel's columns, 11 more on its top rows), from
-# two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same
+# per launch, averaged over the 15 launches of one factorization at this workload
+# (statically pivoted panels in groups of four: 3 launches of K = 512 beyond a
+# group, and 4 each of K = 128, 256, 384 on the next panel's columns and top rows),
+# from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same
 # counters read for a 1 GiB copy (x2.0 and x1.0).  Valid for the sources it was
 # taken on (hash of kernels_update.hip, the kernels, then kernels_lu.hip, the
 # launch schedule); reported as null once either has changed.
-KUPDATE_TRAFFIC = {"source_sha256_16": "3590981e76e895dc", "fetch_bytes": 7.963e8, "write_bytes": 2.607e8,
+KUPDATE_TRAFFIC = {"source_sha256_16": "f740e4d599c1363f", "fetch_bytes": 1.3349e+09, "write_bytes": 4.5187e+08,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 

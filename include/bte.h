@@ -414,11 +414,11 @@ bte_status bte_get_timing(bte_handle* h, double* ms_out);
  *     factors then store each pair's second interchanges in the first panel's L
  *     rows as well (the solves follow).  2: statically pivoted dense factors
  *     take groups of four panels (the next panel's columns and top rows get the
- *     group's earlier panels' updates at depth 128 j, in place, the columns
- *     beyond the group one update of depth 512; a last group that does not fit
- *     goes singly); other factors take pairs.  Measured at Nx = 256, n = 2048:
- *     18.1 ms per FP32 step against 18.5 with pairs (BF16x3 14.5 against
- *     15.1).  0: single panels.  Unlike the other keys this one changes the
+ *     group's earlier panels' updates at depth 128 j, in place and in one
+ *     launch, the columns beyond the group one update of depth 512; a last
+ *     group that does not fit goes singly); other factors take pairs.  Measured
+ *     at Nx = 256, n = 2048: 17.8 ms per FP32 step against 18.5 with pairs
+ *     (BF16x3 14.45 against 15.15).  0: single panels.  Unlike the other keys this one changes the
  *     rounding of the trailing updates (not the pivots of a well-separated
  *     column); it only takes effect at the next factorization.
  *   BTE_TUNE_STATIC_PIVOTING: 0 or 1 (default 1 for the mixed precisions, 0 for
