@@ -34,7 +34,7 @@ MI355X_PEAK_HBM_GBS = 8000.0
 # counters read for a 1 GiB copy (x2.0 and x1.0).  Valid for the sources it was
 # taken on (hash of kernels_update.hip, the kernels, then kernels_lu.hip, the
 # launch schedule); reported as null once either has changed.
-KUPDATE_TRAFFIC = {"source_sha256_16": "f740e4d599c1363f", "fetch_bytes": 1.3349e+09, "write_bytes": 4.5187e+08,
+KUPDATE_TRAFFIC = {"source_sha256_16": "5fec9a410800504f", "fetch_bytes": 1.3351e+09, "write_bytes": 4.5187e+08,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 

@@ -24,8 +24,9 @@
 //             substitution's sequential 16-row steps are paid once per panel
 //             in k_l11inv instead of once per column block;
 //   k_update  A22 -= L21 U12: 128 x 128 MFMA tiles, K = 128 (or 256, two
-//             panels) in double-buffered LDS chunks; blocks of one matrix are
-//             kept on one XCD so that L21 and U12 stay in that XCD's L2.
+//             panels; up to 512, four) in double-buffered LDS chunks; blocks of
+//             one matrix are kept on one XCD so that L21 and U12 stay in that
+//             XCD's L2.
 // Dense systems take the panels in pairs: panel p updates panel p+1's columns
 // at once, its update of the columns beyond is deferred, and after panel p+1
 // one K = 256 update applies both (A22 read and written once per two panels).
@@ -37,7 +38,13 @@
 // interchanges: each panel is k_diag_static (the 128 x 128 diagonal block's
 // factors, U11^-1, L11^-1 and the inverses of L11's diagonal blocks, in
 // place of k_panel, k_dinv and k_l11inv) and k_l21_mfma (L21 = A21 U11^-1),
-// and k_move_down and k_perm_lp have nothing to move (see below).
+// and k_move_down and k_perm_lp have nothing to move (see below).  Their
+// panels go in groups of four: after each of a group's first three panels,
+// one k_update launch over an L-shaped tile set applies the group's panels so
+// far (K = 128 j) to the next panel's columns and to its top rows beyond it
+// (in place: the top rows are the panel's own), and after the group's last
+// panel one K = 512 update applies all four to the columns beyond the group
+// (A22 read and written once per four panels).
 #include <algorithm>
 #include <cfloat>
 #include <climits>
